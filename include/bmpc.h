@@ -1,0 +1,159 @@
+/*
+ * bmpc.h -- C ABI of the MI355X branch-MPC hot path (libbmpc.so).
+ *
+ * The library solves branch model predictive control (BMPC) problems on a
+ * trajectory tree with an augmented-Lagrangian multiple-shooting iLQR whose
+ * inner step is a tree LQR (Riccati recursion with an exact merge of the
+ * children's value functions at every branching node).
+ *
+ * General conventions
+ *  - Every call returns a bmpc_status.  BMPC_OK = 0.  On failure,
+ *    bmpc_last_error() returns a thread-local message (with the node id for
+ *    BMPC_ERR_NOT_PD).
+ *  - Opaque handles (bmpc_tree, bmpc_lqr_plan, bmpc_problem, bmpc_batch,
+ *    bmpc_mlp) are owned by the library: every *_create has a *_destroy.
+ *  - Arrays passed to the library are owned by the caller.  Each argument
+ *    states whether it is a host pointer or a device pointer (device = HBM
+ *    memory of the current HIP device, e.g. torch.Tensor.data_ptr()).
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *    that take a stream are asynchronous on it unless stated otherwise.
+ *  - Handles are not thread-safe; separate handles are independent.
+ *  - All floating point is FP64 except the warm-starter network (BF16
+ *    weights and activations, FP32 accumulation and master weights).
+ *
+ * Trees
+ *  parent[0] = -1, 0 <= parent[i] < i, and parent[] non-decreasing for i >= 1.
+ *  This is the stage-major breadth-first order: the nodes of one stage are
+ *  contiguous and the children of one node are contiguous.  Other orders are
+ *  rejected with BMPC_ERR_TOPOLOGY.  The stage of a node is its depth; a
+ *  leaf is a node with no children; "control nodes" are all other nodes.
+ *  Dynamics are stored on the edge, i.e. at the child: (A_j, B_j, c_j) at
+ *  node j describe x_j = A_j x_{p(j)} + B_j u_{p(j)} + c_j.  Entries of the
+ *  root (j = 0) are ignored.
+ *
+ * Matrix layouts (per plan; see bmpc_lqr_plan_create)
+ *  BMPC_LAYOUT_NODE_MAJOR: entry (r, c) of the matrix of node i at
+ *      X[(i * rows + r) * cols + c]   (each node's matrix contiguous, row-major)
+ *  BMPC_LAYOUT_ELEM_MAJOR: entry (r, c) of the matrix of node i at
+ *      X[(r * cols + c) * N + i]      (structure of arrays: one array per entry)
+ *  Vectors follow the same rule with cols = 1.
+ */
+#ifndef BMPC_H
+#define BMPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BMPC_API __attribute__((visibility("default")))
+
+typedef int32_t bmpc_status;
+enum {
+    BMPC_OK = 0,
+    BMPC_ERR_INVALID_ARG = 1,
+    BMPC_ERR_TOPOLOGY = 2,
+    BMPC_ERR_NOT_PD = 3,     /* a Riccati Hessian H_n was not positive definite */
+    BMPC_ERR_NONFINITE = 4,  /* NaN/Inf met in the iteration */
+    BMPC_ERR_MAXITER = 5,    /* iteration cap reached; outputs hold the last iterate */
+    BMPC_ERR_LINESEARCH = 6, /* no step size accepted several times in a row */
+    BMPC_ERR_HIP = 7,        /* a HIP runtime call failed */
+    BMPC_ERR_OOM = 8,        /* device or host allocation failed */
+    BMPC_ERR_UNSUPPORTED = 9 /* dimension or variant not built into this library */
+};
+
+enum { BMPC_LAYOUT_NODE_MAJOR = 0, BMPC_LAYOUT_ELEM_MAJOR = 1 };
+
+/* Backward-pass variants of the tree LQR. */
+enum {
+    BMPC_RICCATI_AUTO = 0,
+    /* level-parallel: every node of one depth is processed at the same time;
+       branch nodes are merged by the last child to finish (no grid barrier) */
+    BMPC_RICCATI_LEVEL = 1,
+    /* log-depth: associative scan of conditional value functions along each
+       unbranched segment, exact merges at branching nodes */
+    BMPC_RICCATI_SEGSCAN = 2
+};
+
+/* Message of the last failed call on this thread ("" if none). */
+BMPC_API const char* bmpc_last_error(void);
+/* Library version: major*10000 + minor*100 + patch. */
+BMPC_API int32_t bmpc_version(void);
+/* Number of HIP devices visible to the library (0 if none).  Host only; it
+   touches the HIP runtime. */
+BMPC_API int32_t bmpc_device_count(void);
+
+/* ------------------------------------------------------------------------
+ * Topology: tree index sets of the problem statement (Sec. II-B): parent
+ * p(i), children ch(i), stage sets N_k, leaves L.
+ * ---------------------------------------------------------------------- */
+typedef struct bmpc_tree bmpc_tree;
+
+/* parent: host pointer, num_nodes entries, order rules above.  The tree is
+   analysed on the host (stages, children, maximal unbranched segments,
+   root-to-leaf paths) and uploaded to the current device. */
+BMPC_API bmpc_status bmpc_tree_create(const int32_t* parent, int32_t num_nodes, bmpc_tree** out);
+BMPC_API void bmpc_tree_destroy(bmpc_tree* tree);
+/* Host outputs; any pointer may be NULL.  depth = largest stage;
+   num_segments = number of maximal unbranched segments (a segment starts at
+   the root or at a child of a node with >= 2 children and ends at a leaf or
+   at a node with >= 2 children). */
+BMPC_API bmpc_status bmpc_tree_info(const bmpc_tree* tree, int32_t* num_nodes, int32_t* num_leaves,
+                                    int32_t* depth, int32_t* num_segments);
+/* Segment id of every node (host output, num_nodes entries); segments are
+   numbered by increasing start node. */
+BMPC_API bmpc_status bmpc_tree_segments(const bmpc_tree* tree, int32_t* seg_of_node);
+/* Node probability weights: pi_n = total probability of the leaves below n.
+   leaf_prob: host, one entry per leaf in increasing node order.
+   node_weight: host output, num_nodes entries. */
+BMPC_API bmpc_status bmpc_weights_from_probs(const bmpc_tree* tree, const double* leaf_prob,
+                                             double* node_weight);
+
+/* ------------------------------------------------------------------------
+ * Tree LQR (Sec. III, eq. lqr_tree_approx; recursion of eq. tree_Riccati with
+ * the gains of eq. tree_feedback_laws; forward rollout of eq.
+ * forward_comb_rule along every root-to-leaf path).
+ *
+ *   min  sum_{n control} 1/2 [x;u]^T [[Q_n, M_n^T],[M_n, R_n]] [x;u] + q_n^T x + r_n^T u
+ *      + sum_{l leaf} 1/2 x^T Q_l x + q_l^T x
+ *   s.t. x_0 = x0,  x_j = A_j x_{p(j)} + B_j u_{p(j)} + c_j.
+ *
+ * Outputs: the minimiser (x, u), the costates lam_j = P_j x_j + p_j (the
+ * multipliers of the dynamics in the convention L = cost + lam^T (f - x)),
+ * and optionally the gains K, k and value functions P, p.
+ * ---------------------------------------------------------------------- */
+typedef struct bmpc_lqr_plan bmpc_lqr_plan;
+
+/* Allocates device workspace for a tree and dimensions (nx, nu).
+   layout: BMPC_LAYOUT_*.  Returns BMPC_ERR_UNSUPPORTED if (nx, nu) has no
+   compiled kernel (see bmpc_lqr_supported). */
+BMPC_API bmpc_status bmpc_lqr_plan_create(const bmpc_tree* tree, int32_t nx, int32_t nu,
+                                          int32_t layout, bmpc_lqr_plan** out);
+BMPC_API void bmpc_lqr_plan_destroy(bmpc_lqr_plan* plan);
+/* 1 if kernels for (nx, nu, variant) are compiled in, else 0. */
+BMPC_API int32_t bmpc_lqr_supported(int32_t nx, int32_t nu, int32_t variant);
+
+/* All array arguments are DEVICE pointers in the plan's layout, N = number of
+   nodes.  Sizes: A N*nx*nx, B N*nx*nu, c N*nx (edge data, root ignored);
+   Q N*nx*nx, q N*nx (terminal cost at leaves); R N*nu*nu, M N*nu*nx, r N*nu
+   (control nodes; leaf entries ignored); x0 nx.  Outputs x N*nx, u N*nu
+   (leaf entries set to 0), lam N*nx; K N*nu*nx, k N*nu, P N*nx*nx, p N*nx
+   may be NULL (then plan workspace is used).  Inputs and outputs must not
+   overlap.  Asynchronous on `stream`.  A non-positive-definite H_n is
+   reported by bmpc_lqr_check (the affected outputs are then undefined). */
+BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* plan, const double* A, const double* B,
+                                    const double* c, const double* Q, const double* R,
+                                    const double* M, const double* q, const double* r,
+                                    const double* x0, double* x, double* u, double* lam,
+                                    double* K, double* k, double* P, double* p, int32_t variant,
+                                    void* stream);
+/* Synchronises `stream` and reports the numerical status of the last solve
+   on this plan: BMPC_OK, or BMPC_ERR_NOT_PD with *bad_node set (smallest
+   failing node id).  bad_node may be NULL. */
+BMPC_API bmpc_status bmpc_lqr_check(bmpc_lqr_plan* plan, int32_t* bad_node, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BMPC_H */

@@ -1,0 +1,339 @@
+"""CPU FP64 oracle for the branch-MPC hot path (ctypes front end).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+CPU-baseline leg of the benchmark are the only users.  The HIP library never
+loads or calls anything in this package, and this package imports nothing
+from the library.
+
+The C sources (``oracle_lqr.c``, ``oracle_bmpc.c``) hold the arithmetic;
+this module only converts NumPy arrays to pointers.  ``cvf.py`` holds the
+conditional-value-function algebra of the parallel-scan LQR, in NumPy.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SOURCES = ["oracle_lqr.c", "oracle_bmpc.c", "oracle_mlp.c"]
+
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "TOPOLOGY", 3: "NOT_PD", 4: "NONFINITE",
+          5: "MAXITER", 6: "LINESEARCH"}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2; no target-specific flags so the
+    library runs on any x86-64 host)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    srcs = [os.path.join(_HERE, s) for s in SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
+           "-o", tmp] + srcs + ["-lm", "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+class Model(C.Structure):
+    _fields_ = [("model", C.c_int), ("wheelbase", C.c_double), ("dt", C.c_double),
+                ("Qd", C.c_double * 4), ("Rd", C.c_double * 2), ("a_max", C.c_double),
+                ("steer_max", C.c_double), ("obs_r", C.c_double), ("Al", C.c_double * 16),
+                ("Bl", C.c_double * 8)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("N", C.c_int), ("parent", _ip), ("weight", _dp), ("ref", _dp), ("obs", _dp),
+                ("has_obs", _ip), ("x0", _dp), ("model", Model)]
+
+
+class Settings(C.Structure):
+    _fields_ = [("eps_tol", C.c_double), ("tau", C.c_double), ("omega0", C.c_double),
+                ("eta0", C.c_double), ("a_omega", C.c_double), ("b_omega", C.c_double),
+                ("a_eta", C.c_double), ("b_eta", C.c_double), ("rho0", C.c_double),
+                ("mu0", C.c_double), ("armijo_beta", C.c_double), ("n_alpha", C.c_int),
+                ("max_outer", C.c_int), ("max_inner", C.c_int), ("max_ls_fail", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("status", C.c_int), ("outer_it", C.c_int), ("inner_it", C.c_int),
+                ("ls_failures", C.c_int), ("bad_node", C.c_int), ("r_kkt", C.c_double),
+                ("viol", C.c_double), ("rho", C.c_double), ("mu", C.c_double),
+                ("merit", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _declare(L):
+    L.orc_tree_lqr.restype = C.c_int
+    L.orc_tree_lqr.argtypes = [C.c_int, C.c_int, C.c_int, _ip] + [_dp] * 9 + [_dp] * 7 + [_ip]
+    L.orc_settings_default.argtypes = [C.POINTER(Settings)]
+    L.orc_bmpc_solve.restype = C.c_int
+    L.orc_bmpc_solve.argtypes = [C.POINTER(Problem), C.POINTER(Settings), C.c_int, _dp, _dp,
+                                 _dp, _dp, C.POINTER(Stats), _dp, C.c_int]
+    L.orc_rk4.argtypes = [C.POINTER(Model), _dp, _dp, _dp, _dp, _dp]
+    L.orc_node_weights.argtypes = [C.c_int, _ip, _dp, _dp]
+    L.orc_node_refs.argtypes = [C.c_int, _ip, _dp, _dp, C.c_double, C.c_double, _dp]
+    L.orc_node_terms.restype = C.c_double
+    L.orc_node_terms.argtypes = [C.POINTER(Problem), C.c_int, _dp, _dp, _dp, C.c_double, _dp,
+                                 _dp, _dp, _dp, _dp]
+    for name in ("orc_augmented_lagrangian", "orc_violation"):
+        getattr(L, name).restype = C.c_double
+        getattr(L, name).argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_double]
+    L.orc_merit.restype = C.c_double
+    L.orc_merit.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, C.c_double, C.c_double]
+    L.orc_kkt.restype = C.c_double
+    L.orc_kkt.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, C.c_double]
+    L.orc_adjoint.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_double, _dp]
+    L.orc_rollout.argtypes = [C.POINTER(Problem), _dp, _dp]
+    if hasattr(L, "orc_mlp_forward"):
+        _declare_mlp(L)
+
+
+def _declare_mlp(L):
+    L.orc_mlp_forward.argtypes = [C.c_int, _ip, C.c_int, _dp, _dp, _dp, _dp]
+    L.orc_mlp_backward.argtypes = [C.c_int, _ip, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+# ----------------------------------------------------------------------------
+# tree LQR
+# ----------------------------------------------------------------------------
+
+def tree_lqr(parent, A, B, c, Q, R, M, q, r, x0):
+    """Serial tree Riccati (node-major arrays).  Returns a dict with x, u, lam,
+    K, k, P, p; raises on a non-OK status."""
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    N = len(parent)
+    nx = np.shape(A)[1]
+    nu = np.shape(B)[2]
+    A, B, c, Q, R, M, q, r, x0 = (_f64(v) for v in (A, B, c, Q, R, M, q, r, x0))
+    out = {"x": np.zeros((N, nx)), "u": np.zeros((N, nu)), "lam": np.zeros((N, nx)),
+           "K": np.zeros((N, nu, nx)), "k": np.zeros((N, nu)), "P": np.zeros((N, nx, nx)),
+           "p": np.zeros((N, nx))}
+    bad = np.array([-1], dtype=np.int32)
+    st = lib().orc_tree_lqr(N, nx, nu, _i(parent), _d(A), _d(B), _d(c), _d(Q), _d(R), _d(M),
+                            _d(q), _d(r), _d(x0), _d(out["x"]), _d(out["u"]), _d(out["lam"]),
+                            _d(out["K"]), _d(out["k"]), _d(out["P"]), _d(out["p"]), _i(bad))
+    if st != 0:
+        raise OracleError(st, int(bad[0]))
+    return out
+
+
+def tree_lqr_inst(inst):
+    return tree_lqr(inst.parent, inst.A, inst.B, inst.c, inst.Q, inst.R, inst.M, inst.q,
+                    inst.r, inst.x0)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status, node=-1):
+        super().__init__(f"oracle status {STATUS.get(status, status)} (node {node})")
+        self.status = status
+        self.node = node
+
+
+# ----------------------------------------------------------------------------
+# branch-MPC problem
+# ----------------------------------------------------------------------------
+
+def default_settings(**kw) -> Settings:
+    s = Settings()
+    lib().orc_settings_default(C.byref(s))
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def node_weights(parent, leaf_prob):
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    lp = _f64(leaf_prob)
+    w = np.zeros(len(parent))
+    lib().orc_node_weights(len(parent), _i(parent), _d(lp), _d(w))
+    return w
+
+
+def node_refs(parent, leaf_prob, leaf_offset, dt, speed):
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    ref = np.zeros((len(parent), 4))
+    lib().orc_node_refs(len(parent), _i(parent), _d(_f64(leaf_prob)), _d(_f64(leaf_offset)),
+                        dt, speed, _d(ref))
+    return ref
+
+
+class BmpcProblem:
+    """Holds the arrays a ctypes ``Problem`` points to (keeps them alive)."""
+
+    def __init__(self, parent, weight, ref, node_obs_xy, has_obs, x0, model: Model):
+        self.parent = np.ascontiguousarray(parent, dtype=np.int32)
+        self.N = len(self.parent)
+        self.weight = _f64(weight)
+        self.ref = _f64(ref, (self.N, 4))
+        self.obs = _f64(node_obs_xy, (self.N, 2))
+        self.has_obs = np.ascontiguousarray(has_obs, dtype=np.int32)
+        self.x0 = _f64(x0)
+        self.model = model
+        self.c = Problem(self.N, _i(self.parent), _d(self.weight), _d(self.ref), _d(self.obs),
+                         _i(self.has_obs), _d(self.x0), model)
+
+    @property
+    def ptr(self):
+        return C.byref(self.c)
+
+
+def bicycle_model(inst) -> Model:
+    m = Model()
+    m.model = 0
+    m.wheelbase = inst.wheelbase
+    m.dt = inst.dt
+    for i in range(4):
+        m.Qd[i] = inst.q_diag[i]
+    for i in range(2):
+        m.Rd[i] = inst.r_diag[i]
+    m.a_max = inst.a_max
+    m.steer_max = inst.steer_max
+    m.obs_r = inst.obs_radius
+    return m
+
+
+def linear_model(Al, Bl, q_diag, r_diag, a_max=1e3, steer_max=1e3, obs_r=1.5, dt=0.1) -> Model:
+    m = Model()
+    m.model = 1
+    m.dt = dt
+    m.wheelbase = 1.0
+    for i in range(4):
+        m.Qd[i] = q_diag[i]
+    for i in range(2):
+        m.Rd[i] = r_diag[i]
+    m.a_max = a_max
+    m.steer_max = steer_max
+    m.obs_r = obs_r
+    for i, v in enumerate(np.asarray(Al, np.float64).ravel()):
+        m.Al[i] = v
+    for i, v in enumerate(np.asarray(Bl, np.float64).ravel()):
+        m.Bl[i] = v
+    return m
+
+
+def problem_from_instance(inst, x0=None) -> BmpcProblem:
+    w = node_weights(inst.parent, inst.leaf_prob)
+    ref = node_refs(inst.parent, inst.leaf_prob, inst.leaf_offset, inst.dt, inst.ref_speed)
+    has = (inst.node_obstacle >= 0).astype(np.int32)
+    xy = np.zeros((inst.num_nodes, 2))
+    if len(inst.obstacles):
+        xy[has == 1] = inst.obstacles[inst.node_obstacle[has == 1]]
+    return BmpcProblem(inst.parent, w, ref, xy, has, inst.x0 if x0 is None else x0,
+                       bicycle_model(inst))
+
+
+def solve(pb: BmpcProblem, settings: Settings | None = None, warm=None, hist_cap=4096):
+    """Run the AL multiple-shooting iLQR.  ``warm`` may be a dict with any of
+    x, u, lam, ye.  Returns (state dict, stats dict, history array)."""
+    st = settings if settings is not None else default_settings()
+    N = pb.N
+    x = np.zeros((N, 4))
+    u = np.zeros((N, 2))
+    lam = np.zeros((N, 4))
+    ye = np.zeros((N, 5))
+    bits = 0
+    if warm:
+        if "x" in warm and "u" in warm:
+            x[:] = warm["x"]
+            u[:] = warm["u"]
+            bits |= 1
+        if "lam" in warm:
+            lam[:] = warm["lam"]
+            bits |= 2
+        if "ye" in warm:
+            ye[:] = warm["ye"]
+            bits |= 4
+    stats = Stats()
+    hist = np.zeros((hist_cap, 6))
+    lib().orc_bmpc_solve(pb.ptr, C.byref(st), bits, _d(x), _d(u), _d(lam), _d(ye),
+                         C.byref(stats), _d(hist), hist_cap)
+    s = stats.as_dict()
+    return {"x": x, "u": u, "lam": lam, "ye": ye}, s, hist[: s["inner_it"]]
+
+
+def rk4(model: Model, x, u):
+    x = _f64(x)
+    u = _f64(u)
+    xn = np.zeros(4)
+    A = np.zeros((4, 4))
+    B = np.zeros((4, 2))
+    lib().orc_rk4(C.byref(model), _d(x), _d(u), _d(xn), _d(A), _d(B))
+    return xn, A, B
+
+
+def node_terms(pb: BmpcProblem, n, x, u, ye, rho):
+    g = np.zeros(5)
+    gx = np.zeros(4)
+    gu = np.zeros(2)
+    Hxx = np.zeros((4, 4))
+    Huu = np.zeros((2, 2))
+    v = lib().orc_node_terms(pb.ptr, n, _d(_f64(x)), _d(_f64(u)), _d(_f64(ye)), rho, _d(g),
+                             _d(gx), _d(gu), _d(Hxx), _d(Huu))
+    return v, g, gx, gu, Hxx, Huu
+
+
+def augmented_lagrangian(pb, x, u, ye, rho):
+    return lib().orc_augmented_lagrangian(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(ye)), rho)
+
+
+def merit(pb, x, u, lam, ye, rho, mu):
+    return lib().orc_merit(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(lam)), _d(_f64(ye)), rho, mu)
+
+
+def kkt(pb, x, u, lam, ye, rho):
+    return lib().orc_kkt(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(lam)), _d(_f64(ye)), rho)
+
+
+def violation(pb, x, u, ye, rho):
+    return lib().orc_violation(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(ye)), rho)
+
+
+def adjoint(pb, x, u, ye, rho):
+    lam = np.zeros((pb.N, 4))
+    lib().orc_adjoint(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(ye)), rho, _d(lam))
+    return lam
+
+
+def rollout(pb, u):
+    x = np.zeros((pb.N, 4))
+    lib().orc_rollout(pb.ptr, _d(_f64(u)), _d(x))
+    return x

@@ -1,0 +1,112 @@
+/*
+ * CPU FP64 oracle for the branch-MPC hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the HIP path: only
+ * the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * may load it.  It shares no code with the HIP library and includes nothing
+ * from it.  Everything here is plain, serial, double-precision C written
+ * for readability, not speed.
+ *
+ * Array conventions (oracle only): node-major, row-major matrices, i.e.
+ * A[i*nx*nx + r*nx + c] is entry (r, c) of the matrix of node i.
+ * Tree: parent[0] = -1 and 0 <= parent[i] < i for i >= 1.
+ * Edge-indexed dynamics: (A_i, B_i, c_i) stored at node i describe the
+ * transition from parent(i) into i:  x_i = A_i x_p + B_i u_p + c_i.
+ */
+#ifndef BMPC_ORACLE_H
+#define BMPC_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ORC_OK = 0,
+    ORC_ERR_INVALID_ARG = 1,
+    ORC_ERR_TOPOLOGY = 2,
+    ORC_ERR_NOT_PD = 3,
+    ORC_ERR_NONFINITE = 4,
+    ORC_ERR_MAXITER = 5,
+    ORC_ERR_LINESEARCH = 6
+};
+
+/* ---- tree LQR (serial tree Riccati), oracle_lqr.c ---------------------- */
+int orc_tree_lqr(int N, int nx, int nu, const int* parent,
+                 const double* A, const double* B, const double* c,
+                 const double* Q, const double* R, const double* M,
+                 const double* q, const double* r, const double* x0,
+                 double* x, double* u, double* lam,
+                 double* K, double* k, double* P, double* p, int* bad_node);
+
+/* ---- branch-MPC problem and AL multiple-shooting iLQR, oracle_bmpc.c ---- */
+#define ORC_NX 4
+#define ORC_NU 2
+#define ORC_NG 5 /* constraint slots per node: 4 input bounds + 1 obstacle */
+
+typedef struct {
+    int model;          /* 0 = kinematic bicycle (RK4), 1 = linear x+ = Al x + Bl u */
+    double wheelbase;   /* bicycle wheelbase L */
+    double dt;          /* step */
+    double Qd[4];       /* diagonal state weight */
+    double Rd[2];       /* diagonal input weight */
+    double a_max;       /* |u0| <= a_max */
+    double steer_max;   /* |u1| <= steer_max */
+    double obs_r;       /* obstacle radius */
+    double Al[16];      /* linear model only */
+    double Bl[8];       /* linear model only */
+} orc_model;
+
+typedef struct {
+    int N;
+    const int* parent;
+    const double* weight;    /* (N) node probability weight pi_n */
+    const double* ref;       /* (N,4) node reference */
+    const double* obs;       /* (N,2) obstacle centre used by node n */
+    const int* has_obs;      /* (N) 1 if node n carries the obstacle constraint */
+    const double* x0;        /* (4) */
+    orc_model model;
+} orc_problem;
+
+typedef struct {
+    double eps_tol, tau, omega0, eta0, a_omega, b_omega, a_eta, b_eta;
+    double rho0, mu0, armijo_beta;
+    int n_alpha, max_outer, max_inner, max_ls_fail;
+} orc_settings;
+
+typedef struct {
+    int status, outer_it, inner_it, ls_failures, bad_node;
+    double r_kkt, viol, rho, mu, merit;
+} orc_stats;
+
+void orc_settings_default(orc_settings* s);
+
+/* warm bits: 1 = x,u supplied, 2 = lam supplied, 4 = ye supplied */
+int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm,
+                   double* x, double* u, double* lam, double* ye,
+                   orc_stats* stats, double* hist, int hist_cap);
+
+/* pieces exported for pinning */
+void orc_rk4(const orc_model* m, const double* x, const double* u, double* xn,
+             double* A, double* B);
+void orc_node_weights(int N, const int* parent, const double* leaf_prob, double* weight);
+void orc_node_refs(int N, const int* parent, const double* leaf_prob, const double* leaf_offset,
+                   double dt, double speed, double* ref);
+double orc_node_terms(const orc_problem* pb, int n, const double* x, const double* u,
+                      const double* ye, double rho, double* g, double* gx, double* gu,
+                      double* Hxx, double* Huu);
+double orc_augmented_lagrangian(const orc_problem* pb, const double* x, const double* u,
+                                const double* ye, double rho);
+double orc_merit(const orc_problem* pb, const double* x, const double* u, const double* lam,
+                 const double* ye, double rho, double mu);
+double orc_kkt(const orc_problem* pb, const double* x, const double* u, const double* lam,
+               const double* ye, double rho);
+double orc_violation(const orc_problem* pb, const double* x, const double* u,
+                     const double* ye, double rho);
+void orc_adjoint(const orc_problem* pb, const double* x, const double* u,
+                 const double* ye, double rho, double* lam);
+void orc_rollout(const orc_problem* pb, const double* u, double* x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
