@@ -1,0 +1,154 @@
+"""GPU tree LQR vs the CPU oracle (serial tree Riccati), through the C ABI.
+
+Tolerance: normwise relative 1e-9 per output array,
+||a_gpu - a_ref||_inf / ||a_ref||_inf <= 1e-9, for x, u, lam, K, k, P, p.
+"""
+import numpy as np
+import pytest
+
+import bmpc_synth as S
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2506_13624_amd import _lib as L  # noqa: E402
+from paper_2506_13624_amd.layout import empty, from_device, to_device  # noqa: E402
+
+TOL = 1e-9
+
+
+def relerr(a, b):
+    den = max(np.abs(b).max(), 1e-300)
+    return np.abs(a - b).max() / den
+
+
+def random_bfs_tree(seed, depth, max_children=3):
+    rng = np.random.default_rng(seed)
+    parent = [-1]
+    level = [0]
+    for d in range(depth):
+        nxt = []
+        for p in level:
+            k = int(rng.integers(0 if d > 1 else 1, max_children + 1))
+            for _ in range(k):
+                parent.append(p)
+                nxt.append(len(parent) - 1)
+        if not nxt:
+            parent.append(level[-1])
+            nxt.append(len(parent) - 1)
+        level = nxt
+    return np.array(parent, dtype=np.int32)
+
+
+def gpu_lqr(inst, layout, variant=L.RICCATI_AUTO, want_gains=True, repeat=1):
+    par = inst.parent
+    N = len(par)
+    nx, nu = inst.nx, inst.nu
+    tree = L.bmpc_tree_create(par)
+    plan = L.bmpc_lqr_plan_create(tree, nx, nu, layout)
+    try:
+        dev = {k: to_device(getattr(inst, k), layout) for k in "ABcQRMqr"}
+        x0 = to_device(inst.x0, layout)
+        out = {"x": empty((N, nx)), "u": empty((N, nu)), "lam": empty((N, nx))}
+        if want_gains:
+            out.update({"K": empty((N, nu, nx)), "k": empty((N, nu)), "P": empty((N, nx, nx)),
+                        "p": empty((N, nx))})
+        res = []
+        for _ in range(repeat):
+            L.bmpc_lqr_solve(plan, dev["A"], dev["B"], dev["c"], dev["Q"], dev["R"], dev["M"],
+                             dev["q"], dev["r"], x0, out["x"], out["u"], out["lam"], out.get("K"),
+                             out.get("k"), out.get("P"), out.get("p"), variant=variant)
+            st, bad = L.bmpc_lqr_check(plan)
+            shapes = {"x": (N, nx), "u": (N, nu), "lam": (N, nx), "K": (N, nu, nx), "k": (N, nu),
+                      "P": (N, nx, nx), "p": (N, nx)}
+            res.append(({k: from_device(v, shapes[k], layout) for k, v in out.items()}, st, bad))
+        return res if repeat > 1 else res[0]
+    finally:
+        L.bmpc_lqr_plan_destroy(plan)
+        L.bmpc_tree_destroy(tree)
+
+
+def assert_parity(g, o, keys=("x", "u", "lam", "K", "k", "P", "p")):
+    for k in keys:
+        if k in g:
+            e = relerr(g[k], o[k])
+            assert e <= TOL, f"{k}: relative error {e:.3e}"
+
+
+TREES = {
+    "fig1b": np.array([-1, 0, 1, 1, 2, 3, 4, 5, 5, 6, 7, 8], dtype=np.int32),
+    "chain": S.tree_parent(30, [], 1),
+    "ternary": S.tree_parent(9, [1, 3, 6], 3),
+    "wide": S.tree_parent(3, [0], 100),
+    "root_only": np.array([-1], dtype=np.int32),
+    "random_a": random_bfs_tree(1, 9),
+    "random_b": random_bfs_tree(2, 12, 2),
+}
+
+
+@pytest.mark.parametrize("layout", [L.LAYOUT_NODE_MAJOR, L.LAYOUT_ELEM_MAJOR])
+@pytest.mark.parametrize("dims", [(3, 1), (4, 2), (6, 3), (12, 4)])
+@pytest.mark.parametrize("name", sorted(TREES))
+def test_lqr_matches_oracle(name, dims, layout):
+    par = TREES[name]
+    print(f"tree={name} N={len(par)} dims={dims} layout={layout}", flush=True)
+    inst = S.lqr_on(par, dims[0], dims[1], seed=17, random_cost=True)
+    o = oracle.tree_lqr_inst(inst)
+    g, st, bad = gpu_lqr(inst, layout)
+    assert st == 0, bad
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("layout", [L.LAYOUT_NODE_MAJOR, L.LAYOUT_ELEM_MAJOR])
+def test_lqr_microbench_tree_full_size(layout):
+    """nx=12, nu=4, binary branching every 4 stages, 8,185 nodes: every output
+    element against the oracle."""
+    inst = S.lqr_microbench(0)
+    print(f"microbench N={len(inst.parent)} layout={layout}", flush=True)
+    o = oracle.tree_lqr_inst(inst)
+    g, st, bad = gpu_lqr(inst, layout)
+    assert st == 0
+    assert_parity(g, o)
+
+
+def test_lqr_large_tree_full_size():
+    """nx=4, nu=2 random data on the 4096-scenario topology (122,871 nodes)."""
+    par = S.large_tree(0).parent
+    print(f"large tree N={len(par)}", flush=True)
+    inst = S.lqr_on(par, 4, 2, seed=3)
+    o = oracle.tree_lqr_inst(inst)
+    g, st, bad = gpu_lqr(inst, L.LAYOUT_ELEM_MAJOR)
+    assert st == 0
+    assert_parity(g, o)
+
+
+def test_lqr_bitwise_deterministic_across_runs():
+    inst = S.lqr_microbench(1)
+    runs = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR, repeat=3)
+    for k in runs[0][0]:
+        for r in runs[1:]:
+            assert np.array_equal(runs[0][0][k], r[0][k]), k
+
+
+def test_lqr_not_positive_definite_reports_node():
+    par = TREES["fig1b"]
+    inst = S.lqr_on(par, 3, 1, seed=2, random_cost=True)
+    inst.R[5] = -10.0
+    inst.B[7] = 0.0
+    inst.B[8] = 0.0
+    g, st, bad = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR)
+    assert st == 3 and bad == 5
+
+
+def test_lqr_unsupported_dims_rejected():
+    tree = L.bmpc_tree_create(TREES["fig1b"])
+    try:
+        with pytest.raises(L.BmpcError) as e:
+            L.bmpc_lqr_plan_create(tree, 5, 5, L.LAYOUT_NODE_MAJOR)
+        assert e.value.status == 9
+    finally:
+        L.bmpc_tree_destroy(tree)
