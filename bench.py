@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X branch-MPC hot path (one JSON line on stdout).
+
+Default workload: the tree-Riccati microbenchmark, nx=12, nu=4, horizon 40,
+binary branching at stages 0, 4, ..., 36 (1024 scenarios, 8,185 nodes), FP64.
+One step = one tree-LQR solve through the C ABI (level-parallel backward
+Riccati + path forward rollout, costates included) on inputs already
+resident in HBM.  Steps rotate over 12 independent instances (about 0.5 GB)
+so that the 256 MB Infinity Cache cannot hold the working set.
+
+Also reported: per-kernel HIP-event times measured inside the timed region,
+the roofline of the dominant kernel, branch-MPC solve figures when the
+solver is built, and the CPU oracle timed on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+METRIC = "BMPC solves/sec & tree-Riccati nodes/sec at KKT 1e-6, 1 GPU; warm vs cold iters"
+
+
+def lqr_algorithmic(parent, nx, nu):
+    """Algorithmic bytes and FLOPs of one backward and one forward launch.
+
+    Backward: every input read once (A, B, c per edge; Q, R, M, q, r per
+    control node; Q, q per leaf) and K, k, P, p written once per node.
+    Forward: K, k, A, B, c, P, p read once, x, u, lam written once per node.
+    FLOPs (dense): per edge 4n^3 + 4n^2 m + 2n m^2 + 4n^2 + 2nm, per control
+    node m^3/3 + 2m^2 n + 2m n^2 + 2m^2 + 2mn (backward); per edge
+    4n^2 + 2nm + 2n plus 2n^2 for the costate (forward)."""
+    N = len(parent)
+    nch = np.bincount(parent[1:], minlength=N)
+    ctrl = int((nch > 0).sum())
+    leaves = N - ctrl
+    edges = N - 1
+    n, m = nx, nu
+    d = 8
+    bwd_bytes = d * (edges * (n * n + n * m + n) + ctrl * (n * n + m * m + m * n + n + m)
+                     + leaves * (n * n + n) + N * (m * n + m + n * n + n))
+    fwd_bytes = d * (ctrl * (m * n + m) + edges * (n * n + n * m + n) + N * (n * n + n)
+                     + N * (n + m + n))
+    bwd_flops = edges * (4 * n ** 3 + 4 * n * n * m + 2 * n * m * m + 4 * n * n + 2 * n * m) + \
+        ctrl * (m ** 3 / 3 + 2 * m * m * n + 2 * m * n * n + 2 * m * m + 2 * m * n)
+    fwd_flops = edges * (4 * n * n + 2 * n * m + 2 * n) + N * 2 * n * n
+    return {"bwd_bytes": bwd_bytes, "fwd_bytes": fwd_bytes, "bwd_flops": bwd_flops,
+            "fwd_flops": fwd_flops}
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, srcs):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tab = json.load(f)
+    e = tab.get(kernel)
+    if not e or e.get("source_digest") != source_digest(srcs):
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline_lqr(inst, budget_s=10.0):
+    import oracle
+    oracle.tree_lqr_inst(inst)  # warm
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.tree_lqr_inst(inst)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    N = len(inst.parent)
+    return {"value": N * n / el, "unit": "tree-Riccati nodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} serial tree-Riccati solves (backward + forward) of the nx=12, nu=4, "
+                      f"8,185-node tree in {el:.1f} s on one host core"}
+
+
+def run_lqr(args, torch, L):
+    from paper_2506_13624_amd.layout import empty, to_device
+    import bmpc_synth as S
+
+    n_inst = 12
+    insts = [S.lqr_microbench(i) for i in range(n_inst)]
+    par = insts[0].parent
+    N = len(par)
+    nx, nu = 12, 4
+    layout = L.LAYOUT_NODE_MAJOR
+    tree = L.bmpc_tree_create(par)
+    plan = L.bmpc_lqr_plan_create(tree, nx, nu, layout)
+    dev = []
+    for inst in insts:
+        d = {k: to_device(getattr(inst, k), layout) for k in "ABcQRMqr"}
+        d["x0"] = to_device(inst.x0, layout)
+        d["x"] = empty((N, nx))
+        d["u"] = empty((N, nu))
+        d["lam"] = empty((N, nx))
+        d["K"] = empty((N, nu, nx))
+        d["k"] = empty((N, nu))
+        d["P"] = empty((N, nx, nx))
+        d["p"] = empty((N, nx))
+        dev.append(d)
+
+    def step(i):
+        d = dev[i % n_inst]
+        L.bmpc_lqr_solve(plan, d["A"], d["B"], d["c"], d["Q"], d["R"], d["M"], d["q"], d["r"],
+                         d["x0"], d["x"], d["u"], d["lam"], d["K"], d["k"], d["P"], d["p"],
+                         variant=L.RICCATI_LEVEL)
+
+    if args.calib_copy:
+        # plain copy of known size, for scaling rocprofv3 FETCH/WRITE counters
+        nbytes = 512 * 2 ** 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    st, bad = L.bmpc_lqr_check(plan)
+    if st != 0:
+        raise RuntimeError(f"LQR solve failed (status {st}, node {bad})")
+
+    L.bmpc_profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        step(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    elapsed_ms = ev0.elapsed_time(ev1)
+    prof = L.bmpc_profile_read()
+    L.bmpc_profile_enable(False)
+
+    # untimed region: the same number of steps without event pairs, for the
+    # launch-gap-free step time
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        step(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    clean_ms = ev0.elapsed_time(ev1)
+
+    alg = lqr_algorithmic(par, nx, nu)
+    bwd_name = "lqr_backward_level_wave"
+    bwd_ms, bwd_n = prof.get(bwd_name, (float("nan"), 1))
+    fwd_ms, fwd_n = prof.get("lqr_forward_paths", (float("nan"), 1))
+    bwd_avg_s = bwd_ms / bwd_n / 1e3
+    fwd_avg_s = fwd_ms / fwd_n / 1e3
+    srcs = ["paper_2506_13624_amd/csrc/lqr.hip", "paper_2506_13624_amd/csrc/lqr_device.hpp"]
+    achieved = alg["bwd_bytes"] / bwd_avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic(bwd_name, srcs),
+                "kernel": bwd_name, "avg_launch_us": round(bwd_avg_s * 1e6, 2),
+                "algorithmic_bytes_per_launch": alg["bwd_bytes"],
+                "fp64_tflops": round(alg["bwd_flops"] / bwd_avg_s / 1e12, 4),
+                "fp64_frac": round(alg["bwd_flops"] / bwd_avg_s / 1e12 / FP64_PEAK_TFLOPS, 5)}
+    kernels = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]} for k, v in prof.items()}
+    ms_step = clean_ms / args.steps
+    out = {
+        "metric": METRIC,
+        "value": round(N / (ms_step / 1e3), 1),
+        "unit": "tree-Riccati nodes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "tree-Riccati microbenchmark: nx=12, nu=4, horizon 40, binary "
+                               "branching every 4 stages, 1024 scenarios, 8185 nodes, FP64",
+                   "num_nodes": N, "nx": nx, "nu": nu, "instances_rotated": n_inst,
+                   "riccati_variant": "level", "layout": "node-major"},
+        "ms_per_step_with_event_pairs": round(elapsed_ms / args.steps, 5),
+        "kernels": kernels,
+        "forward_GBps": round(alg["fwd_bytes"] / fwd_avg_s / 1e9, 2),
+        "roofline": roofline,
+    }
+    L.bmpc_lqr_plan_destroy(plan)
+    L.bmpc_tree_destroy(tree)
+    return out, insts[0]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="launch one 512 MiB copy first (rocprofv3 counter calibration)")
+    ap.add_argument("--skip-bmpc", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no HIP device visible"}))
+        sys.exit(1)
+    from paper_2506_13624_amd import _lib as L
+
+    out, inst = run_lqr(args, torch, L)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_lqr(inst, args.cpu_budget)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

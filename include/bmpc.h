@@ -153,6 +153,20 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* plan, const double* A, const 
    failing node id).  bad_node may be NULL. */
 BMPC_API bmpc_status bmpc_lqr_check(bmpc_lqr_plan* plan, int32_t* bad_node, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Kernel timing.  When enabled, every kernel launch of the library is
+ * bracketed by a pair of HIP events recorded on its own stream (this adds a
+ * small gap between launches).
+ * ---------------------------------------------------------------------- */
+/* Enable (on != 0) or disable timing; clears the accumulated totals. */
+BMPC_API bmpc_status bmpc_profile_enable(int32_t on);
+/* Waits for the recorded events and returns the number of distinct kernel
+   names timed since the last read; fills up to `cap` entries: names
+   (host, 64 bytes per entry, NUL-terminated), total_ms (host, summed event
+   time) and launches (host, launch count).  Clears the totals.  Any output
+   pointer may be NULL. */
+BMPC_API int32_t bmpc_profile_read(char* names, double* total_ms, int32_t* launches, int32_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,6 +62,8 @@ _sig("bmpc_lqr_plan_destroy", None, [_vp])
 _sig("bmpc_lqr_supported", _i32, [_i32, _i32, _i32])
 _sig("bmpc_lqr_solve", _i32, [_vp] + [_vp] * 16 + [_i32, _vp])
 _sig("bmpc_lqr_check", _i32, [_vp, _pi32, _vp])
+_sig("bmpc_profile_enable", _i32, [_i32])
+_sig("bmpc_profile_read", _i32, [C.c_char_p, _pd, _pi32, _i32])
 
 
 def check(status):
@@ -164,3 +166,21 @@ def bmpc_lqr_check(plan, stream=None):
     bad = _i32(-1)
     st = lib.bmpc_lqr_check(plan, C.byref(bad), stream_ptr(stream))
     return st, bad.value
+
+
+def bmpc_profile_enable(on=True):
+    check(lib.bmpc_profile_enable(1 if on else 0))
+
+
+def bmpc_profile_read(cap=64):
+    """Per-kernel {name: (total_ms, launches)} since the last read."""
+    names = C.create_string_buffer(64 * cap)
+    tot = np.zeros(cap)
+    cnt = np.zeros(cap, dtype=np.int32)
+    n = lib.bmpc_profile_read(names, tot.ctypes.data_as(_pd), cnt.ctypes.data_as(_pi32), cap)
+    out = {}
+    raw = names.raw
+    for i in range(min(n, cap)):
+        nm = raw[64 * i: 64 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[nm] = (float(tot[i]), int(cnt[i]))
+    return out

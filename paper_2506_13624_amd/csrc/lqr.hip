@@ -25,6 +25,7 @@
 
 #include "bmpc_internal.hpp"
 #include "lqr_device.hpp"
+#include "profile.hpp"
 
 namespace bmpc {
 
@@ -411,11 +412,17 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
     const int Z = t.num_leaves;
     hipLaunchKernelGGL(k_init_flag, dim3(1), dim3(1), 0, s, pl->bad);
     const bool lane = pl->kern->bwd_lane != nullptr && pl->nx <= 6;
-    if (lane)
+    if (lane) {
+        ProfScope ps("lqr_backward_level_lane", s);
         hipLaunchKernelGGL(pl->kern->bwd_lane, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
-    else
+    } else {
+        ProfScope ps("lqr_backward_level_wave", s);
         hipLaunchKernelGGL(pl->kern->bwd_wave, dim3(Z), dim3(64), 0, s, t, a, pl->arrive);
-    hipLaunchKernelGGL(pl->kern->fwd, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
+    }
+    {
+        ProfScope ps("lqr_forward_paths", s);
+        hipLaunchKernelGGL(pl->kern->fwd, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
+    }
     BMPC_HIP_TRY(hipGetLastError());
     return BMPC_OK;
 }
