@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/bmpc.h"
+#include "bmpc.h"
 
 namespace bmpc {
 
@@ -42,6 +42,7 @@ struct TreeDev {
     int depth;            // largest stage
     const int* parent;    // N
     const int* child_off; // N+1: children of n are child_off[n] .. child_off[n+1]-1
+    const int4* info;     // N: {first child, end of children, parent, number of children of the parent}
     const int* stage;     // N
     const int* leaves;    // num_leaves, increasing node ids
     const int* leaf_stage;// num_leaves
@@ -61,6 +62,7 @@ struct TreeDev {
 
 struct HostTree {
     std::vector<int> parent, child_off, stage, leaves, leaf_stage, path, first_leaf;
+    std::vector<int4> info;
     std::vector<int> seg_start, seg_end, seg_len, seg_of, seg_pos, seg_nodes, seg_off;
     int N = 0, depth = 0, max_seg_len = 0;
 };

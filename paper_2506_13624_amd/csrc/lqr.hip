@@ -1,4 +1,4 @@
-// Tree LQR on the GPU: backward tree Riccati and forward rollout.
+// Tree LQR on the GPU: backward tree Riccati, forward rollout, costates.
 //
 // Backward (Sec. III-A, eq. tree_Riccati with the gains of eq.
 // tree_feedback_laws).  For node n with children j:
@@ -9,16 +9,20 @@
 // Leaves: P = Q, p = q.
 //
 // Level-parallel schedule without grid barriers: every leaf segment is
-// walked upwards by one worker (a lane, or a wavefront for larger nx); all
-// nodes of one depth are therefore processed at the same time.  When a
-// worker reaches a branching node it counts itself in with an atomic; the
-// last child to arrive merges all children (always in child order, so the
-// result is bitwise reproducible) and carries on upwards, the others stop.
+// walked upwards by one worker (a lane for small nx, a wavefront with LDS
+// staging for larger nx); all nodes of one depth are processed at the same
+// time.  When a worker reaches a branching node it counts itself in with an
+// atomic; the last child to arrive merges all children (always in child
+// order, so results are bitwise reproducible) and carries on upwards, the
+// others stop.  Inside a segment the next node's inputs are loaded while the
+// current node is computed.
 //
-// Forward (Sec. III-B, last paragraph; eq. forward_comb_rule): one lane per
-// root-to-leaf path applies u = K x + k and x_j = A_j x + B_j u + c_j down its
-// path; each node is written by exactly one lane (the path of the first leaf
-// below it), which also writes the costate lam = P x + p.
+// Forward (Sec. III-B, last paragraph; eq. forward_comb_rule): a group of G
+// lanes per root-to-leaf path (lane g owns row g) applies u = K x + k and
+// x_j = A_j x + B_j u + c_j down the path, with the inputs of the next D
+// steps in flight.  Every node is written by exactly one path (the first
+// leaf below it).  The costates lam = P x + p are then computed for all
+// nodes in parallel.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -30,6 +34,55 @@
 namespace bmpc {
 
 // ------------------------------------------------------------------------
+// Hand-over of a finished child's value function to the worker that merges
+// it at a branching node (possibly on another XCD).  The child's (P, p) are
+// written and read with device-scope relaxed atomics, which go to the
+// device-coherent level and bypass the per-XCD L2, and the writer waits for
+// its own stores to complete before it counts itself in.  This avoids a
+// device-scope release fence per worker, which would write back the whole
+// L2 of the XCD.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void st_shared_dev(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_shared_dev(const double* p)
+{
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// all earlier memory operations of this lane have completed
+__device__ __forceinline__ void wait_own_stores()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <int NX, int LAY>
+__device__ __forceinline__ void store_value_dev(const LqrArgs& a, int N, int n, const double (&P)[NX][NX],
+                                                const double (&p)[NX])
+{
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j) st_shared_dev(&a.P[lidx<LAY>(n, i * NX + j, NX * NX, N)], P[i][j]);
+        st_shared_dev(&a.p[lidx<LAY>(n, i, NX, N)], p[i]);
+    }
+}
+
+template <int NX, int LAY>
+__device__ __forceinline__ void load_value_dev(const LqrArgs& a, int N, int j, double (&P)[NX][NX],
+                                               double (&p)[NX])
+{
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+#pragma unroll
+        for (int k = 0; k < NX; ++k) P[i][k] = ld_shared_dev(&a.P[lidx<LAY>(j, i * NX + k, NX * NX, N)]);
+        p[i] = ld_shared_dev(&a.p[lidx<LAY>(j, i, NX, N)]);
+    }
+}
+
+// ------------------------------------------------------------------------
 // lane-per-segment backward
 // ------------------------------------------------------------------------
 template <int NX, int NU, int LAY>
@@ -39,270 +92,527 @@ __global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgs a, int* arri
     if (l >= t.num_leaves) return;
     const int N = t.N;
     int n = t.leaves[l];
+    int4 inf = t.info[n];
     int from = -1;
+    bool pref = false;  // stage/edge hold the inputs of n (single child == from)
     double P[NX][NX], p[NX];
+    StageRegs<NX, NU> stage;
+    EdgeRegs<NX, NU> edge;
     for (;;) {
-        const int c0 = t.child_off[n], c1 = t.child_off[n + 1];
+        const int c0 = inf.x, c1 = inf.y, par = inf.z, nsib = inf.w;
+        // the next node's topology record, in flight while this node is computed
+        const int4 inf_next = par >= 0 ? t.info[par] : make_int4(0, 0, -1, 0);
         if (c0 == c1) {
-            leaf_value<NX, NU, LAY>(a, N, n, P, p);
+            load_value<NX, LAY>(a.Q, a.q, N, n, P, p);
+#pragma unroll
+            for (int e = 0; e < NU * NX; ++e) a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0;
+#pragma unroll
+            for (int e = 0; e < NU; ++e) a.k[lidx<LAY>(n, e, NU, N)] = 0.0;
+            if (nsib == 1) {
+                load_stage<NX, NU, LAY>(a, N, par, stage);
+                load_edge<NX, NU, LAY, false>(a, N, par, n, edge);
+            }
         } else {
-            const bool use_regs = (c1 - c0 == 1) && from == c0;
-            riccati_node<NX, NU, LAY, false>(a, N, n, c0, c1, use_regs, P, p);
+            RicAcc<NX, NU> acc;
+            if (pref) {
+                acc.init(stage);
+                const EdgeRegs<NX, NU> e0 = edge;
+                // inputs of the parent are independent of this step: start them now
+                if (nsib == 1) {
+                    load_stage<NX, NU, LAY>(a, N, par, stage);
+                    load_edge<NX, NU, LAY, false>(a, N, par, n, edge);
+                }
+                acc.add_child(e0, P, p);
+            } else {
+                load_stage<NX, NU, LAY>(a, N, n, stage);
+                acc.init(stage);
+                for (int j = c0; j < c1; ++j) {
+                    load_edge<NX, NU, LAY, false>(a, N, n, j, edge);
+                    if (!(c1 - c0 == 1 && from == j)) load_value_dev<NX, LAY>(a, N, j, P, p);
+                    acc.add_child(edge, P, p);
+                }
+                if (nsib == 1) {
+                    load_stage<NX, NU, LAY>(a, N, par, stage);
+                    load_edge<NX, NU, LAY, false>(a, N, par, n, edge);
+                }
+            }
+            double Kn[NU][NX], kn[NU];
+            if (!acc.finish(Kn, kn, P, p)) atomicMin(a.bad, n);
+#pragma unroll
+            for (int i = 0; i < NU; ++i) {
+#pragma unroll
+                for (int b = 0; b < NX; ++b) a.K[lidx<LAY>(n, i * NX + b, NU * NX, N)] = Kn[i][b];
+                a.k[lidx<LAY>(n, i, NU, N)] = kn[i];
+            }
         }
-        store_value<NX, LAY>(a, N, n, P, p);
-        const int par = t.parent[n];
+        if (nsib > 1)
+            store_value_dev<NX, LAY>(a, N, n, P, p);
+        else
+            store_value<NX, LAY>(a, N, n, P, p);
         if (par < 0) break;
-        const int nsib = t.child_off[par + 1] - t.child_off[par];
+        pref = nsib == 1;
         if (nsib > 1) {
-            __threadfence();
+            wait_own_stores();
             const int old = atomicAdd(&arrive[par], 1);
             if (old != nsib - 1) break;
-            __threadfence();
         }
         from = n;
         n = par;
+        inf = inf_next;
     }
 }
 
 // ------------------------------------------------------------------------
 // wavefront-per-segment backward (LDS staging; used for larger nx)
 // ------------------------------------------------------------------------
+
+// A lane's share of CNT consecutive elements of one node (element e = lane + 64 s).
+template <int CNT>
+struct Slots {
+    static constexpr int S = (CNT + 63) / 64;
+    double v[S];
+
+    template <int LAY>
+    __device__ __forceinline__ void load(const double* __restrict__ base, int node, int N, int lane)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int e = lane + 64 * s;
+            v[s] = (e < CNT) ? base[lidx<LAY>(node, e, CNT, N)] : 0.0;
+        }
+    }
+    template <int LAY>
+    __device__ __forceinline__ void load_dev(const double* base, int node, int N, int lane)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int e = lane + 64 * s;
+            v[s] = (e < CNT) ? ld_shared_dev(&base[lidx<LAY>(node, e, CNT, N)]) : 0.0;
+        }
+    }
+    template <class F>
+    __device__ __forceinline__ void each(int lane, F f) const
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int e = lane + 64 * s;
+            if (e < CNT) f(e, v[s]);
+        }
+    }
+};
+
+// Column counts padded to a multiple of 4 so that tiles of 4 columns can be
+// read with 16-byte LDS loads.
+template <int NX, int NU>
+struct WaveDims {
+    static constexpr int NZ = NX + NU;         // rows of [A B]^T
+    static constexpr int ND = NX + NU + 1;     // columns of [A B c]
+    static constexpr int NDP = (ND + 3) / 4 * 4;
+    static constexpr int NQ = NDP / 4;         // column quads
+    static constexpr int NZP = (NZ + 1) / 2 * 2;
+};
+
+template <int NX, int NU, int LAY>
+struct WaveIn {
+    using Dm = WaveDims<NX, NU>;
+    static constexpr int NZ = Dm::NZ, NDP = Dm::NDP;
+    Slots<NX * NX> Q;
+    Slots<NX> q;
+    Slots<NU * NX> M;
+    Slots<NU * NU> R;
+    Slots<NU> r;
+    Slots<NX * NX> A;
+    Slots<NX * NU> B;
+    Slots<NX> c;
+
+    __device__ __forceinline__ void load_stage(const LqrArgs& a, int N, int n, int lane)
+    {
+        Q.template load<LAY>(a.Q, n, N, lane);
+        q.template load<LAY>(a.q, n, N, lane);
+        M.template load<LAY>(a.M, n, N, lane);
+        R.template load<LAY>(a.R, n, N, lane);
+        r.template load<LAY>(a.r, n, N, lane);
+    }
+    __device__ __forceinline__ void load_edge(const LqrArgs& a, int N, int j, int lane)
+    {
+        A.template load<LAY>(a.A, j, N, lane);
+        B.template load<LAY>(a.B, j, N, lane);
+        c.template load<LAY>(a.c, j, N, lane);
+    }
+    // Z rows 0..NX-1 = [W . w], rows NX.. = [G H g]
+    __device__ __forceinline__ void stage_to(double (*sZ)[NDP], int lane) const
+    {
+        Q.each(lane, [&](int e, double v) { sZ[e / NX][e % NX] = v; });
+        q.each(lane, [&](int e, double v) { sZ[e][NZ] = v; });
+        M.each(lane, [&](int e, double v) { sZ[NX + e / NX][e % NX] = v; });
+        R.each(lane, [&](int e, double v) { sZ[NX + e / NU][NX + e % NU] = v; });
+        r.each(lane, [&](int e, double v) { sZ[NX + e][NZ] = v; });
+    }
+    __device__ __forceinline__ void edge_to(double (*sD)[NDP], int lane) const
+    {
+        A.each(lane, [&](int e, double v) { sD[e / NX][e % NX] = v; });
+        B.each(lane, [&](int e, double v) { sD[e / NU][NX + e % NU] = v; });
+        c.each(lane, [&](int e, double v) { sD[e][NZ] = v; });
+    }
+};
+
+// Single-wavefront workgroups: LDS accesses of one wavefront complete in
+// issue order, so ordering them only needs a compiler-level fence.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int NX, int NU, int LAY>
 __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arrive)
 {
-    constexpr int NZ = NX + NU;       // rows of [A B]^T
-    constexpr int ND = NX + NU + 1;   // columns of [A B c]
-    __shared__ double sD[NX][ND];
-    __shared__ double sP[NX][NX];
-    __shared__ double sp[NX];
-    __shared__ double sS[NX][ND];
-    __shared__ double sZ[NZ][ND];
-    __shared__ double sK[NU][NX + 1];
+    using Dm = WaveDims<NX, NU>;
+    constexpr int NZ = Dm::NZ, NDP = Dm::NDP, NQ = Dm::NQ, NZP = Dm::NZP;
+    __shared__ __align__(16) double sD[NX][NDP];   // [A B c 0..] of the current child edge
+    __shared__ __align__(16) double sP[NX][NX];
+    __shared__ __align__(16) double sp[NX];
+    __shared__ __align__(16) double sS[NX][NDP];   // P [A B c] + [0 0 p]
+    __shared__ __align__(16) double sZ[NZ][NDP];   // [[W . w],[G H g]]
+    __shared__ __align__(16) double sK[NU][NX + 1];
     __shared__ int sgo;
 
     const int l = blockIdx.x;
     const int lane = threadIdx.x;
     const int N = t.N;
     int n = t.leaves[l];
+    int4 inf = t.info[n];
     int from = -1;
+    bool pref = false;
+    WaveIn<NX, NU, LAY> in;
+
+    // padding columns of D stay zero
+    for (int e = lane; e < NX * NDP; e += 64)
+        if (e % NDP >= NZ + 1) sD[e / NDP][e % NDP] = 0.0;
+
+    // S = P [A B c] (+p in the last column), tiles of 1 row x 4 columns;
+    // then Z += [A B]^T S, tiles of 2 rows x 4 columns
+    auto add_child = [&]() {
+        wave_sync();
+        for (int tt = lane; tt < NX * NQ; tt += 64) {
+            const int r = tt / NQ, c4 = 4 * (tt % NQ);
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+            for (int k = 0; k < NX; ++k) {
+                const double pk = sP[r][k];
+                const double2 d01 = *reinterpret_cast<const double2*>(&sD[k][c4]);
+                const double2 d23 = *reinterpret_cast<const double2*>(&sD[k][c4 + 2]);
+                s0 += pk * d01.x;
+                s1 += pk * d01.y;
+                s2 += pk * d23.x;
+                s3 += pk * d23.y;
+            }
+            const double pr = sp[r];
+            if (c4 + 0 == NZ) s0 += pr;
+            if (c4 + 1 == NZ) s1 += pr;
+            if (c4 + 2 == NZ) s2 += pr;
+            if (c4 + 3 == NZ) s3 += pr;
+            *reinterpret_cast<double2*>(&sS[r][c4]) = make_double2(s0, s1);
+            *reinterpret_cast<double2*>(&sS[r][c4 + 2]) = make_double2(s2, s3);
+        }
+        wave_sync();
+        for (int tt = lane; tt < (NZP / 2) * NQ; tt += 64) {
+            const int r0 = 2 * (tt / NQ), c4 = 4 * (tt % NQ);
+            double z[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+            for (int k = 0; k < NX; ++k) {
+                const double2 dr = *reinterpret_cast<const double2*>(&sD[k][r0]);
+                const double2 s01 = *reinterpret_cast<const double2*>(&sS[k][c4]);
+                const double2 s23 = *reinterpret_cast<const double2*>(&sS[k][c4 + 2]);
+                z[0][0] += dr.x * s01.x;
+                z[0][1] += dr.x * s01.y;
+                z[0][2] += dr.x * s23.x;
+                z[0][3] += dr.x * s23.y;
+                z[1][0] += dr.y * s01.x;
+                z[1][1] += dr.y * s01.y;
+                z[1][2] += dr.y * s23.x;
+                z[1][3] += dr.y * s23.y;
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int r = r0 + i;
+                if (r < NZ) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (c4 + j <= NZ) sZ[r][c4 + j] += z[i][j];
+                }
+            }
+        }
+        wave_sync();
+    };
+
     for (;;) {
-        const int c0 = t.child_off[n], c1 = t.child_off[n + 1];
+        const int c0 = inf.x, c1 = inf.y, par = inf.z, nsib = inf.w;
+        const int4 inf_next = par >= 0 ? t.info[par] : make_int4(0, 0, -1, 0);
         if (c0 == c1) {
-            for (int e = lane; e < NX * NX; e += 64)
-                sP[e / NX][e % NX] = a.Q[lidx<LAY>(n, e, NX * NX, N)];
-            for (int e = lane; e < NX; e += 64) sp[e] = a.q[lidx<LAY>(n, e, NX, N)];
+            Slots<NX * NX> Pv;
+            Slots<NX> pv;
+            Pv.template load<LAY>(a.Q, n, N, lane);
+            pv.template load<LAY>(a.q, n, N, lane);
+            Pv.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
+            pv.each(lane, [&](int e, double v) { sp[e] = v; });
             for (int e = lane; e < NU * NX; e += 64) a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0;
             for (int e = lane; e < NU; e += 64) a.k[lidx<LAY>(n, e, NU, N)] = 0.0;
-            __syncthreads();
-        } else {
-            // Z <- stage cost: rows 0..NX-1 hold [W . w], rows NX.. hold [G H g]
-            for (int e = lane; e < NZ * ND; e += 64) {
-                const int r = e / ND, col = e % ND;
-                double v = 0.0;
-                if (r < NX) {
-                    if (col < NX) v = a.Q[lidx<LAY>(n, r * NX + col, NX * NX, N)];
-                    else if (col == NZ) v = a.q[lidx<LAY>(n, r, NX, N)];
-                } else {
-                    const int ru = r - NX;
-                    if (col < NX) v = a.M[lidx<LAY>(n, ru * NX + col, NU * NX, N)];
-                    else if (col < NZ) v = a.R[lidx<LAY>(n, ru * NU + (col - NX), NU * NU, N)];
-                    else v = a.r[lidx<LAY>(n, ru, NU, N)];
-                }
-                sZ[r][col] = v;
+            if (nsib == 1) {
+                in.load_stage(a, N, par, lane);
+                in.load_edge(a, N, n, lane);
             }
-            const bool use_lds = (c1 - c0 == 1) && from == c0;
-            for (int j = c0; j < c1; ++j) {
-                for (int e = lane; e < NX * ND; e += 64) {
-                    const int r = e / ND, col = e % ND;
-                    double v;
-                    if (col < NX) v = a.A[lidx<LAY>(j, r * NX + col, NX * NX, N)];
-                    else if (col < NZ) v = a.B[lidx<LAY>(j, r * NU + (col - NX), NX * NU, N)];
-                    else v = a.c[lidx<LAY>(j, r, NX, N)];
-                    sD[r][col] = v;
+            wave_sync();
+        } else {
+            if (!pref) in.load_stage(a, N, n, lane);
+            in.stage_to(sZ, lane);
+            if (pref) {
+                in.edge_to(sD, lane);  // the only child's P is still in sP
+                if (nsib == 1) {
+                    in.load_stage(a, N, par, lane);
+                    in.load_edge(a, N, n, lane);
                 }
-                if (!use_lds) {
-                    for (int e = lane; e < NX * NX; e += 64)
-                        sP[e / NX][e % NX] = a.P[lidx<LAY>(j, e, NX * NX, N)];
-                    for (int e = lane; e < NX; e += 64) sp[e] = a.p[lidx<LAY>(j, e, NX, N)];
+                add_child();
+            } else {
+                for (int j = c0; j < c1; ++j) {
+                    Slots<NX * NX> Pv;
+                    Slots<NX> pv;
+                    in.load_edge(a, N, j, lane);
+                    const bool keep = (c1 - c0 == 1) && from == j;
+                    if (!keep) {
+                        Pv.template load_dev<LAY>(a.P, j, N, lane);
+                        pv.template load_dev<LAY>(a.p, j, N, lane);
+                    }
+                    wave_sync();
+                    in.edge_to(sD, lane);
+                    if (!keep) {
+                        Pv.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
+                        pv.each(lane, [&](int e, double v) { sp[e] = v; });
+                    }
+                    add_child();
                 }
-                __syncthreads();
-                // S = P [A B c];  last column + p  ->  p + P c
-                for (int e = lane; e < NX * ND; e += 64) {
-                    const int r = e / ND, col = e % ND;
-                    double acc = 0.0;
-#pragma unroll
-                    for (int k = 0; k < NX; ++k) acc += sP[r][k] * sD[k][col];
-                    if (col == NZ) acc += sp[r];
-                    sS[r][col] = acc;
+                if (nsib == 1) {
+                    in.load_stage(a, N, par, lane);
+                    in.load_edge(a, N, n, lane);
                 }
-                __syncthreads();
-                // Z += [A B]^T S on the blocks that are used
-                for (int e = lane; e < NZ * ND; e += 64) {
-                    const int r = e / ND, col = e % ND;
-                    if (r < NX && col >= NX && col < NZ) continue;
-                    double acc = 0.0;
-#pragma unroll
-                    for (int k = 0; k < NX; ++k) acc += sD[k][r] * sS[k][col];
-                    sZ[r][col] += acc;
-                }
-                __syncthreads();
             }
             // gains: lane i < NX solves column i of K, lane NX solves k
             if (lane <= NX) {
-                double L[NU][NU];
+                double L[NU][NU], inv[NU];
 #pragma unroll
                 for (int i = 0; i < NU; ++i)
 #pragma unroll
                     for (int j = 0; j < NU; ++j) L[i][j] = sZ[NX + i][NX + j];
-                const bool ok = chol_inplace<NU>(L);
-                if (!ok) atomicMin(a.bad, n);
+                const bool ok = chol_inplace<NU>(L, inv);
+                if (!ok && lane == 0) atomicMin(a.bad, n);
                 double v[NU];
                 const int col = lane < NX ? lane : NZ;
 #pragma unroll
                 for (int i = 0; i < NU; ++i) v[i] = sZ[NX + i][col];
-                chol_solve<NU>(L, v);
+                chol_solve<NU>(L, inv, v);
 #pragma unroll
                 for (int i = 0; i < NU; ++i) sK[i][lane] = -v[i];
             }
-            __syncthreads();
+            wave_sync();
             for (int e = lane; e < NU * NX; e += 64)
                 a.K[lidx<LAY>(n, e, NU * NX, N)] = sK[e / NX][e % NX];
             for (int e = lane; e < NU; e += 64) a.k[lidx<LAY>(n, e, NU, N)] = sK[e][NX];
-            // P = sym(W + G^T K), p = w + G^T k   (child P in sP no longer needed)
-            double pv[(NX * NX + 63) / 64];
-            double qv[(NX + 63) / 64];
+            // P = sym(W + G^T K), p = w + G^T k   (the child's P in sP is no longer needed)
+            constexpr int PS = (NX * NX + 63) / 64, VS = (NX + 63) / 64;
+            double pv[PS], qv[VS];
 #pragma unroll
-            for (int s = 0; s < (NX * NX + 63) / 64; ++s) {
+            for (int s = 0; s < PS; ++s) {
                 const int e = lane + 64 * s;
                 if (e < NX * NX) {
                     const int i = e / NX, j = e % NX;
-                    double xij = sZ[i][j], xji = sZ[j][i];
                     double tij = 0.0, tji = 0.0;
 #pragma unroll
-                    for (int r = 0; r < NU; ++r) {
-                        tij += sZ[NX + r][i] * sK[r][j];
-                        tji += sZ[NX + r][j] * sK[r][i];
+                    for (int rr = 0; rr < NU; ++rr) {
+                        tij += sZ[NX + rr][i] * sK[rr][j];
+                        tji += sZ[NX + rr][j] * sK[rr][i];
                     }
-                    pv[s] = 0.5 * ((xij + tij) + (xji + tji));
+                    pv[s] = 0.5 * ((sZ[i][j] + tij) + (sZ[j][i] + tji));
                 }
             }
 #pragma unroll
-            for (int s = 0; s < (NX + 63) / 64; ++s) {
+            for (int s = 0; s < VS; ++s) {
                 const int i = lane + 64 * s;
                 if (i < NX) {
                     double tt = 0.0;
 #pragma unroll
-                    for (int r = 0; r < NU; ++r) tt += sZ[NX + r][i] * sK[r][NX];
+                    for (int rr = 0; rr < NU; ++rr) tt += sZ[NX + rr][i] * sK[rr][NX];
                     qv[s] = sZ[i][NZ] + tt;
                 }
             }
-            __syncthreads();
+            wave_sync();
 #pragma unroll
-            for (int s = 0; s < (NX * NX + 63) / 64; ++s) {
+            for (int s = 0; s < PS; ++s) {
                 const int e = lane + 64 * s;
                 if (e < NX * NX) sP[e / NX][e % NX] = pv[s];
             }
 #pragma unroll
-            for (int s = 0; s < (NX + 63) / 64; ++s) {
+            for (int s = 0; s < VS; ++s) {
                 const int i = lane + 64 * s;
                 if (i < NX) sp[i] = qv[s];
             }
-            __syncthreads();
+            wave_sync();
         }
-        for (int e = lane; e < NX * NX; e += 64) a.P[lidx<LAY>(n, e, NX * NX, N)] = sP[e / NX][e % NX];
-        for (int e = lane; e < NX; e += 64) a.p[lidx<LAY>(n, e, NX, N)] = sp[e];
-        const int par = t.parent[n];
-        if (par < 0) break;
-        const int nsib = t.child_off[par + 1] - t.child_off[par];
         if (nsib > 1) {
-            __threadfence();
+            for (int e = lane; e < NX * NX; e += 64)
+                st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], sP[e / NX][e % NX]);
+            for (int e = lane; e < NX; e += 64) st_shared_dev(&a.p[lidx<LAY>(n, e, NX, N)], sp[e]);
+        } else {
+            for (int e = lane; e < NX * NX; e += 64) a.P[lidx<LAY>(n, e, NX * NX, N)] = sP[e / NX][e % NX];
+            for (int e = lane; e < NX; e += 64) a.p[lidx<LAY>(n, e, NX, N)] = sp[e];
+        }
+        if (par < 0) break;
+        pref = nsib == 1;
+        if (nsib > 1) {
+            wait_own_stores();
             __syncthreads();
             if (lane == 0) sgo = (atomicAdd(&arrive[par], 1) == nsib - 1);
             __syncthreads();
             if (!sgo) break;
-            __threadfence();
         }
         from = n;
         n = par;
+        inf = inf_next;
     }
 }
 
 // ------------------------------------------------------------------------
-// lane-per-path forward
+// forward rollout: G lanes per root-to-leaf path, inputs D steps ahead
 // ------------------------------------------------------------------------
+template <int NX, int NU>
+struct FwdStep {
+    int n, m;    // node of this step and the next node on the path (-1: none)
+    int writer;  // this path writes node n
+    double K[NX], k, A[NX], B[NU], c;
+};
+
 template <int NX, int NU, int LAY>
-__global__ void __launch_bounds__(64) k_fwd_lane(TreeDev t, LqrArgs a, int* arrive)
+__device__ __forceinline__ void fwd_fill(const TreeDev& t, const LqrArgs& a, int path, int last, int s,
+                                         int g, FwdStep<NX, NU>& f)
 {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= t.num_leaves) return;
     const int N = t.N, Z = t.num_leaves;
-    const int last = t.leaf_stage[l];
-    double x[NX], u[NU];
+    f.n = s <= last ? t.path[(long)s * Z + path] : -1;
+    f.m = s < last ? t.path[(long)(s + 1) * Z + path] : -1;
+    f.writer = f.n >= 0 ? (t.first_leaf[f.n] == path) : 0;
+    if (f.m >= 0) {
+        if (g < NU) {
 #pragma unroll
-    for (int i = 0; i < NX; ++i) x[i] = a.x0[i];
-    for (int s = 0; s <= last; ++s) {
-        const int n = t.path[(long)s * Z + l];
-        const bool writer = t.first_leaf[n] == l;
-        if (writer) {
-            arrive[n] = 0;
+            for (int j = 0; j < NX; ++j) f.K[j] = a.K[lidx<LAY>(f.n, g * NX + j, NU * NX, N)];
+            f.k = a.k[lidx<LAY>(f.n, g, NU, N)];
+        }
+        if (g < NX) {
 #pragma unroll
-            for (int i = 0; i < NX; ++i) a.x[lidx<LAY>(n, i, NX, N)] = x[i];
+            for (int j = 0; j < NX; ++j) f.A[j] = a.A[lidx<LAY>(f.m, g * NX + j, NX * NX, N)];
 #pragma unroll
-            for (int i = 0; i < NX; ++i) {
-                double acc = a.p[lidx<LAY>(n, i, NX, N)];
+            for (int j = 0; j < NU; ++j) f.B[j] = a.B[lidx<LAY>(f.m, g * NU + j, NX * NU, N)];
+            f.c = a.c[lidx<LAY>(f.m, g, NX, N)];
+        }
+    }
+}
+
+template <int NX, int NU, int LAY, int G, int D>
+__global__ void __launch_bounds__(64) k_fwd_rows(TreeDev t, LqrArgs a)
+{
+    static_assert(G >= NX && G >= NU && 64 % G == 0, "group must cover the rows");
+    const int tid = blockIdx.x * 64 + threadIdx.x;
+    const int path = tid / G;
+    const int g = tid % G;
+    const int base = (int)threadIdx.x - g;
+    const int N = t.N;
+    if (path >= t.num_leaves) return;  // whole group leaves together
+    const int last = t.leaf_stage[path];
+    FwdStep<NX, NU> ring[D];
 #pragma unroll
-                for (int j = 0; j < NX; ++j) acc += a.P[lidx<LAY>(n, i * NX + j, NX * NX, N)] * x[j];
-                a.lam[lidx<LAY>(n, i, NX, N)] = acc;
+    for (int d = 0; d < D; ++d) fwd_fill<NX, NU, LAY>(t, a, path, last, d, g, ring[d]);
+    double xg = g < NX ? a.x0[g] : 0.0;
+    for (int s0 = 0; s0 <= last; s0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int s = s0 + d;
+            if (s <= last) {
+                const FwdStep<NX, NU>& f = ring[d];
+                double xs[NX];
+#pragma unroll
+                for (int j = 0; j < NX; ++j) xs[j] = __shfl(xg, base + j, 64);
+                if (f.writer && g < NX) a.x[lidx<LAY>(f.n, g, NX, N)] = xg;
+                if (s == last) {
+                    if (f.writer && g < NU) a.u[lidx<LAY>(f.n, g, NU, N)] = 0.0;
+                } else {
+                    double ug = 0.0;
+                    if (g < NU) {
+                        ug = f.k;
+#pragma unroll
+                        for (int j = 0; j < NX; ++j) ug += f.K[j] * xs[j];
+                        if (f.writer) a.u[lidx<LAY>(f.n, g, NU, N)] = ug;
+                    }
+                    double us[NU];
+#pragma unroll
+                    for (int j = 0; j < NU; ++j) us[j] = __shfl(ug, base + j, 64);
+                    if (g < NX) {
+                        double acc = f.c;
+#pragma unroll
+                        for (int j = 0; j < NX; ++j) acc += f.A[j] * xs[j];
+#pragma unroll
+                        for (int j = 0; j < NU; ++j) acc += f.B[j] * us[j];
+                        xg = acc;
+                    }
+                }
+                fwd_fill<NX, NU, LAY>(t, a, path, last, s + D, g, ring[d]);
             }
         }
-        if (s == last) {
-            if (writer)
-#pragma unroll
-                for (int i = 0; i < NU; ++i) a.u[lidx<LAY>(n, i, NU, N)] = 0.0;
-            break;
-        }
-#pragma unroll
-        for (int i = 0; i < NU; ++i) {
-            double acc = a.k[lidx<LAY>(n, i, NU, N)];
-#pragma unroll
-            for (int j = 0; j < NX; ++j) acc += a.K[lidx<LAY>(n, i * NX + j, NU * NX, N)] * x[j];
-            u[i] = acc;
-        }
-        if (writer)
-#pragma unroll
-            for (int i = 0; i < NU; ++i) a.u[lidx<LAY>(n, i, NU, N)] = u[i];
-        const int m = t.path[(long)(s + 1) * Z + l];
-        double xn[NX];
-#pragma unroll
-        for (int i = 0; i < NX; ++i) {
-            double acc = a.c[lidx<LAY>(m, i, NX, N)];
-#pragma unroll
-            for (int j = 0; j < NX; ++j) acc += a.A[lidx<LAY>(m, i * NX + j, NX * NX, N)] * x[j];
-#pragma unroll
-            for (int j = 0; j < NU; ++j) acc += a.B[lidx<LAY>(m, i * NU + j, NX * NU, N)] * u[j];
-            xn[i] = acc;
-        }
-#pragma unroll
-        for (int i = 0; i < NX; ++i) x[i] = xn[i];
     }
 }
 
-__global__ void k_init_flag(int* bad) { *bad = INT_MAX; }
+// Costates lam_n = P_n x_n + p_n for every node; also re-arms the branch
+// counters and the positive-definiteness flag for the next solve.
+template <int NX, int LAY>
+__global__ void __launch_bounds__(256) k_costate(TreeDev t, LqrArgs a, int* arrive)
+{
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = t.N;
+    if (tid == 0) {
+        *a.bad_out = *a.bad;
+        *a.bad = INT_MAX;
+    }
+    if (tid >= (long)N * NX) return;
+    int n, i;
+    if constexpr (LAY == BMPC_LAYOUT_NODE_MAJOR) {
+        n = (int)(tid / NX);
+        i = (int)(tid % NX);
+    } else {
+        i = (int)(tid / N);
+        n = (int)(tid % N);
+    }
+    if (i == 0) arrive[n] = 0;
+    double acc = a.p[lidx<LAY>(n, i, NX, N)];
+#pragma unroll
+    for (int j = 0; j < NX; ++j)
+        acc += a.P[lidx<LAY>(n, i * NX + j, NX * NX, N)] * a.x[lidx<LAY>(n, j, NX, N)];
+    a.lam[lidx<LAY>(n, i, NX, N)] = acc;
+}
 
 // ------------------------------------------------------------------------
 // dispatch
 // ------------------------------------------------------------------------
 struct LqrKernels {
-    int nx, nu, layout;
+    int nx, nu, layout, group;
     void (*bwd_lane)(TreeDev, LqrArgs, int*);
     void (*bwd_wave)(TreeDev, LqrArgs, int*);
-    void (*fwd)(TreeDev, LqrArgs, int*);
+    void (*fwd)(TreeDev, LqrArgs);
+    void (*costate)(TreeDev, LqrArgs, int*);
 };
 
 template <int NX, int NU, int LAY, bool LANE>
 static LqrKernels make_k()
 {
-    LqrKernels k{NX, NU, LAY, nullptr, k_bwd_wave<NX, NU, LAY>, k_fwd_lane<NX, NU, LAY>};
+    constexpr int G = NX <= 4 ? 4 : (NX <= 8 ? 8 : 16);
+    LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, k_fwd_rows<NX, NU, LAY, G, 3>,
+                 k_costate<NX, LAY>};
     if constexpr (LANE) k.bwd_lane = k_bwd_lane<NX, NU, LAY>;
     return k;
 }
@@ -330,7 +640,7 @@ struct bmpc_lqr_plan {
     const LqrKernels* kern = nullptr;
     double *K = nullptr, *k = nullptr, *P = nullptr, *p = nullptr;
     int* arrive = nullptr;
-    int* bad = nullptr;
+    int* bad = nullptr;  // [0] live flag, [1] copy taken after the last backward pass
 };
 
 extern "C" {
@@ -366,15 +676,16 @@ BMPC_API bmpc_status bmpc_lqr_plan_create(const bmpc_tree* tree, int32_t nx, int
               hipMalloc(&pl->P, sizeof(double) * N * nx * nx) == hipSuccess &&
               hipMalloc(&pl->p, sizeof(double) * N * nx) == hipSuccess &&
               hipMalloc(&pl->arrive, sizeof(int) * N) == hipSuccess &&
-              hipMalloc(&pl->bad, sizeof(int)) == hipSuccess;
+              hipMalloc(&pl->bad, 2 * sizeof(int)) == hipSuccess;
     if (!ok) {
         bmpc_lqr_plan_destroy(pl);
         return fail(BMPC_ERR_OOM, "device allocation for the LQR plan failed");
     }
+    const int init_bad[2] = {INT_MAX, INT_MAX};
     if (hipMemset(pl->arrive, 0, sizeof(int) * N) != hipSuccess ||
-        hipMemset(pl->bad, 0x7f, sizeof(int)) != hipSuccess) {
+        hipMemcpy(pl->bad, init_bad, sizeof init_bad, hipMemcpyHostToDevice) != hipSuccess) {
         bmpc_lqr_plan_destroy(pl);
-        return fail(BMPC_ERR_HIP, "hipMemset failed");
+        return fail(BMPC_ERR_HIP, "initialising the LQR plan failed");
     }
     *out = pl;
     return BMPC_OK;
@@ -407,12 +718,10 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
                     variant);
     hipStream_t s = (hipStream_t)stream;
     LqrArgs a{A, B, c, Q, R, M, q, r, x0, x, u, lam, K ? K : pl->K, k ? k : pl->k,
-              P ? P : pl->P, p ? p : pl->p, pl->bad};
+              P ? P : pl->P, p ? p : pl->p, pl->bad, pl->bad + 1};
     const TreeDev& t = pl->tree->d;
     const int Z = t.num_leaves;
-    hipLaunchKernelGGL(k_init_flag, dim3(1), dim3(1), 0, s, pl->bad);
-    const bool lane = pl->kern->bwd_lane != nullptr && pl->nx <= 6;
-    if (lane) {
+    if (pl->kern->bwd_lane) {
         ProfScope ps("lqr_backward_level_lane", s);
         hipLaunchKernelGGL(pl->kern->bwd_lane, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
     } else {
@@ -421,7 +730,14 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
     }
     {
         ProfScope ps("lqr_forward_paths", s);
-        hipLaunchKernelGGL(pl->kern->fwd, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
+        const long threads = (long)Z * pl->kern->group;
+        hipLaunchKernelGGL(pl->kern->fwd, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, t, a);
+    }
+    {
+        ProfScope ps("lqr_costate", s);
+        const long threads = (long)t.N * pl->nx;
+        hipLaunchKernelGGL(pl->kern->costate, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                           t, a, pl->arrive);
     }
     BMPC_HIP_TRY(hipGetLastError());
     return BMPC_OK;
@@ -432,7 +748,7 @@ BMPC_API bmpc_status bmpc_lqr_check(bmpc_lqr_plan* pl, int32_t* bad_node, void* 
     if (!pl) return fail(BMPC_ERR_INVALID_ARG, "plan is NULL");
     BMPC_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     int bad = 0;
-    BMPC_HIP_TRY(hipMemcpy(&bad, pl->bad, sizeof(int), hipMemcpyDeviceToHost));
+    BMPC_HIP_TRY(hipMemcpy(&bad, pl->bad + 1, sizeof(int), hipMemcpyDeviceToHost));
     if (bad_node) *bad_node = bad == INT_MAX ? -1 : bad;
     if (bad != INT_MAX)
         return fail(BMPC_ERR_NOT_PD, "Riccati Hessian not positive definite at node %d", bad);

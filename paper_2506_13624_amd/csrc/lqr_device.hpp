@@ -1,5 +1,5 @@
-// Device building blocks of the tree Riccati recursion (one node per lane,
-// everything in registers).  Used by the tree-LQR kernels and by the
+// Device building blocks of the tree Riccati recursion with one node per
+// lane and everything in registers.  Used by the tree-LQR kernels and by the
 // branch-MPC solver.
 #pragma once
 
@@ -10,15 +10,31 @@
 namespace bmpc {
 
 struct LqrArgs {
-    const double *A, *B, *c, *Q, *R, *M, *q, *r, *x0;
-    double *x, *u, *lam, *K, *k, *P, *p;
-    int* bad;
+    const double* __restrict__ A;
+    const double* __restrict__ B;
+    const double* __restrict__ c;
+    const double* __restrict__ Q;
+    const double* __restrict__ R;
+    const double* __restrict__ M;
+    const double* __restrict__ q;
+    const double* __restrict__ r;
+    const double* __restrict__ x0;
+    double* __restrict__ x;
+    double* __restrict__ u;
+    double* __restrict__ lam;
+    double* __restrict__ K;
+    double* __restrict__ k;
+    double* __restrict__ P;
+    double* __restrict__ p;
+    int* bad;      // smallest node whose H was not positive definite (INT_MAX: none)
+    int* bad_out;  // copy of *bad taken after the backward pass
 };
 
-// Cholesky H = L L^T in place (lower triangle used).  False if H is not
-// numerically positive definite.
+// Cholesky H = L L^T in place (lower triangle used); inv receives the
+// reciprocals of the diagonal of L.  False if H is not numerically positive
+// definite.
 template <int n>
-__device__ __forceinline__ bool chol_inplace(double (&H)[n][n])
+__device__ __forceinline__ bool chol_inplace(double (&H)[n][n], double (&inv)[n])
 {
     bool ok = true;
 #pragma unroll
@@ -29,52 +45,96 @@ __device__ __forceinline__ bool chol_inplace(double (&H)[n][n])
         ok = ok && (d > 0.0);
         d = sqrt(d > 0.0 ? d : 1.0);
         H[j][j] = d;
-        const double inv = 1.0 / d;
+        inv[j] = 1.0 / d;
 #pragma unroll
         for (int i = j + 1; i < n; ++i) {
             double s = H[i][j];
 #pragma unroll
             for (int k = 0; k < j; ++k) s -= H[i][k] * H[j][k];
-            H[i][j] = s * inv;
+            H[i][j] = s * inv[j];
         }
     }
     return ok;
 }
 
-// Solve (L L^T) v = v in place.
+// Solve (L L^T) v = v in place, given the reciprocal diagonal.
 template <int n>
-__device__ __forceinline__ void chol_solve(const double (&L)[n][n], double (&v)[n])
+__device__ __forceinline__ void chol_solve(const double (&L)[n][n], const double (&inv)[n], double (&v)[n])
 {
 #pragma unroll
     for (int i = 0; i < n; ++i) {
         double s = v[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= L[i][k] * v[k];
-        v[i] = s / L[i][i];
+        v[i] = s * inv[i];
     }
 #pragma unroll
     for (int i = n - 1; i >= 0; --i) {
         double s = v[i];
 #pragma unroll
         for (int k = i + 1; k < n; ++k) s -= L[k][i] * v[k];
-        v[i] = s / L[i][i];
+        v[i] = s * inv[i];
     }
 }
 
+// Stage cost of one node in registers.
+template <int NX, int NU>
+struct StageRegs {
+    double Q[NX][NX], q[NX], R[NU][NU], M[NU][NX], r[NU];
+};
+
+// Data of one edge (A, B of the transition, c of the child) in registers.
+template <int NX, int NU>
+struct EdgeRegs {
+    double A[NX][NX], B[NX][NU], c[NX];
+};
+
 template <int NX, int NU, int LAY>
-__device__ __forceinline__ void leaf_value(const LqrArgs& a, int N, int n, double (&P)[NX][NX],
-                                           double (&p)[NX])
+__device__ __forceinline__ void load_stage(const LqrArgs& a, int N, int n, StageRegs<NX, NU>& s)
 {
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
 #pragma unroll
-        for (int j = 0; j < NX; ++j) P[i][j] = a.Q[lidx<LAY>(n, i * NX + j, NX * NX, N)];
-        p[i] = a.q[lidx<LAY>(n, i, NX, N)];
+        for (int j = 0; j < NX; ++j) s.Q[i][j] = a.Q[lidx<LAY>(n, i * NX + j, NX * NX, N)];
+        s.q[i] = a.q[lidx<LAY>(n, i, NX, N)];
     }
 #pragma unroll
-    for (int e = 0; e < NU * NX; ++e) a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0;
+    for (int i = 0; i < NU; ++i) {
 #pragma unroll
-    for (int e = 0; e < NU; ++e) a.k[lidx<LAY>(n, e, NU, N)] = 0.0;
+        for (int j = 0; j < NU; ++j) s.R[i][j] = a.R[lidx<LAY>(n, i * NU + j, NU * NU, N)];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) s.M[i][j] = a.M[lidx<LAY>(n, i * NX + j, NU * NX, N)];
+        s.r[i] = a.r[lidx<LAY>(n, i, NU, N)];
+    }
+}
+
+// Edge into child j; with SHARED_AB the Jacobians are stored once at the
+// parent n (all out-edges of n share the linearisation point) while the
+// defect c stays per child.
+template <int NX, int NU, int LAY, bool SHARED_AB>
+__device__ __forceinline__ void load_edge(const LqrArgs& a, int N, int n, int j, EdgeRegs<NX, NU>& e)
+{
+    const int ab = SHARED_AB ? n : j;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+#pragma unroll
+        for (int k = 0; k < NX; ++k) e.A[i][k] = a.A[lidx<LAY>(ab, i * NX + k, NX * NX, N)];
+#pragma unroll
+        for (int k = 0; k < NU; ++k) e.B[i][k] = a.B[lidx<LAY>(ab, i * NU + k, NX * NU, N)];
+        e.c[i] = a.c[lidx<LAY>(j, i, NX, N)];
+    }
+}
+
+template <int NX, int LAY>
+__device__ __forceinline__ void load_value(const double* __restrict__ Pg, const double* __restrict__ pg,
+                                           int N, int j, double (&P)[NX][NX], double (&p)[NX])
+{
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+#pragma unroll
+        for (int k = 0; k < NX; ++k) P[i][k] = Pg[lidx<LAY>(j, i * NX + k, NX * NX, N)];
+        p[i] = pg[lidx<LAY>(j, i, NX, N)];
+    }
 }
 
 template <int NX, int LAY>
@@ -89,69 +149,52 @@ __device__ __forceinline__ void store_value(const LqrArgs& a, int N, int n, cons
     }
 }
 
-// Riccati step at control node n with children c0..c1-1.  If use_regs, the
-// single child's value function is already in (P, p); otherwise every
-// child's is read from a.P / a.p in child order.  With SHARED_AB the
-// Jacobians (A, B) of all out-edges of n are stored once at n (siblings
-// share the linearisation point) and c stays per child.
-template <int NX, int NU, int LAY, bool SHARED_AB>
-__device__ __forceinline__ void riccati_node(const LqrArgs& a, int N, int n, int c0, int c1,
-                                             bool use_regs, double (&P)[NX][NX], double (&p)[NX])
-{
+// Accumulator of one Riccati step: W = Q + sum A^T P A, w, H, G, g.
+template <int NX, int NU>
+struct RicAcc {
     double H[NU][NU], G[NU][NX], g[NU], W[NX][NX], w[NX];
+
+    __device__ __forceinline__ void init(const StageRegs<NX, NU>& s)
+    {
 #pragma unroll
-    for (int i = 0; i < NU; ++i) {
+        for (int i = 0; i < NU; ++i) {
 #pragma unroll
-        for (int j = 0; j < NU; ++j) H[i][j] = a.R[lidx<LAY>(n, i * NU + j, NU * NU, N)];
+            for (int j = 0; j < NU; ++j) H[i][j] = s.R[i][j];
 #pragma unroll
-        for (int j = 0; j < NX; ++j) G[i][j] = a.M[lidx<LAY>(n, i * NX + j, NU * NX, N)];
-        g[i] = a.r[lidx<LAY>(n, i, NU, N)];
-    }
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-#pragma unroll
-        for (int j = 0; j < NX; ++j) W[i][j] = a.Q[lidx<LAY>(n, i * NX + j, NX * NX, N)];
-        w[i] = a.q[lidx<LAY>(n, i, NX, N)];
-    }
-    for (int j = c0; j < c1; ++j) {
-        if (!use_regs) {
-#pragma unroll
-            for (int i = 0; i < NX; ++i) {
-#pragma unroll
-                for (int k = 0; k < NX; ++k) P[i][k] = a.P[lidx<LAY>(j, i * NX + k, NX * NX, N)];
-                p[i] = a.p[lidx<LAY>(j, i, NX, N)];
-            }
+            for (int j = 0; j < NX; ++j) G[i][j] = s.M[i][j];
+            g[i] = s.r[i];
         }
-        const int e = SHARED_AB ? n : j;
-        double Am[NX][NX], Bm[NX][NU], cv[NX];
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
 #pragma unroll
-            for (int k = 0; k < NX; ++k) Am[i][k] = a.A[lidx<LAY>(e, i * NX + k, NX * NX, N)];
-#pragma unroll
-            for (int k = 0; k < NU; ++k) Bm[i][k] = a.B[lidx<LAY>(e, i * NU + k, NX * NU, N)];
-            cv[i] = a.c[lidx<LAY>(j, i, NX, N)];
+            for (int j = 0; j < NX; ++j) W[i][j] = s.Q[i][j];
+            w[i] = s.q[i];
         }
-        // s = p + P c ; PA = P A ; PB = P B
+    }
+
+    // add the child's value function (P, p) seen through edge e
+    __device__ __forceinline__ void add_child(const EdgeRegs<NX, NU>& e, const double (&P)[NX][NX],
+                                              const double (&p)[NX])
+    {
         double s[NX], PA[NX][NX], PB[NX][NU];
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
             double acc = 0.0;
 #pragma unroll
-            for (int k = 0; k < NX; ++k) acc += P[i][k] * cv[k];
+            for (int k = 0; k < NX; ++k) acc += P[i][k] * e.c[k];
             s[i] = p[i] + acc;
 #pragma unroll
             for (int b = 0; b < NX; ++b) {
                 double t = 0.0;
 #pragma unroll
-                for (int k = 0; k < NX; ++k) t += P[i][k] * Am[k][b];
+                for (int k = 0; k < NX; ++k) t += P[i][k] * e.A[k][b];
                 PA[i][b] = t;
             }
 #pragma unroll
             for (int b = 0; b < NU; ++b) {
                 double t = 0.0;
 #pragma unroll
-                for (int k = 0; k < NX; ++k) t += P[i][k] * Bm[k][b];
+                for (int k = 0; k < NX; ++k) t += P[i][k] * e.B[k][b];
                 PB[i][b] = t;
             }
         }
@@ -161,19 +204,19 @@ __device__ __forceinline__ void riccati_node(const LqrArgs& a, int N, int n, int
             for (int b = 0; b < NU; ++b) {
                 double t = 0.0;
 #pragma unroll
-                for (int k = 0; k < NX; ++k) t += Bm[k][i] * PB[k][b];
+                for (int k = 0; k < NX; ++k) t += e.B[k][i] * PB[k][b];
                 H[i][b] += t;
             }
 #pragma unroll
             for (int b = 0; b < NX; ++b) {
                 double t = 0.0;
 #pragma unroll
-                for (int k = 0; k < NX; ++k) t += Bm[k][i] * PA[k][b];
+                for (int k = 0; k < NX; ++k) t += e.B[k][i] * PA[k][b];
                 G[i][b] += t;
             }
             double t = 0.0;
 #pragma unroll
-            for (int k = 0; k < NX; ++k) t += Bm[k][i] * s[k];
+            for (int k = 0; k < NX; ++k) t += e.B[k][i] * s[k];
             g[i] += t;
         }
 #pragma unroll
@@ -182,68 +225,69 @@ __device__ __forceinline__ void riccati_node(const LqrArgs& a, int N, int n, int
             for (int b = 0; b < NX; ++b) {
                 double t = 0.0;
 #pragma unroll
-                for (int k = 0; k < NX; ++k) t += Am[k][i] * PA[k][b];
+                for (int k = 0; k < NX; ++k) t += e.A[k][i] * PA[k][b];
                 W[i][b] += t;
             }
             double t = 0.0;
 #pragma unroll
-            for (int k = 0; k < NX; ++k) t += Am[k][i] * s[k];
+            for (int k = 0; k < NX; ++k) t += e.A[k][i] * s[k];
             w[i] += t;
         }
     }
-    double L[NU][NU];
-#pragma unroll
-    for (int i = 0; i < NU; ++i)
-#pragma unroll
-        for (int j = 0; j < NU; ++j) L[i][j] = H[i][j];
-    if (!chol_inplace<NU>(L)) atomicMin(a.bad, n);
-    double Kn[NU][NX], kn[NU];
-#pragma unroll
-    for (int b = 0; b < NX; ++b) {
-        double v[NU];
-#pragma unroll
-        for (int i = 0; i < NU; ++i) v[i] = G[i][b];
-        chol_solve<NU>(L, v);
-#pragma unroll
-        for (int i = 0; i < NU; ++i) Kn[i][b] = -v[i];
-    }
+
+    // gains K = -H^-1 G, k = -H^-1 g and the new value function; returns
+    // false if H is not positive definite
+    __device__ __forceinline__ bool finish(double (&Kn)[NU][NX], double (&kn)[NU], double (&P)[NX][NX],
+                                          double (&p)[NX]) const
     {
-        double v[NU];
+        double L[NU][NU], inv[NU];
 #pragma unroll
-        for (int i = 0; i < NU; ++i) v[i] = g[i];
-        chol_solve<NU>(L, v);
+        for (int i = 0; i < NU; ++i)
 #pragma unroll
-        for (int i = 0; i < NU; ++i) kn[i] = -v[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NU; ++i) {
-#pragma unroll
-        for (int b = 0; b < NX; ++b) a.K[lidx<LAY>(n, i * NX + b, NU * NX, N)] = Kn[i][b];
-        a.k[lidx<LAY>(n, i, NU, N)] = kn[i];
-    }
-    // X = W + G^T K ; P = (X + X^T)/2 ; p = w + G^T k
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
+            for (int j = 0; j < NU; ++j) L[i][j] = H[i][j];
+        const bool ok = chol_inplace<NU>(L, inv);
 #pragma unroll
         for (int b = 0; b < NX; ++b) {
-            double t = W[i][b];
+            double v[NU];
 #pragma unroll
-            for (int r = 0; r < NU; ++r) t += G[r][i] * Kn[r][b];
-            P[i][b] = t;
+            for (int i = 0; i < NU; ++i) v[i] = G[i][b];
+            chol_solve<NU>(L, inv, v);
+#pragma unroll
+            for (int i = 0; i < NU; ++i) Kn[i][b] = -v[i];
         }
-        double t = w[i];
+        {
+            double v[NU];
 #pragma unroll
-        for (int r = 0; r < NU; ++r) t += G[r][i] * kn[r];
-        p[i] = t;
+            for (int i = 0; i < NU; ++i) v[i] = g[i];
+            chol_solve<NU>(L, inv, v);
+#pragma unroll
+            for (int i = 0; i < NU; ++i) kn[i] = -v[i];
+        }
+        // X = W + G^T K ; P = (X + X^T)/2 ; p = w + G^T k
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+#pragma unroll
+            for (int b = 0; b < NX; ++b) {
+                double t = W[i][b];
+#pragma unroll
+                for (int rr = 0; rr < NU; ++rr) t += G[rr][i] * Kn[rr][b];
+                P[i][b] = t;
+            }
+            double t = w[i];
+#pragma unroll
+            for (int rr = 0; rr < NU; ++rr) t += G[rr][i] * kn[rr];
+            p[i] = t;
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int b = i + 1; b < NX; ++b) {
+                const double m = 0.5 * (P[i][b] + P[b][i]);
+                P[i][b] = m;
+                P[b][i] = m;
+            }
+        return ok;
     }
-#pragma unroll
-    for (int i = 0; i < NX; ++i)
-#pragma unroll
-        for (int b = i + 1; b < NX; ++b) {
-            const double m = 0.5 * (P[i][b] + P[b][i]);
-            P[i][b] = m;
-            P[b][i] = m;
-        }
-}
+};
 
 }  // namespace bmpc

@@ -54,6 +54,12 @@ static bmpc_status analyse(const int32_t* parent, int32_t N, HostTree& h)
     h.child_off[N] += 1;
     h.stage.assign(N, 0);
     for (int i = 1; i < N; ++i) h.stage[i] = h.stage[parent[i]] + 1;
+    h.info.resize(N);
+    for (int i = 0; i < N; ++i) {
+        const int p = parent[i];
+        h.info[i] = make_int4(h.child_off[i], h.child_off[i + 1], p,
+                              p < 0 ? 0 : h.child_off[p + 1] - h.child_off[p]);
+    }
     h.depth = *std::max_element(h.stage.begin(), h.stage.end());
     h.leaves.clear();
     for (int i = 0; i < N; ++i)
@@ -130,7 +136,7 @@ bmpc_status tree_on_device(bmpc_tree* t)
     bmpc_status st;
 #define UP(field) \
     if ((st = upload(t, h.field, &d.field)) != BMPC_OK) return st;
-    UP(parent) UP(child_off) UP(stage) UP(leaves) UP(leaf_stage) UP(path) UP(first_leaf)
+    UP(parent) UP(child_off) UP(info) UP(stage) UP(leaves) UP(leaf_stage) UP(path) UP(first_leaf)
     UP(seg_start) UP(seg_end) UP(seg_len) UP(seg_of) UP(seg_pos) UP(seg_nodes) UP(seg_off)
 #undef UP
     t->on_device = true;
