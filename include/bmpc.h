@@ -154,6 +154,116 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* plan, const double* A, const 
 BMPC_API bmpc_status bmpc_lqr_check(bmpc_lqr_plan* plan, int32_t* bad_node, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Branch-MPC problem (Sec. II-B, eq. bmpc) for a kinematic bicycle.
+ *
+ * State x = [px, py, psi, v], input u = [a, delta].  Dynamics: one RK4 step
+ * of  d/dt x = [v cos psi, v sin psi, v tan(delta)/L, a]  over dt with the
+ * input held.  Node cost: w_n * (1/2 (x - ref_n)^T diag(Qd) (x - ref_n)
+ * + 1/2 u^T diag(Rd) u) at control nodes, w_n * 1/2 (x - ref_n)^T diag(Qd)
+ * (x - ref_n) at leaves.  Constraints g <= 0 in five slots per node:
+ * a - a_max, -a - a_max, delta - steer_max, -delta - steer_max (control
+ * nodes), and obs_radius - |(px, py) - o_n| at nodes with an obstacle.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double wheelbase, dt;
+    double Qd[4], Rd[2];
+    double a_max, steer_max, obs_radius;
+} bmpc_bicycle_params;
+
+/* Parameters of the AL outer loop and iLQR inner loop (Alg. 1).  Defaults
+   from bmpc_settings_default: eps_tol 1e-6, tau 100, omega0 1, eta0 0.1,
+   a_omega = b_omega = 1, a_eta 0.1, b_eta 0.9, rho0 100, mu0 100, Armijo
+   constant 1e-4, n_alpha 10 step sizes 2^0 .. 2^-9, max_outer 50, max_inner
+   100 (per outer iteration), max_ls_fail 3 consecutive line-search failures. */
+typedef struct {
+    double eps_tol, tau, omega0, eta0, a_omega, b_omega, a_eta, b_eta;
+    double rho0, mu0, armijo_beta;
+    int32_t n_alpha, max_outer, max_inner, max_ls_fail, riccati_variant;
+} bmpc_settings;
+
+/* Result of one solve.  r_kkt: last KKT residual of the relaxed problem
+   (infinity norm of the Lagrangian gradient and of the defects); viol:
+   constraint violation max |max(g, -y/rho)|. */
+typedef struct {
+    int32_t status, outer_it, inner_it, ls_failures, bad_node;
+    double r_kkt, viol, rho, mu, merit;
+} bmpc_stats;
+
+typedef struct bmpc_problem bmpc_problem;
+typedef struct bmpc_batch bmpc_batch;
+
+BMPC_API void bmpc_settings_default(bmpc_settings* s);
+BMPC_API void bmpc_bicycle_default(bmpc_bicycle_params* p);
+
+/* Node references for lane following: ref_n = [speed*dt*stage, ybar_n, 0,
+   speed] with ybar_n the leaf_prob-weighted mean of leaf_offset over the
+   leaves below n.  leaf_prob, leaf_offset: host, one entry per leaf in node
+   order; node_ref: host output, N x 4. */
+BMPC_API bmpc_status bmpc_node_refs(const bmpc_tree* tree, const double* leaf_prob, const double* leaf_offset,
+                                    double dt, double speed, double* node_ref);
+
+/* All arrays HOST pointers, node-major: node_weight N, node_ref N x 4,
+   node_obs N x 2 (obstacle centre used by the node), has_obs N (0/1), x0 4.
+   Copied to the current device.  Non-finite data -> BMPC_ERR_NONFINITE. */
+BMPC_API bmpc_status bmpc_problem_create(bmpc_tree* tree, const bmpc_bicycle_params* prm,
+                                         const double* node_weight, const double* node_ref,
+                                         const double* node_obs, const int32_t* has_obs, const double* x0,
+                                         bmpc_problem** out);
+BMPC_API void bmpc_problem_destroy(bmpc_problem* problem);
+/* New measured state (host pointer, 4 entries). */
+BMPC_API bmpc_status bmpc_problem_set_x0(bmpc_problem* problem, const double* x0);
+
+/* Solve one problem (Alg. 1).  x (N x 4), u (N x 2), lam (N x 4, multipliers
+   of the dynamics, convention L = L_a + lam^T (f - x)), ye (N x 5, PHR
+   multiplier estimates): DEVICE pointers, node-major, written on return.
+   warm bits: 1 = start from the given x, u; 2 = given lam; 4 = given ye.
+   Without bit 1 the start is u = 0 with the exact rollout from x0; without
+   bit 2 lam comes from the adjoint sweep at the start point.  Synchronous:
+   returns after the solve with *stats (host) filled.  Returns the solver
+   status (BMPC_ERR_MAXITER / _LINESEARCH / _NONFINITE / _NOT_PD with the
+   last iterate in the outputs). */
+BMPC_API bmpc_status bmpc_solve(bmpc_problem* problem, const bmpc_settings* s, int32_t warm, double* x,
+                                double* u, double* lam, double* ye, bmpc_stats* stats, void* stream);
+
+/* Linearisation and Gauss-Newton quadratisation at a given point (Sec.
+   IV-A): per node n, A (N x 16) and B (N x 8) = Jacobians of the RK4 step at
+   (x_n, u_n) (rows of leaves are zero), c (N x 4) = defect of the edge into
+   n, f(x_p, u_p) - x_n (zero at the root), Q (N x 16), R (N x 4), q (N x 4),
+   r (N x 2) = Gauss-Newton Hessian blocks and gradient of the augmented
+   objective.  Inputs and outputs DEVICE pointers, node-major.  kkt_viol
+   (host, 2 entries, nullable) receives the KKT residual and the constraint
+   violation.  Synchronous if kkt_viol is given, otherwise asynchronous. */
+BMPC_API bmpc_status bmpc_linearize(bmpc_problem* problem, const double* x, const double* u,
+                                    const double* lam, const double* ye, double rho, double* A, double* B,
+                                    double* c, double* Q, double* R, double* q, double* r, double* kkt_viol,
+                                    void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched solve: many independent problems (own trees, own sizes) in one
+ * launch, one workgroup per problem; every problem stops on its own
+ * convergence.  The batch owns the state of every problem.
+ * ---------------------------------------------------------------------- */
+/* problems: host array of `count` handles (they must outlive the batch).
+   hist_cap > 0 records per inner iteration [outer, r_kkt, alpha, mu, rho,
+   merit] for up to hist_cap iterations per problem. */
+BMPC_API bmpc_status bmpc_batch_create(bmpc_problem* const* problems, int32_t count, int32_t hist_cap,
+                                       bmpc_batch** out);
+BMPC_API void bmpc_batch_destroy(bmpc_batch* batch);
+/* Start the solve of every problem (asynchronous on `stream`); warm as in
+   bmpc_solve, applied to the state held by the batch. */
+BMPC_API bmpc_status bmpc_batch_launch(bmpc_batch* batch, const bmpc_settings* s, int32_t warm, void* stream);
+/* Synchronise and copy the `count` results to `stats` (host). */
+BMPC_API bmpc_status bmpc_batch_stats(bmpc_batch* batch, bmpc_stats* stats, void* stream);
+/* Copy the state of problem i between the batch and DEVICE arrays (node-major
+   as in bmpc_solve; NULL parts are skipped): into_batch = 1 writes the batch
+   (warm start), 0 reads it.  Asynchronous. */
+BMPC_API bmpc_status bmpc_batch_state(bmpc_batch* batch, int32_t i, double* x, double* u, double* lam,
+                                      double* ye, int32_t into_batch, void* stream);
+/* Synchronise and copy the iteration history of problem i to hist (host,
+   hist_cap x 6). */
+BMPC_API bmpc_status bmpc_batch_history(bmpc_batch* batch, int32_t i, double* hist, void* stream);
+
+/* ------------------------------------------------------------------------
  * Kernel timing.  When enabled, every kernel launch of the library is
  * bracketed by a pair of HIP events recorded on its own stream (this adds a
  * small gap between launches).

@@ -184,3 +184,147 @@ def bmpc_profile_read(cap=64):
         nm = raw[64 * i: 64 * (i + 1)].split(b"\0", 1)[0].decode()
         out[nm] = (float(tot[i]), int(cnt[i]))
     return out
+
+
+# ----------------------------------------------------------------------------
+# branch-MPC problem and solver
+# ----------------------------------------------------------------------------
+
+class bmpc_bicycle_params(C.Structure):
+    _fields_ = [("wheelbase", C.c_double), ("dt", C.c_double), ("Qd", C.c_double * 4),
+                ("Rd", C.c_double * 2), ("a_max", C.c_double), ("steer_max", C.c_double),
+                ("obs_radius", C.c_double)]
+
+
+class bmpc_settings(C.Structure):
+    _fields_ = [("eps_tol", C.c_double), ("tau", C.c_double), ("omega0", C.c_double),
+                ("eta0", C.c_double), ("a_omega", C.c_double), ("b_omega", C.c_double),
+                ("a_eta", C.c_double), ("b_eta", C.c_double), ("rho0", C.c_double),
+                ("mu0", C.c_double), ("armijo_beta", C.c_double), ("n_alpha", C.c_int32),
+                ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("max_ls_fail", C.c_int32),
+                ("riccati_variant", C.c_int32)]
+
+
+class bmpc_stats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("outer_it", C.c_int32), ("inner_it", C.c_int32),
+                ("ls_failures", C.c_int32), ("bad_node", C.c_int32), ("r_kkt", C.c_double),
+                ("viol", C.c_double), ("rho", C.c_double), ("mu", C.c_double),
+                ("merit", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_sig("bmpc_settings_default", None, [C.POINTER(bmpc_settings)])
+_sig("bmpc_bicycle_default", None, [C.POINTER(bmpc_bicycle_params)])
+_sig("bmpc_node_refs", _i32, [_vp, _pd, _pd, C.c_double, C.c_double, _pd])
+_sig("bmpc_problem_create", _i32, [_vp, C.POINTER(bmpc_bicycle_params), _pd, _pd, _pd, _pi32, _pd,
+                                   C.POINTER(_vp)])
+_sig("bmpc_problem_destroy", None, [_vp])
+_sig("bmpc_problem_set_x0", _i32, [_vp, _pd])
+_sig("bmpc_solve", _i32, [_vp, C.POINTER(bmpc_settings), _i32, _vp, _vp, _vp, _vp,
+                          C.POINTER(bmpc_stats), _vp])
+_sig("bmpc_linearize", _i32, [_vp, _vp, _vp, _vp, _vp, C.c_double] + [_vp] * 7 + [_pd, _vp])
+_sig("bmpc_batch_create", _i32, [C.POINTER(_vp), _i32, _i32, C.POINTER(_vp)])
+_sig("bmpc_batch_destroy", None, [_vp])
+_sig("bmpc_batch_launch", _i32, [_vp, C.POINTER(bmpc_settings), _i32, _vp])
+_sig("bmpc_batch_stats", _i32, [_vp, C.POINTER(bmpc_stats), _vp])
+_sig("bmpc_batch_state", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp])
+_sig("bmpc_batch_history", _i32, [_vp, _i32, _pd, _vp])
+
+
+def bmpc_settings_default(**kw):
+    s = bmpc_settings()
+    lib.bmpc_settings_default(C.byref(s))
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def bmpc_bicycle_default(**kw):
+    p = bmpc_bicycle_params()
+    lib.bmpc_bicycle_default(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def bmpc_node_refs(tree, leaf_prob, leaf_offset, dt, speed, num_nodes):
+    lp, lpp = _hf64(leaf_prob)
+    lo, lop = _hf64(leaf_offset)
+    out = np.zeros((num_nodes, 4))
+    check(lib.bmpc_node_refs(tree, lpp, lop, dt, speed, out.ctypes.data_as(_pd)))
+    return out
+
+
+def bmpc_problem_create(tree, prm, node_weight, node_ref, node_obs, has_obs, x0):
+    w, wp = _hf64(node_weight)
+    r, rp = _hf64(node_ref)
+    o, op = _hf64(node_obs)
+    h, hp = _hi32(has_obs)
+    x, xp = _hf64(x0)
+    out = _vp()
+    check(lib.bmpc_problem_create(tree, C.byref(prm), wp, rp, op, hp, xp, C.byref(out)))
+    return out
+
+
+def bmpc_problem_destroy(h):
+    lib.bmpc_problem_destroy(h)
+
+
+def bmpc_problem_set_x0(h, x0):
+    x, xp = _hf64(x0)
+    check(lib.bmpc_problem_set_x0(h, xp))
+
+
+def bmpc_solve(problem, settings, warm, x, u, lam, ye, stream=None, raise_on_status=False):
+    """x, u, lam, ye: device tensors (node-major).  Returns the stats dict;
+    the solver's own status is reported in stats['status']."""
+    st = bmpc_stats()
+    status = lib.bmpc_solve(problem, C.byref(settings), warm, dptr(x), dptr(u), dptr(lam), dptr(ye),
+                            C.byref(st), stream_ptr(stream))
+    if raise_on_status:
+        check(status)
+    elif status not in (0, 3, 4, 5, 6):
+        check(status)
+    return st.as_dict()
+
+
+def bmpc_linearize(problem, x, u, lam, ye, rho, A, B, c, Q, R, q, r, stream=None):
+    kv = np.zeros(2)
+    check(lib.bmpc_linearize(problem, dptr(x), dptr(u), dptr(lam), dptr(ye), rho, dptr(A), dptr(B),
+                             dptr(c), dptr(Q), dptr(R), dptr(q), dptr(r), kv.ctypes.data_as(_pd),
+                             stream_ptr(stream)))
+    return float(kv[0]), float(kv[1])
+
+
+def bmpc_batch_create(problems, hist_cap=0):
+    arr = (_vp * len(problems))(*[p.value if isinstance(p, _vp) else p for p in problems])
+    out = _vp()
+    check(lib.bmpc_batch_create(arr, len(problems), hist_cap, C.byref(out)))
+    return out
+
+
+def bmpc_batch_destroy(h):
+    lib.bmpc_batch_destroy(h)
+
+
+def bmpc_batch_launch(batch, settings, warm=0, stream=None):
+    check(lib.bmpc_batch_launch(batch, C.byref(settings), warm, stream_ptr(stream)))
+
+
+def bmpc_batch_stats(batch, count, stream=None):
+    arr = (bmpc_stats * count)()
+    check(lib.bmpc_batch_stats(batch, arr, stream_ptr(stream)))
+    return [a.as_dict() for a in arr]
+
+
+def bmpc_batch_state(batch, i, x=None, u=None, lam=None, ye=None, into_batch=False, stream=None):
+    check(lib.bmpc_batch_state(batch, i, dptr(x), dptr(u), dptr(lam), dptr(ye), 1 if into_batch else 0,
+                               stream_ptr(stream)))
+
+
+def bmpc_batch_history(batch, i, hist_cap, stream=None):
+    h = np.zeros((hist_cap, 6))
+    check(lib.bmpc_batch_history(batch, i, h.ctypes.data_as(_pd), stream_ptr(stream)))
+    return h

@@ -44,6 +44,7 @@ struct TreeDev {
     const int* child_off; // N+1: children of n are child_off[n] .. child_off[n+1]-1
     const int4* info;     // N: {first child, end of children, parent, number of children of the parent}
     const int* stage;     // N
+    const int* level_off; // depth+2: nodes of stage t are level_off[t] .. level_off[t+1]-1
     const int* leaves;    // num_leaves, increasing node ids
     const int* leaf_stage;// num_leaves
     const int* path;      // (depth+1) x num_leaves: node at stage t on the path of leaf l
@@ -63,6 +64,7 @@ struct TreeDev {
 struct HostTree {
     std::vector<int> parent, child_off, stage, leaves, leaf_stage, path, first_leaf;
     std::vector<int4> info;
+    std::vector<int> level_off;
     std::vector<int> seg_start, seg_end, seg_len, seg_of, seg_pos, seg_nodes, seg_off;
     int N = 0, depth = 0, max_seg_len = 0;
 };

@@ -1,0 +1,1092 @@
+// Branch-MPC solver: augmented-Lagrangian multiple-shooting iLQR (Sec. IV,
+// Alg. 1) on a trajectory tree, one workgroup per problem instance.
+//
+// The whole iteration runs on the device.  Inner loop (Sec. IV-A): linearise
+// the dynamics and quadratise the augmented objective (eq. AL, Gauss-Newton
+// Hessian) around the current tree, solve the tree LQR (eq. tree_Riccati /
+// tree_feedback_laws, level by level with an exact merge at branching
+// nodes), roll the deviations out linearly, choose the merit penalty mu so
+// that the merit slope is sufficiently negative, evaluate the merit (eq.
+// merit) for every step size of the set in parallel and take the largest
+// one with sufficient decrease (eq. sufficient_decrease).  The loop stops
+// when the KKT residual is below omega.  Outer loop (Sec. IV-B): constraint
+// violation, then either the multiplier update or a larger penalty, and the
+// tolerance schedule.
+//
+// Node-parallel passes give one node per thread (strided); level passes
+// walk the stages with a workgroup barrier per stage.  Sums are reduced
+// with a fixed butterfly per wavefront and a fixed-order sum over
+// wavefronts, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "bmpc_device.hpp"
+#include "bmpc_internal.hpp"
+#include "lqr_device.hpp"
+#include "profile.hpp"
+
+namespace bmpc {
+
+constexpr int NALPHA_MAX = 12;
+
+// Workspace arrays per instance (node-major, doubles per node)
+enum WsOff : int {
+    W_FX = 0,          // 4: f(x_n, u_n)
+    W_A = 4,           // 16: dF/dx at (x_n, u_n), shared by all out-edges of n
+    W_B = 20,          // 8: dF/du
+    W_C = 28,          // 4: defect of the edge into n: f(x_p, u_p) - x_n
+    W_Q = 32,          // 16
+    W_R = 48,          // 4
+    W_QV = 52,         // 4: q
+    W_RV = 56,         // 2: r
+    W_K = 58,          // 8
+    W_KV = 66,         // 2: k
+    W_P = 68,          // 16
+    W_PV = 84,         // 4: p
+    W_DX = 88,         // 4
+    W_DU = 92,         // 2
+    W_LH = 94,         // 4: LQR costates
+    W_NODE = 98
+};
+
+struct InstDesc {
+    int N, T;
+    const int* parent;
+    const int* child_off;
+    const int* level_off;
+    const double* weight;  // N
+    const double* ref;     // N x 4
+    const double* obs;     // N x 2
+    const int* has_obs;    // N
+    const double* x0;      // 4
+    BikeParams prm;
+    double* x;    // N x 4
+    double* u;    // N x 2
+    double* lam;  // N x 4
+    double* ye;   // N x 5
+    double* ws;   // N x W_NODE
+};
+
+struct SolverCfg {
+    double eps_tol, tau, omega0, eta0, a_omega, b_omega, a_eta, b_eta, rho0, mu0, beta;
+    int n_alpha, max_outer, max_inner, max_ls_fail;
+    int warm;  // bits: 1 x,u given, 2 lam given, 4 ye given
+};
+
+struct SolveOut {
+    int status, outer_it, inner_it, ls_failures, bad_node;
+    double r_kkt, viol, rho, mu, merit;
+};
+
+__device__ __forceinline__ void load4(const double* p, double (&v)[4])
+{
+    v[0] = p[0]; v[1] = p[1]; v[2] = p[2]; v[3] = p[3];
+}
+__device__ __forceinline__ void store4(double* p, const double (&v)[4])
+{
+    p[0] = v[0]; p[1] = v[1]; p[2] = v[2]; p[3] = v[3];
+}
+
+__device__ __forceinline__ NodeData node_data(const InstDesc& I, int n)
+{
+    NodeData d;
+    d.w = I.weight[n];
+#pragma unroll
+    for (int i = 0; i < BX; ++i) d.ref[i] = I.ref[n * 4 + i];
+    d.ox = I.obs[n * 2];
+    d.oy = I.obs[n * 2 + 1];
+    d.has_obs = I.has_obs[n] != 0;
+    d.leaf = I.child_off[n] == I.child_off[n + 1];
+    return d;
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = (v != v || o != o) ? NAN : fmax(v, o);
+    }
+    return v;
+}
+
+// Sum (or max) K values over the workgroup; every thread gets the totals.
+template <int BS, int K, bool MAX>
+__device__ __forceinline__ void block_reduce(double (&v)[K], double* sred)
+{
+    constexpr int NW = BS / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = MAX ? wave_max(v[k]) : wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) sred[k * NW + w] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double t = sred[k * NW];
+        for (int i = 1; i < NW; ++i) {
+            const double o = sred[k * NW + i];
+            t = MAX ? ((t != t || o != o) ? NAN : fmax(t, o)) : t + o;
+        }
+        v[k] = t;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- passes
+// Linearise dynamics, quadratise L_a; returns this thread's partial L_a and
+// constraint violation.
+template <int BS>
+__device__ void pass_linearise(const InstDesc& I, double rho, double& La, double& viol)
+{
+    La = 0.0;
+    viol = 0.0;
+    for (int n = threadIdx.x; n < I.N; n += BS) {
+        const NodeData nd = node_data(I, n);
+        double x[BX], u[BU], ye[BG];
+        load4(I.x + n * 4, x);
+        u[0] = I.u[n * 2];
+        u[1] = I.u[n * 2 + 1];
+#pragma unroll
+        for (int s = 0; s < BG; ++s) ye[s] = I.ye[n * BG + s];
+        double q[BX], r[BU], Qh[BX][BX], Rh[BU][BU];
+        La += node_quad(I.prm, nd, x, u, ye, rho, q, r, Qh, Rh);
+        double* w = I.ws + (long)n * W_NODE;
+#pragma unroll
+        for (int i = 0; i < BX; ++i) {
+            w[W_QV + i] = q[i];
+#pragma unroll
+            for (int j = 0; j < BX; ++j) w[W_Q + i * 4 + j] = Qh[i][j];
+        }
+#pragma unroll
+        for (int i = 0; i < BU; ++i) {
+            w[W_RV + i] = r[i];
+#pragma unroll
+            for (int j = 0; j < BU; ++j) w[W_R + i * 2 + j] = Rh[i][j];
+        }
+        double g[BG], dist, ex, ey;
+        bool on[BG];
+        node_constraints(I.prm, nd, x, u, g, on, dist, ex, ey);
+#pragma unroll
+        for (int s = 0; s < BG; ++s)
+            if (on[s]) {
+                const double c = fabs(fmax(g[s], -ye[s] / rho));
+                viol = (c != c) ? NAN : fmax(viol, c);
+            }
+        double xn[BX] = {0.0, 0.0, 0.0, 0.0}, A[BX][BX] = {}, B[BX][BU] = {};
+        if (!nd.leaf) bike_step_jac(I.prm, x, u, xn, A, B);
+#pragma unroll
+        for (int i = 0; i < BX; ++i) {
+            w[W_FX + i] = xn[i];
+#pragma unroll
+            for (int j = 0; j < BX; ++j) w[W_A + i * 4 + j] = A[i][j];
+#pragma unroll
+            for (int j = 0; j < BU; ++j) w[W_B + i * 2 + j] = B[i][j];
+        }
+    }
+}
+
+// Defects and KKT residual (needs the linearisation of the parents):
+// returns partial max residual and partial sums lam.d, |d|^2.
+template <int BS>
+__device__ void pass_defects_kkt(const InstDesc& I, double& rk, double& ld, double& dd)
+{
+    rk = 0.0;
+    ld = 0.0;
+    dd = 0.0;
+    for (int n = threadIdx.x; n < I.N; n += BS) {
+        double* w = I.ws + (long)n * W_NODE;
+        double lam[BX];
+        load4(I.lam + n * 4, lam);
+        if (n > 0) {
+            const double* wp = I.ws + (long)I.parent[n] * W_NODE;
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+                const double d = wp[W_FX + i] - I.x[n * 4 + i];
+                w[W_C + i] = d;
+                ld += lam[i] * d;
+                dd += d * d;
+                rk = (d != d) ? NAN : fmax(rk, fabs(d));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < BX; ++i) w[W_C + i] = 0.0;
+        }
+        const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+        double s[BX] = {0.0, 0.0, 0.0, 0.0};
+        for (int j = c0; j < c1; ++j)
+#pragma unroll
+            for (int i = 0; i < BX; ++i) s[i] += I.lam[j * 4 + i];
+        if (n > 0) {
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+                double gx = w[W_QV + i] - lam[i];
+                if (c1 > c0)
+#pragma unroll
+                    for (int k = 0; k < BX; ++k) gx += w[W_A + k * 4 + i] * s[k];
+                rk = (gx != gx) ? NAN : fmax(rk, fabs(gx));
+            }
+        }
+        if (c1 > c0) {
+#pragma unroll
+            for (int i = 0; i < BU; ++i) {
+                double gu = w[W_RV + i];
+#pragma unroll
+                for (int k = 0; k < BX; ++k) gu += w[W_B + k * 2 + i] * s[k];
+                rk = (gu != gu) ? NAN : fmax(rk, fabs(gu));
+            }
+        }
+    }
+}
+
+// Backward tree Riccati, one stage per barrier.  Returns false (and sets
+// *bad) if some H_n is not positive definite.
+template <int BS>
+__device__ void pass_riccati(const InstDesc& I, int* bad)
+{
+    for (int t = I.T; t >= 0; --t) {
+        const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
+        for (int n = n0 + (int)threadIdx.x; n < n1; n += BS) {
+            double* w = I.ws + (long)n * W_NODE;
+            const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+            if (c0 == c1) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) w[W_P + e] = w[W_Q + e];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w[W_PV + e] = w[W_QV + e];
+                continue;
+            }
+            StageRegs<BX, BU> st;
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+#pragma unroll
+                for (int j = 0; j < BX; ++j) st.Q[i][j] = w[W_Q + i * 4 + j];
+                st.q[i] = w[W_QV + i];
+            }
+#pragma unroll
+            for (int i = 0; i < BU; ++i) {
+#pragma unroll
+                for (int j = 0; j < BU; ++j) st.R[i][j] = w[W_R + i * 2 + j];
+#pragma unroll
+                for (int j = 0; j < BX; ++j) st.M[i][j] = 0.0;
+                st.r[i] = w[W_RV + i];
+            }
+            RicAcc<BX, BU> acc;
+            acc.init(st);
+            EdgeRegs<BX, BU> ed;
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+#pragma unroll
+                for (int j = 0; j < BX; ++j) ed.A[i][j] = w[W_A + i * 4 + j];
+#pragma unroll
+                for (int j = 0; j < BU; ++j) ed.B[i][j] = w[W_B + i * 2 + j];
+            }
+            for (int j = c0; j < c1; ++j) {
+                const double* wj = I.ws + (long)j * W_NODE;
+                double P[BX][BX], p[BX];
+#pragma unroll
+                for (int i = 0; i < BX; ++i) {
+#pragma unroll
+                    for (int k = 0; k < BX; ++k) P[i][k] = wj[W_P + i * 4 + k];
+                    p[i] = wj[W_PV + i];
+                    ed.c[i] = wj[W_C + i];
+                }
+                acc.add_child(ed, P, p);
+            }
+            double K[BU][BX], k[BU], P[BX][BX], p[BX];
+            if (!acc.finish(K, k, P, p)) atomicMin(bad, n);
+#pragma unroll
+            for (int i = 0; i < BU; ++i) {
+#pragma unroll
+                for (int j = 0; j < BX; ++j) w[W_K + i * 4 + j] = K[i][j];
+                w[W_KV + i] = k[i];
+            }
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+#pragma unroll
+                for (int j = 0; j < BX; ++j) w[W_P + i * 4 + j] = P[i][j];
+                w[W_PV + i] = p[i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Forward linear rollout of the deviations (delta x_0 = 0) and the LQR
+// costates lam_hat = P dx + p.
+template <int BS>
+__device__ void pass_forward(const InstDesc& I)
+{
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < BX; ++i) I.ws[W_DX + i] = 0.0;
+    __syncthreads();
+    for (int t = 0; t <= I.T; ++t) {
+        const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
+        for (int n = n0 + (int)threadIdx.x; n < n1; n += BS) {
+            double* w = I.ws + (long)n * W_NODE;
+            double dx[BX];
+            load4(w + W_DX, dx);
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+                double acc = w[W_PV + i];
+#pragma unroll
+                for (int j = 0; j < BX; ++j) acc += w[W_P + i * 4 + j] * dx[j];
+                w[W_LH + i] = acc;
+            }
+            const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+            double du[BU] = {0.0, 0.0};
+            if (c1 > c0) {
+#pragma unroll
+                for (int i = 0; i < BU; ++i) {
+                    double acc = w[W_KV + i];
+#pragma unroll
+                    for (int j = 0; j < BX; ++j) acc += w[W_K + i * 4 + j] * dx[j];
+                    du[i] = acc;
+                }
+                for (int j = c0; j < c1; ++j) {
+                    double* wj = I.ws + (long)j * W_NODE;
+#pragma unroll
+                    for (int i = 0; i < BX; ++i) {
+                        double acc = wj[W_C + i];
+#pragma unroll
+                        for (int k = 0; k < BX; ++k) acc += w[W_A + i * 4 + k] * dx[k];
+#pragma unroll
+                        for (int k = 0; k < BU; ++k) acc += w[W_B + i * 2 + k] * du[k];
+                        wj[W_DX + i] = acc;
+                    }
+                }
+            }
+            w[W_DU] = du[0];
+            w[W_DU + 1] = du[1];
+        }
+        __syncthreads();
+    }
+}
+
+// Adjoint sweep lam_leaf = q, lam_n = q_n + A_n^T sum_children lam (makes the
+// state gradient of the Lagrangian vanish at the current point).
+template <int BS>
+__device__ void pass_adjoint(const InstDesc& I)
+{
+    for (int t = I.T; t >= 0; --t) {
+        const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
+        for (int n = n0 + (int)threadIdx.x; n < n1; n += BS) {
+            const double* w = I.ws + (long)n * W_NODE;
+            const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+            double s[BX] = {0.0, 0.0, 0.0, 0.0};
+            for (int j = c0; j < c1; ++j)
+#pragma unroll
+                for (int i = 0; i < BX; ++i) s[i] += I.lam[j * 4 + i];
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+                double acc = w[W_QV + i];
+                if (c1 > c0)
+#pragma unroll
+                    for (int k = 0; k < BX; ++k) acc += w[W_A + k * 4 + i] * s[k];
+                I.lam[n * 4 + i] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- solver kernel
+template <int BS>
+__global__ void __launch_bounds__(BS) k_bmpc_wg(const InstDesc* __restrict__ insts, SolverCfg cfg,
+                                                SolveOut* __restrict__ outs, int* __restrict__ bad_flags,
+                                                double* __restrict__ hist, int hist_cap)
+{
+    __shared__ double sred[3 * NALPHA_MAX * (BS / 64)];
+    const InstDesc I = insts[blockIdx.x];
+    int* bad = bad_flags + blockIdx.x;
+    const int tid = threadIdx.x;
+    const int N = I.N;
+    if (tid == 0) *bad = INT_MAX;
+
+    // initial point
+    if (!(cfg.warm & 1)) {
+        for (int n = tid; n < N; n += BS) {
+            I.u[n * 2] = 0.0;
+            I.u[n * 2 + 1] = 0.0;
+        }
+        if (tid == 0)
+#pragma unroll
+            for (int i = 0; i < BX; ++i) I.x[i] = I.x0[i];
+        __syncthreads();
+        for (int t = 1; t <= I.T; ++t) {
+            const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
+            for (int n = n0 + tid; n < n1; n += BS) {
+                const int p = I.parent[n];
+                double xp[BX], up[BU] = {0.0, 0.0}, xn[BX];
+                load4(I.x + p * 4, xp);
+                bike_step(I.prm, xp, up, xn);
+                store4(I.x + n * 4, xn);
+            }
+            __syncthreads();
+        }
+    }
+    for (int n = tid; n < N; n += BS) {
+        if (n == 0)
+#pragma unroll
+            for (int i = 0; i < BX; ++i) I.x[i] = I.x0[i];
+        if (I.child_off[n] == I.child_off[n + 1]) {
+            I.u[n * 2] = 0.0;
+            I.u[n * 2 + 1] = 0.0;
+        }
+        if (!(cfg.warm & 4))
+#pragma unroll
+            for (int s = 0; s < BG; ++s) I.ye[n * BG + s] = 0.0;
+    }
+    __syncthreads();
+
+    double rho = cfg.rho0, mu = cfg.mu0, omega = cfg.omega0, eta = cfg.eta0;
+    double r_kkt = INFINITY, viol = INFINITY, merit = 0.0;
+    int status = BMPC_ERR_MAXITER, inner_total = 0, outer = 0, ls_fail = 0, ls_run = 0, nhist = 0;
+
+    if (!(cfg.warm & 2)) {
+        double La, vi;
+        pass_linearise<BS>(I, rho, La, vi);
+        __syncthreads();
+        pass_adjoint<BS>(I);
+    }
+
+    for (outer = 0; outer < cfg.max_outer; ++outer) {
+        for (int inner = 0;; ++inner) {
+            double La_p, vi_p, rk_p, ld_p, dd_p;
+            pass_linearise<BS>(I, rho, La_p, vi_p);
+            __syncthreads();
+            pass_defects_kkt<BS>(I, rk_p, ld_p, dd_p);
+            double mx[2] = {rk_p, vi_p};
+            block_reduce<BS, 2, true>(mx, sred);
+            r_kkt = mx[0];
+            viol = mx[1];
+            if (!(r_kkt == r_kkt)) {
+                status = BMPC_ERR_NONFINITE;
+                goto done;
+            }
+            if (r_kkt <= omega || inner >= cfg.max_inner) break;
+
+            pass_riccati<BS>(I, bad);
+            if (__hip_atomic_load(bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != INT_MAX) {
+                status = BMPC_ERR_NOT_PD;
+                goto done;
+            }
+            pass_forward<BS>(I);
+
+            // merit slope pieces and the current merit
+            double sm[6] = {0.0, 0.0, 0.0, La_p, ld_p, dd_p};
+            for (int n = tid; n < N; n += BS) {
+                const double* w = I.ws + (long)n * W_NODE;
+                double dx[BX];
+                load4(w + W_DX, dx);
+#pragma unroll
+                for (int i = 0; i < BX; ++i) {
+                    sm[0] += w[W_QV + i] * dx[i];
+#pragma unroll
+                    for (int j = 0; j < BX; ++j) sm[1] += dx[i] * w[W_Q + i * 4 + j] * dx[j];
+                }
+                if (I.child_off[n] < I.child_off[n + 1]) {
+#pragma unroll
+                    for (int i = 0; i < BU; ++i) {
+                        sm[0] += w[W_RV + i] * w[W_DU + i];
+#pragma unroll
+                        for (int j = 0; j < BU; ++j) sm[1] += w[W_DU + i] * w[W_R + i * 2 + j] * w[W_DU + j];
+                    }
+                }
+                if (n > 0)
+#pragma unroll
+                    for (int i = 0; i < BX; ++i) sm[2] += (w[W_LH + i] - 2.0 * I.lam[n * 4 + i]) * w[W_C + i];
+            }
+            block_reduce<BS, 6, false>(sm, sred);
+            const double gtd = sm[0], dhd = sm[1], lhd = sm[2], La0 = sm[3], ld0 = sm[4], dd0 = sm[5];
+            if (dd0 > 0.0) {
+                const double mu_hat = (gtd + lhd + 0.5 * dhd) / dd0;
+                if (mu < mu_hat) mu = fmax(mu_hat, 2.0 * mu);
+            }
+            const double phi0 = La0 + ld0 + 0.5 * mu * dd0;
+            const double dphi0 = gtd + lhd - mu * dd0;
+
+            // merit at every trial step size
+            const int na = cfg.n_alpha;
+            double tr[3 * NALPHA_MAX];
+#pragma unroll
+            for (int e = 0; e < 3 * NALPHA_MAX; ++e) tr[e] = 0.0;
+            for (int n = tid; n < N; n += BS) {
+                const double* w = I.ws + (long)n * W_NODE;
+                const NodeData nd = node_data(I, n);
+                double x[BX], u[BU], ye[BG], dx[BX];
+                load4(I.x + n * 4, x);
+                load4(w + W_DX, dx);
+                u[0] = I.u[n * 2];
+                u[1] = I.u[n * 2 + 1];
+#pragma unroll
+                for (int s = 0; s < BG; ++s) ye[s] = I.ye[n * BG + s];
+                const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+                double alpha = 1.0;
+#pragma unroll
+                for (int ka = 0; ka < NALPHA_MAX; ++ka) {
+                    if (ka < na) {
+                        double xt[BX], ut[BU];
+#pragma unroll
+                        for (int i = 0; i < BX; ++i) xt[i] = x[i] + alpha * dx[i];
+#pragma unroll
+                        for (int i = 0; i < BU; ++i) ut[i] = u[i] + alpha * w[W_DU + i];
+                        tr[ka] += node_value(I.prm, nd, xt, ut, ye, rho);
+                        if (c1 > c0) {
+                            double ft[BX];
+                            bike_step(I.prm, xt, ut, ft);
+                            for (int j = c0; j < c1; ++j) {
+                                const double* wj = I.ws + (long)j * W_NODE;
+#pragma unroll
+                                for (int i = 0; i < BX; ++i) {
+                                    const double xj = I.x[j * 4 + i] + alpha * wj[W_DX + i];
+                                    const double lj = I.lam[j * 4 + i] + alpha * (wj[W_LH + i] - I.lam[j * 4 + i]);
+                                    const double d = ft[i] - xj;
+                                    tr[NALPHA_MAX + ka] += lj * d;
+                                    tr[2 * NALPHA_MAX + ka] += d * d;
+                                }
+                            }
+                        }
+                    }
+                    alpha *= 0.5;
+                }
+            }
+            block_reduce<BS, 3 * NALPHA_MAX, false>(tr, sred);
+            double a_star = -1.0, phi_star = NAN, alpha = 1.0;
+            for (int ka = 0; ka < na; ++ka, alpha *= 0.5) {
+                const double phi = tr[ka] + tr[NALPHA_MAX + ka] + 0.5 * mu * tr[2 * NALPHA_MAX + ka];
+                if (a_star < 0.0 && phi <= phi0 + cfg.beta * alpha * dphi0) {
+                    a_star = alpha;
+                    phi_star = phi;
+                }
+            }
+            if (a_star < 0.0) {
+                ++ls_fail;
+                if (++ls_run >= cfg.max_ls_fail) {
+                    status = BMPC_ERR_LINESEARCH;
+                    goto done;
+                }
+                a_star = ldexp(1.0, -(na - 1));
+                phi_star = NAN;
+            } else {
+                ls_run = 0;
+            }
+            for (int n = tid; n < N; n += BS) {
+                const double* w = I.ws + (long)n * W_NODE;
+#pragma unroll
+                for (int i = 0; i < BX; ++i) {
+                    I.x[n * 4 + i] += a_star * w[W_DX + i];
+                    I.lam[n * 4 + i] += a_star * (w[W_LH + i] - I.lam[n * 4 + i]);
+                }
+#pragma unroll
+                for (int i = 0; i < BU; ++i) I.u[n * 2 + i] += a_star * w[W_DU + i];
+            }
+            merit = phi_star;
+            ++inner_total;
+            if (hist && tid == 0 && nhist < hist_cap) {
+                double* h = hist + ((long)blockIdx.x * hist_cap + nhist) * 6;
+                h[0] = outer;
+                h[1] = r_kkt;
+                h[2] = a_star;
+                h[3] = mu;
+                h[4] = rho;
+                h[5] = phi_star;
+                ++nhist;
+            }
+            __syncthreads();
+        }
+
+        // outer update (BCL)
+        if (viol <= eta) {
+            for (int n = tid; n < N; n += BS) {
+                const NodeData nd = node_data(I, n);
+                double x[BX], u[BU], g[BG], dist, ex, ey;
+                bool on[BG];
+                load4(I.x + n * 4, x);
+                u[0] = I.u[n * 2];
+                u[1] = I.u[n * 2 + 1];
+                node_constraints(I.prm, nd, x, u, g, on, dist, ex, ey);
+#pragma unroll
+                for (int s = 0; s < BG; ++s) {
+                    const double y = I.ye[n * BG + s];
+                    I.ye[n * BG + s] = on[s] ? fmax(0.0, y + rho * g[s]) : 0.0;
+                }
+            }
+            __syncthreads();
+            if (fmax(r_kkt, viol) < cfg.eps_tol) {
+                status = BMPC_OK;
+                ++outer;
+                goto done;
+            }
+            omega = omega / pow(rho, cfg.b_omega);
+            eta = eta / pow(rho, cfg.b_eta);
+        } else {
+            rho = cfg.tau * rho;
+            omega = cfg.omega0 / pow(rho, cfg.a_omega);
+            eta = cfg.eta0 / pow(rho, cfg.a_eta);
+        }
+        omega = fmax(omega, cfg.eps_tol);
+    }
+
+done:
+    __syncthreads();
+    if (tid == 0) {
+        SolveOut o;
+        o.status = status;
+        o.outer_it = outer;
+        o.inner_it = inner_total;
+        o.ls_failures = ls_fail;
+        const int bn = __hip_atomic_load(bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        o.bad_node = bn == INT_MAX ? -1 : bn;
+        o.r_kkt = r_kkt;
+        o.viol = viol;
+        o.rho = rho;
+        o.mu = mu;
+        o.merit = merit;
+        outs[blockIdx.x] = o;
+    }
+}
+
+// Linearisation and quadratisation only (row a2), for testing and for
+// callers that bring their own LQR solver.
+template <int BS>
+__global__ void __launch_bounds__(BS) k_bmpc_linearise(InstDesc I, double rho, double* kkt_out)
+{
+    __shared__ double sred[2 * (BS / 64)];
+    double La, vi, rk, ld, dd;
+    pass_linearise<BS>(I, rho, La, vi);
+    __syncthreads();
+    pass_defects_kkt<BS>(I, rk, ld, dd);
+    double mx[2] = {rk, vi};
+    block_reduce<BS, 2, true>(mx, sred);
+    if (threadIdx.x == 0 && kkt_out) {
+        kkt_out[0] = mx[0];
+        kkt_out[1] = mx[1];
+    }
+}
+
+}  // namespace bmpc
+
+using namespace bmpc;
+
+// ------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------
+struct bmpc_problem {
+    bmpc_tree* tree = nullptr;
+    bmpc_bicycle_params prm{};
+    int N = 0;
+    double* d_weight = nullptr;
+    double* d_ref = nullptr;
+    double* d_obs = nullptr;
+    int* d_has = nullptr;
+    double* d_x0 = nullptr;
+    bmpc_batch* self = nullptr;  // one-instance batch used by bmpc_solve
+};
+
+struct bmpc_batch {
+    int count = 0;
+    std::vector<bmpc_problem*> problems;
+    std::vector<int> offset;  // node offset of each instance in the state arrays
+    long total_nodes = 0;
+    InstDesc* d_desc = nullptr;
+    SolveOut* d_out = nullptr;
+    int* d_bad = nullptr;
+    double* d_state = nullptr;  // x | u | lam | ye for all instances
+    double* d_ws = nullptr;
+    double* d_hist = nullptr;
+    int hist_cap = 0;
+    std::vector<InstDesc> h_desc;
+};
+
+static BikeParams to_dev(const bmpc_bicycle_params& p)
+{
+    BikeParams b;
+    b.L = p.wheelbase;
+    b.dt = p.dt;
+    for (int i = 0; i < 4; ++i) b.Qd[i] = p.Qd[i];
+    for (int i = 0; i < 2; ++i) b.Rd[i] = p.Rd[i];
+    b.a_max = p.a_max;
+    b.steer_max = p.steer_max;
+    b.obs_r = p.obs_radius;
+    return b;
+}
+
+static SolverCfg to_cfg(const bmpc_settings& s, int warm)
+{
+    SolverCfg c;
+    c.eps_tol = s.eps_tol;
+    c.tau = s.tau;
+    c.omega0 = s.omega0;
+    c.eta0 = s.eta0;
+    c.a_omega = s.a_omega;
+    c.b_omega = s.b_omega;
+    c.a_eta = s.a_eta;
+    c.b_eta = s.b_eta;
+    c.rho0 = s.rho0;
+    c.mu0 = s.mu0;
+    c.beta = s.armijo_beta;
+    c.n_alpha = s.n_alpha;
+    c.max_outer = s.max_outer;
+    c.max_inner = s.max_inner;
+    c.max_ls_fail = s.max_ls_fail;
+    c.warm = warm;
+    return c;
+}
+
+template <class T>
+static bool dalloc(T** p, size_t n)
+{
+    return hipMalloc((void**)p, std::max<size_t>(1, n) * sizeof(T)) == hipSuccess;
+}
+
+extern "C" {
+
+BMPC_API void bmpc_settings_default(bmpc_settings* s)
+{
+    if (!s) return;
+    s->eps_tol = 1e-6;
+    s->tau = 100.0;
+    s->omega0 = 1.0;
+    s->eta0 = 0.1;
+    s->a_omega = 1.0;
+    s->b_omega = 1.0;
+    s->a_eta = 0.1;
+    s->b_eta = 0.9;
+    s->rho0 = 100.0;
+    s->mu0 = 100.0;
+    s->armijo_beta = 1e-4;
+    s->n_alpha = 10;
+    s->max_outer = 50;
+    s->max_inner = 100;
+    s->max_ls_fail = 3;
+    s->riccati_variant = BMPC_RICCATI_AUTO;
+}
+
+BMPC_API void bmpc_bicycle_default(bmpc_bicycle_params* p)
+{
+    if (!p) return;
+    p->wheelbase = 2.7;
+    p->dt = 0.1;
+    const double Q[4] = {1.0, 1.0, 0.1, 0.1}, R[2] = {0.1, 1.0};
+    for (int i = 0; i < 4; ++i) p->Qd[i] = Q[i];
+    for (int i = 0; i < 2; ++i) p->Rd[i] = R[i];
+    p->a_max = 3.0;
+    p->steer_max = 0.5;
+    p->obs_radius = 1.5;
+}
+
+BMPC_API bmpc_status bmpc_node_refs(const bmpc_tree* t, const double* leaf_prob, const double* leaf_offset,
+                                    double dt, double speed, double* node_ref)
+{
+    if (!t || !leaf_prob || !leaf_offset || !node_ref) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    const HostTree& h = t->h;
+    std::vector<double> w(h.N, 0.0), wy(h.N, 0.0);
+    for (size_t l = 0; l < h.leaves.size(); ++l) {
+        w[h.leaves[l]] = leaf_prob[l];
+        wy[h.leaves[l]] = leaf_prob[l] * leaf_offset[l];
+    }
+    for (int i = h.N - 1; i >= 1; --i) {
+        w[h.parent[i]] += w[i];
+        wy[h.parent[i]] += wy[i];
+    }
+    for (int i = 0; i < h.N; ++i) {
+        node_ref[4 * i + 0] = speed * dt * h.stage[i];
+        node_ref[4 * i + 1] = w[i] > 0.0 ? wy[i] / w[i] : 0.0;
+        node_ref[4 * i + 2] = 0.0;
+        node_ref[4 * i + 3] = speed;
+    }
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_problem_create(bmpc_tree* tree, const bmpc_bicycle_params* prm,
+                                         const double* node_weight, const double* node_ref,
+                                         const double* node_obs, const int32_t* has_obs, const double* x0,
+                                         bmpc_problem** out)
+{
+    if (!tree || !prm || !node_weight || !node_ref || !node_obs || !has_obs || !x0 || !out)
+        return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (!(prm->dt > 0.0) || !(prm->wheelbase > 0.0) || !(prm->obs_radius >= 0.0))
+        return fail(BMPC_ERR_INVALID_ARG, "bicycle parameters must be positive");
+    const int N = tree->h.N;
+    for (int i = 0; i < N; ++i)
+        if (!std::isfinite(node_weight[i]) || node_weight[i] < 0.0)
+            return fail(BMPC_ERR_NONFINITE, "node_weight[%d] must be a finite non-negative number", i);
+    for (int i = 0; i < 4 * N; ++i)
+        if (!std::isfinite(node_ref[i])) return fail(BMPC_ERR_NONFINITE, "node_ref has a non-finite entry");
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(x0[i])) return fail(BMPC_ERR_NONFINITE, "x0 has a non-finite entry");
+    bmpc_status st = tree_on_device(tree);
+    if (st != BMPC_OK) return st;
+    auto* p = new bmpc_problem();
+    p->tree = tree;
+    p->prm = *prm;
+    p->N = N;
+    bool ok = dalloc(&p->d_weight, N) && dalloc(&p->d_ref, 4 * (size_t)N) && dalloc(&p->d_obs, 2 * (size_t)N) &&
+              dalloc(&p->d_has, N) && dalloc(&p->d_x0, 4);
+    if (!ok) {
+        bmpc_problem_destroy(p);
+        return fail(BMPC_ERR_OOM, "device allocation for the problem failed");
+    }
+    if (hipMemcpy(p->d_weight, node_weight, sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_ref, node_ref, sizeof(double) * 4 * N, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_obs, node_obs, sizeof(double) * 2 * N, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_has, has_obs, sizeof(int) * N, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_x0, x0, sizeof(double) * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        bmpc_problem_destroy(p);
+        return fail(BMPC_ERR_HIP, "uploading the problem failed");
+    }
+    *out = p;
+    return BMPC_OK;
+}
+
+BMPC_API void bmpc_batch_destroy(bmpc_batch* b);
+
+BMPC_API void bmpc_problem_destroy(bmpc_problem* p)
+{
+    if (!p) return;
+    if (p->self) bmpc_batch_destroy(p->self);
+    (void)hipFree(p->d_weight);
+    (void)hipFree(p->d_ref);
+    (void)hipFree(p->d_obs);
+    (void)hipFree(p->d_has);
+    (void)hipFree(p->d_x0);
+    delete p;
+}
+
+BMPC_API bmpc_status bmpc_problem_set_x0(bmpc_problem* p, const double* x0)
+{
+    if (!p || !x0) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(x0[i])) return fail(BMPC_ERR_NONFINITE, "x0 has a non-finite entry");
+    BMPC_HIP_TRY(hipMemcpy(p->d_x0, x0, sizeof(double) * 4, hipMemcpyHostToDevice));
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_batch_create(bmpc_problem* const* problems, int32_t count, int32_t hist_cap,
+                                       bmpc_batch** out)
+{
+    if (!problems || count <= 0 || !out || hist_cap < 0) return fail(BMPC_ERR_INVALID_ARG, "bad argument");
+    *out = nullptr;
+    auto* b = new bmpc_batch();
+    b->count = count;
+    b->hist_cap = hist_cap;
+    b->problems.assign(problems, problems + count);
+    b->offset.resize(count);
+    long tot = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!problems[i]) {
+            delete b;
+            return fail(BMPC_ERR_INVALID_ARG, "problem %d is NULL", i);
+        }
+        b->offset[i] = (int)tot;
+        tot += problems[i]->N;
+    }
+    b->total_nodes = tot;
+    bool ok = dalloc(&b->d_desc, count) && dalloc(&b->d_out, count) && dalloc(&b->d_bad, count) &&
+              dalloc(&b->d_state, (size_t)tot * 15) && dalloc(&b->d_ws, (size_t)tot * W_NODE) &&
+              (hist_cap == 0 || dalloc(&b->d_hist, (size_t)count * hist_cap * 6));
+    if (!ok) {
+        bmpc_batch_destroy(b);
+        return fail(BMPC_ERR_OOM, "device allocation for the batch failed");
+    }
+    if (hipMemset(b->d_state, 0, sizeof(double) * tot * 15) != hipSuccess) {
+        bmpc_batch_destroy(b);
+        return fail(BMPC_ERR_HIP, "hipMemset failed");
+    }
+    b->h_desc.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const bmpc_problem* p = problems[i];
+        InstDesc& d = b->h_desc[i];
+        d.N = p->N;
+        d.T = p->tree->h.depth;
+        d.parent = p->tree->d.parent;
+        d.child_off = p->tree->d.child_off;
+        d.level_off = p->tree->d.level_off;
+        d.weight = p->d_weight;
+        d.ref = p->d_ref;
+        d.obs = p->d_obs;
+        d.has_obs = p->d_has;
+        d.x0 = p->d_x0;
+        d.prm = to_dev(p->prm);
+        const long o = b->offset[i];
+        d.x = b->d_state + o * 4;
+        d.u = b->d_state + tot * 4 + o * 2;
+        d.lam = b->d_state + tot * 6 + o * 4;
+        d.ye = b->d_state + tot * 10 + o * 5;
+        d.ws = b->d_ws + o * W_NODE;
+    }
+    if (hipMemcpy(b->d_desc, b->h_desc.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice) != hipSuccess) {
+        bmpc_batch_destroy(b);
+        return fail(BMPC_ERR_HIP, "uploading the batch descriptors failed");
+    }
+    *out = b;
+    return BMPC_OK;
+}
+
+BMPC_API void bmpc_batch_destroy(bmpc_batch* b)
+{
+    if (!b) return;
+    (void)hipFree(b->d_desc);
+    (void)hipFree(b->d_out);
+    (void)hipFree(b->d_bad);
+    (void)hipFree(b->d_state);
+    (void)hipFree(b->d_ws);
+    (void)hipFree(b->d_hist);
+    delete b;
+}
+
+BMPC_API bmpc_status bmpc_batch_launch(bmpc_batch* b, const bmpc_settings* s, int32_t warm, void* stream)
+{
+    if (!b || !s) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    if (s->n_alpha < 1 || s->n_alpha > NALPHA_MAX)
+        return fail(BMPC_ERR_INVALID_ARG, "n_alpha must be in [1, %d]", NALPHA_MAX);
+    if (s->riccati_variant != BMPC_RICCATI_AUTO && s->riccati_variant != BMPC_RICCATI_LEVEL)
+        return fail(BMPC_ERR_UNSUPPORTED, "Riccati variant %d is not available in the batched solver",
+                    s->riccati_variant);
+    hipStream_t st = (hipStream_t)stream;
+    const SolverCfg cfg = to_cfg(*s, warm);
+    ProfScope ps("bmpc_solve_workgroup", st);
+    hipLaunchKernelGGL(k_bmpc_wg<256>, dim3(b->count), dim3(256), 0, st, b->d_desc, cfg, b->d_out, b->d_bad,
+                       b->d_hist, b->hist_cap);
+    BMPC_HIP_TRY(hipGetLastError());
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_batch_stats(bmpc_batch* b, bmpc_stats* stats, void* stream)
+{
+    if (!b || !stats) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    BMPC_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    std::vector<SolveOut> o(b->count);
+    BMPC_HIP_TRY(hipMemcpy(o.data(), b->d_out, sizeof(SolveOut) * b->count, hipMemcpyDeviceToHost));
+    int worst = BMPC_OK;
+    for (int i = 0; i < b->count; ++i) {
+        stats[i].status = o[i].status;
+        stats[i].outer_it = o[i].outer_it;
+        stats[i].inner_it = o[i].inner_it;
+        stats[i].ls_failures = o[i].ls_failures;
+        stats[i].bad_node = o[i].bad_node;
+        stats[i].r_kkt = o[i].r_kkt;
+        stats[i].viol = o[i].viol;
+        stats[i].rho = o[i].rho;
+        stats[i].mu = o[i].mu;
+        stats[i].merit = o[i].merit;
+        if (o[i].status != BMPC_OK && worst == BMPC_OK) worst = o[i].status;
+    }
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_batch_state(bmpc_batch* b, int32_t i, double* x, double* u, double* lam, double* ye,
+                                      int32_t into_batch, void* stream)
+{
+    if (!b || i < 0 || i >= b->count) return fail(BMPC_ERR_INVALID_ARG, "bad instance index");
+    hipStream_t st = (hipStream_t)stream;
+    const InstDesc& d = b->h_desc[i];
+    const size_t N = d.N;
+    struct {
+        double* ext;
+        double* in;
+        size_t n;
+    } parts[4] = {{x, d.x, 4 * N}, {u, d.u, 2 * N}, {lam, d.lam, 4 * N}, {ye, d.ye, 5 * N}};
+    for (auto& pt : parts) {
+        if (!pt.ext) continue;
+        if (into_batch)
+            BMPC_HIP_TRY(hipMemcpyAsync(pt.in, pt.ext, sizeof(double) * pt.n, hipMemcpyDeviceToDevice, st));
+        else
+            BMPC_HIP_TRY(hipMemcpyAsync(pt.ext, pt.in, sizeof(double) * pt.n, hipMemcpyDeviceToDevice, st));
+    }
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_batch_history(bmpc_batch* b, int32_t i, double* hist, void* stream)
+{
+    if (!b || i < 0 || i >= b->count || !hist) return fail(BMPC_ERR_INVALID_ARG, "bad argument");
+    if (!b->d_hist) return fail(BMPC_ERR_INVALID_ARG, "batch was created without history");
+    BMPC_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    BMPC_HIP_TRY(hipMemcpy(hist, b->d_hist + (size_t)i * b->hist_cap * 6, sizeof(double) * b->hist_cap * 6,
+                           hipMemcpyDeviceToHost));
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_solve(bmpc_problem* p, const bmpc_settings* s, int32_t warm, double* x, double* u,
+                                double* lam, double* ye, bmpc_stats* stats, void* stream)
+{
+    if (!p || !s || !x || !u || !lam || !ye || !stats) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    bmpc_status st;
+    if (!p->self) {
+        bmpc_problem* one[1] = {p};
+        if ((st = bmpc_batch_create(one, 1, 0, &p->self)) != BMPC_OK) return st;
+    }
+    if (warm && (st = bmpc_batch_state(p->self, 0, (warm & 1) ? x : nullptr, (warm & 1) ? u : nullptr,
+                                       (warm & 2) ? lam : nullptr, (warm & 4) ? ye : nullptr, 1, stream)) != BMPC_OK)
+        return st;
+    if ((st = bmpc_batch_launch(p->self, s, warm, stream)) != BMPC_OK) return st;
+    if ((st = bmpc_batch_state(p->self, 0, x, u, lam, ye, 0, stream)) != BMPC_OK) return st;
+    if ((st = bmpc_batch_stats(p->self, stats, stream)) != BMPC_OK) return st;
+    if (stats->status != BMPC_OK) {
+        if (stats->status == BMPC_ERR_NOT_PD)
+            return fail(BMPC_ERR_NOT_PD, "Riccati Hessian not positive definite at node %d", stats->bad_node);
+        return fail(stats->status, "solver stopped with status %d after %d inner iterations", stats->status,
+                    stats->inner_it);
+    }
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_linearize(bmpc_problem* p, const double* x, const double* u, const double* lam,
+                                    const double* ye, double rho, double* A, double* B, double* c, double* Q,
+                                    double* R, double* q, double* r, double* kkt_viol, void* stream)
+{
+    if (!p || !x || !u || !lam || !ye || !A || !B || !c || !Q || !R || !q || !r)
+        return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    if (!(rho > 0.0)) return fail(BMPC_ERR_INVALID_ARG, "rho must be positive");
+    bmpc_status st;
+    if (!p->self) {
+        bmpc_problem* one[1] = {p};
+        if ((st = bmpc_batch_create(one, 1, 0, &p->self)) != BMPC_OK) return st;
+    }
+    hipStream_t sm = (hipStream_t)stream;
+    if ((st = bmpc_batch_state(p->self, 0, const_cast<double*>(x), const_cast<double*>(u),
+                               const_cast<double*>(lam), const_cast<double*>(ye), 1, stream)) != BMPC_OK)
+        return st;
+    const InstDesc& d = p->self->h_desc[0];
+    double* kk = nullptr;
+    if (kkt_viol) BMPC_HIP_TRY(hipMalloc(&kk, 2 * sizeof(double)));
+    {
+        ProfScope ps("bmpc_linearise", sm);
+        hipLaunchKernelGGL(k_bmpc_linearise<256>, dim3(1), dim3(256), 0, sm, d, rho, kk);
+    }
+    BMPC_HIP_TRY(hipGetLastError());
+    // unpack the workspace rows into the caller's node-major arrays
+    const size_t N = d.N;
+    const size_t pitch = sizeof(double) * W_NODE;
+    struct {
+        double* dst;
+        int off, w;
+    } parts[7] = {{A, W_A, 16}, {B, W_B, 8}, {c, W_C, 4}, {Q, W_Q, 16}, {R, W_R, 4}, {q, W_QV, 4}, {r, W_RV, 2}};
+    for (auto& pt : parts)
+        BMPC_HIP_TRY(hipMemcpy2DAsync(pt.dst, sizeof(double) * pt.w, d.ws + pt.off, pitch, sizeof(double) * pt.w,
+                                      N, hipMemcpyDeviceToDevice, sm));
+    if (kkt_viol) {
+        BMPC_HIP_TRY(hipMemcpyAsync(kkt_viol, kk, 2 * sizeof(double), hipMemcpyDeviceToHost, sm));
+        BMPC_HIP_TRY(hipStreamSynchronize(sm));
+        (void)hipFree(kk);
+    }
+    return BMPC_OK;
+}
+
+}  // extern "C"

@@ -61,6 +61,9 @@ static bmpc_status analyse(const int32_t* parent, int32_t N, HostTree& h)
                               p < 0 ? 0 : h.child_off[p + 1] - h.child_off[p]);
     }
     h.depth = *std::max_element(h.stage.begin(), h.stage.end());
+    h.level_off.assign(h.depth + 2, 0);
+    for (int i = 0; i < N; ++i) h.level_off[h.stage[i] + 1]++;
+    for (int s = 0; s <= h.depth; ++s) h.level_off[s + 1] += h.level_off[s];
     h.leaves.clear();
     for (int i = 0; i < N; ++i)
         if (h.child_off[i] == h.child_off[i + 1]) h.leaves.push_back(i);
@@ -136,7 +139,7 @@ bmpc_status tree_on_device(bmpc_tree* t)
     bmpc_status st;
 #define UP(field) \
     if ((st = upload(t, h.field, &d.field)) != BMPC_OK) return st;
-    UP(parent) UP(child_off) UP(info) UP(stage) UP(leaves) UP(leaf_stage) UP(path) UP(first_leaf)
+    UP(parent) UP(child_off) UP(info) UP(stage) UP(level_off) UP(leaves) UP(leaf_stage) UP(path) UP(first_leaf)
     UP(seg_start) UP(seg_end) UP(seg_len) UP(seg_of) UP(seg_pos) UP(seg_nodes) UP(seg_off)
 #undef UP
     t->on_device = true;
