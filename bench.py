@@ -208,6 +208,136 @@ def run_lqr(args, torch, L):
     return out, insts[0]
 
 
+def _oracle_batch_solve(args):
+    import bmpc_synth as S
+    import oracle
+    i = args
+    inst = _BATCH_CACHE[i]
+    t0 = time.perf_counter()
+    _, st, _ = oracle.solve(oracle.problem_from_instance(inst))
+    return st["status"], st["inner_it"], time.perf_counter() - t0
+
+
+_BATCH_CACHE = None
+
+
+def cpu_baseline_bmpc(insts, budget_s=10.0):
+    """Oracle solves of the batched workload spread over the host cores (one
+    instance per process), for about budget_s seconds."""
+    global _BATCH_CACHE
+    import multiprocessing as mp
+    _BATCH_CACHE = insts
+    cores = min(16, os.cpu_count() or 1)
+    ctx = mp.get_context("fork")
+    done = 0
+    conv = 0
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        idx = 0
+        while time.perf_counter() - t0 < budget_s and idx < len(insts):
+            chunk = list(range(idx, min(len(insts), idx + cores)))
+            idx += len(chunk)
+            for stt, it, dt in pool.map(_oracle_batch_solve, chunk):
+                done += 1
+                conv += stt == 0
+    el = time.perf_counter() - t0
+    return {"value": conv / el, "unit": "BMPC solves/s (KKT <= 1e-6)", "cores": cores, "kind": "oracle",
+            "sample": f"{done} cold oracle solves of the first {done} batched instances "
+                      f"({conv} converged) in {el:.1f} s, one instance per process on {cores} cores"}
+
+
+def run_bmpc(args, torch, L):
+    import bmpc_synth as S
+    from paper_2506_13624_amd.bicycle import Problem
+
+    out = {}
+    st = L.bmpc_settings_default()
+    # single branch-MPC problem (53 nodes): solve latency
+    single = [Problem(S.single_bmpc(i)) for i in range(8)]
+    b1 = [L.bmpc_batch_create([p.handle]) for p in single]
+    for b in b1:
+        L.bmpc_batch_launch(b, st)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    ev0.record()
+    for _ in range(reps):
+        for b in b1:
+            L.bmpc_batch_launch(b, st)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_single = ev0.elapsed_time(ev1) / (reps * len(b1))
+    st1 = [L.bmpc_batch_stats(b, 1)[0] for b in b1]
+    out["bmpc_single"] = {
+        "workload": "single branch-MPC tree: bicycle, horizon 20, trunk 5 stages then 3 branches, "
+                    "53 nodes, seeds 0-7, cold start",
+        "ms_per_solve": round(ms_single, 4), "solves_per_s": round(1e3 / ms_single, 1),
+        "converged": sum(s["status"] == 0 for s in st1), "of": len(st1),
+        "mean_inner_it": float(np.mean([s["inner_it"] for s in st1]))}
+    for b in b1:
+        L.bmpc_batch_destroy(b)
+    for p in single:
+        p.close()
+
+    # batched: 512 instances of uneven size in one launch
+    insts = S.batched_instances(512)
+    pbs = [Problem(i) for i in insts]
+    b = L.bmpc_batch_create([p.handle for p in pbs])
+    L.bmpc_batch_launch(b, st)  # warm-up (also compiles nothing; first launch)
+    torch.cuda.synchronize()
+    L.bmpc_profile_enable(True)
+    ev0.record()
+    L.bmpc_batch_launch(b, st)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_cold = ev0.elapsed_time(ev1)
+    s_cold = L.bmpc_batch_stats(b, len(insts))
+    # receding-horizon step, then warm and cold solves of the same shifted problems
+    L.bmpc_batch_shift(b)
+    ev0.record()
+    L.bmpc_batch_launch(b, st, warm=7)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_warm = ev0.elapsed_time(ev1)
+    s_warm = L.bmpc_batch_stats(b, len(insts))
+    ev0.record()
+    L.bmpc_batch_launch(b, st, warm=0)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_cold2 = ev0.elapsed_time(ev1)
+    s_cold2 = L.bmpc_batch_stats(b, len(insts))
+    prof = L.bmpc_profile_read()
+    L.bmpc_profile_enable(False)
+    nodes = sum(i.num_nodes for i in insts)
+
+    def conv(ss):
+        return int(sum(x["status"] == 0 for x in ss))
+
+    def mean_it(ss):
+        v = [x["inner_it"] for x in ss if x["status"] == 0]
+        return float(np.mean(v)) if v else None
+
+    out["bmpc_batched"] = {
+        "workload": "512 bicycle branch-MPC instances in one launch: branches U{2..8} at stage U{0..5}, "
+                    f"horizon U{{20..60}}, {nodes} nodes in total",
+        "cold": {"ms": round(ms_cold, 3), "converged": conv(s_cold), "mean_inner_it": mean_it(s_cold),
+                 "solves_per_s": round(conv(s_cold) / (ms_cold / 1e3), 1)},
+        "shifted_warm": {"ms": round(ms_warm, 3), "converged": conv(s_warm), "mean_inner_it": mean_it(s_warm),
+                         "solves_per_s": round(conv(s_warm) / (ms_warm / 1e3), 1)},
+        "cold_same_shifted_problems": {"ms": round(ms_cold2, 3), "converged": conv(s_cold2),
+                                       "mean_inner_it": mean_it(s_cold2),
+                                       "solves_per_s": round(conv(s_cold2) / (ms_cold2 / 1e3), 1)},
+        "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]} for k, v in prof.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["bmpc_batched"]["cpu_baseline"] = cpu_baseline_bmpc(insts, args.cpu_budget)
+    L.bmpc_batch_destroy(b)
+    for p in pbs:
+        p.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +361,8 @@ def main():
     from paper_2506_13624_amd import _lib as L
 
     out, inst = run_lqr(args, torch, L)
+    if not args.skip_bmpc:
+        out.update(run_bmpc(args, torch, L))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_lqr(inst, args.cpu_budget)
     else:

@@ -259,6 +259,16 @@ BMPC_API bmpc_status bmpc_batch_stats(bmpc_batch* batch, bmpc_stats* stats, void
    (warm start), 0 reads it.  Asynchronous. */
 BMPC_API bmpc_status bmpc_batch_state(bmpc_batch* batch, int32_t i, double* x, double* u, double* lam,
                                       double* ye, int32_t into_batch, void* stream);
+/* Receding-horizon step for every problem of the batch, in place: the
+   measured state becomes x0' = F(x0, u_0); node n of the next problem stands
+   for the old nodes one stage later on the same scenarios (its children), so
+   its state, input, costate, PHR multipliers and reference become the
+   weight-averaged values of its children; a node whose children are leaves
+   repeats its own input; leaves keep costate and multipliers, extrapolate
+   the reference from the parent and are rolled out from the new parent.
+   The result is the shifted warm start for bmpc_batch_launch(warm = 7).
+   The problems' x0 and references are updated.  Asynchronous. */
+BMPC_API bmpc_status bmpc_batch_shift(bmpc_batch* batch, void* stream);
 /* Synchronise and copy the iteration history of problem i to hist (host,
    hist_cap x 6). */
 BMPC_API bmpc_status bmpc_batch_history(bmpc_batch* batch, int32_t i, double* hist, void* stream);

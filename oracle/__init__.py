@@ -108,6 +108,7 @@ def _declare(L):
     L.orc_kkt.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, C.c_double]
     L.orc_adjoint.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_double, _dp]
     L.orc_rollout.argtypes = [C.POINTER(Problem), _dp, _dp]
+    L.orc_shift.argtypes = [C.POINTER(Problem)] + [_dp] * 10
     if hasattr(L, "orc_mlp_forward"):
         _declare_mlp(L)
 
@@ -337,3 +338,18 @@ def rollout(pb, u):
     x = np.zeros((pb.N, 4))
     lib().orc_rollout(pb.ptr, _d(_f64(u)), _d(x))
     return x
+
+
+def shift(pb: BmpcProblem, state):
+    """Shifted warm start after one simulated step.  Returns (new problem,
+    shifted state dict)."""
+    N = pb.N
+    ref = np.zeros((N, 4))
+    x0 = np.zeros(4)
+    out = {"x": np.zeros((N, 4)), "u": np.zeros((N, 2)), "lam": np.zeros((N, 4)),
+           "ye": np.zeros((N, 5))}
+    st = {k: _f64(state[k]) for k in ("x", "u", "lam", "ye")}
+    lib().orc_shift(pb.ptr, _d(st["x"]), _d(st["u"]), _d(st["lam"]), _d(st["ye"]), _d(ref), _d(x0),
+                    _d(out["x"]), _d(out["u"]), _d(out["lam"]), _d(out["ye"]))
+    new = BmpcProblem(pb.parent, pb.weight, ref, pb.obs, pb.has_obs, x0, pb.model)
+    return new, out

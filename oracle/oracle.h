@@ -105,6 +105,9 @@ double orc_violation(const orc_problem* pb, const double* x, const double* u,
 void orc_adjoint(const orc_problem* pb, const double* x, const double* u,
                  const double* ye, double rho, double* lam);
 void orc_rollout(const orc_problem* pb, const double* u, double* x);
+void orc_shift(const orc_problem* pb, const double* x, const double* u, const double* lam,
+               const double* ye, double* ref_new, double* x0_new, double* xs, double* us,
+               double* lams, double* yes);
 
 #ifdef __cplusplus
 }

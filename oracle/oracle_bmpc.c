@@ -634,3 +634,75 @@ done:
     free(lt);
     return status;
 }
+
+/* ------------------------------------------------------------------------
+ * Shifted warm start after one simulated step (receding horizon).
+ * The measured state moves to x0' = F(x0, u_0).  Node n of the new problem
+ * stands for the old nodes one stage later on the same scenarios, i.e. its
+ * children: every value (state, input, costate, PHR multipliers, reference)
+ * becomes the pi-weighted mean over the children (the plain mean if their
+ * weights sum to zero); a node whose children are leaves repeats its own
+ * input.  Leaves keep their costate and multipliers, extrapolate the
+ * reference linearly from the parent, and take the state rolled out from
+ * the new parent state and input.
+ * ---------------------------------------------------------------------- */
+void orc_shift(const orc_problem* pb, const double* x, const double* u, const double* lam,
+               const double* ye, double* ref_new, double* x0_new, double* xs, double* us,
+               double* lams, double* yes)
+{
+    const int N = pb->N;
+    int* nch = child_counts(pb);
+    orc_rk4(&pb->model, pb->x0, u, x0_new, NULL, NULL);
+    for (int n = 0; n < N; ++n) {
+        if (nch[n] == 0) continue;
+        double w = 0.0, wu = 0.0;
+        int cnt = 0, cnt_ctrl = 0;
+        for (int j = n + 1; j < N; ++j)
+            if (pb->parent[j] == n) {
+                w += pb->weight[j];
+                cnt++;
+                if (nch[j] > 0) {
+                    wu += pb->weight[j];
+                    cnt_ctrl++;
+                }
+            }
+        double sx[NX] = {0}, sl[NX] = {0}, sr[4] = {0}, sy[NG] = {0}, su[NU] = {0};
+        for (int j = n + 1; j < N; ++j) {
+            if (pb->parent[j] != n) continue;
+            const double f = w > 0.0 ? pb->weight[j] / w : 1.0 / cnt;
+            for (int a = 0; a < NX; ++a) {
+                sx[a] += f * x[j * NX + a];
+                sl[a] += f * lam[j * NX + a];
+            }
+            for (int a = 0; a < 4; ++a) sr[a] += f * pb->ref[j * 4 + a];
+            for (int a = 0; a < NG; ++a) sy[a] += f * ye[j * NG + a];
+            if (nch[j] > 0) {
+                const double fu = wu > 0.0 ? pb->weight[j] / wu : 1.0 / cnt_ctrl;
+                for (int a = 0; a < NU; ++a) su[a] += fu * u[j * NU + a];
+            }
+        }
+        for (int a = 0; a < NX; ++a) {
+            xs[n * NX + a] = sx[a];
+            lams[n * NX + a] = sl[a];
+        }
+        for (int a = 0; a < 4; ++a) ref_new[n * 4 + a] = sr[a];
+        for (int a = 0; a < NG; ++a) yes[n * NG + a] = sy[a];
+        for (int a = 0; a < NU; ++a) us[n * NU + a] = cnt_ctrl > 0 ? su[a] : u[n * NU + a];
+    }
+    for (int a = 0; a < NX; ++a) xs[a] = x0_new[a];
+    for (int n = 1; n < N; ++n) {
+        if (nch[n] != 0) continue;
+        const int p = pb->parent[n];
+        for (int a = 0; a < 4; ++a) ref_new[n * 4 + a] = 2.0 * pb->ref[n * 4 + a] - pb->ref[p * 4 + a];
+        for (int a = 0; a < NX; ++a) lams[n * NX + a] = lam[n * NX + a];
+        for (int a = 0; a < NG; ++a) yes[n * NG + a] = ye[n * NG + a];
+        for (int a = 0; a < NU; ++a) us[n * NU + a] = 0.0;
+    }
+    /* leaves: roll out from the shifted parents (parents precede children) */
+    for (int n = 1; n < N; ++n)
+        if (nch[n] == 0) {
+            const int p = pb->parent[n];
+            orc_rk4(&pb->model, xs + p * NX, us + p * NU, xs + n * NX, NULL, NULL);
+        }
+    free(nch);
+}

@@ -231,6 +231,7 @@ _sig("bmpc_batch_launch", _i32, [_vp, C.POINTER(bmpc_settings), _i32, _vp])
 _sig("bmpc_batch_stats", _i32, [_vp, C.POINTER(bmpc_stats), _vp])
 _sig("bmpc_batch_state", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp])
 _sig("bmpc_batch_history", _i32, [_vp, _i32, _pd, _vp])
+_sig("bmpc_batch_shift", _i32, [_vp, _vp])
 
 
 def bmpc_settings_default(**kw):
@@ -328,3 +329,7 @@ def bmpc_batch_history(batch, i, hist_cap, stream=None):
     h = np.zeros((hist_cap, 6))
     check(lib.bmpc_batch_history(batch, i, h.ctypes.data_as(_pd), stream_ptr(stream)))
     return h
+
+
+def bmpc_batch_shift(batch, stream=None):
+    check(lib.bmpc_batch_shift(batch, stream_ptr(stream)))

@@ -679,6 +679,101 @@ __global__ void __launch_bounds__(BS) k_bmpc_linearise(InstDesc I, double rho, d
     }
 }
 
+// Shifted warm start after one simulated step: x0' = F(x0, u_0); every
+// non-leaf node takes the weight-averaged values of its children (the old
+// nodes one stage later on the same scenarios), a node whose children are
+// leaves repeats its own input, leaves keep costates and multipliers,
+// extrapolate their reference and are rolled out from the new parent.
+// The workspace rows serve as scratch for the new values.
+template <int BS>
+__global__ void __launch_bounds__(BS) k_bmpc_shift(const InstDesc* __restrict__ insts)
+{
+    const InstDesc I = insts[blockIdx.x];
+    const int N = I.N, tid = threadIdx.x;
+    double* ref = const_cast<double*>(I.ref);
+    double* x0 = const_cast<double*>(I.x0);
+    // scratch columns inside each workspace row
+    constexpr int T_X = W_Q, T_U = W_Q + 4, T_L = W_Q + 6, T_Y = W_Q + 10, T_R = W_K;
+    for (int n = tid; n < N; n += BS) {
+        double* w = I.ws + (long)n * W_NODE;
+        const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+        if (c0 == c1) {
+            const int p = I.parent[n];
+            for (int a = 0; a < 4; ++a) {
+                w[T_L + a] = I.lam[n * 4 + a];
+                w[T_R + a] = p >= 0 ? 2.0 * ref[n * 4 + a] - ref[p * 4 + a] : ref[n * 4 + a];
+            }
+            for (int a = 0; a < BG; ++a) w[T_Y + a] = I.ye[n * BG + a];
+            w[T_U] = 0.0;
+            w[T_U + 1] = 0.0;
+            continue;
+        }
+        double wsum = 0.0, wu = 0.0;
+        int nctrl = 0;
+        for (int j = c0; j < c1; ++j) {
+            wsum += I.weight[j];
+            if (I.child_off[j] < I.child_off[j + 1]) {
+                wu += I.weight[j];
+                ++nctrl;
+            }
+        }
+        double sx[4] = {}, sl[4] = {}, sr[4] = {}, sy[BG] = {}, su[2] = {};
+        for (int j = c0; j < c1; ++j) {
+            const double f = wsum > 0.0 ? I.weight[j] / wsum : 1.0 / (c1 - c0);
+            for (int a = 0; a < 4; ++a) {
+                sx[a] += f * I.x[j * 4 + a];
+                sl[a] += f * I.lam[j * 4 + a];
+                sr[a] += f * ref[j * 4 + a];
+            }
+            for (int a = 0; a < BG; ++a) sy[a] += f * I.ye[j * BG + a];
+            if (I.child_off[j] < I.child_off[j + 1]) {
+                const double fu = wu > 0.0 ? I.weight[j] / wu : 1.0 / nctrl;
+                su[0] += fu * I.u[j * 2];
+                su[1] += fu * I.u[j * 2 + 1];
+            }
+        }
+        for (int a = 0; a < 4; ++a) {
+            w[T_X + a] = sx[a];
+            w[T_L + a] = sl[a];
+            w[T_R + a] = sr[a];
+        }
+        for (int a = 0; a < BG; ++a) w[T_Y + a] = sy[a];
+        w[T_U] = nctrl > 0 ? su[0] : I.u[n * 2];
+        w[T_U + 1] = nctrl > 0 ? su[1] : I.u[n * 2 + 1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double xr[BX], ur[BU] = {I.u[0], I.u[1]}, xn[BX];
+        load4(I.x0, xr);
+        bike_step(I.prm, xr, ur, xn);
+        for (int a = 0; a < 4; ++a) I.ws[T_X + a] = xn[a];
+    }
+    __syncthreads();
+    // leaves are rolled out from their (already shifted) parents
+    for (int n = tid; n < N; n += BS) {
+        if (I.child_off[n] != I.child_off[n + 1] || n == 0) continue;
+        const double* wp = I.ws + (long)I.parent[n] * W_NODE;
+        double xp[BX], up[BU] = {wp[T_U], wp[T_U + 1]}, xn[BX];
+        load4(wp + T_X, xp);
+        bike_step(I.prm, xp, up, xn);
+        for (int a = 0; a < 4; ++a) I.ws[(long)n * W_NODE + T_X + a] = xn[a];
+    }
+    __syncthreads();
+    for (int n = tid; n < N; n += BS) {
+        const double* w = I.ws + (long)n * W_NODE;
+        for (int a = 0; a < 4; ++a) {
+            I.x[n * 4 + a] = w[T_X + a];
+            I.lam[n * 4 + a] = w[T_L + a];
+            ref[n * 4 + a] = w[T_R + a];
+        }
+        for (int a = 0; a < BG; ++a) I.ye[n * BG + a] = w[T_Y + a];
+        I.u[n * 2] = w[T_U];
+        I.u[n * 2 + 1] = w[T_U + 1];
+        if (n == 0)
+            for (int a = 0; a < 4; ++a) x0[a] = w[T_X + a];
+    }
+}
+
 }  // namespace bmpc
 
 using namespace bmpc;
@@ -1010,6 +1105,18 @@ BMPC_API bmpc_status bmpc_batch_state(bmpc_batch* b, int32_t i, double* x, doubl
         else
             BMPC_HIP_TRY(hipMemcpyAsync(pt.ext, pt.in, sizeof(double) * pt.n, hipMemcpyDeviceToDevice, st));
     }
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_batch_shift(bmpc_batch* b, void* stream)
+{
+    if (!b) return fail(BMPC_ERR_INVALID_ARG, "batch is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    {
+        ProfScope ps("bmpc_shift", st);
+        hipLaunchKernelGGL(k_bmpc_shift<256>, dim3(b->count), dim3(256), 0, st, b->d_desc);
+    }
+    BMPC_HIP_TRY(hipGetLastError());
     return BMPC_OK;
 }
 

@@ -166,3 +166,35 @@ def test_nonfinite_initial_state_rejected():
     with pytest.raises(L.BmpcError) as e:
         Problem(inst)
     assert e.value.status == 4
+
+
+def test_shift_matches_oracle_and_warm_solve_agrees():
+    insts = [S.single_bmpc(s) for s in (1, 4)] + S.batched_instances(512)[:2]
+    pbs = [Problem(i) for i in insts]
+    b = L.bmpc_batch_create([p.handle for p in pbs])
+    st = L.bmpc_settings_default()
+    L.bmpc_batch_launch(b, st)
+    stats = L.bmpc_batch_stats(b, len(insts))
+    L.bmpc_batch_shift(b)
+    torch.cuda.synchronize()
+    for i, inst in enumerate(insts):
+        N = inst.num_nodes
+        opb = oracle.problem_from_instance(inst)
+        o, os_, _ = oracle.solve(opb)
+        assert os_["status"] == stats[i]["status"]
+        onew, os = oracle.shift(opb, o)
+        x, u, lam, ye = zeros(N, 4), zeros(N, 2), zeros(N, 4), zeros(N, 5)
+        L.bmpc_batch_state(b, i, x=x, u=u, lam=lam, ye=ye)
+        torch.cuda.synchronize()
+        g = {"x": host(x, (N, 4)), "u": host(u, (N, 2)), "lam": host(lam, (N, 4)), "ye": host(ye, (N, 5))}
+        for k in g:
+            assert np.abs(g[k] - os[k]).max() <= 1e-5 * max(1.0, np.abs(os[k]).max()), k
+    L.bmpc_batch_launch(b, st, warm=7)
+    stats2 = L.bmpc_batch_stats(b, len(insts))
+    for i, inst in enumerate(insts):
+        print(f"warm instance {i}: status {stats2[i]['status']} inner {stats2[i]['inner_it']} "
+              f"(cold before {stats[i]['inner_it']})", flush=True)
+        assert stats2[i]["status"] in (0, 5, 6)
+    L.bmpc_batch_destroy(b)
+    for p in pbs:
+        p.close()

@@ -338,3 +338,66 @@ def test_single_bmpc_seeds_converge_or_report():
         else:
             assert stats["status"] in (5, 6)
     assert ok >= 0.9 * len(seeds)
+
+
+# ----------------------------------------------------------------------------
+# shifted warm start
+# ----------------------------------------------------------------------------
+
+def test_shift_on_a_chain_is_the_one_stage_shift():
+    inst = S.small_bicycle(6, [], 1, seed=3)
+    pb = oracle.problem_from_instance(inst)
+    N = pb.N
+    rng = np.random.default_rng(0)
+    st = {"u": rng.normal(0, 0.3, (N, 2)), "lam": rng.normal(0, 1, (N, 4)), "ye": np.abs(rng.normal(0, 1, (N, 5)))}
+    st["u"][-1] = 0
+    st["x"] = oracle.rollout(pb, st["u"])
+    new, s = oracle.shift(pb, st)
+    x0n = oracle.rk4(pb.model, inst.x0, st["u"][0])[0]
+    assert np.allclose(new.x0, x0n)
+    # node t takes the values of node t+1; the last control node repeats its input
+    assert np.allclose(s["x"][1:N - 1], st["x"][2:N])
+    assert np.allclose(s["x"][0], x0n)
+    assert np.allclose(s["u"][:N - 2], st["u"][1:N - 1])
+    assert np.allclose(s["u"][N - 2], st["u"][N - 2])
+    assert np.allclose(s["lam"][:N - 1], st["lam"][1:])
+    assert np.allclose(s["ye"][:N - 1], st["ye"][1:])
+    # references move one stage ahead
+    assert np.allclose(new.ref[:, 0], pb.ref[:, 0] + inst.ref_speed * inst.dt)
+    # leaf state rolled out from the shifted parent
+    assert np.allclose(s["x"][N - 1], oracle.rk4(pb.model, s["x"][N - 2], s["u"][N - 2])[0])
+
+
+def test_shift_averages_children_with_probability_weights():
+    # root -> {1, 2}; 1 -> 3 -> 5 (leaf), 2 -> 4 -> 6 (leaf)
+    par = np.array([-1, 0, 0, 1, 2, 3, 4], dtype=np.int32)
+    w = np.array([1.0, 0.25, 0.75, 0.25, 0.75, 0.25, 0.75])
+    N = len(par)
+    rng = np.random.default_rng(1)
+    ref = rng.normal(0, 1, (N, 4))
+    model = oracle.bicycle_model(S.single_bmpc(0))
+    pb = oracle.BmpcProblem(par, w, ref, np.zeros((N, 2)), np.zeros(N, np.int32), [0, 0, 0, 8.0], model)
+    st = {"x": rng.normal(0, 1, (N, 4)), "u": rng.normal(0, 0.2, (N, 2)), "lam": rng.normal(0, 1, (N, 4)),
+          "ye": rng.normal(0, 1, (N, 5))}
+    new, s = oracle.shift(pb, st)
+    assert np.allclose(s["lam"][0], 0.25 * st["lam"][1] + 0.75 * st["lam"][2])
+    assert np.allclose(s["u"][0], 0.25 * st["u"][1] + 0.75 * st["u"][2])
+    assert np.allclose(new.ref[0], 0.25 * ref[1] + 0.75 * ref[2])
+    assert np.allclose(s["x"][1], st["x"][3]) and np.allclose(s["u"][1], st["u"][3])
+    assert np.allclose(s["u"][3], st["u"][3])  # children are leaves: input repeated
+    assert np.allclose(new.ref[5], 2 * ref[5] - ref[3])
+
+
+def test_shifted_warm_start_needs_fewer_iterations_than_cold():
+    fewer = 0
+    for seed in range(6):
+        pb = oracle.problem_from_instance(S.single_bmpc(seed))
+        st, stats, _ = oracle.solve(pb)
+        if stats["status"] != 0:
+            continue
+        new, ws = oracle.shift(pb, st)
+        _, s_warm, _ = oracle.solve(new, warm=ws)
+        _, s_cold, _ = oracle.solve(new)
+        if s_warm["status"] == 0 and (s_cold["status"] != 0 or s_warm["inner_it"] < s_cold["inner_it"]):
+            fewer += 1
+    assert fewer >= 4
