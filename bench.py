@@ -293,7 +293,17 @@ def run_bmpc(args, torch, L):
     torch.cuda.synchronize()
     ms_cold = ev0.elapsed_time(ev1)
     s_cold = L.bmpc_batch_stats(b, len(insts))
+    # the same cold batch with the log-depth (segment-scan) backward pass
+    st_seg = L.bmpc_settings_default(riccati_variant=L.RICCATI_SEGSCAN)
+    ev0.record()
+    L.bmpc_batch_launch(b, st_seg)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_cold_seg = ev0.elapsed_time(ev1)
+    s_cold_seg = L.bmpc_batch_stats(b, len(insts))
     # receding-horizon step, then warm and cold solves of the same shifted problems
+    L.bmpc_batch_launch(b, st)  # back to the level-parallel solution at t
+    torch.cuda.synchronize()
     L.bmpc_batch_shift(b)
     ev0.record()
     L.bmpc_batch_launch(b, st, warm=7)
@@ -323,6 +333,9 @@ def run_bmpc(args, torch, L):
                     f"horizon U{{20..60}}, {nodes} nodes in total",
         "cold": {"ms": round(ms_cold, 3), "converged": conv(s_cold), "mean_inner_it": mean_it(s_cold),
                  "solves_per_s": round(conv(s_cold) / (ms_cold / 1e3), 1)},
+        "cold_segment_scan": {"ms": round(ms_cold_seg, 3), "converged": conv(s_cold_seg),
+                              "mean_inner_it": mean_it(s_cold_seg),
+                              "solves_per_s": round(conv(s_cold_seg) / (ms_cold_seg / 1e3), 1)},
         "shifted_warm": {"ms": round(ms_warm, 3), "converged": conv(s_warm), "mean_inner_it": mean_it(s_warm),
                          "solves_per_s": round(conv(s_warm) / (ms_warm / 1e3), 1)},
         "cold_same_shifted_problems": {"ms": round(ms_cold2, 3), "converged": conv(s_cold2),

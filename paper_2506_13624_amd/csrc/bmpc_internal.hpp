@@ -58,15 +58,17 @@ struct TreeDev {
     const int* seg_pos;   // N: position of the node inside its segment (0 = top)
     const int* seg_nodes; // N: nodes of all segments, segment by segment, top to bottom
     const int* seg_off;   // S+1: offsets into seg_nodes
+    const int* seg_depth; // S: number of branching ancestors of the segment
     int max_seg_len;
+    int max_seg_depth;
 };
 
 struct HostTree {
     std::vector<int> parent, child_off, stage, leaves, leaf_stage, path, first_leaf;
     std::vector<int4> info;
     std::vector<int> level_off;
-    std::vector<int> seg_start, seg_end, seg_len, seg_of, seg_pos, seg_nodes, seg_off;
-    int N = 0, depth = 0, max_seg_len = 0;
+    std::vector<int> seg_start, seg_end, seg_len, seg_of, seg_pos, seg_nodes, seg_off, seg_depth;
+    int N = 0, depth = 0, max_seg_len = 0, max_seg_depth = 0;
 };
 
 }  // namespace bmpc

@@ -28,6 +28,7 @@
 #include "bmpc_device.hpp"
 #include "bmpc_internal.hpp"
 #include "lqr_device.hpp"
+#include "cvf_device.hpp"
 #include "profile.hpp"
 
 namespace bmpc {
@@ -51,7 +52,9 @@ enum WsOff : int {
     W_DX = 88,         // 4
     W_DU = 92,         // 2
     W_LH = 94,         // 4: LQR costates
-    W_NODE = 98
+    W_S0 = 98,         // 56: conditional value function (A, c, C, P, p), scan buffer 0
+    W_S1 = 154,        // 56: scan buffer 1
+    W_NODE = 210
 };
 
 struct InstDesc {
@@ -70,6 +73,15 @@ struct InstDesc {
     double* lam;  // N x 4
     double* ye;   // N x 5
     double* ws;   // N x W_NODE
+    // maximal unbranched segments (segment-scan variant)
+    const int* seg_of;
+    const int* seg_pos;
+    const int* seg_len;
+    const int* seg_nodes;
+    const int* seg_off;
+    const int* seg_end;
+    const int* seg_depth;
+    int max_seg_len, max_seg_depth;
 };
 
 struct SolverCfg {
@@ -325,6 +337,218 @@ __device__ void pass_riccati(const InstDesc& I, int* bad)
     }
 }
 
+// ---------------------------------------------------------------- segment scan
+__device__ __forceinline__ void cvf_load(const double* w, Cvf<BX>& e)
+{
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) {
+            e.A[i][j] = w[i * 4 + j];
+            e.C[i][j] = w[20 + i * 4 + j];
+            e.P[i][j] = w[36 + i * 4 + j];
+        }
+        e.c[i] = w[16 + i];
+        e.p[i] = w[52 + i];
+    }
+}
+__device__ __forceinline__ void cvf_store(double* w, const Cvf<BX>& e)
+{
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) {
+            w[i * 4 + j] = e.A[i][j];
+            w[20 + i * 4 + j] = e.C[i][j];
+            w[36 + i * 4 + j] = e.P[i][j];
+        }
+        w[16 + i] = e.c[i];
+        w[52 + i] = e.p[i];
+    }
+}
+
+__device__ __forceinline__ void stage_from_ws(const double* w, StageRegs<BX, BU>& st)
+{
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) st.Q[i][j] = w[W_Q + i * 4 + j];
+        st.q[i] = w[W_QV + i];
+    }
+#pragma unroll
+    for (int i = 0; i < BU; ++i) {
+#pragma unroll
+        for (int j = 0; j < BU; ++j) st.R[i][j] = w[W_R + i * 2 + j];
+#pragma unroll
+        for (int j = 0; j < BX; ++j) st.M[i][j] = 0.0;
+        st.r[i] = w[W_RV + i];
+    }
+}
+
+__device__ __forceinline__ void edge_from_ws(const double* w, const double* wj, EdgeRegs<BX, BU>& ed)
+{
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) ed.A[i][j] = w[W_A + i * 4 + j];
+#pragma unroll
+        for (int j = 0; j < BU; ++j) ed.B[i][j] = w[W_B + i * 2 + j];
+        ed.c[i] = wj[W_C + i];
+    }
+}
+
+// Riccati merge at node n over all its children (children's P, p ready);
+// stores K, k, P, p of n.  Leaves: P = Q, p = q.
+__device__ __forceinline__ void riccati_merge_ws(const InstDesc& I, int n, int* bad)
+{
+    double* w = I.ws + (long)n * W_NODE;
+    const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+    if (c0 == c1) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) w[W_P + e] = w[W_Q + e];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[W_PV + e] = w[W_QV + e];
+        return;
+    }
+    StageRegs<BX, BU> st;
+    stage_from_ws(w, st);
+    RicAcc<BX, BU> acc;
+    acc.init(st);
+    for (int j = c0; j < c1; ++j) {
+        const double* wj = I.ws + (long)j * W_NODE;
+        EdgeRegs<BX, BU> ed;
+        edge_from_ws(w, wj, ed);
+        double P[BX][BX], p[BX];
+#pragma unroll
+        for (int i = 0; i < BX; ++i) {
+#pragma unroll
+            for (int k = 0; k < BX; ++k) P[i][k] = wj[W_P + i * 4 + k];
+            p[i] = wj[W_PV + i];
+        }
+        acc.add_child(ed, P, p);
+    }
+    double K[BU][BX], k[BU], P[BX][BX], p[BX];
+    if (!acc.finish(K, k, P, p)) atomicMin(bad, n);
+#pragma unroll
+    for (int i = 0; i < BU; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) w[W_K + i * 4 + j] = K[i][j];
+        w[W_KV + i] = k[i];
+    }
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) w[W_P + i * 4 + j] = P[i][j];
+        w[W_PV + i] = p[i];
+    }
+}
+
+// Log-depth backward pass: conditional value functions are composed along
+// every maximal unbranched segment by a Hillis-Steele suffix scan; branching
+// nodes are merged exactly (deepest segments first); then every segment
+// node gets its value function by composing its suffix with the value
+// function of the segment's end, and its gains from its child's value
+// function (eq. feedback_laws).
+template <int BS>
+__device__ void pass_riccati_segscan(const InstDesc& I, int* bad)
+{
+    const int N = I.N;
+    for (int n = threadIdx.x; n < N; n += BS) {
+        if (I.child_off[n + 1] - I.child_off[n] != 1) continue;
+        const double* w = I.ws + (long)n * W_NODE;
+        const double* wj = I.ws + (long)I.child_off[n] * W_NODE;
+        StageRegs<BX, BU> st;
+        stage_from_ws(w, st);
+        EdgeRegs<BX, BU> ed;
+        edge_from_ws(w, wj, ed);
+        Cvf<BX> e;
+        if (!cvf_element<BX, BU>(st.Q, st.R, st.M, st.q, st.r, ed.A, ed.B, ed.c, e)) atomicMin(bad, n);
+        cvf_store(I.ws + (long)n * W_NODE + W_S0, e);
+    }
+    __syncthreads();
+    int src = W_S0, dst = W_S1;
+    for (int span = 1; span < I.max_seg_len - 1; span <<= 1) {
+        for (int n = threadIdx.x; n < N; n += BS) {
+            if (I.child_off[n + 1] - I.child_off[n] != 1) continue;
+            const int s = I.seg_of[n], pos = I.seg_pos[n], len = I.seg_len[s];
+            Cvf<BX> a;
+            cvf_load(I.ws + (long)n * W_NODE + src, a);
+            if (pos + span < len - 1) {
+                const int partner = I.seg_nodes[I.seg_off[s] + pos + span];
+                Cvf<BX> b, o;
+                cvf_load(I.ws + (long)partner * W_NODE + src, b);
+                cvf_combine<BX>(a, b, o);
+                cvf_store(I.ws + (long)n * W_NODE + dst, o);
+            } else {
+                cvf_store(I.ws + (long)n * W_NODE + dst, a);
+            }
+        }
+        __syncthreads();
+        const int t = src;
+        src = dst;
+        dst = t;
+    }
+    for (int d = I.max_seg_depth; d >= 0; --d) {
+        for (int n = threadIdx.x; n < N; n += BS) {
+            const int s = I.seg_of[n];
+            if (I.seg_depth[s] == d && I.seg_end[s] == n) riccati_merge_ws(I, n, bad);
+        }
+        __syncthreads();
+        for (int n = threadIdx.x; n < N; n += BS) {
+            const int s = I.seg_of[n];
+            if (I.seg_depth[s] != d || I.child_off[n + 1] - I.child_off[n] != 1) continue;
+            const double* we = I.ws + (long)I.seg_end[s] * W_NODE;
+            double Pv[BX][BX], pv[BX], P[BX][BX], p[BX];
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+#pragma unroll
+                for (int k = 0; k < BX; ++k) Pv[i][k] = we[W_P + i * 4 + k];
+                pv[i] = we[W_PV + i];
+            }
+            Cvf<BX> a;
+            cvf_load(I.ws + (long)n * W_NODE + src, a);
+            cvf_apply_value<BX>(a, Pv, pv, P, p);
+            double* w = I.ws + (long)n * W_NODE;
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+#pragma unroll
+                for (int k = 0; k < BX; ++k) w[W_P + i * 4 + k] = P[i][k];
+                w[W_PV + i] = p[i];
+            }
+        }
+        __syncthreads();
+    }
+    // gains of the segment nodes from their only child's value function
+    for (int n = threadIdx.x; n < N; n += BS) {
+        if (I.child_off[n + 1] - I.child_off[n] != 1) continue;
+        double* w = I.ws + (long)n * W_NODE;
+        const double* wj = I.ws + (long)I.child_off[n] * W_NODE;
+        StageRegs<BX, BU> st;
+        stage_from_ws(w, st);
+        EdgeRegs<BX, BU> ed;
+        edge_from_ws(w, wj, ed);
+        double Pc[BX][BX], pc[BX];
+#pragma unroll
+        for (int i = 0; i < BX; ++i) {
+#pragma unroll
+            for (int k = 0; k < BX; ++k) Pc[i][k] = wj[W_P + i * 4 + k];
+            pc[i] = wj[W_PV + i];
+        }
+        RicAcc<BX, BU> acc;
+        acc.init(st);
+        acc.add_child(ed, Pc, pc);
+        double K[BU][BX], k[BU], P[BX][BX], p[BX];
+        if (!acc.finish(K, k, P, p)) atomicMin(bad, n);
+#pragma unroll
+        for (int i = 0; i < BU; ++i) {
+#pragma unroll
+            for (int j = 0; j < BX; ++j) w[W_K + i * 4 + j] = K[i][j];
+            w[W_KV + i] = k[i];
+        }
+    }
+    __syncthreads();
+}
+
 // Forward linear rollout of the deviations (delta x_0 = 0) and the LQR
 // costates lam_hat = P dx + p.
 template <int BS>
@@ -405,7 +629,7 @@ __device__ void pass_adjoint(const InstDesc& I)
 }
 
 // ---------------------------------------------------------------- solver kernel
-template <int BS>
+template <int BS, bool SEGSCAN>
 __global__ void __launch_bounds__(BS) k_bmpc_wg(const InstDesc* __restrict__ insts, SolverCfg cfg,
                                                 SolveOut* __restrict__ outs, int* __restrict__ bad_flags,
                                                 double* __restrict__ hist, int hist_cap)
@@ -480,7 +704,10 @@ __global__ void __launch_bounds__(BS) k_bmpc_wg(const InstDesc* __restrict__ ins
             }
             if (r_kkt <= omega || inner >= cfg.max_inner) break;
 
-            pass_riccati<BS>(I, bad);
+            if constexpr (SEGSCAN)
+                pass_riccati_segscan<BS>(I, bad);
+            else
+                pass_riccati<BS>(I, bad);
             if (__hip_atomic_load(bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != INT_MAX) {
                 status = BMPC_ERR_NOT_PD;
                 goto done;
@@ -1025,6 +1252,16 @@ BMPC_API bmpc_status bmpc_batch_create(bmpc_problem* const* problems, int32_t co
         d.lam = b->d_state + tot * 6 + o * 4;
         d.ye = b->d_state + tot * 10 + o * 5;
         d.ws = b->d_ws + o * W_NODE;
+        const TreeDev& td = p->tree->d;
+        d.seg_of = td.seg_of;
+        d.seg_pos = td.seg_pos;
+        d.seg_len = td.seg_len;
+        d.seg_nodes = td.seg_nodes;
+        d.seg_off = td.seg_off;
+        d.seg_end = td.seg_end;
+        d.seg_depth = td.seg_depth;
+        d.max_seg_len = td.max_seg_len;
+        d.max_seg_depth = td.max_seg_depth;
     }
     if (hipMemcpy(b->d_desc, b->h_desc.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice) != hipSuccess) {
         bmpc_batch_destroy(b);
@@ -1051,14 +1288,20 @@ BMPC_API bmpc_status bmpc_batch_launch(bmpc_batch* b, const bmpc_settings* s, in
     if (!b || !s) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
     if (s->n_alpha < 1 || s->n_alpha > NALPHA_MAX)
         return fail(BMPC_ERR_INVALID_ARG, "n_alpha must be in [1, %d]", NALPHA_MAX);
-    if (s->riccati_variant != BMPC_RICCATI_AUTO && s->riccati_variant != BMPC_RICCATI_LEVEL)
-        return fail(BMPC_ERR_UNSUPPORTED, "Riccati variant %d is not available in the batched solver",
-                    s->riccati_variant);
+    if (s->riccati_variant != BMPC_RICCATI_AUTO && s->riccati_variant != BMPC_RICCATI_LEVEL &&
+        s->riccati_variant != BMPC_RICCATI_SEGSCAN)
+        return fail(BMPC_ERR_INVALID_ARG, "unknown Riccati variant %d", s->riccati_variant);
     hipStream_t st = (hipStream_t)stream;
     const SolverCfg cfg = to_cfg(*s, warm);
-    ProfScope ps("bmpc_solve_workgroup", st);
-    hipLaunchKernelGGL(k_bmpc_wg<256>, dim3(b->count), dim3(256), 0, st, b->d_desc, cfg, b->d_out, b->d_bad,
-                       b->d_hist, b->hist_cap);
+    if (s->riccati_variant == BMPC_RICCATI_SEGSCAN) {
+        ProfScope ps("bmpc_solve_workgroup_segscan", st);
+        hipLaunchKernelGGL((k_bmpc_wg<256, true>), dim3(b->count), dim3(256), 0, st, b->d_desc, cfg, b->d_out,
+                           b->d_bad, b->d_hist, b->hist_cap);
+    } else {
+        ProfScope ps("bmpc_solve_workgroup_level", st);
+        hipLaunchKernelGGL((k_bmpc_wg<256, false>), dim3(b->count), dim3(256), 0, st, b->d_desc, cfg, b->d_out,
+                           b->d_bad, b->d_hist, b->hist_cap);
+    }
     BMPC_HIP_TRY(hipGetLastError());
     return BMPC_OK;
 }

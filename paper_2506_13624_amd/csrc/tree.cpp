@@ -109,6 +109,12 @@ static bmpc_status analyse(const int32_t* parent, int32_t N, HostTree& h)
     h.seg_nodes.assign(N, -1);
     for (int i = 0; i < N; ++i) h.seg_nodes[h.seg_off[h.seg_of[i]] + h.seg_pos[i]] = i;
     h.max_seg_len = *std::max_element(h.seg_len.begin(), h.seg_len.end());
+    h.seg_depth.assign(S, 0);
+    for (int s = 0; s < S; ++s) {
+        const int p = parent[h.seg_start[s]];
+        h.seg_depth[s] = p < 0 ? 0 : h.seg_depth[h.seg_of[p]] + 1;  // parent segments come first
+    }
+    h.max_seg_depth = *std::max_element(h.seg_depth.begin(), h.seg_depth.end());
     return BMPC_OK;
 }
 
@@ -136,11 +142,12 @@ bmpc_status tree_on_device(bmpc_tree* t)
     d.depth = h.depth;
     d.num_segments = (int)h.seg_start.size();
     d.max_seg_len = h.max_seg_len;
+    d.max_seg_depth = h.max_seg_depth;
     bmpc_status st;
 #define UP(field) \
     if ((st = upload(t, h.field, &d.field)) != BMPC_OK) return st;
     UP(parent) UP(child_off) UP(info) UP(stage) UP(level_off) UP(leaves) UP(leaf_stage) UP(path) UP(first_leaf)
-    UP(seg_start) UP(seg_end) UP(seg_len) UP(seg_of) UP(seg_pos) UP(seg_nodes) UP(seg_off)
+    UP(seg_start) UP(seg_end) UP(seg_len) UP(seg_of) UP(seg_pos) UP(seg_nodes) UP(seg_off) UP(seg_depth)
 #undef UP
     t->on_device = true;
     return BMPC_OK;

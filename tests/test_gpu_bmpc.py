@@ -198,3 +198,34 @@ def test_shift_matches_oracle_and_warm_solve_agrees():
     L.bmpc_batch_destroy(b)
     for p in pbs:
         p.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 5])
+def test_segment_scan_variant_matches_level_and_oracle(seed):
+    """The log-depth backward pass (segment scan of conditional value
+    functions, exact merges at branching nodes) reaches the same iterates:
+    same status and iteration counts as the level-parallel pass and the
+    oracle, solution within the same bar."""
+    inst = S.single_bmpc(seed)
+    g1, s1 = gpu_solve(inst, L.bmpc_settings_default(riccati_variant=L.RICCATI_LEVEL))
+    g2, s2 = gpu_solve(inst, L.bmpc_settings_default(riccati_variant=L.RICCATI_SEGSCAN))
+    assert s1["status"] == s2["status"]
+    assert s1["inner_it"] == s2["inner_it"] and s1["outer_it"] == s2["outer_it"]
+    assert np.abs(g1["x"] - g2["x"]).max() <= 1e-7 * max(1.0, np.abs(g1["x"]).max())
+    _compare(inst, g2, s2)
+
+
+def test_segment_scan_batch_matches_level():
+    insts = S.batched_instances(512)[:16]
+    pbs = [Problem(i) for i in insts]
+    b = L.bmpc_batch_create([p.handle for p in pbs])
+    L.bmpc_batch_launch(b, L.bmpc_settings_default(riccati_variant=L.RICCATI_LEVEL))
+    sl = L.bmpc_batch_stats(b, len(insts))
+    L.bmpc_batch_launch(b, L.bmpc_settings_default(riccati_variant=L.RICCATI_SEGSCAN))
+    ss = L.bmpc_batch_stats(b, len(insts))
+    L.bmpc_batch_destroy(b)
+    for p in pbs:
+        p.close()
+    same = sum(a["status"] == c["status"] and a["inner_it"] == c["inner_it"] for a, c in zip(sl, ss))
+    print(f"segment scan vs level: {same}/{len(insts)} identical status and iteration counts", flush=True)
+    assert same >= len(insts) - 1
