@@ -183,9 +183,10 @@ typedef struct {
 
 /* Result of one solve.  r_kkt: last KKT residual of the relaxed problem
    (infinity norm of the Lagrangian gradient and of the defects); viol:
-   constraint violation max |max(g, -y/rho)|. */
+   constraint violation max |max(g, -y/rho)|; start: 1 if the solve began
+   from the caller's start point, 0 if from the cold start. */
 typedef struct {
-    int32_t status, outer_it, inner_it, ls_failures, bad_node;
+    int32_t status, outer_it, inner_it, ls_failures, bad_node, start;
     double r_kkt, viol, rho, mu, merit;
 } bmpc_stats;
 
@@ -216,9 +217,13 @@ BMPC_API bmpc_status bmpc_problem_set_x0(bmpc_problem* problem, const double* x0
 /* Solve one problem (Alg. 1).  x (N x 4), u (N x 2), lam (N x 4, multipliers
    of the dynamics, convention L = L_a + lam^T (f - x)), ye (N x 5, PHR
    multiplier estimates): DEVICE pointers, node-major, written on return.
-   warm bits: 1 = start from the given x, u; 2 = given lam; 4 = given ye.
-   Without bit 1 the start is u = 0 with the exact rollout from x0; without
-   bit 2 lam comes from the adjoint sweep at the start point.  Synchronous:
+   warm bits: 1 = start from the given x, u; 8 = start from the given u with
+   x from the exact rollout from x0 (wins over 1); 2 = given lam; 4 = given
+   ye (clamped at zero); 16 = guarded: also form the cold start and keep it
+   instead if its max(KKT residual, violation) at rho0 is smaller than the
+   given start's (stats->start tells which was used).  Without bits 1 and 8
+   the start is u = 0 with the exact rollout from x0; without bit 2 lam comes
+   from the adjoint sweep at the start point.  Synchronous:
    returns after the solve with *stats (host) filled.  Returns the solver
    status (BMPC_ERR_MAXITER / _LINESEARCH / _NONFINITE / _NOT_PD with the
    last iterate in the outputs). */
@@ -272,6 +277,55 @@ BMPC_API bmpc_status bmpc_batch_shift(bmpc_batch* batch, void* stream);
 /* Synchronise and copy the iteration history of problem i to hist (host,
    hist_cap x 6). */
 BMPC_API bmpc_status bmpc_batch_history(bmpc_batch* batch, int32_t i, double* hist, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start.  The paper motivates the augmented Lagrangian by how
+ * easily it is warm-started (Introduction; Sec. III); this library adds a
+ * multilayer perceptron that maps a problem description to a starting
+ * iterate.  Network: widths w_0 .. w_L; hidden layers
+ *   A_{l+1} = gelu(A_l W_l + b_l),   gelu(z) = z/2 (1 + erf(z / sqrt 2)),
+ * output Y = A_{L-1} W_{L-1} + b_{L-1} (linear).  Weights and activations
+ * are BF16 (round to nearest even), every product accumulates in FP32 on the
+ * matrix cores; master weights, gradients and Adam moments are FP32.
+ * Parameter vector (FP32, host): W_0 .. W_{L-1} (each w_l x w_{l+1},
+ * row-major), then b_0 .. b_{L-1}.  Loss: mean over all B * w_L outputs of
+ * (Y - T)^2.  Device arrays X (B x w_0), Y and T (B x w_L) are row-major
+ * FP32.  The network owns all its device memory; calls on one network must
+ * not overlap.
+ * ---------------------------------------------------------------------- */
+typedef struct bmpc_mlp bmpc_mlp;
+/* widths: host array of n_layers + 1 entries (each in [1, 65536]);
+   n_layers in [1, 16]; max_batch >= 1 bounds B of every later call.
+   Parameters start at zero.  BMPC_ERR_OOM if device memory runs out. */
+BMPC_API bmpc_status bmpc_mlp_create(const int32_t* widths, int32_t n_layers, int32_t max_batch,
+                                     bmpc_mlp** out);
+BMPC_API void bmpc_mlp_destroy(bmpc_mlp* net);
+/* Length of the parameter vector (0 for NULL). */
+BMPC_API int64_t bmpc_mlp_num_params(const bmpc_mlp* net);
+/* Load parameters (host FP32, synchronous) and reset the Adam state.
+   BMPC_ERR_NONFINITE on a NaN/Inf entry. */
+BMPC_API bmpc_status bmpc_mlp_set_params(bmpc_mlp* net, const float* params);
+/* Copy the FP32 master parameters to host (synchronous). */
+BMPC_API bmpc_status bmpc_mlp_get_params(bmpc_mlp* net, float* params);
+/* Inference: Y = network(X) for B rows, 1 <= B <= max_batch.  X is
+   converted to BF16 first.  Asynchronous on `stream`. */
+BMPC_API bmpc_status bmpc_mlp_forward(bmpc_mlp* net, const float* X, int32_t B, float* Y, void* stream);
+/* Loss and its gradient with respect to the FP32 master parameters
+   (evaluated through the BF16 copies); grad (host, num_params, nullable)
+   and loss (host, nullable) are filled, then the call synchronises. */
+BMPC_API bmpc_status bmpc_mlp_gradients(bmpc_mlp* net, const float* X, const float* T, int32_t B,
+                                        float* grad, float* loss, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step
+   size lr > 0) on the loss of (X, T); loss (host, nullable) receives the
+   loss before the step and makes the call synchronous. */
+BMPC_API bmpc_status bmpc_mlp_train_step(bmpc_mlp* net, const float* X, const float* T, int32_t B, float lr,
+                                         float* loss, void* stream);
+/* The network's matrix-core GEMM on its own: C (M x N, FP32, row-major) =
+   op(A) op(B) with BF16 bit patterns A (M x K, or K x M when trans_a) and
+   B (K x N, or N x K when trans_b), all device, row-major.  trans_a and
+   trans_b together are BMPC_ERR_UNSUPPORTED.  Asynchronous. */
+BMPC_API bmpc_status bmpc_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t trans_a,
+                                    const uint16_t* B, int32_t trans_b, float* C, void* stream);
 
 /* ------------------------------------------------------------------------
  * Kernel timing.  When enabled, every kernel launch of the library is

@@ -78,7 +78,7 @@ class Settings(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("status", C.c_int), ("outer_it", C.c_int), ("inner_it", C.c_int),
-                ("ls_failures", C.c_int), ("bad_node", C.c_int), ("r_kkt", C.c_double),
+                ("ls_failures", C.c_int), ("bad_node", C.c_int), ("start", C.c_int), ("r_kkt", C.c_double),
                 ("viol", C.c_double), ("rho", C.c_double), ("mu", C.c_double),
                 ("merit", C.c_double)]
 
@@ -114,8 +114,13 @@ def _declare(L):
 
 
 def _declare_mlp(L):
-    L.orc_mlp_forward.argtypes = [C.c_int, _ip, C.c_int, _dp, _dp, _dp, _dp]
-    L.orc_mlp_backward.argtypes = [C.c_int, _ip, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+    for name in ("orc_bf16", "orc_gelu", "orc_gelu_prime"):
+        getattr(L, name).restype = C.c_double
+        getattr(L, name).argtypes = [C.c_double]
+    L.orc_mlp_forward.argtypes = [C.c_int, _ip, C.c_int, _dp, _dp, C.c_int, _dp]
+    L.orc_mlp_backward.argtypes = [C.c_int, _ip, C.c_int, _dp, _dp, _dp, C.c_int, _dp, _dp]
+    L.orc_adam.argtypes = [C.c_long, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double, C.c_double,
+                           C.c_double]
 
 
 def _d(a):
@@ -262,9 +267,11 @@ def problem_from_instance(inst, x0=None) -> BmpcProblem:
                        bicycle_model(inst))
 
 
-def solve(pb: BmpcProblem, settings: Settings | None = None, warm=None, hist_cap=4096):
+def solve(pb: BmpcProblem, settings: Settings | None = None, warm=None, hist_cap=4096, guarded=False):
     """Run the AL multiple-shooting iLQR.  ``warm`` may be a dict with any of
-    x, u, lam, ye.  Returns (state dict, stats dict, history array)."""
+    x, u, lam, ye; u without x starts from the rollout of u.  ``guarded``
+    keeps the cold start instead when it is better by max(KKT residual,
+    violation).  Returns (state dict, stats dict, history array)."""
     st = settings if settings is not None else default_settings()
     N = pb.N
     x = np.zeros((N, 4))
@@ -277,12 +284,17 @@ def solve(pb: BmpcProblem, settings: Settings | None = None, warm=None, hist_cap
             x[:] = warm["x"]
             u[:] = warm["u"]
             bits |= 1
+        elif "u" in warm:
+            u[:] = warm["u"]
+            bits |= 8
         if "lam" in warm:
             lam[:] = warm["lam"]
             bits |= 2
         if "ye" in warm:
             ye[:] = warm["ye"]
             bits |= 4
+    if guarded:
+        bits |= 16
     stats = Stats()
     hist = np.zeros((hist_cap, 6))
     lib().orc_bmpc_solve(pb.ptr, C.byref(st), bits, _d(x), _d(u), _d(lam), _d(ye),
@@ -353,3 +365,59 @@ def shift(pb: BmpcProblem, state):
                     _d(out["x"]), _d(out["u"]), _d(out["lam"]), _d(out["ye"]))
     new = BmpcProblem(pb.parent, pb.weight, ref, pb.obs, pb.has_obs, x0, pb.model)
     return new, out
+
+
+# ----------------------------------------------------------------------------
+# warm-start network (oracle_mlp.c)
+# ----------------------------------------------------------------------------
+
+def mlp_num_params(widths):
+    w = list(widths)
+    return sum(w[l] * w[l + 1] + w[l + 1] for l in range(len(w) - 1))
+
+
+def bf16(x):
+    """Nearest BF16 value of each entry (ties to even), as float64."""
+    f = lib().orc_bf16
+    a = np.asarray(x, dtype=np.float64)
+    return np.array([f(float(v)) for v in a.ravel()]).reshape(a.shape)
+
+
+def gelu(z):
+    return lib().orc_gelu(float(z))
+
+
+def gelu_prime(z):
+    return lib().orc_gelu_prime(float(z))
+
+
+def mlp_forward(widths, params, X, quant=True):
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    X = _f64(X)
+    B = X.shape[0]
+    Y = np.zeros((B, int(w[-1])))
+    p = _f64(params)
+    st = lib().orc_mlp_forward(len(w) - 1, _i(w), B, _d(p), _d(X), int(quant), _d(Y))
+    if st != 0:
+        raise OracleError(st)
+    return Y
+
+
+def mlp_loss_grad(widths, params, X, T, quant=True):
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    X, T, p = _f64(X), _f64(T), _f64(params)
+    B = X.shape[0]
+    g = np.zeros_like(p)
+    loss = np.zeros(1)
+    st = lib().orc_mlp_backward(len(w) - 1, _i(w), B, _d(p), _d(X), _d(T), int(quant), _d(g), _d(loss))
+    if st != 0:
+        raise OracleError(st)
+    return float(loss[0]), g
+
+
+def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays p, m, v."""
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    lib().orc_adam(p.size, _d(p), _d(g), _d(m), _d(v), int(t), lr, b1, b2, eps)

@@ -74,13 +74,15 @@ typedef struct {
 } orc_settings;
 
 typedef struct {
-    int status, outer_it, inner_it, ls_failures, bad_node;
+    int status, outer_it, inner_it, ls_failures, bad_node, start;
     double r_kkt, viol, rho, mu, merit;
 } orc_stats;
 
 void orc_settings_default(orc_settings* s);
 
-/* warm bits: 1 = x,u supplied, 2 = lam supplied, 4 = ye supplied */
+/* warm bits: 1 = x,u supplied, 2 = lam supplied, 4 = ye supplied (clamped at
+   zero), 8 = u supplied with x from the rollout, 16 = keep the cold start
+   instead if its max(KKT residual, violation) is smaller */
 int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm,
                    double* x, double* u, double* lam, double* ye,
                    orc_stats* stats, double* hist, int hist_cap);
@@ -108,6 +110,16 @@ void orc_rollout(const orc_problem* pb, const double* u, double* x);
 void orc_shift(const orc_problem* pb, const double* x, const double* u, const double* lam,
                const double* ye, double* ref_new, double* x0_new, double* xs, double* us,
                double* lams, double* yes);
+
+/* ---- warm-start network, oracle_mlp.c ---------------------------------- */
+double orc_bf16(double x);
+double orc_gelu(double z);
+double orc_gelu_prime(double z);
+int orc_mlp_forward(int L, const int* w, int B, const double* params, const double* X, int quant, double* Y);
+int orc_mlp_backward(int L, const int* w, int B, const double* params, const double* X, const double* T,
+                     int quant, double* grad, double* loss);
+void orc_adam(long n, double* p, const double* g, double* m, double* v, int t, double lr, double b1, double b2,
+              double eps);
 
 #ifdef __cplusplus
 }

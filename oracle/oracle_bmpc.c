@@ -443,6 +443,32 @@ void orc_rollout(const orc_problem* pb, const double* u, double* x)
                 NULL);
 }
 
+/* Start point.  warm bits: 1 = x, u given; 8 = u given and x from the
+ * exact rollout; 4 = ye given (negative entries set to zero); 2 = lam given,
+ * otherwise lam from the adjoint sweep.  No bit: u = 0 and the rollout. */
+static void start_point(const orc_problem* pb, const int* nch, int warm, double* x, double* u,
+                        double* lam, double* ye, double rho)
+{
+    const int N = pb->N;
+    if (!(warm & (1 | 8))) memset(u, 0, sizeof(double) * (size_t)N * NU);
+    for (int n = 0; n < N; ++n)
+        if (nch[n] == 0) memset(u + n * NU, 0, sizeof(double) * NU);
+    if ((warm & 8) || !(warm & 1)) orc_rollout(pb, u, x);
+    memcpy(x, pb->x0, sizeof(double) * NX);
+    for (int i = 0; i < N * NG; ++i) ye[i] = (warm & 4) ? (ye[i] > 0.0 ? ye[i] : 0.0) : 0.0;
+    if (!(warm & 2)) orc_adjoint(pb, x, u, ye, rho, lam);
+}
+
+/* quality of a start point: max(KKT residual, violation), NaN counted as +inf */
+static double start_measure(const orc_problem* pb, const double* x, const double* u, const double* lam,
+                            const double* ye, double rho)
+{
+    const double k = orc_kkt(pb, x, u, lam, ye, rho);
+    const double v = orc_violation(pb, x, u, ye, rho);
+    if (isnan(k) || isnan(v)) return INFINITY;
+    return k > v ? k : v;
+}
+
 /* ------------------------------------------------------------------------
  * AL multiple-shooting iLQR (Sec. IV, Alg. 1).
  * ---------------------------------------------------------------------- */
@@ -483,16 +509,37 @@ int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm, doub
     double r_kkt = INFINITY, viol = INFINITY, phi_last = 0.0;
     int inner_total = 0, outer = 0, ls_fail = 0, ls_fail_run = 0;
 
-    /* initial point: cold = zero inputs and exact rollout (d = 0) */
-    if (!(warm & 1)) {
-        memset(u, 0, sizeof(double) * (size_t)N * nu);
-        orc_rollout(pb, u, x);
+    /* initial point: cold = zero inputs and exact rollout (d = 0); bit 16
+     * compares the caller's start with the cold one and keeps the better */
+    int start_used = (warm & (1 | 4 | 8)) ? 1 : 0;
+    if (warm & 16) {
+        double* xs = malloc(sizeof(double) * (size_t)N * nx);
+        double* us = malloc(sizeof(double) * (size_t)N * nu);
+        double* ls = malloc(sizeof(double) * (size_t)N * nx);
+        double* ys = malloc(sizeof(double) * (size_t)N * NG);
+        memcpy(xs, x, sizeof(double) * (size_t)N * nx);
+        memcpy(us, u, sizeof(double) * (size_t)N * nu);
+        memcpy(ls, lam, sizeof(double) * (size_t)N * nx);
+        memcpy(ys, ye, sizeof(double) * (size_t)N * NG);
+        start_point(pb, nch, 0, x, u, lam, ye, rho);
+        const double m_cold = start_measure(pb, x, u, lam, ye, rho);
+        memcpy(x, xs, sizeof(double) * (size_t)N * nx);
+        memcpy(u, us, sizeof(double) * (size_t)N * nu);
+        memcpy(lam, ls, sizeof(double) * (size_t)N * nx);
+        memcpy(ye, ys, sizeof(double) * (size_t)N * NG);
+        free(xs);
+        free(us);
+        free(ls);
+        free(ys);
+        start_point(pb, nch, warm & 15, x, u, lam, ye, rho);
+        const double m_given = start_measure(pb, x, u, lam, ye, rho);
+        if (m_cold < m_given) {
+            start_point(pb, nch, 0, x, u, lam, ye, rho);
+            start_used = 0;
+        }
+    } else {
+        start_point(pb, nch, warm, x, u, lam, ye, rho);
     }
-    memcpy(x, pb->x0, sizeof(double) * nx);
-    if (!(warm & 4)) memset(ye, 0, sizeof(double) * (size_t)N * NG);
-    for (int n = 0; n < N; ++n)
-        if (nch[n] == 0) memset(u + n * nu, 0, sizeof(double) * nu);
-    if (!(warm & 2)) orc_adjoint(pb, x, u, ye, rho, lam);
 
     for (outer = 0; outer < st->max_outer; ++outer) {
         for (int inner = 0;; ++inner) {
@@ -623,6 +670,7 @@ done:
         stats->inner_it = inner_total;
         stats->ls_failures = ls_fail;
         stats->bad_node = bad;
+        stats->start = start_used;
         stats->r_kkt = r_kkt;
         stats->viol = viol;
         stats->rho = rho;

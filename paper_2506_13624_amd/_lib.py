@@ -207,7 +207,7 @@ class bmpc_settings(C.Structure):
 
 class bmpc_stats(C.Structure):
     _fields_ = [("status", C.c_int32), ("outer_it", C.c_int32), ("inner_it", C.c_int32),
-                ("ls_failures", C.c_int32), ("bad_node", C.c_int32), ("r_kkt", C.c_double),
+                ("ls_failures", C.c_int32), ("bad_node", C.c_int32), ("start", C.c_int32), ("r_kkt", C.c_double),
                 ("viol", C.c_double), ("rho", C.c_double), ("mu", C.c_double),
                 ("merit", C.c_double)]
 
@@ -333,3 +333,78 @@ def bmpc_batch_history(batch, i, hist_cap, stream=None):
 
 def bmpc_batch_shift(batch, stream=None):
     check(lib.bmpc_batch_shift(batch, stream_ptr(stream)))
+
+
+# ----------------------------------------------------------------------------
+# warm-start network
+# ----------------------------------------------------------------------------
+
+_pf32 = C.POINTER(C.c_float)
+_sig("bmpc_mlp_create", _i32, [_pi32, _i32, _i32, C.POINTER(_vp)])
+_sig("bmpc_mlp_destroy", None, [_vp])
+_sig("bmpc_mlp_num_params", C.c_int64, [_vp])
+_sig("bmpc_mlp_set_params", _i32, [_vp, _pf32])
+_sig("bmpc_mlp_get_params", _i32, [_vp, _pf32])
+_sig("bmpc_mlp_forward", _i32, [_vp, _vp, _i32, _vp, _vp])
+_sig("bmpc_mlp_gradients", _i32, [_vp, _vp, _vp, _i32, _pf32, _pf32, _vp])
+_sig("bmpc_mlp_train_step", _i32, [_vp, _vp, _vp, _i32, C.c_float, _pf32, _vp])
+_sig("bmpc_gemm_bf16", _i32, [_i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp])
+
+
+def _hf32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(_pf32)
+
+
+def bmpc_mlp_create(widths, max_batch):
+    w, pw = _hi32(widths)
+    out = _vp()
+    check(lib.bmpc_mlp_create(pw, len(w) - 1, max_batch, C.byref(out)))
+    return out
+
+
+def bmpc_mlp_destroy(h):
+    lib.bmpc_mlp_destroy(h)
+
+
+def bmpc_mlp_num_params(h):
+    return int(lib.bmpc_mlp_num_params(h))
+
+
+def bmpc_mlp_set_params(h, params):
+    p, pp = _hf32(params)
+    if p.size != bmpc_mlp_num_params(h):
+        raise ValueError("parameter vector of the wrong length")
+    check(lib.bmpc_mlp_set_params(h, pp))
+
+
+def bmpc_mlp_get_params(h):
+    p = np.zeros(bmpc_mlp_num_params(h), dtype=np.float32)
+    check(lib.bmpc_mlp_get_params(h, p.ctypes.data_as(_pf32)))
+    return p
+
+
+def bmpc_mlp_forward(h, X, Y, stream=None):
+    """X (B, w_0) and Y (B, w_L): float32 device tensors."""
+    check(lib.bmpc_mlp_forward(h, dptr(X), X.shape[0], dptr(Y), stream_ptr(stream)))
+
+
+def bmpc_mlp_gradients(h, X, T, stream=None):
+    g = np.zeros(bmpc_mlp_num_params(h), dtype=np.float32)
+    loss = np.zeros(1, dtype=np.float32)
+    check(lib.bmpc_mlp_gradients(h, dptr(X), dptr(T), X.shape[0], g.ctypes.data_as(_pf32),
+                                 loss.ctypes.data_as(_pf32), stream_ptr(stream)))
+    return float(loss[0]), g
+
+
+def bmpc_mlp_train_step(h, X, T, lr, want_loss=True, stream=None):
+    loss = np.zeros(1, dtype=np.float32)
+    check(lib.bmpc_mlp_train_step(h, dptr(X), dptr(T), X.shape[0], lr,
+                                  loss.ctypes.data_as(_pf32) if want_loss else None, stream_ptr(stream)))
+    return float(loss[0]) if want_loss else None
+
+
+def bmpc_gemm_bf16(M, N, K, A, trans_a, B, trans_b, C_out, stream=None):
+    """A, B: int16/bfloat16 device tensors holding BF16 bit patterns; C_out float32."""
+    check(lib.bmpc_gemm_bf16(M, N, K, dptr(A), int(trans_a), dptr(B), int(trans_b), dptr(C_out),
+                             stream_ptr(stream)))

@@ -87,11 +87,11 @@ struct InstDesc {
 struct SolverCfg {
     double eps_tol, tau, omega0, eta0, a_omega, b_omega, a_eta, b_eta, rho0, mu0, beta;
     int n_alpha, max_outer, max_inner, max_ls_fail;
-    int warm;  // bits: 1 x,u given, 2 lam given, 4 ye given
+    int warm;  // bits: 1 x,u given, 2 lam given, 4 ye given, 8 u given (x rolled out), 16 guarded
 };
 
 struct SolveOut {
-    int status, outer_it, inner_it, ls_failures, bad_node;
+    int status, outer_it, inner_it, ls_failures, bad_node, start;
     double r_kkt, viol, rho, mu, merit;
 };
 
@@ -628,6 +628,96 @@ __device__ void pass_adjoint(const InstDesc& I)
     }
 }
 
+// Start point.  warm bits: 1 = x, u given; 8 = u given, x by rollout from
+// x0; 4 = ye given (clamped at zero); 2 = lam given, otherwise lam from the
+// adjoint sweep at the start.  No bit: cold start u = 0 and exact rollout.
+template <int BS>
+__device__ void build_start(const InstDesc& I, int warm, double rho)
+{
+    const int tid = threadIdx.x, N = I.N;
+    for (int n = tid; n < N; n += BS) {
+        if (!(warm & (1 | 8)) || I.child_off[n] == I.child_off[n + 1]) {
+            I.u[n * 2] = 0.0;
+            I.u[n * 2 + 1] = 0.0;
+        }
+        if (n == 0)
+#pragma unroll
+            for (int i = 0; i < BX; ++i) I.x[i] = I.x0[i];
+#pragma unroll
+        for (int s = 0; s < BG; ++s) I.ye[n * BG + s] = (warm & 4) ? fmax(I.ye[n * BG + s], 0.0) : 0.0;
+    }
+    __syncthreads();
+    if ((warm & 8) || !(warm & 1)) {
+        for (int t = 1; t <= I.T; ++t) {
+            const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
+            for (int n = n0 + tid; n < n1; n += BS) {
+                const int p = I.parent[n];
+                double xp[BX], up[BU] = {I.u[p * 2], I.u[p * 2 + 1]}, xn[BX];
+                load4(I.x + p * 4, xp);
+                bike_step(I.prm, xp, up, xn);
+                store4(I.x + n * 4, xn);
+            }
+            __syncthreads();
+        }
+    }
+    if (!(warm & 2)) {
+        double La, vi;
+        pass_linearise<BS>(I, rho, La, vi);
+        __syncthreads();
+        pass_adjoint<BS>(I);
+    }
+}
+
+// Quality of a start point: max(KKT residual, constraint violation), with
+// NaN mapped to +inf.
+template <int BS>
+__device__ double start_measure(const InstDesc& I, double rho, double* sred)
+{
+    double La, vi, rk, ld, dd;
+    pass_linearise<BS>(I, rho, La, vi);
+    __syncthreads();
+    pass_defects_kkt<BS>(I, rk, ld, dd);
+    double mx[2] = {rk, vi};
+    block_reduce<BS, 2, true>(mx, sred);
+    if (!(mx[0] == mx[0]) || !(mx[1] == mx[1])) return INFINITY;
+    return fmax(mx[0], mx[1]);
+}
+
+// Save (save = true) the caller's x, u, lam, ye into the node workspace
+// slots of the step (dx, du, costate step, scan scratch), or restore them.
+template <int BS>
+__device__ void stash_state(const InstDesc& I, bool save)
+{
+    for (int n = threadIdx.x; n < I.N; n += BS) {
+        double* w = I.ws + (long)n * W_NODE;
+#pragma unroll
+        for (int i = 0; i < BX; ++i) {
+            if (save) {
+                w[W_DX + i] = I.x[n * 4 + i];
+                w[W_LH + i] = I.lam[n * 4 + i];
+            } else {
+                I.x[n * 4 + i] = w[W_DX + i];
+                I.lam[n * 4 + i] = w[W_LH + i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < BU; ++i) {
+            if (save)
+                w[W_DU + i] = I.u[n * 2 + i];
+            else
+                I.u[n * 2 + i] = w[W_DU + i];
+        }
+#pragma unroll
+        for (int k = 0; k < BG; ++k) {
+            if (save)
+                w[W_S0 + k] = I.ye[n * BG + k];
+            else
+                I.ye[n * BG + k] = w[W_S0 + k];
+        }
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- solver kernel
 template <int BS, bool SEGSCAN>
 __global__ void __launch_bounds__(BS) k_bmpc_wg(const InstDesc* __restrict__ insts, SolverCfg cfg,
@@ -641,51 +731,26 @@ __global__ void __launch_bounds__(BS) k_bmpc_wg(const InstDesc* __restrict__ ins
     const int N = I.N;
     if (tid == 0) *bad = INT_MAX;
 
-    // initial point
-    if (!(cfg.warm & 1)) {
-        for (int n = tid; n < N; n += BS) {
-            I.u[n * 2] = 0.0;
-            I.u[n * 2 + 1] = 0.0;
-        }
-        if (tid == 0)
-#pragma unroll
-            for (int i = 0; i < BX; ++i) I.x[i] = I.x0[i];
-        __syncthreads();
-        for (int t = 1; t <= I.T; ++t) {
-            const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
-            for (int n = n0 + tid; n < n1; n += BS) {
-                const int p = I.parent[n];
-                double xp[BX], up[BU] = {0.0, 0.0}, xn[BX];
-                load4(I.x + p * 4, xp);
-                bike_step(I.prm, xp, up, xn);
-                store4(I.x + n * 4, xn);
-            }
-            __syncthreads();
-        }
-    }
-    for (int n = tid; n < N; n += BS) {
-        if (n == 0)
-#pragma unroll
-            for (int i = 0; i < BX; ++i) I.x[i] = I.x0[i];
-        if (I.child_off[n] == I.child_off[n + 1]) {
-            I.u[n * 2] = 0.0;
-            I.u[n * 2 + 1] = 0.0;
-        }
-        if (!(cfg.warm & 4))
-#pragma unroll
-            for (int s = 0; s < BG; ++s) I.ye[n * BG + s] = 0.0;
-    }
-    __syncthreads();
-
     double rho = cfg.rho0, mu = cfg.mu0, omega = cfg.omega0, eta = cfg.eta0;
     double r_kkt = INFINITY, viol = INFINITY, merit = 0.0;
     int status = BMPC_ERR_MAXITER, inner_total = 0, outer = 0, ls_fail = 0, ls_run = 0, nhist = 0;
+    int start_used = (cfg.warm & (1 | 4 | 8)) ? 1 : 0;
 
-    if (!(cfg.warm & 2)) {
-        double La, vi;
-        pass_linearise<BS>(I, rho, La, vi);
-        __syncthreads();
-        pass_adjoint<BS>(I);
+    if (cfg.warm & 16) {
+        // guarded start: keep the given start only if it is at least as
+        // good as the cold one by max(KKT residual, violation) at rho0
+        stash_state<BS>(I, true);
+        build_start<BS>(I, 0, rho);
+        const double m_cold = start_measure<BS>(I, rho, sred);
+        stash_state<BS>(I, false);
+        build_start<BS>(I, cfg.warm & 15, rho);
+        const double m_given = start_measure<BS>(I, rho, sred);
+        if (m_cold < m_given) {
+            build_start<BS>(I, 0, rho);
+            start_used = 0;
+        }
+    } else {
+        build_start<BS>(I, cfg.warm, rho);
     }
 
     for (outer = 0; outer < cfg.max_outer; ++outer) {
@@ -879,6 +944,7 @@ done:
         o.ls_failures = ls_fail;
         const int bn = __hip_atomic_load(bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         o.bad_node = bn == INT_MAX ? -1 : bn;
+        o.start = start_used;
         o.r_kkt = r_kkt;
         o.viol = viol;
         o.rho = rho;
@@ -1291,6 +1357,7 @@ BMPC_API bmpc_status bmpc_batch_launch(bmpc_batch* b, const bmpc_settings* s, in
     if (s->riccati_variant != BMPC_RICCATI_AUTO && s->riccati_variant != BMPC_RICCATI_LEVEL &&
         s->riccati_variant != BMPC_RICCATI_SEGSCAN)
         return fail(BMPC_ERR_INVALID_ARG, "unknown Riccati variant %d", s->riccati_variant);
+    if (warm < 0 || warm > 31) return fail(BMPC_ERR_INVALID_ARG, "warm bits %d outside [0, 31]", warm);
     hipStream_t st = (hipStream_t)stream;
     const SolverCfg cfg = to_cfg(*s, warm);
     if (s->riccati_variant == BMPC_RICCATI_SEGSCAN) {
@@ -1319,6 +1386,7 @@ BMPC_API bmpc_status bmpc_batch_stats(bmpc_batch* b, bmpc_stats* stats, void* st
         stats[i].inner_it = o[i].inner_it;
         stats[i].ls_failures = o[i].ls_failures;
         stats[i].bad_node = o[i].bad_node;
+        stats[i].start = o[i].start;
         stats[i].r_kkt = o[i].r_kkt;
         stats[i].viol = o[i].viol;
         stats[i].rho = o[i].rho;
@@ -1382,7 +1450,7 @@ BMPC_API bmpc_status bmpc_solve(bmpc_problem* p, const bmpc_settings* s, int32_t
         bmpc_problem* one[1] = {p};
         if ((st = bmpc_batch_create(one, 1, 0, &p->self)) != BMPC_OK) return st;
     }
-    if (warm && (st = bmpc_batch_state(p->self, 0, (warm & 1) ? x : nullptr, (warm & 1) ? u : nullptr,
+    if (warm && (st = bmpc_batch_state(p->self, 0, (warm & 1) ? x : nullptr, (warm & (1 | 8)) ? u : nullptr,
                                        (warm & 2) ? lam : nullptr, (warm & 4) ? ye : nullptr, 1, stream)) != BMPC_OK)
         return st;
     if ((st = bmpc_batch_launch(p->self, s, warm, stream)) != BMPC_OK) return st;

@@ -1,0 +1,465 @@
+// Warm-start network: a multilayer perceptron with GELU hidden activations
+// and a linear output, trained with Adam on the mean squared error.
+// Weights and activations are BF16, products accumulate in FP32 on the
+// matrix cores (MFMA 16x16x16 BF16), master weights and optimiser state are
+// FP32.
+//
+// Layer l:  Z_{l+1} = A_l W_l + b_l,  A_{l+1} = gelu(Z_{l+1}) (hidden) or
+// Y = Z_L (output), with gelu(z) = z/2 (1 + erf(z/sqrt 2)).
+// Backward: dW_l = A_l^T dZ_{l+1}, db_l = column sums of dZ_{l+1},
+// dZ_l = (dZ_{l+1} W_l^T) * gelu'(Z_l).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "bmpc_internal.hpp"
+#include "profile.hpp"
+
+namespace bmpc {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// float -> bf16 bits, round to nearest, ties to even (NaN stays NaN)
+__host__ __device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x0040u);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+__host__ __device__ __forceinline__ float bf2f(uint16_t h)
+{
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+enum Epi { EPI_GELU = 0, EPI_LINEAR = 1, EPI_GELU_BACK = 2, EPI_STORE = 3 };
+
+// C = op(A) op(B) for bf16 inputs with fp32 accumulation.
+//   op(A)[m][k] = TA ? A[k*lda + m] : A[m*lda + k]
+//   op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n]
+// Workgroup tile 64 x 64 (four wavefronts of 32 x 32, each 2 x 2 MFMA 16x16
+// tiles), K advanced 16 at a time through LDS.  Out-of-range elements are
+// zero.  Epilogues:
+//   EPI_GELU:      Z = acc + bias (fp32 out), O = bf16(gelu(Z))
+//   EPI_LINEAR:    Z = acc + bias (fp32 out)
+//   EPI_GELU_BACK: O = bf16(acc * gelu'(Zin))
+//   EPI_STORE:     Z = acc (fp32 out)
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
+                                                   const uint16_t* __restrict__ B, int ldb,
+                                                   const float* __restrict__ bias, const float* __restrict__ Zin,
+                                                   float* __restrict__ Zout, uint16_t* __restrict__ O, int ldc)
+{
+    __shared__ uint16_t sA[64][16 + 4];  // [m][k]
+    __shared__ uint16_t sB[16][64 + 4];  // [k][n]
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        // stage A (64 x 16) and B (16 x 64): 4 elements each per thread
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + 256 * e;
+            {
+                const int m = idx >> 4, k = idx & 15;
+                const int gm = m0 + m, gk = k0 + k;
+                uint16_t v = 0;
+                if (gm < M && gk < K) v = TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
+                sA[m][k] = v;
+            }
+            {
+                const int k = idx >> 6, n = idx & 63;
+                const int gk = k0 + k, gn = n0 + n;
+                uint16_t v = 0;
+                if (gk < K && gn < N) v = TB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn];
+                sB[k][n] = v;
+            }
+        }
+        __syncthreads();
+        // MFMA operands: lane holds A[row = lane%16][k = 4*(lane/16) + 0..3]
+        // and B[k = 4*(lane/16) + 0..3][col = lane%16]
+        const int r = lane & 15, kq = (lane >> 4) * 4;
+        bf16x4_t a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            a[i] = bf16x4_t{(short)sA[wm + 16 * i + r][kq], (short)sA[wm + 16 * i + r][kq + 1],
+                            (short)sA[wm + 16 * i + r][kq + 2], (short)sA[wm + 16 * i + r][kq + 3]};
+            b[i] = bf16x4_t{(short)sB[kq][wn + 16 * i + r], (short)sB[kq + 1][wn + 16 * i + r],
+                            (short)sB[kq + 2][wn + 16 * i + r], (short)sB[kq + 3][wn + 16 * i + r]};
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // result: lane holds C[row = 4*(lane/16) + q][col = lane%16], q = 0..3
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+                const int gn = n0 + wn + 16 * j + (lane & 15);
+                if (gm >= M || gn >= N) continue;
+                const long o = (long)gm * ldc + gn;
+                float v = acc[i][j][q];
+                if constexpr (EPI == EPI_GELU) {
+                    v += bias[gn];
+                    Zout[o] = v;
+                    O[o] = f2bf(gelu(v));
+                } else if constexpr (EPI == EPI_LINEAR) {
+                    Zout[o] = v + bias[gn];
+                } else if constexpr (EPI == EPI_GELU_BACK) {
+                    O[o] = f2bf(v * gelu_grad(Zin[o]));
+                } else {
+                    Zout[o] = v;
+                }
+            }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// dY = 2 (Y - T) / (B * N) in bf16; per-block partial sums of (Y - T)^2
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ Y, const float* __restrict__ T,
+                                             uint16_t* __restrict__ dY, float* __restrict__ partial, long n,
+                                             float scale)
+{
+    __shared__ float s[256];
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    float e2 = 0.f;
+    if (i < n) {
+        const float d = Y[i] - T[i];
+        e2 = d * d;
+        dY[i] = f2bf(2.0f * d * scale);
+    }
+    s[threadIdx.x] = e2;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+__global__ void k_sum_partials(const float* __restrict__ partial, int n, float scale, float* __restrict__ out)
+{
+    __shared__ float s[256];
+    float t = 0.f;
+    for (int i = threadIdx.x; i < n; i += 256) t += partial[i];
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0] * scale;
+}
+
+// db[n] = sum_m dZ[m][n] (fixed order: one thread per column)
+__global__ void k_colsum_bf16(const uint16_t* __restrict__ dZ, int M, int N, float* __restrict__ db)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int m = 0; m < M; ++m) s += bf2f(dZ[(long)m * N + n]);
+    db[n] = s;
+}
+
+// Adam on fp32 master parameters; refreshes the bf16 copy of weights.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, uint16_t* __restrict__ pbf, long n, float lr, float b1, float b2,
+                       float eps, float c1, float c2)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    p[i] = pi;
+    if (pbf) pbf[i] = f2bf(pi);
+}
+
+}  // namespace bmpc
+
+using namespace bmpc;
+
+struct bmpc_mlp {
+    int L = 0, max_batch = 0;
+    std::vector<int> w;          // widths, L+1
+    std::vector<long> woff, boff;  // offsets of W_l, b_l in the flat parameter vector
+    long nparam = 0;
+    float* p = nullptr;          // fp32 master parameters (all W then b, layer by layer)
+    float* g = nullptr;          // gradients
+    float* m = nullptr;          // Adam moments
+    float* v = nullptr;
+    uint16_t* pbf = nullptr;     // bf16 copy of the parameters
+    std::vector<uint16_t*> act;  // A_l bf16, B x w_l (act[0] = input)
+    std::vector<float*> z;       // Z_l fp32, B x w_l (l >= 1)
+    std::vector<uint16_t*> dz;   // dZ_l bf16, B x w_l (l >= 1)
+    float* partial = nullptr;
+    float* loss = nullptr;
+    long step = 0;
+};
+
+static bmpc_status mlp_forward_impl(bmpc_mlp* net, const float* X, int B, hipStream_t s)
+{
+    const int L = net->L;
+    const long nin = (long)B * net->w[0];
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((nin + 255) / 256)), dim3(256), 0, s, X, net->act[0], nin);
+    for (int l = 0; l < L; ++l) {
+        const int K = net->w[l], N = net->w[l + 1];
+        dim3 grid((N + 63) / 64, (B + 63) / 64);
+        const uint16_t* W = net->pbf + net->woff[l];
+        const float* b = net->p + net->boff[l];
+        if (l < L - 1) {
+            ProfScope ps("mlp_gemm_forward", s);
+            hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_GELU>), grid, dim3(256), 0, s, B, N, K, net->act[l], K, W,
+                               N, b, nullptr, net->z[l + 1], net->act[l + 1], N);
+        } else {
+            ProfScope ps("mlp_gemm_forward", s);
+            hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_LINEAR>), grid, dim3(256), 0, s, B, N, K, net->act[l],
+                               K, W, N, b, nullptr, net->z[l + 1], nullptr, N);
+        }
+    }
+    BMPC_HIP_TRY(hipGetLastError());
+    return BMPC_OK;
+}
+
+// loss and gradients into net->g (no update)
+static bmpc_status mlp_backward_impl(bmpc_mlp* net, const float* T, int B, hipStream_t s)
+{
+    const int L = net->L;
+    const int NO = net->w[L];
+    const long n = (long)B * NO;
+    const int nb = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, net->z[L], T, net->dz[L], net->partial, n, 1.0f / (float)n);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, net->partial, nb, 1.0f / (float)n, net->loss);
+    for (int l = L - 1; l >= 0; --l) {
+        const int K = net->w[l], N = net->w[l + 1];
+        // dW_l = A_l^T dZ_{l+1}: (K x B) (B x N)
+        {
+            ProfScope ps("mlp_gemm_weight_grad", s);
+            dim3 grid((N + 63) / 64, (K + 63) / 64);
+            hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI_STORE>), grid, dim3(256), 0, s, K, N, B, net->act[l], K,
+                               net->dz[l + 1], N, nullptr, nullptr, net->g + net->woff[l], nullptr, N);
+        }
+        hipLaunchKernelGGL(k_colsum_bf16, dim3((N + 255) / 256), dim3(256), 0, s, net->dz[l + 1], B, N,
+                           net->g + net->boff[l]);
+        if (l > 0) {
+            // dZ_l = (dZ_{l+1} W_l^T) * gelu'(Z_l): (B x N) (N x K)
+            ProfScope ps("mlp_gemm_input_grad", s);
+            dim3 grid((K + 63) / 64, (B + 63) / 64);
+            hipLaunchKernelGGL((k_gemm_bf16<false, true, EPI_GELU_BACK>), grid, dim3(256), 0, s, B, K, N,
+                               net->dz[l + 1], N, net->pbf + net->woff[l], N, nullptr, net->z[l], nullptr,
+                               net->dz[l], K);
+        }
+    }
+    BMPC_HIP_TRY(hipGetLastError());
+    return BMPC_OK;
+}
+
+extern "C" {
+
+BMPC_API bmpc_status bmpc_mlp_create(const int32_t* widths, int32_t n_layers, int32_t max_batch, bmpc_mlp** out)
+{
+    if (!widths || n_layers < 1 || n_layers > 16 || max_batch < 1 || !out)
+        return fail(BMPC_ERR_INVALID_ARG, "bad network shape");
+    *out = nullptr;
+    for (int l = 0; l <= n_layers; ++l)
+        if (widths[l] < 1 || widths[l] > 65536) return fail(BMPC_ERR_INVALID_ARG, "layer width %d out of range", l);
+    auto* net = new bmpc_mlp();
+    net->L = n_layers;
+    net->max_batch = max_batch;
+    net->w.assign(widths, widths + n_layers + 1);
+    long off = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        net->woff.push_back(off);
+        off += (long)widths[l] * widths[l + 1];
+    }
+    for (int l = 0; l < n_layers; ++l) {
+        net->boff.push_back(off);
+        off += widths[l + 1];
+    }
+    net->nparam = off;
+    bool ok = hipMalloc(&net->p, sizeof(float) * off) == hipSuccess &&
+              hipMalloc(&net->g, sizeof(float) * off) == hipSuccess &&
+              hipMalloc(&net->m, sizeof(float) * off) == hipSuccess &&
+              hipMalloc(&net->v, sizeof(float) * off) == hipSuccess &&
+              hipMalloc(&net->pbf, sizeof(uint16_t) * off) == hipSuccess &&
+              hipMalloc(&net->loss, sizeof(float)) == hipSuccess &&
+              hipMalloc(&net->partial, sizeof(float) * (((long)max_batch * widths[n_layers] + 255) / 256 + 1)) ==
+                  hipSuccess;
+    net->act.assign(n_layers + 1, nullptr);
+    net->z.assign(n_layers + 1, nullptr);
+    net->dz.assign(n_layers + 1, nullptr);
+    for (int l = 0; l <= n_layers && ok; ++l) {
+        const size_t e = (size_t)max_batch * widths[l];
+        ok = hipMalloc(&net->act[l], sizeof(uint16_t) * e) == hipSuccess;
+        if (ok && l > 0)
+            ok = hipMalloc(&net->z[l], sizeof(float) * e) == hipSuccess &&
+                 hipMalloc(&net->dz[l], sizeof(uint16_t) * e) == hipSuccess;
+    }
+    if (!ok) {
+        bmpc_mlp_destroy(net);
+        return fail(BMPC_ERR_OOM, "device allocation for the network failed");
+    }
+    if (hipMemset(net->p, 0, sizeof(float) * off) != hipSuccess ||
+        hipMemset(net->m, 0, sizeof(float) * off) != hipSuccess ||
+        hipMemset(net->v, 0, sizeof(float) * off) != hipSuccess ||
+        hipMemset(net->pbf, 0, sizeof(uint16_t) * off) != hipSuccess) {
+        bmpc_mlp_destroy(net);
+        return fail(BMPC_ERR_HIP, "initialising the network failed");
+    }
+    *out = net;
+    return BMPC_OK;
+}
+
+BMPC_API void bmpc_mlp_destroy(bmpc_mlp* net)
+{
+    if (!net) return;
+    (void)hipFree(net->p);
+    (void)hipFree(net->g);
+    (void)hipFree(net->m);
+    (void)hipFree(net->v);
+    (void)hipFree(net->pbf);
+    (void)hipFree(net->loss);
+    (void)hipFree(net->partial);
+    for (auto* a : net->act) (void)hipFree(a);
+    for (auto* a : net->z) (void)hipFree(a);
+    for (auto* a : net->dz) (void)hipFree(a);
+    delete net;
+}
+
+BMPC_API int64_t bmpc_mlp_num_params(const bmpc_mlp* net) { return net ? net->nparam : 0; }
+
+BMPC_API bmpc_status bmpc_mlp_set_params(bmpc_mlp* net, const float* params)
+{
+    if (!net || !params) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    for (long i = 0; i < net->nparam; ++i)
+        if (!std::isfinite(params[i])) return fail(BMPC_ERR_NONFINITE, "parameter %ld is not finite", i);
+    BMPC_HIP_TRY(hipMemcpy(net->p, params, sizeof(float) * net->nparam, hipMemcpyHostToDevice));
+    std::vector<uint16_t> h(net->nparam);
+    for (long i = 0; i < net->nparam; ++i) h[i] = f2bf(params[i]);
+    BMPC_HIP_TRY(hipMemcpy(net->pbf, h.data(), sizeof(uint16_t) * net->nparam, hipMemcpyHostToDevice));
+    BMPC_HIP_TRY(hipMemset(net->m, 0, sizeof(float) * net->nparam));
+    BMPC_HIP_TRY(hipMemset(net->v, 0, sizeof(float) * net->nparam));
+    net->step = 0;
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_mlp_get_params(bmpc_mlp* net, float* params)
+{
+    if (!net || !params) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    BMPC_HIP_TRY(hipMemcpy(params, net->p, sizeof(float) * net->nparam, hipMemcpyDeviceToHost));
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_mlp_forward(bmpc_mlp* net, const float* X, int32_t B, float* Y, void* stream)
+{
+    if (!net || !X || !Y) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    if (B < 1 || B > net->max_batch) return fail(BMPC_ERR_INVALID_ARG, "batch %d outside [1, %d]", B, net->max_batch);
+    hipStream_t s = (hipStream_t)stream;
+    bmpc_status st = mlp_forward_impl(net, X, B, s);
+    if (st != BMPC_OK) return st;
+    BMPC_HIP_TRY(hipMemcpyAsync(Y, net->z[net->L], sizeof(float) * (size_t)B * net->w[net->L],
+                                hipMemcpyDeviceToDevice, s));
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_mlp_gradients(bmpc_mlp* net, const float* X, const float* T, int32_t B, float* grad,
+                                        float* loss, void* stream)
+{
+    if (!net || !X || !T) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    if (B < 1 || B > net->max_batch) return fail(BMPC_ERR_INVALID_ARG, "batch %d outside [1, %d]", B, net->max_batch);
+    hipStream_t s = (hipStream_t)stream;
+    bmpc_status st;
+    if ((st = mlp_forward_impl(net, X, B, s)) != BMPC_OK) return st;
+    if ((st = mlp_backward_impl(net, T, B, s)) != BMPC_OK) return st;
+    if (grad)
+        BMPC_HIP_TRY(hipMemcpyAsync(grad, net->g, sizeof(float) * net->nparam, hipMemcpyDeviceToHost, s));
+    if (loss) BMPC_HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, s));
+    BMPC_HIP_TRY(hipStreamSynchronize(s));
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_mlp_train_step(bmpc_mlp* net, const float* X, const float* T, int32_t B, float lr,
+                                         float* loss, void* stream)
+{
+    if (!net || !X || !T) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    if (B < 1 || B > net->max_batch) return fail(BMPC_ERR_INVALID_ARG, "batch %d outside [1, %d]", B, net->max_batch);
+    if (!(lr > 0.0f)) return fail(BMPC_ERR_INVALID_ARG, "learning rate must be positive");
+    hipStream_t s = (hipStream_t)stream;
+    bmpc_status st;
+    if ((st = mlp_forward_impl(net, X, B, s)) != BMPC_OK) return st;
+    if ((st = mlp_backward_impl(net, T, B, s)) != BMPC_OK) return st;
+    net->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f / (1.0f - powf(b1, (float)net->step));
+    const float c2 = 1.0f / (1.0f - powf(b2, (float)net->step));
+    {
+        ProfScope ps("mlp_adam", s);
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((net->nparam + 255) / 256)), dim3(256), 0, s, net->p, net->g,
+                           net->m, net->v, net->pbf, net->nparam, lr, b1, b2, eps, c1, c2);
+    }
+    BMPC_HIP_TRY(hipGetLastError());
+    if (loss) {
+        BMPC_HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, s));
+        BMPC_HIP_TRY(hipStreamSynchronize(s));
+    }
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t trans_a,
+                                    const uint16_t* B, int32_t trans_b, float* C, void* stream)
+{
+    if (!A || !B || !C || M < 1 || N < 1 || K < 1) return fail(BMPC_ERR_INVALID_ARG, "bad GEMM arguments");
+    hipStream_t s = (hipStream_t)stream;
+    dim3 grid((N + 63) / 64, (M + 63) / 64);
+    const int lda = trans_a ? M : K, ldb = trans_b ? K : N;
+    if (!trans_a && !trans_b)
+        hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_STORE>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                           nullptr, nullptr, C, nullptr, N);
+    else if (trans_a && !trans_b)
+        hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI_STORE>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                           nullptr, nullptr, C, nullptr, N);
+    else if (!trans_a && trans_b)
+        hipLaunchKernelGGL((k_gemm_bf16<false, true, EPI_STORE>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                           nullptr, nullptr, C, nullptr, N);
+    else
+        return fail(BMPC_ERR_UNSUPPORTED, "both operands transposed is not supported");
+    BMPC_HIP_TRY(hipGetLastError());
+    return BMPC_OK;
+}
+
+}  // extern "C"

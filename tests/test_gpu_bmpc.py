@@ -229,3 +229,28 @@ def test_segment_scan_batch_matches_level():
     same = sum(a["status"] == c["status"] and a["inner_it"] == c["inner_it"] for a, c in zip(sl, ss))
     print(f"segment scan vs level: {same}/{len(insts)} identical status and iteration counts", flush=True)
     assert same >= len(insts) - 1
+
+
+def test_rollout_start_and_guard_match_oracle():
+    """Start from inputs alone (states by rollout, warm bit 8) and the guard
+    (bit 16) that keeps the cold start when the given one is worse: same
+    start choice, iteration counts and solution as the oracle."""
+    inst = S.single_bmpc(2)
+    opb = oracle.problem_from_instance(inst)
+    cold, cs, _ = oracle.solve(opb)
+    N = inst.num_nodes
+    cases = [({"u": cold["u"], "ye": cold["ye"]}, False), ({"u": np.full_like(cold["u"], 40.0),
+                                                            "ye": -cold["ye"]}, True),
+             ({"u": cold["u"], "ye": cold["ye"]}, True)]
+    for warm, guarded in cases:
+        o, os_, _ = oracle.solve(opb, warm=warm, guarded=guarded)
+        pb = Problem(inst)
+        x, u, lam, ye = zeros(N, 4), dev(warm["u"]), zeros(N, 4), dev(warm["ye"])
+        bits = 8 | 4 | (16 if guarded else 0)
+        gs = L.bmpc_solve(pb.handle, L.bmpc_settings_default(), bits, x, u, lam, ye)
+        pb.close()
+        print(f"bits {bits}: gpu start {gs['start']} inner {gs['inner_it']}; oracle start {os_['start']} "
+              f"inner {os_['inner_it']}", flush=True)
+        assert gs["start"] == os_["start"] and gs["status"] == os_["status"]
+        assert gs["inner_it"] == os_["inner_it"]
+        assert np.abs(host(x, (N, 4)) - o["x"]).max() <= 1e-5 * max(1.0, np.abs(o["x"]).max())

@@ -401,3 +401,29 @@ def test_shifted_warm_start_needs_fewer_iterations_than_cold():
         if s_warm["status"] == 0 and (s_cold["status"] != 0 or s_warm["inner_it"] < s_cold["inner_it"]):
             fewer += 1
     assert fewer >= 4
+
+
+def test_rollout_start_and_guard():
+    """Warm start from inputs alone (states by the exact rollout) and the
+    guard that falls back to the cold start when the given start is worse
+    by max(KKT residual, violation)."""
+    inst = S.single_bmpc(2)
+    pb = oracle.problem_from_instance(inst)
+    cold, cs, _ = oracle.solve(pb)
+    assert cs["status"] == 0 and cs["start"] == 0
+    # inputs of the solution: the rollout reproduces its states (the
+    # solution's defects are below the tolerance), so the solve is short
+    ws, wst, _ = oracle.solve(pb, warm={"u": cold["u"], "ye": cold["ye"]})
+    assert wst["status"] == 0 and wst["start"] == 1
+    assert wst["inner_it"] < cs["inner_it"] / 2
+    assert np.abs(ws["x"] - cold["x"]).max() < 1e-5
+    # a useless start is replaced by the cold one: same iterates as cold
+    bad_u = np.full_like(cold["u"], 40.0)
+    gs, gst, _ = oracle.solve(pb, warm={"u": bad_u, "ye": -cold["ye"]}, guarded=True)
+    assert gst["start"] == 0
+    assert gst["inner_it"] == cs["inner_it"] and gst["outer_it"] == cs["outer_it"]
+    np.testing.assert_array_equal(gs["x"], cold["x"])
+    # a good start survives the guard unchanged
+    hs, hst, _ = oracle.solve(pb, warm={"u": cold["u"], "ye": cold["ye"]}, guarded=True)
+    assert hst["start"] == 1 and hst["inner_it"] == wst["inner_it"]
+    np.testing.assert_array_equal(hs["x"], ws["x"])
