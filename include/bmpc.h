@@ -213,6 +213,16 @@ BMPC_API bmpc_status bmpc_problem_create(bmpc_tree* tree, const bmpc_bicycle_par
 BMPC_API void bmpc_problem_destroy(bmpc_problem* problem);
 /* New measured state (host pointer, 4 entries). */
 BMPC_API bmpc_status bmpc_problem_set_x0(bmpc_problem* problem, const double* x0);
+/* Replace all data of a problem on the same tree (host arrays as in
+   bmpc_problem_create; synchronous).  Batches holding the problem see the
+   new data at their next launch. */
+BMPC_API bmpc_status bmpc_problem_update(bmpc_problem* problem, const double* node_weight,
+                                         const double* node_ref, const double* node_obs,
+                                         const int32_t* has_obs, const double* x0);
+/* Number of warm-start network outputs the problem takes (see
+   bmpc_batch_start_from_network): 6 per control node + 1 per node with an
+   obstacle. */
+BMPC_API bmpc_status bmpc_problem_output_width(const bmpc_problem* problem, int32_t* width);
 
 /* Solve one problem (Alg. 1).  x (N x 4), u (N x 2), lam (N x 4, multipliers
    of the dynamics, convention L = L_a + lam^T (f - x)), ye (N x 5, PHR
@@ -274,6 +284,18 @@ BMPC_API bmpc_status bmpc_batch_state(bmpc_batch* batch, int32_t i, double* x, d
    The result is the shifted warm start for bmpc_batch_launch(warm = 7).
    The problems' x0 and references are updated.  Asynchronous. */
 BMPC_API bmpc_status bmpc_batch_shift(bmpc_batch* batch, void* stream);
+/* Start points of problems 0 .. rows-1 from warm-start network outputs.
+   Y: DEVICE, rows x width FP32, row-major; row i belongs to problem i:
+   first u of every control node in node order (2 each), then the PHR
+   multiplier estimate of every active constraint slot in (node, slot)
+   order: slots 0-3 (input bounds) of control nodes, slot 4 (obstacle) of
+   nodes that carry one.  Writes u and ye of the batch state (leaf inputs
+   and inactive slots zero); follow with bmpc_batch_launch(warm = 8 | 4,
+   plus 16 to guard against a poor prediction), which rolls the states out
+   from x0 and takes lam from the adjoint sweep.  width must equal
+   bmpc_problem_output_width of every problem used.  Asynchronous. */
+BMPC_API bmpc_status bmpc_batch_start_from_network(bmpc_batch* batch, const float* Y, int32_t rows,
+                                                   int32_t width, void* stream);
 /* Synchronise and copy the iteration history of problem i to hist (host,
    hist_cap x 6). */
 BMPC_API bmpc_status bmpc_batch_history(bmpc_batch* batch, int32_t i, double* hist, void* stream);

@@ -221,6 +221,9 @@ _sig("bmpc_node_refs", _i32, [_vp, _pd, _pd, C.c_double, C.c_double, _pd])
 _sig("bmpc_problem_create", _i32, [_vp, C.POINTER(bmpc_bicycle_params), _pd, _pd, _pd, _pi32, _pd,
                                    C.POINTER(_vp)])
 _sig("bmpc_problem_destroy", None, [_vp])
+_sig("bmpc_problem_update", _i32, [_vp, _pd, _pd, _pd, _pi32, _pd])
+_sig("bmpc_problem_output_width", _i32, [_vp, _pi32])
+_sig("bmpc_batch_start_from_network", _i32, [_vp, _vp, _i32, _i32, _vp])
 _sig("bmpc_problem_set_x0", _i32, [_vp, _pd])
 _sig("bmpc_solve", _i32, [_vp, C.POINTER(bmpc_settings), _i32, _vp, _vp, _vp, _vp,
                           C.POINTER(bmpc_stats), _vp])
@@ -278,6 +281,21 @@ def bmpc_problem_set_x0(h, x0):
     check(lib.bmpc_problem_set_x0(h, xp))
 
 
+def bmpc_problem_update(h, node_weight, node_ref, node_obs, has_obs, x0):
+    w, wp = _hf64(node_weight)
+    r, rp = _hf64(node_ref)
+    o, op = _hf64(node_obs)
+    hs, hp = _hi32(has_obs)
+    x, xp = _hf64(x0)
+    check(lib.bmpc_problem_update(h, wp, rp, op, hp, xp))
+
+
+def bmpc_problem_output_width(h):
+    w = C.c_int32()
+    check(lib.bmpc_problem_output_width(h, C.byref(w)))
+    return w.value
+
+
 def bmpc_solve(problem, settings, warm, x, u, lam, ye, stream=None, raise_on_status=False):
     """x, u, lam, ye: device tensors (node-major).  Returns the stats dict;
     the solver's own status is reported in stats['status']."""
@@ -329,6 +347,11 @@ def bmpc_batch_history(batch, i, hist_cap, stream=None):
     h = np.zeros((hist_cap, 6))
     check(lib.bmpc_batch_history(batch, i, h.ctypes.data_as(_pd), stream_ptr(stream)))
     return h
+
+
+def bmpc_batch_start_from_network(batch, Y, rows, width, stream=None):
+    """Y: float32 device tensor (rows x width)."""
+    check(lib.bmpc_batch_start_from_network(batch, dptr(Y), rows, width, stream_ptr(stream)))
 
 
 def bmpc_batch_shift(batch, stream=None):

@@ -1083,6 +1083,8 @@ struct bmpc_problem {
     double* d_obs = nullptr;
     int* d_has = nullptr;
     double* d_x0 = nullptr;
+    int n_control = 0;  // nodes with children
+    int n_obs = 0;      // nodes carrying the obstacle constraint
     bmpc_batch* self = nullptr;  // one-instance batch used by bmpc_solve
 };
 
@@ -1100,6 +1102,61 @@ struct bmpc_batch {
     int hist_cap = 0;
     std::vector<InstDesc> h_desc;
 };
+
+// Scatter one row of network outputs per problem into its start point:
+// u of every control node (node order), then the PHR multiplier estimates of
+// every active constraint slot in (node, slot) order (slots 0-3 of control
+// nodes, slot 4 of nodes with an obstacle).  Inactive slots and leaf inputs
+// become zero; x and lam are left to the solver's rollout and adjoint sweep.
+template <int BS>
+__global__ void __launch_bounds__(BS) k_start_from_outputs(const InstDesc* __restrict__ insts,
+                                                           const float* __restrict__ Y, int width)
+{
+    __shared__ int s_c[BS], s_a[BS];
+    __shared__ int s_nctl;
+    const InstDesc I = insts[blockIdx.x];
+    const float* y = Y + (long)blockIdx.x * width;
+    const int tid = threadIdx.x, N = I.N;
+    if (tid == 0) s_nctl = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int n = tid; n < N; n += BS) mine += I.child_off[n + 1] > I.child_off[n] ? 1 : 0;
+    atomicAdd(&s_nctl, mine);
+    __syncthreads();
+    const int ye_base = 2 * s_nctl;
+    int carry_c = 0, carry_a = 0;
+    for (int base = 0; base < N; base += BS) {
+        const int n = base + tid;
+        const bool in = n < N;
+        const bool ctl = in && I.child_off[n + 1] > I.child_off[n];
+        const bool obs = in && I.has_obs[n] != 0;
+        const int c = ctl ? 1 : 0, a = (ctl ? 4 : 0) + (obs ? 1 : 0);
+        s_c[tid] = c;
+        s_a[tid] = a;
+        __syncthreads();
+        for (int off = 1; off < BS; off <<= 1) {  // inclusive Hillis-Steele scan
+            const int vc = tid >= off ? s_c[tid - off] : 0;
+            const int va = tid >= off ? s_a[tid - off] : 0;
+            __syncthreads();
+            s_c[tid] += vc;
+            s_a[tid] += va;
+            __syncthreads();
+        }
+        if (in) {
+            const int ic = carry_c + s_c[tid] - c;  // exclusive prefixes
+            int ia = ye_base + carry_a + s_a[tid] - a;
+            I.u[n * 2] = ctl ? (double)y[2 * ic] : 0.0;
+            I.u[n * 2 + 1] = ctl ? (double)y[2 * ic + 1] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) I.ye[n * BG + k] = ctl ? (double)y[ia + k] : 0.0;
+            if (ctl) ia += 4;
+            I.ye[n * BG + 4] = obs ? (double)y[ia] : 0.0;
+        }
+        carry_c += s_c[BS - 1];
+        carry_a += s_a[BS - 1];
+        __syncthreads();
+    }
+}
 
 static BikeParams to_dev(const bmpc_bicycle_params& p)
 {
@@ -1201,6 +1258,35 @@ BMPC_API bmpc_status bmpc_node_refs(const bmpc_tree* t, const double* leaf_prob,
     return BMPC_OK;
 }
 
+static bmpc_status check_problem_data(int N, const double* node_weight, const double* node_ref,
+                                      const int32_t* has_obs, const double* x0)
+{
+    for (int i = 0; i < N; ++i)
+        if (!std::isfinite(node_weight[i]) || node_weight[i] < 0.0)
+            return fail(BMPC_ERR_NONFINITE, "node_weight[%d] must be a finite non-negative number", i);
+    for (int i = 0; i < 4 * N; ++i)
+        if (!std::isfinite(node_ref[i])) return fail(BMPC_ERR_NONFINITE, "node_ref has a non-finite entry");
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(x0[i])) return fail(BMPC_ERR_NONFINITE, "x0 has a non-finite entry");
+    for (int i = 0; i < N; ++i)
+        if (has_obs[i] != 0 && has_obs[i] != 1) return fail(BMPC_ERR_INVALID_ARG, "has_obs[%d] must be 0 or 1", i);
+    return BMPC_OK;
+}
+
+static bmpc_status upload_problem_data(bmpc_problem* p, const double* node_weight, const double* node_ref,
+                                       const double* node_obs, const int32_t* has_obs, const double* x0)
+{
+    const int N = p->N;
+    BMPC_HIP_TRY(hipMemcpy(p->d_weight, node_weight, sizeof(double) * N, hipMemcpyHostToDevice));
+    BMPC_HIP_TRY(hipMemcpy(p->d_ref, node_ref, sizeof(double) * 4 * N, hipMemcpyHostToDevice));
+    BMPC_HIP_TRY(hipMemcpy(p->d_obs, node_obs, sizeof(double) * 2 * N, hipMemcpyHostToDevice));
+    BMPC_HIP_TRY(hipMemcpy(p->d_has, has_obs, sizeof(int) * N, hipMemcpyHostToDevice));
+    BMPC_HIP_TRY(hipMemcpy(p->d_x0, x0, sizeof(double) * 4, hipMemcpyHostToDevice));
+    p->n_obs = 0;
+    for (int i = 0; i < N; ++i) p->n_obs += has_obs[i];
+    return BMPC_OK;
+}
+
 BMPC_API bmpc_status bmpc_problem_create(bmpc_tree* tree, const bmpc_bicycle_params* prm,
                                          const double* node_weight, const double* node_ref,
                                          const double* node_obs, const int32_t* has_obs, const double* x0,
@@ -1212,34 +1298,43 @@ BMPC_API bmpc_status bmpc_problem_create(bmpc_tree* tree, const bmpc_bicycle_par
     if (!(prm->dt > 0.0) || !(prm->wheelbase > 0.0) || !(prm->obs_radius >= 0.0))
         return fail(BMPC_ERR_INVALID_ARG, "bicycle parameters must be positive");
     const int N = tree->h.N;
-    for (int i = 0; i < N; ++i)
-        if (!std::isfinite(node_weight[i]) || node_weight[i] < 0.0)
-            return fail(BMPC_ERR_NONFINITE, "node_weight[%d] must be a finite non-negative number", i);
-    for (int i = 0; i < 4 * N; ++i)
-        if (!std::isfinite(node_ref[i])) return fail(BMPC_ERR_NONFINITE, "node_ref has a non-finite entry");
-    for (int i = 0; i < 4; ++i)
-        if (!std::isfinite(x0[i])) return fail(BMPC_ERR_NONFINITE, "x0 has a non-finite entry");
-    bmpc_status st = tree_on_device(tree);
+    bmpc_status st = check_problem_data(N, node_weight, node_ref, has_obs, x0);
+    if (st != BMPC_OK) return st;
+    st = tree_on_device(tree);
     if (st != BMPC_OK) return st;
     auto* p = new bmpc_problem();
     p->tree = tree;
     p->prm = *prm;
     p->N = N;
+    for (int i = 0; i < N; ++i) p->n_control += tree->h.child_off[i + 1] > tree->h.child_off[i] ? 1 : 0;
     bool ok = dalloc(&p->d_weight, N) && dalloc(&p->d_ref, 4 * (size_t)N) && dalloc(&p->d_obs, 2 * (size_t)N) &&
               dalloc(&p->d_has, N) && dalloc(&p->d_x0, 4);
     if (!ok) {
         bmpc_problem_destroy(p);
         return fail(BMPC_ERR_OOM, "device allocation for the problem failed");
     }
-    if (hipMemcpy(p->d_weight, node_weight, sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_ref, node_ref, sizeof(double) * 4 * N, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_obs, node_obs, sizeof(double) * 2 * N, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_has, has_obs, sizeof(int) * N, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_x0, x0, sizeof(double) * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    if ((st = upload_problem_data(p, node_weight, node_ref, node_obs, has_obs, x0)) != BMPC_OK) {
         bmpc_problem_destroy(p);
-        return fail(BMPC_ERR_HIP, "uploading the problem failed");
+        return st;
     }
     *out = p;
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_problem_update(bmpc_problem* p, const double* node_weight, const double* node_ref,
+                                         const double* node_obs, const int32_t* has_obs, const double* x0)
+{
+    if (!p || !node_weight || !node_ref || !node_obs || !has_obs || !x0)
+        return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    bmpc_status st = check_problem_data(p->N, node_weight, node_ref, has_obs, x0);
+    if (st != BMPC_OK) return st;
+    return upload_problem_data(p, node_weight, node_ref, node_obs, has_obs, x0);
+}
+
+BMPC_API bmpc_status bmpc_problem_output_width(const bmpc_problem* p, int32_t* width)
+{
+    if (!p || !width) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    *width = 6 * p->n_control + p->n_obs;
     return BMPC_OK;
 }
 
@@ -1416,6 +1511,25 @@ BMPC_API bmpc_status bmpc_batch_state(bmpc_batch* b, int32_t i, double* x, doubl
         else
             BMPC_HIP_TRY(hipMemcpyAsync(pt.ext, pt.in, sizeof(double) * pt.n, hipMemcpyDeviceToDevice, st));
     }
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_batch_start_from_network(bmpc_batch* b, const float* Y, int32_t rows, int32_t width,
+                                                   void* stream)
+{
+    if (!b || !Y) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    if (rows < 1 || rows > b->count) return fail(BMPC_ERR_INVALID_ARG, "rows %d outside [1, %d]", rows, b->count);
+    for (int i = 0; i < rows; ++i) {
+        const int w = 6 * b->problems[i]->n_control + b->problems[i]->n_obs;
+        if (w != width)
+            return fail(BMPC_ERR_INVALID_ARG, "problem %d needs %d network outputs, got %d", i, w, width);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    {
+        ProfScope ps("bmpc_start_from_network", st);
+        hipLaunchKernelGGL(k_start_from_outputs<256>, dim3(rows), dim3(256), 0, st, b->d_desc, Y, width);
+    }
+    BMPC_HIP_TRY(hipGetLastError());
     return BMPC_OK;
 }
 

@@ -1,0 +1,149 @@
+"""Learned warm start on the GPU: output scatter (index work, bit-exact),
+the network start path against the oracle given the same predicted start,
+and a small end-to-end train/evaluate run."""
+import numpy as np
+import pytest
+
+import bmpc_synth as S
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2506_13624_amd import _lib as L  # noqa: E402
+from paper_2506_13624_amd import warmstart as W  # noqa: E402
+from paper_2506_13624_amd.bicycle import ProblemPool  # noqa: E402
+
+
+def _f32_exact(rng, shape, lo, hi):
+    return rng.uniform(lo, hi, shape).astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("kind", ["learned_topology", "batched_large"])
+def test_scatter_roundtrip_is_exact(kind):
+    if kind == "learned_topology":
+        insts = [S.learned_topology_instance(i) for i in range(3)]
+    else:
+        base = next(i for i in S.batched_instances(512) if i.num_nodes > 300)
+        insts = [base] * 3
+    print(f"scatter {kind} N={insts[0].num_nodes}", flush=True)
+    pool = ProblemPool(insts[0].parent, 3, first_inst=insts[0])
+    pool.load(insts)
+    width = L.bmpc_problem_output_width(pool.handles[0])
+    rng = np.random.default_rng(0)
+    N = insts[0].num_nodes
+    us = [_f32_exact(rng, (N, 2), -3, 3) for _ in insts]
+    yes = [_f32_exact(rng, (N, 5), -1, 2) for _ in insts]
+    Y = np.array([W.targets(inst, u, ye) for inst, u, ye in zip(insts, us, yes)])
+    assert Y.shape[1] == width
+    if kind == "learned_topology":
+        assert width == 734
+    L.bmpc_batch_start_from_network(pool.batch, torch.from_numpy(Y.astype(np.float32)).cuda(), 3, width)
+    s = W.read_states(pool, 3)
+    pool.close()
+    for i, inst in enumerate(insts):
+        ctl, pairs = W.output_layout(inst)
+        want_u = np.zeros((N, 2))
+        want_u[ctl] = us[i][ctl]
+        want_ye = np.zeros((N, 5))
+        want_ye[pairs[:, 0], pairs[:, 1]] = yes[i][pairs[:, 0], pairs[:, 1]]
+        np.testing.assert_array_equal(s["u"][i], want_u)
+        np.testing.assert_array_equal(s["ye"][i], want_ye)
+
+
+def test_width_mismatch_rejected():
+    inst = S.learned_topology_instance(0)
+    pool = ProblemPool(inst.parent, 1, first_inst=inst)
+    Y = torch.zeros((1, 733), dtype=torch.float32, device="cuda")
+    with pytest.raises(L.BmpcError) as e:
+        L.bmpc_batch_start_from_network(pool.batch, Y, 1, 733)
+    assert e.value.status == 1
+    pool.close()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    insts = [S.learned_topology_instance(i) for i in range(2048)]
+    X, T, ok, its = W.generate(insts)
+    print(f"generated {len(insts)}: {ok.sum()} converged, mean inner {its.mean():.1f}", flush=True)
+    starter = W.WarmStarter(T.shape[1], max_batch=1024, seed=0)
+    log, secs, rate = starter.fit(X[ok], T[ok], steps=600, batch=512, lr=2e-3, log_every=100)
+    print(f"training log {log}; {rate:.0f} samples/s", flush=True)
+    yield starter, log
+    starter.close()
+
+
+def test_training_loss_decreases(trained):
+    _, log = trained
+    assert log[-1][1] < 0.5 * log[0][1]
+
+
+def test_inference_network_folds_standardisation(trained):
+    """The inference network (standardisation folded into the first and last
+    layers, weights re-rounded to BF16) agrees with the training network on
+    standardised data, to the BF16 weight rounding."""
+    starter, _ = trained
+    insts = [S.learned_topology_instance(300_000 + i) for i in range(64)]
+    X = np.array([W.features(i) for i in insts])
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    Y = torch.empty((64, 734), dtype=torch.float32, device="cuda")
+    starter.predict(Xd, Y)
+    Xn = torch.from_numpy(((X - starter.x_mean) / starter.x_std).astype(np.float32)).cuda()
+    Yn = torch.empty((64, 734), dtype=torch.float32, device="cuda")
+    L.bmpc_mlp_forward(starter.train_net, Xn, Yn)
+    ref = Yn.cpu().numpy() * starter.t_std + starter.t_mean
+    err = np.abs(Y.cpu().numpy() - ref) / starter.t_std
+    print(f"fold: max standardised deviation {err.max():.3e}", flush=True)
+    assert err.max() < 0.1
+
+
+def test_network_start_matches_oracle_from_same_prediction(trained):
+    """Given the network's predicted start, the GPU solver and the oracle
+    take the same start decision, iteration count and solution."""
+    starter, _ = trained
+    insts = [S.learned_topology_instance(100_000 + i) for i in range(4)]
+    pool = ProblemPool(insts[0].parent, len(insts), first_inst=insts[0])
+    stats, _ = W.solve_with_network(pool, insts, starter)
+    X = torch.from_numpy(np.array([W.features(i) for i in insts], dtype=np.float32)).cuda()
+    Y = torch.empty((len(insts), 734), dtype=torch.float32, device="cuda")
+    starter.predict(X, Y)
+    Yh = Y.cpu().numpy().astype(np.float64)
+    s = W.read_states(pool, len(insts), parts=("x", "u"))
+    pool.close()
+    for i, inst in enumerate(insts):
+        ctl, pairs = W.output_layout(inst)
+        N = inst.num_nodes
+        u0 = np.zeros((N, 2))
+        u0[ctl] = Yh[i, :2 * len(ctl)].reshape(-1, 2)
+        ye0 = np.zeros((N, 5))
+        ye0[pairs[:, 0], pairs[:, 1]] = Yh[i, 2 * len(ctl):]
+        o, os_, _ = oracle.solve(oracle.problem_from_instance(inst), warm={"u": u0, "ye": ye0}, guarded=True)
+        g = stats[i]
+        print(f"instance {i}: gpu start {g['start']} status {g['status']} inner {g['inner_it']}; "
+              f"oracle start {os_['start']} status {os_['status']} inner {os_['inner_it']}", flush=True)
+        assert g["start"] == os_["start"] and g["status"] == os_["status"]
+        assert g["inner_it"] == os_["inner_it"]
+        if os_["status"] == 0:
+            assert np.abs(s["x"][i] - o["x"]).max() <= 1e-5 * max(1.0, np.abs(o["x"]).max())
+
+
+def test_network_start_not_worse_than_cold(trained):
+    starter, _ = trained
+    insts = [S.learned_topology_instance(200_000 + i) for i in range(256)]
+    pool = ProblemPool(insts[0].parent, len(insts), first_inst=insts[0])
+    pool.load(insts)
+    L.bmpc_batch_launch(pool.batch, L.bmpc_settings_default())
+    cold = L.bmpc_batch_stats(pool.batch, len(insts))
+    net, t = W.solve_with_network(pool, insts, starter)
+    pool.close()
+    c_ok = sum(s["status"] == 0 for s in cold)
+    n_ok = sum(s["status"] == 0 for s in net)
+    c_it = np.mean([s["inner_it"] for s in cold])
+    n_it = np.mean([s["inner_it"] for s in net])
+    used = sum(s["start"] for s in net)
+    print(f"cold: {c_ok} converged, mean inner {c_it:.1f}; network: {n_ok} converged, mean inner {n_it:.1f}, "
+          f"network start kept on {used}; {t}", flush=True)
+    assert n_ok >= c_ok - 3
