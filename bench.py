@@ -351,6 +351,107 @@ def run_bmpc(args, torch, L):
     return out
 
 
+def mlp_flops_per_sample(widths):
+    """Dense multiply-adds x 2 of one training sample: forward Z = A W, weight
+    gradient A^T dZ and input gradient dZ W^T (not for the first layer)."""
+    fwd = sum(widths[l] * widths[l + 1] for l in range(len(widths) - 1))
+    dinp = sum(widths[l] * widths[l + 1] for l in range(1, len(widths) - 1))
+    return 2 * fwd, 2 * (2 * fwd + dinp)
+
+
+def run_warmstart(args, torch, L):
+    import bmpc_synth as S
+    from paper_2506_13624_amd import warmstart as W
+    from paper_2506_13624_amd.bicycle import ProblemPool
+
+    out = {}
+    n_train, n_val, n_test = args.ws_train, 1024, 1024
+    t0 = time.perf_counter()
+    Xtr, Ttr, oktr, ittr = W.generate(S.learned_topology_instance(i) for i in range(n_train))
+    gen_s = time.perf_counter() - t0
+    Xva, Tva, okva, _ = W.generate(S.learned_topology_instance(500_000 + i) for i in range(n_val))
+    starter = W.WarmStarter(Ttr.shape[1], max_batch=1024, seed=0)
+    log, train_s, rate = starter.fit(Xtr[oktr], Ttr[oktr], steps=args.ws_steps, batch=1024, lr=2e-3,
+                                     log_every=max(args.ws_steps // 8, 1))
+    val_loss = starter.loss(Xva[okva], Tva[okva])
+    # per-kernel times of training steps (event pairs around every launch)
+    xb = torch.from_numpy(((Xtr[:1024] - starter.x_mean) / starter.x_std).astype(np.float32)).cuda()
+    tb = torch.from_numpy(((Ttr[:1024] - starter.t_mean) / starter.t_std).astype(np.float32)).cuda()
+    prof_steps = 200
+    L.bmpc_profile_enable(True)
+    for _ in range(prof_steps):
+        L.bmpc_mlp_train_step(starter.train_net, xb, tb, 1e-6, want_loss=False)
+    prof = L.bmpc_profile_read()
+    L.bmpc_profile_enable(False)
+    fwd_f, train_f = mlp_flops_per_sample(starter.widths)
+    gemm_ms = sum(v[0] for k, v in prof.items() if k.startswith("mlp_gemm"))
+    step_flops = train_f * 1024
+    gemm_tflops = step_flops * prof_steps / (gemm_ms / 1e3) / 1e12 if gemm_ms > 0 else None
+
+    test = [S.learned_topology_instance(1_000_000 + i) for i in range(n_test)]
+    pool = ProblemPool(test[0].parent, n_test, first_inst=test[0])
+    st = L.bmpc_settings_default()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed_launch(warm):
+        torch.cuda.synchronize()
+        ev[0].record()
+        L.bmpc_batch_launch(pool.batch, st, warm=warm)
+        ev[1].record()
+        ss = L.bmpc_batch_stats(pool.batch, n_test)
+        torch.cuda.synchronize()
+        return ss, ev[0].elapsed_time(ev[1])
+
+    def summary(ss, ms, extra=None):
+        conv = [x for x in ss if x["status"] == 0]
+        d = {"ms": round(ms, 3), "converged": len(conv), "of": len(ss),
+             "mean_inner_it": round(float(np.mean([x["inner_it"] for x in conv])), 2) if conv else None,
+             "solves_per_s": round(len(conv) / (ms / 1e3), 1)}
+        if extra:
+            d.update(extra)
+        return d
+
+    pool.load(test)
+    L.bmpc_batch_launch(pool.batch, st)  # warm-up
+    s_cold, ms_cold = timed_launch(0)
+    s_net, t_net = W.solve_with_network(pool, test, starter)
+    # one receding-horizon step: shifted warm start vs cold vs network on the
+    # same shifted problems
+    pool.load(test)
+    L.bmpc_batch_launch(pool.batch, st)
+    L.bmpc_batch_shift(pool.batch)
+    torch.cuda.synchronize()
+    F_shift = W.shifted_features(pool, test)
+    s_shift, ms_shift = timed_launch(7)
+    s_cold2, ms_cold2 = timed_launch(0)
+    s_net2, t_net2 = W.solve_with_network(pool, test, starter, feats=F_shift)
+    pool.close()
+    starter.close()
+
+    def net_summary(ss, t):
+        return summary(ss, t["network_ms"] + t["solve_ms"],
+                       {"network_ms": round(t["network_ms"], 4), "network_start_kept": int(sum(x["start"] for x in ss))})
+
+    out["learned_warm_start"] = {
+        "workload": f"bicycle branch-MPC, horizon 30, 4 branches at stage 4 (109 nodes); network 44-256-256-256-734 "
+                    f"GELU, BF16 weights/activations, FP32 accumulate; trained on {int(oktr.sum())} converged cold "
+                    f"solves of {n_train} seeded instances, validated on {int(okva.sum())}, tested on {n_test}",
+        "data_generation": {"instances": n_train, "converged": int(oktr.sum()), "seconds": round(gen_s, 2),
+                            "mean_inner_it": round(float(ittr[oktr].mean()), 2)},
+        "training": {"steps": args.ws_steps, "batch": 1024, "samples_per_s": round(rate, 0),
+                     "loss_log": [(int(a), round(float(b), 5)) for a, b in log],
+                     "validation_loss": round(float(val_loss), 5),
+                     "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]} for k, v in prof.items()},
+                     "mfma_bf16": {"flops_per_step": step_flops, "gemm_tflops": round(gemm_tflops, 3) if gemm_tflops else None,
+                                   "peak_tflops": 2500.0,
+                                   "frac": round(gemm_tflops / 2500.0, 5) if gemm_tflops else None}},
+        "fresh_problems": {"cold": summary(s_cold, ms_cold), "network": net_summary(s_net, t_net)},
+        "after_one_shift": {"shifted_warm": summary(s_shift, ms_shift), "cold": summary(s_cold2, ms_cold2),
+                            "network": net_summary(s_net2, t_net2)},
+    }
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,6 +462,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="launch one 512 MiB copy first (rocprofv3 counter calibration)")
     ap.add_argument("--skip-bmpc", action="store_true")
+    ap.add_argument("--skip-warmstart", action="store_true")
+    ap.add_argument("--ws-train", type=int, default=16384, help="training instances of the learned warm start")
+    ap.add_argument("--ws-steps", type=int, default=3000, help="training steps (batch 1024)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -376,6 +480,8 @@ def main():
     out, inst = run_lqr(args, torch, L)
     if not args.skip_bmpc:
         out.update(run_bmpc(args, torch, L))
+    if not args.skip_bmpc and not args.skip_warmstart:
+        out.update(run_warmstart(args, torch, L))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_lqr(inst, args.cpu_budget)
     else:

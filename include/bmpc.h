@@ -179,6 +179,9 @@ typedef struct {
     double eps_tol, tau, omega0, eta0, a_omega, b_omega, a_eta, b_eta;
     double rho0, mu0, armijo_beta;
     int32_t n_alpha, max_outer, max_inner, max_ls_fail, riccati_variant;
+    /* threads per problem in batched solves: 64, 128 or 256; 0 = the value
+       chosen by bmpc_batch_tune for the batch, else 256 */
+    int32_t block_size;
 } bmpc_settings;
 
 /* Result of one solve.  r_kkt: last KKT residual of the relaxed problem
@@ -219,6 +222,9 @@ BMPC_API bmpc_status bmpc_problem_set_x0(bmpc_problem* problem, const double* x0
 BMPC_API bmpc_status bmpc_problem_update(bmpc_problem* problem, const double* node_weight,
                                          const double* node_ref, const double* node_obs,
                                          const int32_t* has_obs, const double* x0);
+/* Current measured state (host output, 4 entries; synchronous).  Reflects
+   bmpc_batch_shift, which advances it on the device. */
+BMPC_API bmpc_status bmpc_problem_get_x0(const bmpc_problem* problem, double* x0);
 /* Number of warm-start network outputs the problem takes (see
    bmpc_batch_start_from_network): 6 per control node + 1 per node with an
    obstacle. */
@@ -327,6 +333,11 @@ BMPC_API int64_t bmpc_mlp_num_params(const bmpc_mlp* net);
 /* Load parameters (host FP32, synchronous) and reset the Adam state.
    BMPC_ERR_NONFINITE on a NaN/Inf entry. */
 BMPC_API bmpc_status bmpc_mlp_set_params(bmpc_mlp* net, const float* params);
+/* Input map applied in FP32 before the input is rounded to BF16:
+   A_0 = bf16((X - shift) * scale) column by column (host arrays of w_0
+   entries; synchronous).  Default shift 0, scale 1.  Lets a caller feed
+   raw features whose mean is large against their spread. */
+BMPC_API bmpc_status bmpc_mlp_set_input_map(bmpc_mlp* net, const float* shift, const float* scale);
 /* Copy the FP32 master parameters to host (synchronous). */
 BMPC_API bmpc_status bmpc_mlp_get_params(bmpc_mlp* net, float* params);
 /* Inference: Y = network(X) for B rows, 1 <= B <= max_batch.  X is
@@ -348,6 +359,38 @@ BMPC_API bmpc_status bmpc_mlp_train_step(bmpc_mlp* net, const float* X, const fl
    trans_b together are BMPC_ERR_UNSUPPORTED.  Asynchronous. */
 BMPC_API bmpc_status bmpc_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t trans_a,
                                     const uint16_t* B, int32_t trans_b, float* C, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Launch configuration of batched solves and graph replay.
+ * ---------------------------------------------------------------------- */
+/* Autotuner: time every compiled (backward variant, threads per problem)
+   pair on this batch (reps solves each, with settings s and warm bits warm,
+   each from the batch's current state) and keep the fastest for launches
+   with riccati_variant = BMPC_RICCATI_AUTO and block_size = 0.  The batch
+   state is restored afterwards; its stats and history are those of the last
+   run.  variant_out, block_out (host, nullable) receive the choice and
+   ms_out (host, nullable, bmpc_batch_tune_candidates() entries) the mean
+   time of each candidate.  Synchronous.  Different choices sum the merit and
+   KKT reductions in different orders, so iterates can differ by rounding. */
+BMPC_API bmpc_status bmpc_batch_tune(bmpc_batch* batch, const bmpc_settings* s, int32_t warm, int32_t reps,
+                                     int32_t* variant_out, int32_t* block_out, double* ms_out, void* stream);
+/* Number of tuning candidates; fills up to cap of their (variant, block)
+   pairs in tuning order (host arrays, nullable). */
+BMPC_API int32_t bmpc_batch_tune_candidates(int32_t* variants, int32_t* blocks, int32_t cap);
+
+/* Graph capture of asynchronous library calls on a created (non-default)
+   stream: bmpc_graph_begin(stream), then any of bmpc_batch_launch,
+   bmpc_batch_shift, bmpc_batch_start_from_network, bmpc_batch_state,
+   bmpc_mlp_forward, bmpc_lqr_solve on that stream, then
+   bmpc_graph_end(stream, &graph).  Synchronous calls (stats, history,
+   tuning, *_create) fail inside a capture.  bmpc_graph_launch replays the
+   whole sequence with the arguments it was recorded with (same buffers,
+   same settings).  Kernel timing skips launches inside a capture. */
+typedef struct bmpc_graph bmpc_graph;
+BMPC_API bmpc_status bmpc_graph_begin(void* stream);
+BMPC_API bmpc_status bmpc_graph_end(void* stream, bmpc_graph** out);
+BMPC_API bmpc_status bmpc_graph_launch(bmpc_graph* graph, void* stream);
+BMPC_API void bmpc_graph_destroy(bmpc_graph* graph);
 
 /* ------------------------------------------------------------------------
  * Kernel timing.  When enabled, every kernel launch of the library is

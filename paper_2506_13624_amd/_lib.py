@@ -202,7 +202,7 @@ class bmpc_settings(C.Structure):
                 ("a_eta", C.c_double), ("b_eta", C.c_double), ("rho0", C.c_double),
                 ("mu0", C.c_double), ("armijo_beta", C.c_double), ("n_alpha", C.c_int32),
                 ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("max_ls_fail", C.c_int32),
-                ("riccati_variant", C.c_int32)]
+                ("riccati_variant", C.c_int32), ("block_size", C.c_int32)]
 
 
 class bmpc_stats(C.Structure):
@@ -223,6 +223,7 @@ _sig("bmpc_problem_create", _i32, [_vp, C.POINTER(bmpc_bicycle_params), _pd, _pd
 _sig("bmpc_problem_destroy", None, [_vp])
 _sig("bmpc_problem_update", _i32, [_vp, _pd, _pd, _pd, _pi32, _pd])
 _sig("bmpc_problem_output_width", _i32, [_vp, _pi32])
+_sig("bmpc_problem_get_x0", _i32, [_vp, _pd])
 _sig("bmpc_batch_start_from_network", _i32, [_vp, _vp, _i32, _i32, _vp])
 _sig("bmpc_problem_set_x0", _i32, [_vp, _pd])
 _sig("bmpc_solve", _i32, [_vp, C.POINTER(bmpc_settings), _i32, _vp, _vp, _vp, _vp,
@@ -288,6 +289,12 @@ def bmpc_problem_update(h, node_weight, node_ref, node_obs, has_obs, x0):
     hs, hp = _hi32(has_obs)
     x, xp = _hf64(x0)
     check(lib.bmpc_problem_update(h, wp, rp, op, hp, xp))
+
+
+def bmpc_problem_get_x0(h):
+    x = np.zeros(4)
+    check(lib.bmpc_problem_get_x0(h, x.ctypes.data_as(_pd)))
+    return x
 
 
 def bmpc_problem_output_width(h):
@@ -368,6 +375,7 @@ _sig("bmpc_mlp_destroy", None, [_vp])
 _sig("bmpc_mlp_num_params", C.c_int64, [_vp])
 _sig("bmpc_mlp_set_params", _i32, [_vp, _pf32])
 _sig("bmpc_mlp_get_params", _i32, [_vp, _pf32])
+_sig("bmpc_mlp_set_input_map", _i32, [_vp, _pf32, _pf32])
 _sig("bmpc_mlp_forward", _i32, [_vp, _vp, _i32, _vp, _vp])
 _sig("bmpc_mlp_gradients", _i32, [_vp, _vp, _vp, _i32, _pf32, _pf32, _vp])
 _sig("bmpc_mlp_train_step", _i32, [_vp, _vp, _vp, _i32, C.c_float, _pf32, _vp])
@@ -401,6 +409,12 @@ def bmpc_mlp_set_params(h, params):
     check(lib.bmpc_mlp_set_params(h, pp))
 
 
+def bmpc_mlp_set_input_map(h, shift, scale):
+    a, pa = _hf32(shift)
+    b, pb = _hf32(scale)
+    check(lib.bmpc_mlp_set_input_map(h, pa, pb))
+
+
 def bmpc_mlp_get_params(h):
     p = np.zeros(bmpc_mlp_num_params(h), dtype=np.float32)
     check(lib.bmpc_mlp_get_params(h, p.ctypes.data_as(_pf32)))
@@ -431,3 +445,51 @@ def bmpc_gemm_bf16(M, N, K, A, trans_a, B, trans_b, C_out, stream=None):
     """A, B: int16/bfloat16 device tensors holding BF16 bit patterns; C_out float32."""
     check(lib.bmpc_gemm_bf16(M, N, K, dptr(A), int(trans_a), dptr(B), int(trans_b), dptr(C_out),
                              stream_ptr(stream)))
+
+
+# ----------------------------------------------------------------------------
+# launch configuration and graphs
+# ----------------------------------------------------------------------------
+
+_sig("bmpc_batch_tune", _i32, [_vp, _vp, _i32, _i32, _pi32, _pi32, _pd, _vp])
+_sig("bmpc_batch_tune_candidates", _i32, [_pi32, _pi32, _i32])
+_sig("bmpc_graph_begin", _i32, [_vp])
+_sig("bmpc_graph_end", _i32, [_vp, C.POINTER(_vp)])
+_sig("bmpc_graph_launch", _i32, [_vp, _vp])
+_sig("bmpc_graph_destroy", None, [_vp])
+
+
+def bmpc_batch_tune_candidates():
+    n = lib.bmpc_batch_tune_candidates(None, None, 0)
+    v = np.zeros(n, dtype=np.int32)
+    b = np.zeros(n, dtype=np.int32)
+    lib.bmpc_batch_tune_candidates(v.ctypes.data_as(_pi32), b.ctypes.data_as(_pi32), n)
+    return list(zip(v.tolist(), b.tolist()))
+
+
+def bmpc_batch_tune(batch, settings, warm=0, reps=1, stream=None):
+    """Returns (variant, block_size, {(variant, block): mean ms})."""
+    cands = bmpc_batch_tune_candidates()
+    v, b = C.c_int32(), C.c_int32()
+    ms = np.zeros(len(cands))
+    check(lib.bmpc_batch_tune(batch, C.byref(settings), warm, reps, C.byref(v), C.byref(b),
+                              ms.ctypes.data_as(_pd), stream_ptr(stream)))
+    return v.value, b.value, dict(zip(cands, ms.tolist()))
+
+
+def bmpc_graph_begin(stream):
+    check(lib.bmpc_graph_begin(stream_ptr(stream)))
+
+
+def bmpc_graph_end(stream):
+    out = _vp()
+    check(lib.bmpc_graph_end(stream_ptr(stream), C.byref(out)))
+    return out
+
+
+def bmpc_graph_launch(graph, stream=None):
+    check(lib.bmpc_graph_launch(graph, stream_ptr(stream)))
+
+
+def bmpc_graph_destroy(graph):
+    lib.bmpc_graph_destroy(graph)

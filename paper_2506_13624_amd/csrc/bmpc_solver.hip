@@ -1101,6 +1101,8 @@ struct bmpc_batch {
     double* d_hist = nullptr;
     int hist_cap = 0;
     std::vector<InstDesc> h_desc;
+    int tuned_variant = 0;  // set by bmpc_batch_tune (0 = not tuned)
+    int tuned_block = 0;
 };
 
 // Scatter one row of network outputs per problem into its start point:
@@ -1156,6 +1158,29 @@ __global__ void __launch_bounds__(BS) k_start_from_outputs(const InstDesc* __res
         carry_a += s_a[BS - 1];
         __syncthreads();
     }
+}
+
+// Batched solver instantiations: threads per problem x backward variant.
+struct WgKernel {
+    int block;
+    bool segscan;
+    void (*fn)(const InstDesc*, SolverCfg, SolveOut*, int*, double*, int);
+    const char* name;
+};
+static const WgKernel kWgKernels[] = {
+    {64, false, k_bmpc_wg<64, false>, "bmpc_solve_wg64_level"},
+    {128, false, k_bmpc_wg<128, false>, "bmpc_solve_wg128_level"},
+    {256, false, k_bmpc_wg<256, false>, "bmpc_solve_wg256_level"},
+    {64, true, k_bmpc_wg<64, true>, "bmpc_solve_wg64_segscan"},
+    {128, true, k_bmpc_wg<128, true>, "bmpc_solve_wg128_segscan"},
+    {256, true, k_bmpc_wg<256, true>, "bmpc_solve_wg256_segscan"},
+};
+
+static const WgKernel* find_wg(int block, bool segscan)
+{
+    for (const auto& k : kWgKernels)
+        if (k.block == block && k.segscan == segscan) return &k;
+    return &kWgKernels[2];
 }
 
 static BikeParams to_dev(const bmpc_bicycle_params& p)
@@ -1220,6 +1245,7 @@ BMPC_API void bmpc_settings_default(bmpc_settings* s)
     s->max_inner = 100;
     s->max_ls_fail = 3;
     s->riccati_variant = BMPC_RICCATI_AUTO;
+    s->block_size = 0;
 }
 
 BMPC_API void bmpc_bicycle_default(bmpc_bicycle_params* p)
@@ -1329,6 +1355,13 @@ BMPC_API bmpc_status bmpc_problem_update(bmpc_problem* p, const double* node_wei
     bmpc_status st = check_problem_data(p->N, node_weight, node_ref, has_obs, x0);
     if (st != BMPC_OK) return st;
     return upload_problem_data(p, node_weight, node_ref, node_obs, has_obs, x0);
+}
+
+BMPC_API bmpc_status bmpc_problem_get_x0(const bmpc_problem* p, double* x0)
+{
+    if (!p || !x0) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    BMPC_HIP_TRY(hipMemcpy(x0, p->d_x0, sizeof(double) * 4, hipMemcpyDeviceToHost));
+    return BMPC_OK;
 }
 
 BMPC_API bmpc_status bmpc_problem_output_width(const bmpc_problem* p, int32_t* width)
@@ -1453,19 +1486,98 @@ BMPC_API bmpc_status bmpc_batch_launch(bmpc_batch* b, const bmpc_settings* s, in
         s->riccati_variant != BMPC_RICCATI_SEGSCAN)
         return fail(BMPC_ERR_INVALID_ARG, "unknown Riccati variant %d", s->riccati_variant);
     if (warm < 0 || warm > 31) return fail(BMPC_ERR_INVALID_ARG, "warm bits %d outside [0, 31]", warm);
+    if (s->block_size != 0 && s->block_size != 64 && s->block_size != 128 && s->block_size != 256)
+        return fail(BMPC_ERR_INVALID_ARG, "block_size must be 0, 64, 128 or 256");
+    int variant = s->riccati_variant, block = s->block_size;
+    if (variant == BMPC_RICCATI_AUTO) variant = b->tuned_variant ? b->tuned_variant : BMPC_RICCATI_LEVEL;
+    if (block == 0) block = b->tuned_block ? b->tuned_block : 256;
+    const WgKernel* k = find_wg(block, variant == BMPC_RICCATI_SEGSCAN);
     hipStream_t st = (hipStream_t)stream;
     const SolverCfg cfg = to_cfg(*s, warm);
-    if (s->riccati_variant == BMPC_RICCATI_SEGSCAN) {
-        ProfScope ps("bmpc_solve_workgroup_segscan", st);
-        hipLaunchKernelGGL((k_bmpc_wg<256, true>), dim3(b->count), dim3(256), 0, st, b->d_desc, cfg, b->d_out,
-                           b->d_bad, b->d_hist, b->hist_cap);
-    } else {
-        ProfScope ps("bmpc_solve_workgroup_level", st);
-        hipLaunchKernelGGL((k_bmpc_wg<256, false>), dim3(b->count), dim3(256), 0, st, b->d_desc, cfg, b->d_out,
-                           b->d_bad, b->d_hist, b->hist_cap);
+    {
+        ProfScope ps(k->name, st);
+        hipLaunchKernelGGL(k->fn, dim3(b->count), dim3(k->block), 0, st, b->d_desc, cfg, b->d_out, b->d_bad,
+                           b->d_hist, b->hist_cap);
     }
     BMPC_HIP_TRY(hipGetLastError());
     return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_batch_tune(bmpc_batch* b, const bmpc_settings* s, int32_t warm, int32_t reps,
+                                     int32_t* variant_out, int32_t* block_out, double* ms_out, void* stream)
+{
+    if (!b || !s) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    if (reps < 1 || reps > 100) return fail(BMPC_ERR_INVALID_ARG, "reps must be in [1, 100]");
+    if (warm < 0 || warm > 31) return fail(BMPC_ERR_INVALID_ARG, "warm bits %d outside [0, 31]", warm);
+    if (s->n_alpha < 1 || s->n_alpha > NALPHA_MAX)
+        return fail(BMPC_ERR_INVALID_ARG, "n_alpha must be in [1, %d]", NALPHA_MAX);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = sizeof(double) * (size_t)b->total_nodes * 15;
+    double* saved = nullptr;
+    if (hipMalloc(&saved, bytes) != hipSuccess) return fail(BMPC_ERR_OOM, "no memory to save the batch state");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bmpc_status rc = BMPC_OK;
+    const SolverCfg cfg = to_cfg(*s, warm);
+    const WgKernel* best = nullptr;
+    double best_ms = INFINITY;
+    int idx = 0;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+        hipMemcpyAsync(saved, b->d_state, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        rc = fail(BMPC_ERR_HIP, "setting up the tuning runs failed");
+        goto out;
+    }
+    for (const auto& k : kWgKernels) {
+        double tot = 0.0;
+        for (int r = 0; r < reps; ++r) {
+            float ms = 0.f;
+            if (hipMemcpyAsync(b->d_state, saved, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipEventRecord(e0, st) != hipSuccess) {
+                rc = fail(BMPC_ERR_HIP, "tuning run failed");
+                goto out;
+            }
+            hipLaunchKernelGGL(k.fn, dim3(b->count), dim3(k.block), 0, st, b->d_desc, cfg, b->d_out, b->d_bad,
+                               b->d_hist, b->hist_cap);
+            if (hipGetLastError() != hipSuccess || hipEventRecord(e1, st) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = fail(BMPC_ERR_HIP, "tuning run of %s failed", k.name);
+                goto out;
+            }
+            tot += ms;
+        }
+        const double avg = tot / reps;
+        if (ms_out) ms_out[idx] = avg;
+        if (avg < best_ms) {
+            best_ms = avg;
+            best = &k;
+        }
+        ++idx;
+    }
+    b->tuned_variant = best->segscan ? BMPC_RICCATI_SEGSCAN : BMPC_RICCATI_LEVEL;
+    b->tuned_block = best->block;
+    if (variant_out) *variant_out = b->tuned_variant;
+    if (block_out) *block_out = b->tuned_block;
+out:
+    if (hipMemcpyAsync(b->d_state, saved, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        if (rc == BMPC_OK) rc = fail(BMPC_ERR_HIP, "restoring the batch state failed");
+    }
+    (void)hipFree(saved);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
+}
+
+BMPC_API int32_t bmpc_batch_tune_candidates(int32_t* variants, int32_t* blocks, int32_t cap)
+{
+    int n = 0;
+    for (const auto& k : kWgKernels) {
+        if (n < cap) {
+            if (variants) variants[n] = k.segscan ? BMPC_RICCATI_SEGSCAN : BMPC_RICCATI_LEVEL;
+            if (blocks) blocks[n] = k.block;
+        }
+        ++n;
+    }
+    return n;
 }
 
 BMPC_API bmpc_status bmpc_batch_stats(bmpc_batch* b, bmpc_stats* stats, void* stream)

@@ -141,10 +141,15 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const ui
             }
 }
 
-__global__ void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, long n)
+// Network input: bf16((x - shift_c) * scale_c) for column c (FP32 affine
+// map first, so standardisation happens before the rounding).
+__global__ void k_input_bf16(const float* __restrict__ x, const float* __restrict__ shift,
+                             const float* __restrict__ scale, uint16_t* __restrict__ y, long n, int cols)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = f2bf(x[i]);
+    if (i >= n) return;
+    const int c = (int)(i % cols);
+    y[i] = f2bf((x[i] - shift[c]) * scale[c]);
 }
 
 // dY = 2 (Y - T) / (B * N) in bf16; per-block partial sums of (Y - T)^2
@@ -229,6 +234,8 @@ struct bmpc_mlp {
     std::vector<uint16_t*> dz;   // dZ_l bf16, B x w_l (l >= 1)
     float* partial = nullptr;
     float* loss = nullptr;
+    float* in_shift = nullptr;  // w_0: input affine map (x - shift) * scale
+    float* in_scale = nullptr;
     long step = 0;
 };
 
@@ -236,7 +243,8 @@ static bmpc_status mlp_forward_impl(bmpc_mlp* net, const float* X, int B, hipStr
 {
     const int L = net->L;
     const long nin = (long)B * net->w[0];
-    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((nin + 255) / 256)), dim3(256), 0, s, X, net->act[0], nin);
+    hipLaunchKernelGGL(k_input_bf16, dim3((unsigned)((nin + 255) / 256)), dim3(256), 0, s, X, net->in_shift,
+                       net->in_scale, net->act[0], nin, net->w[0]);
     for (int l = 0; l < L; ++l) {
         const int K = net->w[l], N = net->w[l + 1];
         dim3 grid((N + 63) / 64, (B + 63) / 64);
@@ -318,6 +326,8 @@ BMPC_API bmpc_status bmpc_mlp_create(const int32_t* widths, int32_t n_layers, in
               hipMalloc(&net->v, sizeof(float) * off) == hipSuccess &&
               hipMalloc(&net->pbf, sizeof(uint16_t) * off) == hipSuccess &&
               hipMalloc(&net->loss, sizeof(float)) == hipSuccess &&
+              hipMalloc(&net->in_shift, sizeof(float) * widths[0]) == hipSuccess &&
+              hipMalloc(&net->in_scale, sizeof(float) * widths[0]) == hipSuccess &&
               hipMalloc(&net->partial, sizeof(float) * (((long)max_batch * widths[n_layers] + 255) / 256 + 1)) ==
                   hipSuccess;
     net->act.assign(n_layers + 1, nullptr);
@@ -334,7 +344,10 @@ BMPC_API bmpc_status bmpc_mlp_create(const int32_t* widths, int32_t n_layers, in
         bmpc_mlp_destroy(net);
         return fail(BMPC_ERR_OOM, "device allocation for the network failed");
     }
-    if (hipMemset(net->p, 0, sizeof(float) * off) != hipSuccess ||
+    std::vector<float> ones(widths[0], 1.0f);
+    if (hipMemset(net->in_shift, 0, sizeof(float) * widths[0]) != hipSuccess ||
+        hipMemcpy(net->in_scale, ones.data(), sizeof(float) * widths[0], hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(net->p, 0, sizeof(float) * off) != hipSuccess ||
         hipMemset(net->m, 0, sizeof(float) * off) != hipSuccess ||
         hipMemset(net->v, 0, sizeof(float) * off) != hipSuccess ||
         hipMemset(net->pbf, 0, sizeof(uint16_t) * off) != hipSuccess) {
@@ -355,6 +368,8 @@ BMPC_API void bmpc_mlp_destroy(bmpc_mlp* net)
     (void)hipFree(net->pbf);
     (void)hipFree(net->loss);
     (void)hipFree(net->partial);
+    (void)hipFree(net->in_shift);
+    (void)hipFree(net->in_scale);
     for (auto* a : net->act) (void)hipFree(a);
     for (auto* a : net->z) (void)hipFree(a);
     for (auto* a : net->dz) (void)hipFree(a);
@@ -375,6 +390,17 @@ BMPC_API bmpc_status bmpc_mlp_set_params(bmpc_mlp* net, const float* params)
     BMPC_HIP_TRY(hipMemset(net->m, 0, sizeof(float) * net->nparam));
     BMPC_HIP_TRY(hipMemset(net->v, 0, sizeof(float) * net->nparam));
     net->step = 0;
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_mlp_set_input_map(bmpc_mlp* net, const float* shift, const float* scale)
+{
+    if (!net || !shift || !scale) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    for (int c = 0; c < net->w[0]; ++c)
+        if (!std::isfinite(shift[c]) || !std::isfinite(scale[c]))
+            return fail(BMPC_ERR_NONFINITE, "input map entry %d is not finite", c);
+    BMPC_HIP_TRY(hipMemcpy(net->in_shift, shift, sizeof(float) * net->w[0], hipMemcpyHostToDevice));
+    BMPC_HIP_TRY(hipMemcpy(net->in_scale, scale, sizeof(float) * net->w[0], hipMemcpyHostToDevice));
     return BMPC_OK;
 }
 

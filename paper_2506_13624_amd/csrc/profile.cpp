@@ -60,6 +60,9 @@ bool profiling_enabled() { return g_on; }
 ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), s_(s)
 {
     if (!g_on) return;
+    // no event pairs inside a stream capture: they would become graph nodes
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> lk(g_mu);
     a_ = take_event();
     if (a_) (void)hipEventRecord(a_, s_);

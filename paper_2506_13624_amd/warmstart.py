@@ -18,9 +18,10 @@ adjoint sweep (warm bits 8 | 4), and the guard (bit 16) keeps the cold start
 when the predicted one is worse by max(KKT residual, violation).
 
 Network training and inference run in the library's BF16 matrix-core
-kernels (bmpc_mlp_*).  Input and target standardisation is folded into the
-first and last layers of the inference network, so inference is the GEMM
-chain alone.  This module is data handling around those calls.
+kernels (bmpc_mlp_*).  The inference network takes raw features: input
+standardisation is its FP32 input map and target de-standardisation is
+folded into its last layer.  This module is data handling around those
+calls.
 """
 from __future__ import annotations
 
@@ -143,8 +144,8 @@ def join_params(Ws, bs):
 
 class WarmStarter:
     """Trains the network on standardised data and serves raw-unit
-    predictions through an inference network with the standardisation
-    folded into its first and last layers."""
+    predictions through an inference network that standardises its input
+    and de-standardises its output itself."""
 
     def __init__(self, out_width, hidden=HIDDEN, max_batch=1024, seed=0):
         self.widths = [NUM_FEATURES, *hidden, out_width]
@@ -199,18 +200,16 @@ class WarmStarter:
         return log, secs, steps * batch / secs
 
     def _fold(self):
+        """Inference network: input standardisation as the network's FP32
+        input map, target de-standardisation folded into the last layer
+        (t = t_n s + m  =>  W_L s[None, :], b_L s + m)."""
         Ws, bs = split_params(self.widths, L.bmpc_mlp_get_params(self.train_net).astype(np.float64))
-        # x_n = (x - m) / s  =>  x_n W + b = x (W / s[:, None]) + (b - (m / s) W)
-        W0 = Ws[0] / self.x_std[:, None]
-        b0 = bs[0] - (self.x_mean / self.x_std) @ Ws[0]
-        # t = t_n s + m
-        WL = Ws[-1] * self.t_std[None, :]
-        bL = bs[-1] * self.t_std + self.t_mean
-        Ws2 = [W0] + Ws[1:-1] + [WL] if len(Ws) > 1 else [W0 * self.t_std[None, :]]
-        bs2 = [b0] + bs[1:-1] + [bL] if len(bs) > 1 else [b0 * self.t_std + self.t_mean]
+        Ws[-1] = Ws[-1] * self.t_std[None, :]
+        bs[-1] = bs[-1] * self.t_std + self.t_mean
         if self.infer_net is None:
             self.infer_net = L.bmpc_mlp_create(self.widths, self.max_batch)
-        L.bmpc_mlp_set_params(self.infer_net, join_params(Ws2, bs2))
+        L.bmpc_mlp_set_params(self.infer_net, join_params(Ws, bs))
+        L.bmpc_mlp_set_input_map(self.infer_net, self.x_mean, 1.0 / self.x_std)
 
     def predict(self, X_dev, Y_dev, stream=None):
         """Raw-unit outputs for raw features (float32 device tensors)."""
@@ -230,23 +229,37 @@ class WarmStarter:
         return tot / cnt
 
 
-def solve_with_network(pool, insts, starter, settings=None, guarded=True):
-    """Load `insts` into the pool, predict their start points and solve.
-    Returns (stats list, timing dict in ms: network, scatter+solve)."""
+def solve_with_network(pool, insts, starter, settings=None, guarded=True, feats=None):
+    """Predict start points for the problems loaded in the pool (instances
+    `insts`, or raw feature rows `feats`) and solve them.  With `insts` the
+    pool is loaded first.  Returns (stats list, timing dict in ms: network
+    inference, scatter + solve)."""
     import torch
     st = settings or L.bmpc_settings_default()
-    pool.load(insts)
-    X = torch.from_numpy(np.array([features(i) for i in insts], dtype=np.float32)).cuda()
+    if feats is None:
+        pool.load(insts)
+        feats = np.array([features(i) for i in insts])
+    rows = len(feats)
+    X = torch.from_numpy(np.asarray(feats, dtype=np.float32)).cuda()
     width = L.bmpc_problem_output_width(pool.handles[0])
-    Y = torch.empty((len(insts), width), dtype=torch.float32, device="cuda")
+    Y = torch.empty((rows, width), dtype=torch.float32, device="cuda")
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     e[0].record()
     starter.predict(X, Y)
     e[1].record()
-    L.bmpc_batch_start_from_network(pool.batch, Y, len(insts), width)
+    L.bmpc_batch_start_from_network(pool.batch, Y, rows, width)
     L.bmpc_batch_launch(pool.batch, st, warm=WARM_BITS | (GUARD_BIT if guarded else 0))
     e[2].record()
-    stats = L.bmpc_batch_stats(pool.batch, pool.size)[:len(insts)]
+    stats = L.bmpc_batch_stats(pool.batch, pool.size)[:rows]
     torch.cuda.synchronize()
     return stats, {"network_ms": e[0].elapsed_time(e[1]), "solve_ms": e[1].elapsed_time(e[2])}
+
+
+def shifted_features(pool, insts):
+    """Features of the pool's problems after bmpc_batch_shift: the advanced
+    measured state with the instances' scenarios."""
+    F = np.array([features(i) for i in insts])
+    for k, h in enumerate(pool.handles[:len(insts)]):
+        F[k, :4] = L.bmpc_problem_get_x0(h)
+    return F

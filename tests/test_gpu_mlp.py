@@ -170,3 +170,24 @@ def test_batch_bounds_rejected():
         L.bmpc_mlp_set_params(h, np.full(L.bmpc_mlp_num_params(h), np.nan, dtype=np.float32))
     assert e.value.status == 4
     L.bmpc_mlp_destroy(h)
+
+
+def test_input_map_matches_oracle_on_mapped_inputs():
+    """The FP32 input map (x - shift) * scale runs before the BF16 rounding;
+    the same FP32 operations on the host followed by the oracle agree."""
+    B = 29
+    rng = np.random.default_rng(12)
+    p = _params(WIDTHS, rng)
+    X = (rng.normal(0, 1, (B, WIDTHS[0])) * 3 + 20).astype(np.float32)
+    shift = rng.normal(20, 1, WIDTHS[0]).astype(np.float32)
+    scale = rng.uniform(0.2, 2.0, WIDTHS[0]).astype(np.float32)
+    h = _net(WIDTHS, 64, p)
+    L.bmpc_mlp_set_input_map(h, shift, scale)
+    Y = torch.zeros(B * WIDTHS[-1], dtype=torch.float32, device="cuda")
+    L.bmpc_mlp_forward(h, torch.from_numpy(X).cuda(), Y)
+    torch.cuda.synchronize()
+    L.bmpc_mlp_destroy(h)
+    Xm = ((X - shift[None, :]) * scale[None, :]).astype(np.float32)
+    want = oracle.mlp_forward(WIDTHS, p.astype(np.float64), Xm.astype(np.float64), quant=True)
+    got = Y.cpu().numpy().reshape(B, -1).astype(np.float64)
+    assert np.abs(got - want).max() <= 2e-3 * max(1.0, np.abs(want).max())

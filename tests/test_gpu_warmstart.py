@@ -82,9 +82,11 @@ def test_training_loss_decreases(trained):
 
 
 def test_inference_network_folds_standardisation(trained):
-    """The inference network (standardisation folded into the first and last
-    layers, weights re-rounded to BF16) agrees with the training network on
-    standardised data, to the BF16 weight rounding."""
+    """The inference network (input standardisation as its FP32 input map,
+    de-standardisation folded into the last layer, whose weights are rounded
+    to BF16 again) agrees with the training network on standardised data.
+    Rounding the rescaled last-layer weights moves each by 2^-9 relative;
+    over 256 terms that is ~16 x 2^-9 x |a w| ~ 2e-3 standardised units."""
     starter, _ = trained
     insts = [S.learned_topology_instance(300_000 + i) for i in range(64)]
     X = np.array([W.features(i) for i in insts])
@@ -97,7 +99,7 @@ def test_inference_network_folds_standardisation(trained):
     ref = Yn.cpu().numpy() * starter.t_std + starter.t_mean
     err = np.abs(Y.cpu().numpy() - ref) / starter.t_std
     print(f"fold: max standardised deviation {err.max():.3e}", flush=True)
-    assert err.max() < 0.1
+    assert err.max() < 2e-2
 
 
 def test_network_start_matches_oracle_from_same_prediction(trained):
