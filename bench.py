@@ -452,6 +452,82 @@ def run_warmstart(args, torch, L):
     return out
 
 
+def run_large_tree(args, torch, L):
+    """Tree LQR on the 4096-scenario bicycle tree (122,871 nodes): the Gauss-
+    Newton LQR subproblem at the cold start, level-parallel vs segment-scan
+    backward; plus the time per AL inner iteration of the batched solver
+    (one workgroup) on this tree."""
+    import bmpc_synth as S
+    from paper_2506_13624_amd.bicycle import Problem
+
+    inst = S.large_tree(0)
+    par = inst.parent
+    N = len(par)
+    pb = Problem(inst)
+    st0 = L.bmpc_settings_default(max_outer=0)
+    x = torch.zeros(N * 4, dtype=torch.float64, device="cuda")
+    u = torch.zeros(N * 2, dtype=torch.float64, device="cuda")
+    lam = torch.zeros(N * 4, dtype=torch.float64, device="cuda")
+    ye = torch.zeros(N * 5, dtype=torch.float64, device="cuda")
+    L.bmpc_solve(pb.handle, st0, 0, x, u, lam, ye)  # cold start only (rollout + adjoint)
+    A, B, c, Q, R, q, r = (torch.zeros(N * k, dtype=torch.float64, device="cuda") for k in (16, 8, 4, 16, 4, 4, 2))
+    L.bmpc_linearize(pb.handle, x, u, lam, ye, 100.0, A, B, c, Q, R, q, r)
+    # the LQR takes the step Jacobians on the edge into each child
+    pidx = torch.from_numpy(np.maximum(par, 0).astype(np.int64)).cuda()
+    Ae = A.view(N, 16)[pidx].contiguous().view(-1)
+    Be = B.view(N, 8)[pidx].contiguous().view(-1)
+    M = torch.zeros(N * 8, dtype=torch.float64, device="cuda")
+    x0 = torch.zeros(4, dtype=torch.float64, device="cuda")
+    tree = L.bmpc_tree_create(par)
+    plan = L.bmpc_lqr_plan_create(tree, 4, 2, L.LAYOUT_NODE_MAJOR)
+    outs = [torch.empty(N * k, dtype=torch.float64, device="cuda") for k in (4, 2, 4, 8, 2, 16, 4)]
+    alg = lqr_algorithmic(par, 4, 2)
+    res = {}
+    steps = max(20, args.steps // 10)
+    for name, variant, kname in (("level", L.RICCATI_LEVEL, "lqr_backward_level_lane"),
+                                 ("segment_scan", L.RICCATI_SEGSCAN, "lqr_backward_segscan")):
+        def step():
+            L.bmpc_lqr_solve(plan, Ae, Be, c, Q, R, M, q, r, x0, *outs, variant=variant)
+        for _ in range(5):
+            step()
+        torch.cuda.synchronize()
+        status, bad = L.bmpc_lqr_check(plan)
+        L.bmpc_profile_enable(True)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        prof = L.bmpc_profile_read()
+        L.bmpc_profile_enable(False)
+        bwd_us = prof[kname][0] / prof[kname][1] * 1e3
+        tot_us = sum(v[0] for v in prof.values()) / steps * 1e3
+        res[name] = {"backward_us": round(bwd_us, 2), "lqr_solve_us": round(tot_us, 2), "status": int(status),
+                     "backward_GBps": round(alg["bwd_bytes"] / (bwd_us * 1e-6) / 1e9, 2),
+                     "backward_hbm_frac": round(alg["bwd_bytes"] / (bwd_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
+                     "backward_fp64_TFLOPs": round(alg["bwd_flops"] / (bwd_us * 1e-6) / 1e12, 4),
+                     "backward_fp64_frac": round(alg["bwd_flops"] / (bwd_us * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 6),
+                     "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]}
+                                 for k, v in prof.items()}}
+    L.bmpc_lqr_plan_destroy(plan)
+    L.bmpc_tree_destroy(tree)
+    # AL iterations of the workgroup solver on this tree
+    st = L.bmpc_settings_default(max_outer=1, max_inner=5)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    s = L.bmpc_solve(pb.handle, st, 0, x, u, lam, ye)
+    ev[1].record()
+    torch.cuda.synchronize()
+    pb.close()
+    return {"large_tree": {
+        "workload": "bicycle tree, horizon 80, binary branching every 5 stages to stage 55 (4096 scenarios, "
+                    f"{N} nodes, 8191 segments); tree LQR of the Gauss-Newton subproblem at the cold start, nx=4, nu=2",
+        "algorithmic_bytes_backward": alg["bwd_bytes"], "flops_backward": alg["bwd_flops"],
+        "lqr": res,
+        "al_solver_one_workgroup": {"inner_iterations": s["inner_it"],
+                                    "ms_per_inner_iteration": round(ev[0].elapsed_time(ev[1]) / max(s["inner_it"], 1), 3)},
+    }}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -463,6 +539,7 @@ def main():
                     help="launch one 512 MiB copy first (rocprofv3 counter calibration)")
     ap.add_argument("--skip-bmpc", action="store_true")
     ap.add_argument("--skip-warmstart", action="store_true")
+    ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--ws-train", type=int, default=16384, help="training instances of the learned warm start")
     ap.add_argument("--ws-steps", type=int, default=3000, help="training steps (batch 1024)")
     args = ap.parse_args()
@@ -482,6 +559,8 @@ def main():
         out.update(run_bmpc(args, torch, L))
     if not args.skip_bmpc and not args.skip_warmstart:
         out.update(run_warmstart(args, torch, L))
+    if not args.skip_bmpc and not args.skip_large:
+        out.update(run_large_tree(args, torch, L))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_lqr(inst, args.cpu_budget)
     else:

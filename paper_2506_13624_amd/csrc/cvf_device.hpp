@@ -13,6 +13,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "lqr_device.hpp"  // chol_inplace, chol_solve
+
 namespace bmpc {
 
 template <int NX>

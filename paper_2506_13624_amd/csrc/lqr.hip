@@ -28,6 +28,7 @@
 #include <climits>
 
 #include "bmpc_internal.hpp"
+#include "cvf_device.hpp"
 #include "lqr_device.hpp"
 #include "profile.hpp"
 
@@ -159,6 +160,168 @@ __global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgs a, int* arri
         from = n;
         n = par;
         inf = inf_next;
+    }
+}
+
+// ------------------------------------------------------------------------
+// log-depth backward: segment scan of conditional value functions
+// ------------------------------------------------------------------------
+// One wavefront per maximal unbranched segment, with the same dataflow over
+// segments as the level-parallel kernels (the last child segment to reach a
+// branching node merges its children and carries on with the segment that
+// ends there).  Inside a segment the single-child nodes become conditional
+// value functions (Sec. II-A, eqs. sol_min and comb_rule with the corrected
+// signs), one per lane; a Hillis-Steele suffix scan composes every node's
+// element with all elements below it in log2(length) rounds, and applying
+// the value function of the segment's end node then gives every node's
+// (P, p) at once (eq. V_ki_min).  Gains K, k follow from one Riccati step
+// on the child's value (eq. tree_feedback_laws).  Segments longer than 64
+// nodes are done in chunks of 64 from the bottom.
+template <int NX>
+struct ValueLds {
+    double P[NX][NX], p[NX];
+};
+
+template <int NX, int NU, int LAY>
+__global__ void __launch_bounds__(64) k_bwd_seg(TreeDev t, LqrArgs a, int* arrive)
+{
+    __shared__ Cvf<NX> sbuf[2][64];
+    __shared__ ValueLds<NX> sval[64];
+    __shared__ ValueLds<NX> send;
+    __shared__ int sgo;
+    const int lane = threadIdx.x;
+    const int N = t.N;
+    int s = t.seg_of[t.leaves[blockIdx.x]];
+    for (;;) {
+        const int off = t.seg_off[s], len = t.seg_len[s];
+        const int e = t.seg_nodes[off + len - 1];
+        // value function of the segment's bottom node: terminal cost at a
+        // leaf, the exact merge of all children at a branching node
+        if (lane == 0) {
+            const int4 inf = t.info[e];
+            double P[NX][NX], p[NX];
+            if (inf.x == inf.y) {
+                load_value<NX, LAY>(a.Q, a.q, N, e, P, p);
+#pragma unroll
+                for (int i = 0; i < NU * NX; ++i) a.K[lidx<LAY>(e, i, NU * NX, N)] = 0.0;
+#pragma unroll
+                for (int i = 0; i < NU; ++i) a.k[lidx<LAY>(e, i, NU, N)] = 0.0;
+            } else {
+                StageRegs<NX, NU> st;
+                load_stage<NX, NU, LAY>(a, N, e, st);
+                RicAcc<NX, NU> acc;
+                acc.init(st);
+                for (int j = inf.x; j < inf.y; ++j) {
+                    EdgeRegs<NX, NU> ed;
+                    load_edge<NX, NU, LAY, false>(a, N, e, j, ed);
+                    double Pj[NX][NX], pj[NX];
+                    load_value_dev<NX, LAY>(a, N, j, Pj, pj);
+                    acc.add_child(ed, Pj, pj);
+                }
+                double Kn[NU][NX], kn[NU];
+                if (!acc.finish(Kn, kn, P, p)) atomicMin(a.bad, e);
+#pragma unroll
+                for (int i = 0; i < NU; ++i) {
+#pragma unroll
+                    for (int b = 0; b < NX; ++b) a.K[lidx<LAY>(e, i * NX + b, NU * NX, N)] = Kn[i][b];
+                    a.k[lidx<LAY>(e, i, NU, N)] = kn[i];
+                }
+            }
+            if (len == 1 && inf.z >= 0)
+                store_value_dev<NX, LAY>(a, N, e, P, p);
+            else
+                store_value<NX, LAY>(a, N, e, P, p);
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+#pragma unroll
+                for (int j = 0; j < NX; ++j) send.P[i][j] = P[i][j];
+                send.p[i] = p[i];
+            }
+        }
+        __syncthreads();
+        // single-child nodes at positions [0, len-1), bottom chunk first
+        for (int hi = len - 1; hi > 0;) {
+            const int lo = hi > 64 ? hi - 64 : 0;
+            const int cnt = hi - lo;
+            const int pos = lo + lane;
+            const bool act = lane < cnt;
+            const int n = act ? t.seg_nodes[off + pos] : 0;
+            const int j = act ? t.seg_nodes[off + pos + 1] : 0;
+            StageRegs<NX, NU> st;
+            EdgeRegs<NX, NU> ed;
+            if (act) {
+                load_stage<NX, NU, LAY>(a, N, n, st);
+                load_edge<NX, NU, LAY, false>(a, N, n, j, ed);
+                if (!cvf_element<NX, NU>(st.Q, st.R, st.M, st.q, st.r, ed.A, ed.B, ed.c, sbuf[0][lane]))
+                    atomicMin(a.bad, n);
+            }
+            __syncthreads();
+            int cur = 0;
+            for (int span = 1; span < cnt; span <<= 1) {
+                if (act) {
+                    if (lane + span < cnt)
+                        cvf_combine<NX>(sbuf[cur][lane], sbuf[cur][lane + span], sbuf[cur ^ 1][lane]);
+                    else
+                        sbuf[cur ^ 1][lane] = sbuf[cur][lane];
+                }
+                __syncthreads();
+                cur ^= 1;
+            }
+            double P[NX][NX], p[NX];
+            if (act) {
+                cvf_apply_value<NX>(sbuf[cur][lane], send.P, send.p, P, p);
+#pragma unroll
+                for (int i = 0; i < NX; ++i) {
+#pragma unroll
+                    for (int k = 0; k < NX; ++k) sval[lane].P[i][k] = P[i][k];
+                    sval[lane].p[i] = p[i];
+                }
+            }
+            __syncthreads();
+            if (act) {
+                const ValueLds<NX>& ch = lane + 1 < cnt ? sval[lane + 1] : send;
+                double Pc[NX][NX], pc[NX];
+#pragma unroll
+                for (int i = 0; i < NX; ++i) {
+#pragma unroll
+                    for (int k = 0; k < NX; ++k) Pc[i][k] = ch.P[i][k];
+                    pc[i] = ch.p[i];
+                }
+                RicAcc<NX, NU> acc;
+                acc.init(st);
+                acc.add_child(ed, Pc, pc);
+                double Kn[NU][NX], kn[NU], P1[NX][NX], p1[NX];
+                if (!acc.finish(Kn, kn, P1, p1)) atomicMin(a.bad, n);
+#pragma unroll
+                for (int i = 0; i < NU; ++i) {
+#pragma unroll
+                    for (int b = 0; b < NX; ++b) a.K[lidx<LAY>(n, i * NX + b, NU * NX, N)] = Kn[i][b];
+                    a.k[lidx<LAY>(n, i, NU, N)] = kn[i];
+                }
+                if (pos == 0 && t.info[n].z >= 0)
+                    store_value_dev<NX, LAY>(a, N, n, P, p);
+                else
+                    store_value<NX, LAY>(a, N, n, P, p);
+            }
+            __syncthreads();
+            if (lane == 0) send = sval[0];
+            __syncthreads();
+            hi = lo;
+        }
+        // count in at the branching node above the segment
+        const int top = t.seg_nodes[off];
+        const int4 tinf = t.info[top];
+        const int par = tinf.z;
+        if (par < 0) break;
+        if (lane == 0) {
+            wait_own_stores();
+            const int old = atomicAdd(&arrive[par], 1);
+            sgo = old == tinf.w - 1;
+        }
+        __syncthreads();
+        if (!sgo) break;
+        s = t.seg_of[par];
+        __syncthreads();
     }
 }
 
@@ -603,6 +766,7 @@ struct LqrKernels {
     int nx, nu, layout, group;
     void (*bwd_lane)(TreeDev, LqrArgs, int*);
     void (*bwd_wave)(TreeDev, LqrArgs, int*);
+    void (*bwd_seg)(TreeDev, LqrArgs, int*);
     void (*fwd)(TreeDev, LqrArgs);
     void (*costate)(TreeDev, LqrArgs, int*);
 };
@@ -611,9 +775,10 @@ template <int NX, int NU, int LAY, bool LANE>
 static LqrKernels make_k()
 {
     constexpr int G = NX <= 4 ? 4 : (NX <= 8 ? 8 : 16);
-    LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, k_fwd_rows<NX, NU, LAY, G, 3>,
+    LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, nullptr, k_fwd_rows<NX, NU, LAY, G, 3>,
                  k_costate<NX, LAY>};
     if constexpr (LANE) k.bwd_lane = k_bwd_lane<NX, NU, LAY>;
+    if constexpr (NX <= 4) k.bwd_seg = k_bwd_seg<NX, NU, LAY>;
     return k;
 }
 
@@ -650,6 +815,7 @@ BMPC_API int32_t bmpc_lqr_supported(int32_t nx, int32_t nu, int32_t variant)
     const LqrKernels* k = find_kernels(nx, nu, 0);
     if (!k) return 0;
     if (variant == BMPC_RICCATI_AUTO || variant == BMPC_RICCATI_LEVEL) return 1;
+    if (variant == BMPC_RICCATI_SEGSCAN) return k->bwd_seg ? 1 : 0;
     return 0;
 }
 
@@ -713,15 +879,19 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
     if (!pl) return fail(BMPC_ERR_INVALID_ARG, "plan is NULL");
     if (!A || !B || !c || !Q || !R || !M || !q || !r || !x0 || !x || !u || !lam)
         return fail(BMPC_ERR_INVALID_ARG, "NULL input or output array");
-    if (variant != BMPC_RICCATI_AUTO && variant != BMPC_RICCATI_LEVEL)
-        return fail(BMPC_ERR_UNSUPPORTED, "Riccati variant %d is not available for the tree LQR",
-                    variant);
+    if (variant != BMPC_RICCATI_AUTO && variant != BMPC_RICCATI_LEVEL && variant != BMPC_RICCATI_SEGSCAN)
+        return fail(BMPC_ERR_INVALID_ARG, "unknown Riccati variant %d", variant);
+    if (variant == BMPC_RICCATI_SEGSCAN && !pl->kern->bwd_seg)
+        return fail(BMPC_ERR_UNSUPPORTED, "the segment-scan backward pass is compiled for nx <= 4 only");
     hipStream_t s = (hipStream_t)stream;
     LqrArgs a{A, B, c, Q, R, M, q, r, x0, x, u, lam, K ? K : pl->K, k ? k : pl->k,
               P ? P : pl->P, p ? p : pl->p, pl->bad, pl->bad + 1};
     const TreeDev& t = pl->tree->d;
     const int Z = t.num_leaves;
-    if (pl->kern->bwd_lane) {
+    if (variant == BMPC_RICCATI_SEGSCAN) {
+        ProfScope ps("lqr_backward_segscan", s);
+        hipLaunchKernelGGL(pl->kern->bwd_seg, dim3(Z), dim3(64), 0, s, t, a, pl->arrive);
+    } else if (pl->kern->bwd_lane) {
         ProfScope ps("lqr_backward_level_lane", s);
         hipLaunchKernelGGL(pl->kern->bwd_lane, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
     } else {

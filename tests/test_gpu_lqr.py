@@ -152,3 +152,66 @@ def test_lqr_unsupported_dims_rejected():
         assert e.value.status == 9
     finally:
         L.bmpc_tree_destroy(tree)
+
+
+SEG_TREES = dict(TREES)
+SEG_TREES["long_chain"] = S.tree_parent(150, [], 1)         # one segment in 3 chunks of <= 64
+SEG_TREES["long_branches"] = S.tree_parent(90, [2], 3)       # 3 leaf segments of 88 nodes
+SEG_TREES["cfg0_topology"] = S.tree_parent(20, [4], 3)
+
+
+@pytest.mark.parametrize("layout", [L.LAYOUT_NODE_MAJOR, L.LAYOUT_ELEM_MAJOR])
+@pytest.mark.parametrize("dims", [(3, 1), (4, 2)])
+@pytest.mark.parametrize("name", sorted(SEG_TREES))
+def test_lqr_segment_scan_matches_oracle(name, dims, layout):
+    """Log-depth backward pass (segment scan of conditional value functions,
+    exact merges at branching nodes) against the serial oracle."""
+    par = SEG_TREES[name]
+    print(f"segscan tree={name} N={len(par)} dims={dims} layout={layout}", flush=True)
+    inst = S.lqr_on(par, dims[0], dims[1], seed=19, random_cost=True, a_scale=0.03)
+    o = oracle.tree_lqr_inst(inst)
+    g, st, bad = gpu_lqr(inst, layout, variant=L.RICCATI_SEGSCAN)
+    assert st == 0, bad
+    assert_parity(g, o)
+
+
+def test_lqr_segment_scan_large_tree_full_size():
+    """nx=4, nu=2 on the 4096-scenario topology (122,871 nodes, 8,191
+    segments), segment scan against the oracle and the level pass."""
+    par = S.large_tree(0).parent
+    print(f"segscan large tree N={len(par)}", flush=True)
+    inst = S.lqr_on(par, 4, 2, seed=3)
+    o = oracle.tree_lqr_inst(inst)
+    g, st, bad = gpu_lqr(inst, L.LAYOUT_ELEM_MAJOR, variant=L.RICCATI_SEGSCAN)
+    assert st == 0
+    assert_parity(g, o)
+
+
+def test_lqr_segment_scan_deterministic_and_guarded():
+    inst = S.lqr_on(SEG_TREES["long_branches"], 4, 2, seed=5)
+    runs = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR, variant=L.RICCATI_SEGSCAN, repeat=3)
+    for k in runs[0][0]:
+        for r in runs[1:]:
+            assert np.array_equal(runs[0][0][k], r[0][k]), k
+    assert L.bmpc_lqr_supported(4, 2, L.RICCATI_SEGSCAN) == 1
+    assert L.bmpc_lqr_supported(12, 4, L.RICCATI_SEGSCAN) == 0
+    tree = L.bmpc_tree_create(SEG_TREES["fig1b"])
+    plan = L.bmpc_lqr_plan_create(tree, 12, 4, L.LAYOUT_NODE_MAJOR)
+    try:
+        z = torch.zeros(12 * 12 * 12, dtype=torch.float64, device="cuda")
+        with pytest.raises(L.BmpcError) as e:
+            L.bmpc_lqr_solve(plan, z, z, z, z, z, z, z, z, z, z, z, z, variant=L.RICCATI_SEGSCAN)
+        assert e.value.status == 9
+    finally:
+        L.bmpc_lqr_plan_destroy(plan)
+        L.bmpc_tree_destroy(tree)
+
+
+def test_lqr_segment_scan_not_positive_definite_reports_node():
+    par = TREES["fig1b"]
+    inst = S.lqr_on(par, 3, 1, seed=2, random_cost=True)
+    inst.R[5] = -10.0
+    inst.B[7] = 0.0
+    inst.B[8] = 0.0
+    g, st, bad = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR, variant=L.RICCATI_SEGSCAN)
+    assert st == 3 and bad == 5
