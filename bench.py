@@ -33,6 +33,11 @@ FP64_PEAK_TFLOPS = 78.6
 METRIC = "BMPC solves/sec & tree-Riccati nodes/sec at KKT 1e-6, 1 GPU; warm vs cold iters"
 
 
+def progress(msg):
+    """One progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def lqr_algorithmic(parent, nx, nu):
     """Algorithmic bytes and FLOPs of one backward and one forward launch.
 
@@ -367,12 +372,14 @@ def run_warmstart(args, torch, L):
     out = {}
     n_train, n_val, n_test = args.ws_train, 1024, 1024
     t0 = time.perf_counter()
-    Xtr, Ttr, oktr, ittr = W.generate(S.learned_topology_instance(i) for i in range(n_train))
+    Xtr, Ttr, oktr, ittr = W.generate((S.learned_topology_instance(i) for i in range(n_train)),
+                                      progress=lambda d, n: progress(f"generated {d}/{n}") if d % 4096 == 0 else None)
     gen_s = time.perf_counter() - t0
     Xva, Tva, okva, _ = W.generate(S.learned_topology_instance(500_000 + i) for i in range(n_val))
     starter = W.WarmStarter(Ttr.shape[1], max_batch=1024, seed=0)
     log, train_s, rate = starter.fit(Xtr[oktr], Ttr[oktr], steps=args.ws_steps, batch=1024, lr=2e-3,
                                      log_every=max(args.ws_steps // 8, 1))
+    progress(f"trained {args.ws_steps} steps")
     val_loss = starter.loss(Xva[okva], Tva[okva])
     # per-kernel times of training steps (event pairs around every launch)
     xb = torch.from_numpy(((Xtr[:1024] - starter.x_mean) / starter.x_std).astype(np.float32)).cuda()
@@ -554,14 +561,19 @@ def main():
         sys.exit(1)
     from paper_2506_13624_amd import _lib as L
 
+    progress("tree-Riccati microbenchmark")
     out, inst = run_lqr(args, torch, L)
     if not args.skip_bmpc:
+        progress("branch-MPC single and batched solves")
         out.update(run_bmpc(args, torch, L))
     if not args.skip_bmpc and not args.skip_warmstart:
+        progress("learned warm start")
         out.update(run_warmstart(args, torch, L))
     if not args.skip_bmpc and not args.skip_large:
+        progress("large tree")
         out.update(run_large_tree(args, torch, L))
     if not args.no_cpu_baseline:
+        progress("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline_lqr(inst, args.cpu_budget)
     else:
         out["cpu_baseline"] = None

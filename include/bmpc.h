@@ -182,6 +182,9 @@ typedef struct {
     /* threads per problem in batched solves: 64, 128 or 256; 0 = the value
        chosen by bmpc_batch_tune for the batch, else 256 */
     int32_t block_size;
+    /* cap on inner iterations summed over all outer iterations (0 = none);
+       reaching it ends the solve with BMPC_ERR_MAXITER */
+    int32_t max_iter_total;
 } bmpc_settings;
 
 /* Result of one solve.  r_kkt: last KKT residual of the relaxed problem

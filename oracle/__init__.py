@@ -73,7 +73,8 @@ class Settings(C.Structure):
                 ("eta0", C.c_double), ("a_omega", C.c_double), ("b_omega", C.c_double),
                 ("a_eta", C.c_double), ("b_eta", C.c_double), ("rho0", C.c_double),
                 ("mu0", C.c_double), ("armijo_beta", C.c_double), ("n_alpha", C.c_int),
-                ("max_outer", C.c_int), ("max_inner", C.c_int), ("max_ls_fail", C.c_int)]
+                ("max_outer", C.c_int), ("max_inner", C.c_int), ("max_ls_fail", C.c_int),
+                ("max_iter_total", C.c_int)]
 
 
 class Stats(C.Structure):

@@ -71,6 +71,7 @@ typedef struct {
     double eps_tol, tau, omega0, eta0, a_omega, b_omega, a_eta, b_eta;
     double rho0, mu0, armijo_beta;
     int n_alpha, max_outer, max_inner, max_ls_fail;
+    int max_iter_total; /* cap on inner iterations over all outer ones, 0 = none */
 } orc_settings;
 
 typedef struct {

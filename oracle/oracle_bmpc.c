@@ -47,6 +47,7 @@ void orc_settings_default(orc_settings* s)
     s->max_outer = 50;
     s->max_inner = 100;
     s->max_ls_fail = 3;
+    s->max_iter_total = 0;
 }
 
 /* ------------------------------------------------------------------------
@@ -555,6 +556,11 @@ int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm, doub
                 goto done;
             }
             if (r_kkt <= omega || inner >= st->max_inner) break;
+            /* total iteration cap (0 = none): stop before a further step */
+            if (st->max_iter_total > 0 && inner_total >= st->max_iter_total) {
+                status = ORC_ERR_MAXITER;
+                goto done;
+            }
 
             /* search direction: tree LQR in the deviations, delta x_0 = 0 */
             int lst = orc_tree_lqr(N, NX, NU, pb->parent, A, B, c, Q, R, M, q, r, zero_x, dx,

@@ -202,7 +202,8 @@ class bmpc_settings(C.Structure):
                 ("a_eta", C.c_double), ("b_eta", C.c_double), ("rho0", C.c_double),
                 ("mu0", C.c_double), ("armijo_beta", C.c_double), ("n_alpha", C.c_int32),
                 ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("max_ls_fail", C.c_int32),
-                ("riccati_variant", C.c_int32), ("block_size", C.c_int32)]
+                ("riccati_variant", C.c_int32), ("block_size", C.c_int32),
+                ("max_iter_total", C.c_int32)]
 
 
 class bmpc_stats(C.Structure):

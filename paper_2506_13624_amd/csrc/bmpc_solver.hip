@@ -86,7 +86,7 @@ struct InstDesc {
 
 struct SolverCfg {
     double eps_tol, tau, omega0, eta0, a_omega, b_omega, a_eta, b_eta, rho0, mu0, beta;
-    int n_alpha, max_outer, max_inner, max_ls_fail;
+    int n_alpha, max_outer, max_inner, max_ls_fail, max_total;
     int warm;  // bits: 1 x,u given, 2 lam given, 4 ye given, 8 u given (x rolled out), 16 guarded
 };
 
@@ -768,6 +768,11 @@ __global__ void __launch_bounds__(BS) k_bmpc_wg(const InstDesc* __restrict__ ins
                 goto done;
             }
             if (r_kkt <= omega || inner >= cfg.max_inner) break;
+            // total iteration cap (0 = none): stop before a further step
+            if (cfg.max_total > 0 && inner_total >= cfg.max_total) {
+                status = BMPC_ERR_MAXITER;
+                goto done;
+            }
 
             if constexpr (SEGSCAN)
                 pass_riccati_segscan<BS>(I, bad);
@@ -1213,6 +1218,7 @@ static SolverCfg to_cfg(const bmpc_settings& s, int warm)
     c.n_alpha = s.n_alpha;
     c.max_outer = s.max_outer;
     c.max_inner = s.max_inner;
+    c.max_total = s.max_iter_total;
     c.max_ls_fail = s.max_ls_fail;
     c.warm = warm;
     return c;
@@ -1246,6 +1252,7 @@ BMPC_API void bmpc_settings_default(bmpc_settings* s)
     s->max_ls_fail = 3;
     s->riccati_variant = BMPC_RICCATI_AUTO;
     s->block_size = 0;
+    s->max_iter_total = 0;
 }
 
 BMPC_API void bmpc_bicycle_default(bmpc_bicycle_params* p)

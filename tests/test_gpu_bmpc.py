@@ -254,3 +254,45 @@ def test_rollout_start_and_guard_match_oracle():
         assert gs["start"] == os_["start"] and gs["status"] == os_["status"]
         assert gs["inner_it"] == os_["inner_it"]
         assert np.abs(host(x, (N, 4)) - o["x"]).max() <= 1e-5 * max(1.0, np.abs(o["x"]).max())
+
+
+def test_large_tree_iteration_path_follows_oracle():
+    """4096-scenario bicycle tree (122,871 nodes): the first AL inner
+    iterations (KKT residual, accepted step, merit parameter, penalty) and
+    the iterate after them agree with the oracle."""
+    inst = S.large_tree(0)
+    N = inst.num_nodes
+    st = L.bmpc_settings_default(max_outer=1, max_inner=4)
+    pb = Problem(inst)
+    cap = 8
+    b = L.bmpc_batch_create([pb.handle], hist_cap=cap)
+    L.bmpc_batch_launch(b, st)
+    gs = L.bmpc_batch_stats(b, 1)[0]
+    h = L.bmpc_batch_history(b, 0, cap)
+    x = zeros(N, 4)
+    L.bmpc_batch_state(b, 0, x=x)
+    torch.cuda.synchronize()
+    L.bmpc_batch_destroy(b)
+    pb.close()
+    o, os_, oh = oracle.solve(oracle.problem_from_instance(inst),
+                              oracle.default_settings(max_outer=1, max_inner=4))
+    print(f"large tree: gpu inner {gs['inner_it']} r_kkt {gs['r_kkt']:.6e}; oracle inner {os_['inner_it']} "
+          f"r_kkt {os_['r_kkt']:.6e}", flush=True)
+    assert gs["inner_it"] == os_["inner_it"] == 4
+    np.testing.assert_allclose(h[:4, :5], oh[:4, :5], rtol=1e-6)
+    assert gs["r_kkt"] == pytest.approx(os_["r_kkt"], rel=1e-6)
+    assert np.abs(host(x, (N, 4)) - o["x"]).max() <= 1e-6 * max(1.0, np.abs(o["x"]).max())
+
+
+def test_total_iteration_cap_matches_oracle():
+    insts = S.batched_instances(512)[:8]
+    pbs = [Problem(i) for i in insts]
+    b = L.bmpc_batch_create([p.handle for p in pbs])
+    L.bmpc_batch_launch(b, L.bmpc_settings_default(max_iter_total=25))
+    stats = L.bmpc_batch_stats(b, len(insts))
+    L.bmpc_batch_destroy(b)
+    for p in pbs:
+        p.close()
+    for i, inst in enumerate(insts):
+        _, os_, _ = oracle.solve(oracle.problem_from_instance(inst), oracle.default_settings(max_iter_total=25))
+        assert stats[i]["status"] == os_["status"] and stats[i]["inner_it"] == os_["inner_it"] <= 25

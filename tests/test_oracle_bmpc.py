@@ -427,3 +427,16 @@ def test_rollout_start_and_guard():
     hs, hst, _ = oracle.solve(pb, warm={"u": cold["u"], "ye": cold["ye"]}, guarded=True)
     assert hst["start"] == 1 and hst["inner_it"] == wst["inner_it"]
     np.testing.assert_array_equal(hs["x"], ws["x"])
+
+
+def test_total_iteration_cap():
+    inst = S.single_bmpc(0)
+    pb = oracle.problem_from_instance(inst)
+    _, full, fh = oracle.solve(pb)
+    assert full["inner_it"] > 10
+    x, st, h = oracle.solve(pb, oracle.default_settings(max_iter_total=10))
+    assert st["status"] == 5 and st["inner_it"] == 10
+    np.testing.assert_array_equal(h, fh[:10])
+    # a cap above the iterations needed changes nothing
+    _, st2, _ = oracle.solve(pb, oracle.default_settings(max_iter_total=full["inner_it"] + 1))
+    assert st2["status"] == full["status"] and st2["inner_it"] == full["inner_it"]
