@@ -180,7 +180,8 @@ def run_lqr(args, torch, L):
     fwd_ms, fwd_n = prof.get("lqr_forward_paths", (float("nan"), 1))
     bwd_avg_s = bwd_ms / bwd_n / 1e3
     fwd_avg_s = fwd_ms / fwd_n / 1e3
-    srcs = ["paper_2506_13624_amd/csrc/lqr.hip", "paper_2506_13624_amd/csrc/lqr_device.hpp"]
+    srcs = ["paper_2506_13624_amd/csrc/lqr.hip", "paper_2506_13624_amd/csrc/lqr_device.hpp",
+            "paper_2506_13624_amd/csrc/cvf_device.hpp"]
     achieved = alg["bwd_bytes"] / bwd_avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
@@ -306,8 +307,25 @@ def run_bmpc(args, torch, L):
     torch.cuda.synchronize()
     ms_cold_seg = ev0.elapsed_time(ev1)
     s_cold_seg = L.bmpc_batch_stats(b, len(insts))
+    # autotuner: every (backward variant, threads per problem) pair timed on this batch
+    progress("autotuning the batched solver")
+    tv, tb, cand = L.bmpc_batch_tune(b, st, warm=0, reps=1)
+    ev0.record()
+    L.bmpc_batch_launch(b, st)  # AUTO: the tuned pair
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_tuned = ev0.elapsed_time(ev1)
+    s_tuned = L.bmpc_batch_stats(b, len(insts))
+    # the same with a cap of 200 inner iterations per problem
+    st_cap = L.bmpc_settings_default(max_iter_total=200)
+    ev0.record()
+    L.bmpc_batch_launch(b, st_cap)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_cap = ev0.elapsed_time(ev1)
+    s_cap = L.bmpc_batch_stats(b, len(insts))
     # receding-horizon step, then warm and cold solves of the same shifted problems
-    L.bmpc_batch_launch(b, st)  # back to the level-parallel solution at t
+    L.bmpc_batch_launch(b, st)  # back to the solution at t
     torch.cuda.synchronize()
     L.bmpc_batch_shift(b)
     ev0.record()
@@ -322,6 +340,25 @@ def run_bmpc(args, torch, L):
     torch.cuda.synchronize()
     ms_cold2 = ev0.elapsed_time(ev1)
     s_cold2 = L.bmpc_batch_stats(b, len(insts))
+    # closed loop: [shift, warm solve] captured once in a HIP graph, replayed
+    L.bmpc_batch_launch(b, st, warm=7)  # solution of the shifted problems
+    torch.cuda.synchronize()
+    gs = torch.cuda.Stream()
+    L.bmpc_graph_begin(gs)
+    L.bmpc_batch_shift(b, stream=gs)
+    L.bmpc_batch_launch(b, st, warm=7, stream=gs)
+    graph = L.bmpc_graph_end(gs)
+    loop_ms, loop_conv = [], []
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(5):
+        g0.record(gs)
+        L.bmpc_graph_launch(graph, gs)
+        g1.record(gs)
+        ss = L.bmpc_batch_stats(b, len(insts), stream=gs)
+        loop_ms.append(g0.elapsed_time(g1))
+        loop_conv.append(int(sum(x["status"] == 0 for x in ss)))
+    L.bmpc_graph_destroy(graph)
     prof = L.bmpc_profile_read()
     L.bmpc_profile_enable(False)
     nodes = sum(i.num_nodes for i in insts)
@@ -346,6 +383,17 @@ def run_bmpc(args, torch, L):
         "cold_same_shifted_problems": {"ms": round(ms_cold2, 3), "converged": conv(s_cold2),
                                        "mean_inner_it": mean_it(s_cold2),
                                        "solves_per_s": round(conv(s_cold2) / (ms_cold2 / 1e3), 1)},
+        "autotuner": {"chosen": {"variant": "segment_scan" if tv == L.RICCATI_SEGSCAN else "level",
+                                 "threads_per_problem": tb},
+                      "candidates_ms": {f"{'segment_scan' if v == L.RICCATI_SEGSCAN else 'level'}/{blk}": round(t, 3)
+                                        for (v, blk), t in cand.items()}},
+        "cold_tuned": {"ms": round(ms_tuned, 3), "converged": conv(s_tuned), "mean_inner_it": mean_it(s_tuned),
+                       "solves_per_s": round(conv(s_tuned) / (ms_tuned / 1e3), 1)},
+        "cold_tuned_cap_200_iterations": {"ms": round(ms_cap, 3), "converged": conv(s_cap),
+                                          "mean_inner_it": mean_it(s_cap),
+                                          "solves_per_s": round(conv(s_cap) / (ms_cap / 1e3), 1)},
+        "closed_loop_graph_replay": {"captured": "shift + shifted-warm solve", "steps": len(loop_ms),
+                                     "ms_per_step": [round(v, 3) for v in loop_ms], "converged": loop_conv},
         "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]} for k, v in prof.items()},
     }
     if not args.no_cpu_baseline:
