@@ -420,10 +420,13 @@ def run_warmstart(args, torch, L):
     out = {}
     n_train, n_val, n_test = args.ws_train, 1024, 1024
     t0 = time.perf_counter()
-    Xtr, Ttr, oktr, ittr = W.generate((S.learned_topology_instance(i) for i in range(n_train)),
-                                      progress=lambda d, n: progress(f"generated {d}/{n}") if d % 4096 == 0 else None)
+    gen_settings = L.bmpc_settings_default(max_iter_total=300)
+    Xtr, Ttr, oktr, ittr = W.generate((S.learned_topology_instance(i) for i in range(n_train)), pool_size=2048,
+                                      settings=gen_settings,
+                                      progress=lambda d, n: progress(f"generated {d}/{n}") if d % 16384 == 0 else None)
     gen_s = time.perf_counter() - t0
-    Xva, Tva, okva, _ = W.generate(S.learned_topology_instance(500_000 + i) for i in range(n_val))
+    Xva, Tva, okva, _ = W.generate((S.learned_topology_instance(500_000 + i) for i in range(n_val)),
+                                   settings=gen_settings)
     starter = W.WarmStarter(Ttr.shape[1], max_batch=1024, seed=0)
     log, train_s, rate = starter.fit(Xtr[oktr], Ttr[oktr], steps=args.ws_steps, batch=1024, lr=2e-3,
                                      log_every=max(args.ws_steps // 8, 1))
@@ -492,6 +495,7 @@ def run_warmstart(args, torch, L):
                     f"GELU, BF16 weights/activations, FP32 accumulate; trained on {int(oktr.sum())} converged cold "
                     f"solves of {n_train} seeded instances, validated on {int(okva.sum())}, tested on {n_test}",
         "data_generation": {"instances": n_train, "converged": int(oktr.sum()), "seconds": round(gen_s, 2),
+                            "iteration_cap": 300,
                             "mean_inner_it": round(float(ittr[oktr].mean()), 2)},
         "training": {"steps": args.ws_steps, "batch": 1024, "samples_per_s": round(rate, 0),
                      "loss_log": [(int(a), round(float(b), 5)) for a, b in log],
@@ -595,7 +599,7 @@ def main():
     ap.add_argument("--skip-bmpc", action="store_true")
     ap.add_argument("--skip-warmstart", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
-    ap.add_argument("--ws-train", type=int, default=16384, help="training instances of the learned warm start")
+    ap.add_argument("--ws-train", type=int, default=200000, help="training instances of the learned warm start")
     ap.add_argument("--ws-steps", type=int, default=3000, help="training steps (batch 1024)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -719,14 +721,14 @@ __device__ void stash_state(const InstDesc& I, bool save)
 }
 
 // ---------------------------------------------------------------- solver kernel
+// The whole of Alg. 1 for problem idx, run by one workgroup.
 template <int BS, bool SEGSCAN>
-__global__ void __launch_bounds__(BS) k_bmpc_wg(const InstDesc* __restrict__ insts, SolverCfg cfg,
-                                                SolveOut* __restrict__ outs, int* __restrict__ bad_flags,
-                                                double* __restrict__ hist, int hist_cap)
+__device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, int idx, const SolverCfg& cfg,
+                                          SolveOut* __restrict__ outs, int* __restrict__ bad_flags,
+                                          double* __restrict__ hist, int hist_cap, double* sred)
 {
-    __shared__ double sred[3 * NALPHA_MAX * (BS / 64)];
-    const InstDesc I = insts[blockIdx.x];
-    int* bad = bad_flags + blockIdx.x;
+    const InstDesc I = insts[idx];
+    int* bad = bad_flags + idx;
     const int tid = threadIdx.x;
     const int N = I.N;
     if (tid == 0) *bad = INT_MAX;
@@ -895,7 +897,7 @@ __global__ void __launch_bounds__(BS) k_bmpc_wg(const InstDesc* __restrict__ ins
             merit = phi_star;
             ++inner_total;
             if (hist && tid == 0 && nhist < hist_cap) {
-                double* h = hist + ((long)blockIdx.x * hist_cap + nhist) * 6;
+                double* h = hist + ((long)idx * hist_cap + nhist) * 6;
                 h[0] = outer;
                 h[1] = r_kkt;
                 h[2] = a_star;
@@ -955,9 +957,35 @@ done:
         o.rho = rho;
         o.mu = mu;
         o.merit = merit;
-        outs[blockIdx.x] = o;
+        outs[idx] = o;
+    }
+    __syncthreads();
+}
+
+// Persistent batched solver: every workgroup takes the next problem from a
+// queue (problems in decreasing size order) until the queue is empty, so a
+// workgroup that finishes early starts another problem instead of idling
+// while the slowest ones iterate.  Each problem is solved start to end by
+// one workgroup, so results do not depend on the schedule.
+template <int BS, bool SEGSCAN>
+__global__ void __launch_bounds__(BS) k_bmpc_wg(const InstDesc* __restrict__ insts, SolverCfg cfg,
+                                                SolveOut* __restrict__ outs, int* __restrict__ bad_flags,
+                                                double* __restrict__ hist, int hist_cap,
+                                                const int* __restrict__ order, int count, int* queue)
+{
+    __shared__ double sred[3 * NALPHA_MAX * (BS / 64)];
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(queue, 1);
+        __syncthreads();
+        const int q = s_next;
+        __syncthreads();
+        if (q >= count) break;
+        solve_one<BS, SEGSCAN>(insts, order[q], cfg, outs, bad_flags, hist, hist_cap, sred);
     }
 }
+
+__global__ void k_reset_queue(int* queue) { *queue = 0; }
 
 // Linearisation and quadratisation only (row a2), for testing and for
 // callers that bring their own LQR solver.
@@ -1108,6 +1136,8 @@ struct bmpc_batch {
     std::vector<InstDesc> h_desc;
     int tuned_variant = 0;  // set by bmpc_batch_tune (0 = not tuned)
     int tuned_block = 0;
+    int* d_order = nullptr;  // problems by decreasing node count (work queue order)
+    int* d_queue = nullptr;  // next queue position, reset before every solve
 };
 
 // Scatter one row of network outputs per problem into its start point:
@@ -1169,7 +1199,7 @@ __global__ void __launch_bounds__(BS) k_start_from_outputs(const InstDesc* __res
 struct WgKernel {
     int block;
     bool segscan;
-    void (*fn)(const InstDesc*, SolverCfg, SolveOut*, int*, double*, int);
+    void (*fn)(const InstDesc*, SolverCfg, SolveOut*, int*, double*, int, const int*, int, int*);
     const char* name;
 };
 static const WgKernel kWgKernels[] = {
@@ -1186,6 +1216,33 @@ static const WgKernel* find_wg(int block, bool segscan)
     for (const auto& k : kWgKernels)
         if (k.block == block && k.segscan == segscan) return &k;
     return &kWgKernels[2];
+}
+
+// Workgroups that fit on the device at once for this kernel (the persistent
+// grid); never more than the number of problems.
+static int resident_groups(const WgKernel& k, int count)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, long> cache;  // (device, kernel) -> groups
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return count;
+    long cap = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find({dev, (const void*)k.fn});
+        if (it != cache.end()) {
+            cap = it->second;
+        } else {
+            int per_cu = 0, cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k.fn, k.block, 0) != hipSuccess ||
+                per_cu < 1 || cus < 1)
+                return count;
+            cap = (long)per_cu * cus;
+            cache[{dev, (const void*)k.fn}] = cap;
+        }
+    }
+    return (int)(cap < count ? cap : count);
 }
 
 static BikeParams to_dev(const bmpc_bicycle_params& p)
@@ -1228,6 +1285,19 @@ template <class T>
 static bool dalloc(T** p, size_t n)
 {
     return hipMalloc((void**)p, std::max<size_t>(1, n) * sizeof(T)) == hipSuccess;
+}
+
+// Reset the work queue and start the persistent solver kernel (both are
+// plain kernel launches, so the pair can be captured into a graph).
+static bmpc_status launch_solver(bmpc_batch* b, const WgKernel& k, const SolverCfg& cfg, hipStream_t st)
+{
+    const int grid = resident_groups(k, b->count);
+    ProfScope ps(k.name, st);
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, st, b->d_queue);
+    hipLaunchKernelGGL(k.fn, dim3(grid), dim3(k.block), 0, st, b->d_desc, cfg, b->d_out, b->d_bad, b->d_hist,
+                       b->hist_cap, b->d_order, b->count, b->d_queue);
+    BMPC_HIP_TRY(hipGetLastError());
+    return BMPC_OK;
 }
 
 extern "C" {
@@ -1422,6 +1492,7 @@ BMPC_API bmpc_status bmpc_batch_create(bmpc_problem* const* problems, int32_t co
     }
     b->total_nodes = tot;
     bool ok = dalloc(&b->d_desc, count) && dalloc(&b->d_out, count) && dalloc(&b->d_bad, count) &&
+              dalloc(&b->d_order, count) && dalloc(&b->d_queue, 1) &&
               dalloc(&b->d_state, (size_t)tot * 15) && dalloc(&b->d_ws, (size_t)tot * W_NODE) &&
               (hist_cap == 0 || dalloc(&b->d_hist, (size_t)count * hist_cap * 6));
     if (!ok) {
@@ -1464,7 +1535,12 @@ BMPC_API bmpc_status bmpc_batch_create(bmpc_problem* const* problems, int32_t co
         d.max_seg_len = td.max_seg_len;
         d.max_seg_depth = td.max_seg_depth;
     }
-    if (hipMemcpy(b->d_desc, b->h_desc.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice) != hipSuccess) {
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return problems[a]->N > problems[c]->N; });
+    if (hipMemcpy(b->d_desc, b->h_desc.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_order, order.data(), sizeof(int) * count, hipMemcpyHostToDevice) != hipSuccess) {
         bmpc_batch_destroy(b);
         return fail(BMPC_ERR_HIP, "uploading the batch descriptors failed");
     }
@@ -1475,6 +1551,8 @@ BMPC_API bmpc_status bmpc_batch_create(bmpc_problem* const* problems, int32_t co
 BMPC_API void bmpc_batch_destroy(bmpc_batch* b)
 {
     if (!b) return;
+    (void)hipFree(b->d_order);
+    (void)hipFree(b->d_queue);
     (void)hipFree(b->d_desc);
     (void)hipFree(b->d_out);
     (void)hipFree(b->d_bad);
@@ -1501,13 +1579,7 @@ BMPC_API bmpc_status bmpc_batch_launch(bmpc_batch* b, const bmpc_settings* s, in
     const WgKernel* k = find_wg(block, variant == BMPC_RICCATI_SEGSCAN);
     hipStream_t st = (hipStream_t)stream;
     const SolverCfg cfg = to_cfg(*s, warm);
-    {
-        ProfScope ps(k->name, st);
-        hipLaunchKernelGGL(k->fn, dim3(b->count), dim3(k->block), 0, st, b->d_desc, cfg, b->d_out, b->d_bad,
-                           b->d_hist, b->hist_cap);
-    }
-    BMPC_HIP_TRY(hipGetLastError());
-    return BMPC_OK;
+    return launch_solver(b, *k, cfg, st);
 }
 
 BMPC_API bmpc_status bmpc_batch_tune(bmpc_batch* b, const bmpc_settings* s, int32_t warm, int32_t reps,
@@ -1542,9 +1614,7 @@ BMPC_API bmpc_status bmpc_batch_tune(bmpc_batch* b, const bmpc_settings* s, int3
                 rc = fail(BMPC_ERR_HIP, "tuning run failed");
                 goto out;
             }
-            hipLaunchKernelGGL(k.fn, dim3(b->count), dim3(k.block), 0, st, b->d_desc, cfg, b->d_out, b->d_bad,
-                               b->d_hist, b->hist_cap);
-            if (hipGetLastError() != hipSuccess || hipEventRecord(e1, st) != hipSuccess ||
+            if (launch_solver(b, k, cfg, st) != BMPC_OK || hipEventRecord(e1, st) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                 rc = fail(BMPC_ERR_HIP, "tuning run of %s failed", k.name);
                 goto out;

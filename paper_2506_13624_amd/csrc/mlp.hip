@@ -10,6 +10,7 @@
 // dZ_l = (dZ_{l+1} W_l^T) * gelu'(Z_l).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -52,93 +53,171 @@ enum Epi { EPI_GELU = 0, EPI_LINEAR = 1, EPI_GELU_BACK = 2, EPI_STORE = 3 };
 // C = op(A) op(B) for bf16 inputs with fp32 accumulation.
 //   op(A)[m][k] = TA ? A[k*lda + m] : A[m*lda + k]
 //   op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n]
-// Workgroup tile 64 x 64 (four wavefronts of 32 x 32, each 2 x 2 MFMA 16x16
-// tiles), K advanced 16 at a time through LDS.  Out-of-range elements are
-// zero.  Epilogues:
+// One wavefront per 32 x 32 tile of C (2 x 2 MFMA 16x16x16 tiles), so that
+// batch-sized GEMMs still spread over every CU.  K advances 32 at a time
+// through LDS; operands are fetched from global memory as 8-element (16-byte)
+// runs along their contiguous dimension and the next K stage is fetched into
+// registers while the current one is multiplied.  LDS holds A as [m][k] and
+// B as [n][k], so each lane reads its four consecutive k of an MFMA operand
+// with one 8-byte load.  Out-of-range elements are zero.
+// Split K: blockIdx.z takes K range [z*kchunk, (z+1)*kchunk); with more
+// than one split the raw products go to Zout + z*M*ldc (summed later in a
+// fixed order) and the epilogue must be EPI_STORE.
+// Epilogues:
 //   EPI_GELU:      Z = acc + bias (fp32 out), O = bf16(gelu(Z))
 //   EPI_LINEAR:    Z = acc + bias (fp32 out)
 //   EPI_GELU_BACK: O = bf16(acc * gelu'(Zin))
 //   EPI_STORE:     Z = acc (fp32 out)
-template <bool TA, bool TB, int EPI>
-__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
-                                                   const uint16_t* __restrict__ B, int ldb,
-                                                   const float* __restrict__ bias, const float* __restrict__ Zin,
-                                                   float* __restrict__ Zout, uint16_t* __restrict__ O, int ldc)
+constexpr int MLP_MAX_SPLITS = 8;  // split-K factor limit of the weight gradient
+constexpr int GT = 32;       // tile edge
+constexpr int GK = 32;       // K per stage
+constexpr int GLD = GK + 8;  // LDS row stride in elements (80 bytes: 16-byte aligned rows)
+
+struct Run8 {
+    uint4 v;  // 8 bf16
+};
+
+// 8 consecutive elements p[0..7] (valid ones: first `valid`), as one 16-byte
+// load when all are valid and the address is 16-byte aligned
+__device__ __forceinline__ uint4 load_run8(const uint16_t* __restrict__ p, int valid)
 {
-    __shared__ uint16_t sA[64][16 + 4];  // [m][k]
-    __shared__ uint16_t sB[16][64 + 4];  // [k][n]
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    if (valid >= 8 && ((reinterpret_cast<uintptr_t>(p) & 15u) == 0)) return *reinterpret_cast<const uint4*>(p);
+    uint16_t t[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = e < valid ? p[e] : (uint16_t)0;
+    uint4 r;
+    memcpy(&r, t, 16);
+    return r;
+}
+
+template <bool TRANS>
+struct TileLoad {
+    // operand X with logical rows r (m for A, n for B) and reduction index k:
+    //   TRANS == false: X[r*ld + k] (k contiguous),  TRANS == true: X[k*ld + r]
+    // Each lane fetches two runs of 8 per stage.
+    uint4 run[2];
+    __device__ __forceinline__ void fetch(const uint16_t* __restrict__ X, int ld, int rows, int K, int r0, int k0,
+                                          int kend, int lane)
+    {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int c = lane + 64 * e;  // 128 runs of 8 per 32 x 32 tile
+            if (!TRANS) {
+                const int r = r0 + (c >> 2), k = k0 + (c & 3) * 8;
+                const int valid = (r < rows) ? (kend - k) : 0;
+                run[e] = valid > 0 ? load_run8(X + (long)r * ld + k, valid) : make_uint4(0, 0, 0, 0);
+            } else {
+                const int k = k0 + (c >> 2), r = r0 + (c & 3) * 8;
+                const int valid = (k < kend) ? (rows - r) : 0;
+                run[e] = valid > 0 ? load_run8(X + (long)k * ld + r, valid) : make_uint4(0, 0, 0, 0);
+            }
+        }
+        (void)K;
+    }
+    __device__ __forceinline__ void store(uint16_t (*S)[GLD], int lane) const
+    {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int c = lane + 64 * e;
+            if (!TRANS) {
+                *reinterpret_cast<uint4*>(&S[c >> 2][(c & 3) * 8]) = run[e];
+            } else {
+                uint16_t t[8];
+                memcpy(t, &run[e], 16);
+                const int k = c >> 2, r = (c & 3) * 8;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) S[r + q][k] = t[q];
+            }
+        }
+    }
+};
+
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(64) k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
+                                                  const uint16_t* __restrict__ B, int ldb,
+                                                  const float* __restrict__ bias, const float* __restrict__ Zin,
+                                                  float* __restrict__ Zout, uint16_t* __restrict__ O, int ldc,
+                                                  int kchunk)
+{
+    __shared__ __align__(16) uint16_t sA[GT][GLD];  // [m][k]
+    __shared__ __align__(16) uint16_t sB[GT][GLD];  // [n][k]
+    const int lane = threadIdx.x;
+    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
     f32x4_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        // stage A (64 x 16) and B (16 x 64): 4 elements each per thread
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = tid + 256 * e;
-            {
-                const int m = idx >> 4, k = idx & 15;
-                const int gm = m0 + m, gk = k0 + k;
-                uint16_t v = 0;
-                if (gm < M && gk < K) v = TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
-                sA[m][k] = v;
-            }
-            {
-                const int k = idx >> 6, n = idx & 63;
-                const int gk = k0 + k, gn = n0 + n;
-                uint16_t v = 0;
-                if (gk < K && gn < N) v = TB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn];
-                sB[k][n] = v;
-            }
-        }
+    // op(B)[k][n]: with TB the storage is B[n][k] (k contiguous), otherwise B[k][n]
+    TileLoad<TA> la;
+    TileLoad<!TB> lb;
+    if (kbeg < kend) {
+        la.fetch(A, lda, M, K, m0, kbeg, kend, lane);
+        lb.fetch(B, ldb, N, K, n0, kbeg, kend, lane);
+    }
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        la.store(sA, lane);
+        lb.store(sB, lane);
         __syncthreads();
-        // MFMA operands: lane holds A[row = lane%16][k = 4*(lane/16) + 0..3]
-        // and B[k = 4*(lane/16) + 0..3][col = lane%16]
-        const int r = lane & 15, kq = (lane >> 4) * 4;
-        bf16x4_t a[2], b[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            a[i] = bf16x4_t{(short)sA[wm + 16 * i + r][kq], (short)sA[wm + 16 * i + r][kq + 1],
-                            (short)sA[wm + 16 * i + r][kq + 2], (short)sA[wm + 16 * i + r][kq + 3]};
-            b[i] = bf16x4_t{(short)sB[kq][wn + 16 * i + r], (short)sB[kq + 1][wn + 16 * i + r],
-                            (short)sB[kq + 2][wn + 16 * i + r], (short)sB[kq + 3][wn + 16 * i + r]};
+        if (k0 + GK < kend) {  // next stage in flight during the products
+            la.fetch(A, lda, M, K, m0, k0 + GK, kend, lane);
+            lb.fetch(B, ldb, N, K, n0, k0 + GK, kend, lane);
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int kk = 0; kk < GK; kk += 16) {
+            bf16x4_t a[2], b[2];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *reinterpret_cast<const bf16x4_t*>(&sA[16 * i + r][kk + kq]);
+                b[i] = *reinterpret_cast<const bf16x4_t*>(&sB[16 * i + r][kk + kq]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
-    // result: lane holds C[row = 4*(lane/16) + q][col = lane%16], q = 0..3
+    // result: lane holds C[row = 4*(lane/16) + q][col = lane%16] of each 16x16 tile
+    float* Zdst = Zout ? Zout + (long)blockIdx.z * M * ldc : nullptr;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
-                const int gn = n0 + wn + 16 * j + (lane & 15);
+                const int gm = m0 + 16 * i + 4 * (lane >> 4) + q;
+                const int gn = n0 + 16 * j + (lane & 15);
                 if (gm >= M || gn >= N) continue;
                 const long o = (long)gm * ldc + gn;
                 float v = acc[i][j][q];
                 if constexpr (EPI == EPI_GELU) {
                     v += bias[gn];
-                    Zout[o] = v;
+                    Zdst[o] = v;
                     O[o] = f2bf(gelu(v));
                 } else if constexpr (EPI == EPI_LINEAR) {
-                    Zout[o] = v + bias[gn];
+                    Zdst[o] = v + bias[gn];
                 } else if constexpr (EPI == EPI_GELU_BACK) {
                     O[o] = f2bf(v * gelu_grad(Zin[o]));
                 } else {
-                    Zout[o] = v;
+                    Zdst[o] = v;
                 }
             }
+}
+
+// out[i] = sum over s of part[s*n + i], in split order
+__global__ void k_sum_splits(const float* __restrict__ part, int splits, long n, float* __restrict__ out)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float t = part[i];
+    for (int s = 1; s < splits; ++s) t += part[(long)s * n + i];
+    out[i] = t;
 }
 
 // Network input: bf16((x - shift_c) * scale_c) for column c (FP32 affine
@@ -234,6 +313,7 @@ struct bmpc_mlp {
     std::vector<uint16_t*> dz;   // dZ_l bf16, B x w_l (l >= 1)
     float* partial = nullptr;
     float* loss = nullptr;
+    float* gpart = nullptr;     // split-K partial weight gradients
     float* in_shift = nullptr;  // w_0: input affine map (x - shift) * scale
     float* in_scale = nullptr;
     long step = 0;
@@ -247,17 +327,17 @@ static bmpc_status mlp_forward_impl(bmpc_mlp* net, const float* X, int B, hipStr
                        net->in_scale, net->act[0], nin, net->w[0]);
     for (int l = 0; l < L; ++l) {
         const int K = net->w[l], N = net->w[l + 1];
-        dim3 grid((N + 63) / 64, (B + 63) / 64);
+        dim3 grid((N + GT - 1) / GT, (B + GT - 1) / GT, 1);
         const uint16_t* W = net->pbf + net->woff[l];
         const float* b = net->p + net->boff[l];
         if (l < L - 1) {
             ProfScope ps("mlp_gemm_forward", s);
-            hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_GELU>), grid, dim3(256), 0, s, B, N, K, net->act[l], K, W,
-                               N, b, nullptr, net->z[l + 1], net->act[l + 1], N);
+            hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_GELU>), grid, dim3(64), 0, s, B, N, K, net->act[l], K, W,
+                               N, b, nullptr, net->z[l + 1], net->act[l + 1], N, K);
         } else {
             ProfScope ps("mlp_gemm_forward", s);
-            hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_LINEAR>), grid, dim3(256), 0, s, B, N, K, net->act[l],
-                               K, W, N, b, nullptr, net->z[l + 1], nullptr, N);
+            hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_LINEAR>), grid, dim3(64), 0, s, B, N, K, net->act[l],
+                               K, W, N, b, nullptr, net->z[l + 1], nullptr, N, K);
         }
     }
     BMPC_HIP_TRY(hipGetLastError());
@@ -277,20 +357,35 @@ static bmpc_status mlp_backward_impl(bmpc_mlp* net, const float* T, int B, hipSt
         const int K = net->w[l], N = net->w[l + 1];
         // dW_l = A_l^T dZ_{l+1}: (K x B) (B x N)
         {
+            // split the batch (the reduction) so that small weight matrices
+            // still occupy the whole chip; partial products are summed in a
+            // fixed order, so the gradient does not depend on the schedule
+            const int tiles = ((N + GT - 1) / GT) * ((K + GT - 1) / GT);
+            int splits = (512 + tiles - 1) / tiles;
+            splits = std::min(splits, std::max(1, B / 128));
+            splits = std::max(1, std::min(splits, MLP_MAX_SPLITS));
+            const int kchunk = ((B + splits - 1) / splits + GK - 1) / GK * GK;
+            splits = (B + kchunk - 1) / kchunk;
+            dim3 grid((N + GT - 1) / GT, (K + GT - 1) / GT, splits);
+            float* dst = splits > 1 ? net->gpart : net->g + net->woff[l];
             ProfScope ps("mlp_gemm_weight_grad", s);
-            dim3 grid((N + 63) / 64, (K + 63) / 64);
-            hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI_STORE>), grid, dim3(256), 0, s, K, N, B, net->act[l], K,
-                               net->dz[l + 1], N, nullptr, nullptr, net->g + net->woff[l], nullptr, N);
+            hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI_STORE>), grid, dim3(64), 0, s, K, N, B, net->act[l], K,
+                               net->dz[l + 1], N, nullptr, nullptr, dst, nullptr, N, kchunk);
+            if (splits > 1) {
+                const long nel = (long)K * N;
+                hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s, net->gpart,
+                                   splits, nel, net->g + net->woff[l]);
+            }
         }
         hipLaunchKernelGGL(k_colsum_bf16, dim3((N + 255) / 256), dim3(256), 0, s, net->dz[l + 1], B, N,
                            net->g + net->boff[l]);
         if (l > 0) {
             // dZ_l = (dZ_{l+1} W_l^T) * gelu'(Z_l): (B x N) (N x K)
             ProfScope ps("mlp_gemm_input_grad", s);
-            dim3 grid((K + 63) / 64, (B + 63) / 64);
-            hipLaunchKernelGGL((k_gemm_bf16<false, true, EPI_GELU_BACK>), grid, dim3(256), 0, s, B, K, N,
+            dim3 grid((K + GT - 1) / GT, (B + GT - 1) / GT, 1);
+            hipLaunchKernelGGL((k_gemm_bf16<false, true, EPI_GELU_BACK>), grid, dim3(64), 0, s, B, K, N,
                                net->dz[l + 1], N, net->pbf + net->woff[l], N, nullptr, net->z[l], nullptr,
-                               net->dz[l], K);
+                               net->dz[l], K, N);
         }
     }
     BMPC_HIP_TRY(hipGetLastError());
@@ -320,12 +415,15 @@ BMPC_API bmpc_status bmpc_mlp_create(const int32_t* widths, int32_t n_layers, in
         off += widths[l + 1];
     }
     net->nparam = off;
+    long max_wprod = 1;
+    for (int l = 0; l < n_layers; ++l) max_wprod = std::max(max_wprod, (long)widths[l] * widths[l + 1]);
     bool ok = hipMalloc(&net->p, sizeof(float) * off) == hipSuccess &&
               hipMalloc(&net->g, sizeof(float) * off) == hipSuccess &&
               hipMalloc(&net->m, sizeof(float) * off) == hipSuccess &&
               hipMalloc(&net->v, sizeof(float) * off) == hipSuccess &&
               hipMalloc(&net->pbf, sizeof(uint16_t) * off) == hipSuccess &&
               hipMalloc(&net->loss, sizeof(float)) == hipSuccess &&
+              hipMalloc(&net->gpart, sizeof(float) * MLP_MAX_SPLITS * max_wprod) == hipSuccess &&
               hipMalloc(&net->in_shift, sizeof(float) * widths[0]) == hipSuccess &&
               hipMalloc(&net->in_scale, sizeof(float) * widths[0]) == hipSuccess &&
               hipMalloc(&net->partial, sizeof(float) * (((long)max_batch * widths[n_layers] + 255) / 256 + 1)) ==
@@ -368,6 +466,7 @@ BMPC_API void bmpc_mlp_destroy(bmpc_mlp* net)
     (void)hipFree(net->pbf);
     (void)hipFree(net->loss);
     (void)hipFree(net->partial);
+    (void)hipFree(net->gpart);
     (void)hipFree(net->in_shift);
     (void)hipFree(net->in_scale);
     for (auto* a : net->act) (void)hipFree(a);
@@ -471,17 +570,17 @@ BMPC_API bmpc_status bmpc_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint1
 {
     if (!A || !B || !C || M < 1 || N < 1 || K < 1) return fail(BMPC_ERR_INVALID_ARG, "bad GEMM arguments");
     hipStream_t s = (hipStream_t)stream;
-    dim3 grid((N + 63) / 64, (M + 63) / 64);
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, 1);
     const int lda = trans_a ? M : K, ldb = trans_b ? K : N;
     if (!trans_a && !trans_b)
-        hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_STORE>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
-                           nullptr, nullptr, C, nullptr, N);
+        hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_STORE>), grid, dim3(64), 0, s, M, N, K, A, lda, B, ldb,
+                           nullptr, nullptr, C, nullptr, N, K);
     else if (trans_a && !trans_b)
-        hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI_STORE>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
-                           nullptr, nullptr, C, nullptr, N);
+        hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI_STORE>), grid, dim3(64), 0, s, M, N, K, A, lda, B, ldb,
+                           nullptr, nullptr, C, nullptr, N, K);
     else if (!trans_a && trans_b)
-        hipLaunchKernelGGL((k_gemm_bf16<false, true, EPI_STORE>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
-                           nullptr, nullptr, C, nullptr, N);
+        hipLaunchKernelGGL((k_gemm_bf16<false, true, EPI_STORE>), grid, dim3(64), 0, s, M, N, K, A, lda, B, ldb,
+                           nullptr, nullptr, C, nullptr, N, K);
     else
         return fail(BMPC_ERR_UNSUPPORTED, "both operands transposed is not supported");
     BMPC_HIP_TRY(hipGetLastError());

@@ -191,3 +191,28 @@ def test_input_map_matches_oracle_on_mapped_inputs():
     want = oracle.mlp_forward(WIDTHS, p.astype(np.float64), Xm.astype(np.float64), quant=True)
     got = Y.cpu().numpy().reshape(B, -1).astype(np.float64)
     assert np.abs(got - want).max() <= 2e-3 * max(1.0, np.abs(want).max())
+
+
+@pytest.mark.parametrize("B", [256, 512, 1000])
+def test_gradients_split_batch_match_oracle(B):
+    """Large batches split the weight-gradient reduction over several
+    workgroups and sum the parts in a fixed order."""
+    widths = [44, 64, 64, 96]
+    rng = np.random.default_rng(B)
+    p = _params(widths, rng)
+    X = rng.normal(0, 1, (B, widths[0])).astype(np.float32)
+    T = rng.normal(0, 1, (B, widths[-1])).astype(np.float32)
+    h = _net(widths, 1024, p)
+    loss, g = L.bmpc_mlp_gradients(h, torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    _, g2 = L.bmpc_mlp_gradients(h, torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    L.bmpc_mlp_destroy(h)
+    assert np.array_equal(g, g2)  # deterministic
+    oloss, og = oracle.mlp_loss_grad(widths, p.astype(np.float64), X.astype(np.float64), T.astype(np.float64),
+                                     quant=True)
+    assert loss == pytest.approx(oloss, rel=1e-3)
+    off = 0
+    blocks = [widths[l] * widths[l + 1] for l in range(3)] + widths[1:]
+    for i, n in enumerate(blocks):
+        err = np.abs(g[off:off + n].astype(np.float64) - og[off:off + n]).max() / np.abs(og[off:off + n]).max()
+        assert err <= 1e-2, (i, err)
+        off += n
