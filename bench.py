@@ -418,7 +418,7 @@ def run_warmstart(args, torch, L):
     from paper_2506_13624_amd.bicycle import ProblemPool
 
     out = {}
-    n_train, n_val, n_test = args.ws_train, 1024, 1024
+    n_train, n_val, n_test = args.ws_train, 1024, args.ws_test
     t0 = time.perf_counter()
     gen_settings = L.bmpc_settings_default(max_iter_total=300)
     Xtr, Ttr, oktr, ittr = W.generate((S.learned_topology_instance(i) for i in range(n_train)), pool_size=2048,
@@ -448,7 +448,7 @@ def run_warmstart(args, torch, L):
 
     test = [S.learned_topology_instance(1_000_000 + i) for i in range(n_test)]
     pool = ProblemPool(test[0].parent, n_test, first_inst=test[0])
-    st = L.bmpc_settings_default()
+    st = L.bmpc_settings_default(max_iter_total=args.ws_cap)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
     def timed_launch(warm):
@@ -464,25 +464,31 @@ def run_warmstart(args, torch, L):
         conv = [x for x in ss if x["status"] == 0]
         d = {"ms": round(ms, 3), "converged": len(conv), "of": len(ss),
              "mean_inner_it": round(float(np.mean([x["inner_it"] for x in conv])), 2) if conv else None,
+             "total_inner_it": int(sum(x["inner_it"] for x in ss)),
              "solves_per_s": round(len(conv) / (ms / 1e3), 1)}
         if extra:
             d.update(extra)
         return d
 
+    progress("learned warm start: evaluation")
     pool.load(test)
     L.bmpc_batch_launch(pool.batch, st)  # warm-up
     s_cold, ms_cold = timed_launch(0)
-    s_net, t_net = W.solve_with_network(pool, test, starter)
+    feats = np.array([W.features(i) for i in test])
+    s_net, t_net = W.solve_with_network(pool, None, starter, st, feats=feats)
+    s_netu, t_netu = W.solve_with_network(pool, None, starter, st, guarded=False, feats=feats)
+    s_neto, t_neto = W.solve_with_network(pool, None, starter, st, guarded=False, feats=feats,
+                                          with_multipliers=False)
     # one receding-horizon step: shifted warm start vs cold vs network on the
     # same shifted problems
-    pool.load(test)
     L.bmpc_batch_launch(pool.batch, st)
     L.bmpc_batch_shift(pool.batch)
     torch.cuda.synchronize()
     F_shift = W.shifted_features(pool, test)
     s_shift, ms_shift = timed_launch(7)
     s_cold2, ms_cold2 = timed_launch(0)
-    s_net2, t_net2 = W.solve_with_network(pool, test, starter, feats=F_shift)
+    s_net2, t_net2 = W.solve_with_network(pool, test, starter, st, feats=F_shift)
+    s_net2u, t_net2u = W.solve_with_network(pool, test, starter, st, guarded=False, feats=F_shift)
     pool.close()
     starter.close()
 
@@ -504,9 +510,15 @@ def run_warmstart(args, torch, L):
                      "mfma_bf16": {"flops_per_step": step_flops, "gemm_tflops": round(gemm_tflops, 3) if gemm_tflops else None,
                                    "peak_tflops": 2500.0,
                                    "frac": round(gemm_tflops / 2500.0, 5) if gemm_tflops else None}},
-        "fresh_problems": {"cold": summary(s_cold, ms_cold), "network": net_summary(s_net, t_net)},
+        "evaluation": f"{n_test} test problems per launch (persistent queue), at most {args.ws_cap} inner "
+                      "iterations per problem; solves/s counts converged problems over the launch time "
+                      "(network inference included for network starts)",
+        "fresh_problems": {"cold": summary(s_cold, ms_cold), "network_guarded": net_summary(s_net, t_net),
+                           "network_unguarded": net_summary(s_netu, t_netu),
+                           "network_inputs_only": net_summary(s_neto, t_neto)},
         "after_one_shift": {"shifted_warm": summary(s_shift, ms_shift), "cold": summary(s_cold2, ms_cold2),
-                            "network": net_summary(s_net2, t_net2)},
+                            "network_guarded": net_summary(s_net2, t_net2),
+                            "network_unguarded": net_summary(s_net2u, t_net2u)},
     }
     return out
 
@@ -601,6 +613,8 @@ def main():
     ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--ws-train", type=int, default=200000, help="training instances of the learned warm start")
     ap.add_argument("--ws-steps", type=int, default=3000, help="training steps (batch 1024)")
+    ap.add_argument("--ws-test", type=int, default=8192, help="test problems of the learned warm start")
+    ap.add_argument("--ws-cap", type=int, default=300, help="inner-iteration cap in the warm-start evaluation")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",

@@ -283,6 +283,14 @@ BMPC_API bmpc_status bmpc_batch_stats(bmpc_batch* batch, bmpc_stats* stats, void
    (warm start), 0 reads it.  Asynchronous. */
 BMPC_API bmpc_status bmpc_batch_state(bmpc_batch* batch, int32_t i, double* x, double* u, double* lam,
                                       double* ye, int32_t into_batch, void* stream);
+/* The same for all problems at once: x (T x 4), u (T x 2), lam (T x 4),
+   ye (T x 5) DEVICE arrays, T = bmpc_batch_total_nodes, problems
+   concatenated in batch order (problem i starts at row sum_{k<i} N_k).
+   NULL parts are skipped.  Asynchronous. */
+BMPC_API bmpc_status bmpc_batch_state_all(bmpc_batch* batch, double* x, double* u, double* lam, double* ye,
+                                          int32_t into_batch, void* stream);
+/* Total number of nodes over all problems of the batch (0 for NULL). */
+BMPC_API int64_t bmpc_batch_total_nodes(const bmpc_batch* batch);
 /* Receding-horizon step for every problem of the batch, in place: the
    measured state becomes x0' = F(x0, u_0); node n of the next problem stands
    for the old nodes one stage later on the same scenarios (its children), so

@@ -226,6 +226,8 @@ _sig("bmpc_problem_update", _i32, [_vp, _pd, _pd, _pd, _pi32, _pd])
 _sig("bmpc_problem_output_width", _i32, [_vp, _pi32])
 _sig("bmpc_problem_get_x0", _i32, [_vp, _pd])
 _sig("bmpc_batch_start_from_network", _i32, [_vp, _vp, _i32, _i32, _vp])
+_sig("bmpc_batch_state_all", _i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp])
+_sig("bmpc_batch_total_nodes", C.c_int64, [_vp])
 _sig("bmpc_problem_set_x0", _i32, [_vp, _pd])
 _sig("bmpc_solve", _i32, [_vp, C.POINTER(bmpc_settings), _i32, _vp, _vp, _vp, _vp,
                           C.POINTER(bmpc_stats), _vp])
@@ -349,6 +351,15 @@ def bmpc_batch_stats(batch, count, stream=None):
 def bmpc_batch_state(batch, i, x=None, u=None, lam=None, ye=None, into_batch=False, stream=None):
     check(lib.bmpc_batch_state(batch, i, dptr(x), dptr(u), dptr(lam), dptr(ye), 1 if into_batch else 0,
                                stream_ptr(stream)))
+
+
+def bmpc_batch_state_all(batch, x=None, u=None, lam=None, ye=None, into_batch=False, stream=None):
+    check(lib.bmpc_batch_state_all(batch, dptr(x), dptr(u), dptr(lam), dptr(ye), 1 if into_batch else 0,
+                                   stream_ptr(stream)))
+
+
+def bmpc_batch_total_nodes(batch):
+    return int(lib.bmpc_batch_total_nodes(batch))
 
 
 def bmpc_batch_history(batch, i, hist_cap, stream=None):

@@ -1703,6 +1703,30 @@ BMPC_API bmpc_status bmpc_batch_state(bmpc_batch* b, int32_t i, double* x, doubl
     return BMPC_OK;
 }
 
+BMPC_API bmpc_status bmpc_batch_state_all(bmpc_batch* b, double* x, double* u, double* lam, double* ye,
+                                          int32_t into_batch, void* stream)
+{
+    if (!b) return fail(BMPC_ERR_INVALID_ARG, "batch is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t T = (size_t)b->total_nodes;
+    struct {
+        double* ext;
+        double* in;
+        size_t n;
+    } parts[4] = {{x, b->d_state, 4 * T}, {u, b->d_state + 4 * T, 2 * T}, {lam, b->d_state + 6 * T, 4 * T},
+                  {ye, b->d_state + 10 * T, 5 * T}};
+    for (auto& pt : parts) {
+        if (!pt.ext) continue;
+        if (into_batch)
+            BMPC_HIP_TRY(hipMemcpyAsync(pt.in, pt.ext, sizeof(double) * pt.n, hipMemcpyDeviceToDevice, st));
+        else
+            BMPC_HIP_TRY(hipMemcpyAsync(pt.ext, pt.in, sizeof(double) * pt.n, hipMemcpyDeviceToDevice, st));
+    }
+    return BMPC_OK;
+}
+
+BMPC_API int64_t bmpc_batch_total_nodes(const bmpc_batch* b) { return b ? b->total_nodes : 0; }
+
 BMPC_API bmpc_status bmpc_batch_start_from_network(bmpc_batch* b, const float* Y, int32_t rows, int32_t width,
                                                    void* stream)
 {

@@ -529,8 +529,8 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
             wave_sync();
         } else {
             if (!pref) in.load_stage(a, N, n, lane);
-            in.stage_to(sZ, lane);
             if (pref) {
+                in.stage_to(sZ, lane);
                 in.edge_to(sD, lane);  // the only child's P is still in sP
                 if (nsib == 1) {
                     in.load_stage(a, N, par, lane);
@@ -538,22 +538,38 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                 }
                 add_child();
             } else {
-                for (int j = c0; j < c1; ++j) {
-                    Slots<NX * NX> Pv;
-                    Slots<NX> pv;
-                    in.load_edge(a, N, j, lane);
+                // children two at a time: both edges and both value functions
+                // are requested before either is used
+                for (int j = c0; j < c1; j += 2) {
+                    const bool two = j + 1 < c1;
+                    Slots<NX * NX> Pv0, Pv1;
+                    Slots<NX> pv0, pv1;
+                    WaveIn<NX, NU, LAY> in1;
                     const bool keep = (c1 - c0 == 1) && from == j;
+                    in.load_edge(a, N, j, lane);
                     if (!keep) {
-                        Pv.template load_dev<LAY>(a.P, j, N, lane);
-                        pv.template load_dev<LAY>(a.p, j, N, lane);
+                        Pv0.template load_dev<LAY>(a.P, j, N, lane);
+                        pv0.template load_dev<LAY>(a.p, j, N, lane);
                     }
+                    if (two) {
+                        in1.load_edge(a, N, j + 1, lane);
+                        Pv1.template load_dev<LAY>(a.P, j + 1, N, lane);
+                        pv1.template load_dev<LAY>(a.p, j + 1, N, lane);
+                    }
+                    if (j == c0) in.stage_to(sZ, lane);  // stage data requested with the first children
                     wave_sync();
                     in.edge_to(sD, lane);
                     if (!keep) {
-                        Pv.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
-                        pv.each(lane, [&](int e, double v) { sp[e] = v; });
+                        Pv0.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
+                        pv0.each(lane, [&](int e, double v) { sp[e] = v; });
                     }
                     add_child();
+                    if (two) {
+                        in1.edge_to(sD, lane);
+                        Pv1.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
+                        pv1.each(lane, [&](int e, double v) { sp[e] = v; });
+                        add_child();
+                    }
                 }
                 if (nsib == 1) {
                     in.load_stage(a, N, par, lane);

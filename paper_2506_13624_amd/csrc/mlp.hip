@@ -267,14 +267,27 @@ __global__ void k_sum_partials(const float* __restrict__ partial, int n, float s
     if (threadIdx.x == 0) *out = s[0] * scale;
 }
 
-// db[n] = sum_m dZ[m][n] (fixed order: one thread per column)
-__global__ void k_colsum_bf16(const uint16_t* __restrict__ dZ, int M, int N, float* __restrict__ db)
+// db[n] = sum_m dZ[m][n].  A block covers 32 columns with 8 row groups;
+// thread (c, g) sums rows g, g + 8, ... of column c (reads of 32 consecutive
+// columns are coalesced), then the 8 partial sums are added in group order,
+// so the result does not depend on timing.
+__global__ void __launch_bounds__(256) k_colsum_bf16(const uint16_t* __restrict__ dZ, int M, int N,
+                                                     float* __restrict__ db)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    float s = 0.f;
-    for (int m = 0; m < M; ++m) s += bf2f(dZ[(long)m * N + n]);
-    db[n] = s;
+    __shared__ float part[8][33];
+    const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int n = blockIdx.x * 32 + c;
+    float acc = 0.f;
+    if (n < N)
+        for (int m = g; m < M; m += 8) acc += bf2f(dZ[(long)m * N + n]);
+    part[g][c] = acc;
+    __syncthreads();
+    if (g == 0 && n < N) {
+        float t = part[0][c];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) t += part[q][c];
+        db[n] = t;
+    }
 }
 
 // Adam on fp32 master parameters; refreshes the bf16 copy of weights.
@@ -377,7 +390,7 @@ static bmpc_status mlp_backward_impl(bmpc_mlp* net, const float* T, int B, hipSt
                                    splits, nel, net->g + net->woff[l]);
             }
         }
-        hipLaunchKernelGGL(k_colsum_bf16, dim3((N + 255) / 256), dim3(256), 0, s, net->dz[l + 1], B, N,
+        hipLaunchKernelGGL(k_colsum_bf16, dim3((N + 31) / 32), dim3(256), 0, s, net->dz[l + 1], B, N,
                            net->g + net->boff[l]);
         if (l > 0) {
             // dZ_l = (dZ_{l+1} W_l^T) * gelu'(Z_l): (B x N) (N x K)

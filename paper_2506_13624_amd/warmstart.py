@@ -81,15 +81,16 @@ def targets(inst, u, ye) -> np.ndarray:
 
 
 def read_states(pool, count, parts=("u", "ye")):
-    """Copy the batch state of problems 0 .. count-1 to host arrays."""
+    """Copy the batch state of problems 0 .. count-1 to host arrays (one
+    device copy per part for the whole pool)."""
     import torch
     N = pool.N
     dims = {"x": 4, "u": 2, "lam": 4, "ye": 5}
-    dev = {k: torch.empty((count, N * dims[k]), dtype=torch.float64, device="cuda") for k in parts}
-    for i in range(count):
-        L.bmpc_batch_state(pool.batch, i, **{k: dev[k][i] for k in parts})
+    T = L.bmpc_batch_total_nodes(pool.batch)
+    dev = {k: torch.empty(T * dims[k], dtype=torch.float64, device="cuda") for k in parts}
+    L.bmpc_batch_state_all(pool.batch, **dev)
     torch.cuda.synchronize()
-    return {k: dev[k].cpu().numpy().reshape(count, N, dims[k]) for k in parts}
+    return {k: dev[k].cpu().numpy().reshape(pool.size, N, dims[k])[:count] for k in parts}
 
 
 def generate(instances, pool_size=512, settings=None, progress=None):
@@ -98,6 +99,7 @@ def generate(instances, pool_size=512, settings=None, progress=None):
     insts = list(instances)
     st = settings or L.bmpc_settings_default()
     pool = ProblemPool(insts[0].parent, min(pool_size, len(insts)), first_inst=insts[0])
+    ctl, pairs = output_layout(insts[0])
     X, T, ok, its = [], [], [], []
     try:
         for c0 in range(0, len(insts), pool.size):
@@ -106,16 +108,16 @@ def generate(instances, pool_size=512, settings=None, progress=None):
             L.bmpc_batch_launch(pool.batch, st)
             stats = L.bmpc_batch_stats(pool.batch, pool.size)[:len(chunk)]
             s = read_states(pool, len(chunk))
-            for i, inst in enumerate(chunk):
-                X.append(features(inst))
-                T.append(targets(inst, s["u"][i], s["ye"][i]))
-                ok.append(stats[i]["status"] == 0)
-                its.append(stats[i]["inner_it"])
+            X.append(np.array([features(inst) for inst in chunk]))
+            T.append(np.concatenate([s["u"][:, ctl].reshape(len(chunk), -1),
+                                     s["ye"][:, pairs[:, 0], pairs[:, 1]]], axis=1))
+            ok.extend(x["status"] == 0 for x in stats)
+            its.extend(x["inner_it"] for x in stats)
             if progress:
                 progress(c0 + len(chunk), len(insts))
     finally:
         pool.close()
-    return np.array(X), np.array(T), np.array(ok), np.array(its)
+    return np.concatenate(X), np.concatenate(T), np.array(ok), np.array(its)
 
 
 def init_params(widths, seed=0):
@@ -229,10 +231,12 @@ class WarmStarter:
         return tot / cnt
 
 
-def solve_with_network(pool, insts, starter, settings=None, guarded=True, feats=None):
+def solve_with_network(pool, insts, starter, settings=None, guarded=True, feats=None, with_multipliers=True):
     """Predict start points for the problems loaded in the pool (instances
     `insts`, or raw feature rows `feats`) and solve them.  With `insts` the
-    pool is loaded first.  Returns (stats list, timing dict in ms: network
+    pool is loaded first.  The network runs in chunks of its batch limit.
+    with_multipliers=False keeps only the predicted inputs (multipliers
+    start at zero).  Returns (stats list, timing dict in ms: network
     inference, scatter + solve)."""
     import torch
     st = settings or L.bmpc_settings_default()
@@ -246,10 +250,12 @@ def solve_with_network(pool, insts, starter, settings=None, guarded=True, feats=
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     e[0].record()
-    starter.predict(X, Y)
+    for j in range(0, rows, starter.max_batch):
+        starter.predict(X[j:j + starter.max_batch], Y[j:j + starter.max_batch])
     e[1].record()
     L.bmpc_batch_start_from_network(pool.batch, Y, rows, width)
-    L.bmpc_batch_launch(pool.batch, st, warm=WARM_BITS | (GUARD_BIT if guarded else 0))
+    warm = 8 | (4 if with_multipliers else 0) | (GUARD_BIT if guarded else 0)
+    L.bmpc_batch_launch(pool.batch, st, warm=warm)
     e[2].record()
     stats = L.bmpc_batch_stats(pool.batch, pool.size)[:rows]
     torch.cuda.synchronize()
