@@ -132,16 +132,28 @@ struct TileLoad {
     }
 };
 
-template <bool TA, bool TB, int EPI>
-__global__ void __launch_bounds__(64) k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
-                                                  const uint16_t* __restrict__ B, int ldb,
-                                                  const float* __restrict__ bias, const float* __restrict__ Zin,
-                                                  float* __restrict__ Zout, uint16_t* __restrict__ O, int ldc,
-                                                  int kchunk)
+// ordering of one wavefront's own LDS accesses (its LDS operations complete
+// in issue order; only the compiler must not move them)
+__device__ __forceinline__ void wave_lds_sync()
 {
-    __shared__ __align__(16) uint16_t sA[GT][GLD];  // [m][k]
-    __shared__ __align__(16) uint16_t sB[GT][GLD];  // [n][k]
-    const int lane = threadIdx.x;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int GW = 4;  // wavefronts per workgroup, each on every GW-th K stage
+
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(64 * GW) k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
+                                                       const uint16_t* __restrict__ B, int ldb,
+                                                       const float* __restrict__ bias, const float* __restrict__ Zin,
+                                                       float* __restrict__ Zout, uint16_t* __restrict__ O, int ldc,
+                                                       int kchunk)
+{
+    __shared__ __align__(16) uint16_t sA[GW][GT][GLD];  // per wave: [m][k]
+    __shared__ __align__(16) uint16_t sB[GW][GT][GLD];  // per wave: [n][k]
+    __shared__ float red[GW][GT][GT + 1];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
@@ -154,26 +166,27 @@ __global__ void __launch_bounds__(64) k_gemm_bf16(int M, int N, int K, const uin
     // op(B)[k][n]: with TB the storage is B[n][k] (k contiguous), otherwise B[k][n]
     TileLoad<TA> la;
     TileLoad<!TB> lb;
-    if (kbeg < kend) {
-        la.fetch(A, lda, M, K, m0, kbeg, kend, lane);
-        lb.fetch(B, ldb, N, K, n0, kbeg, kend, lane);
+    int k0 = kbeg + w * GK;
+    if (k0 < kend) {
+        la.fetch(A, lda, M, K, m0, k0, kend, lane);
+        lb.fetch(B, ldb, N, K, n0, k0, kend, lane);
     }
     const int r = lane & 15, kq = (lane >> 4) * 4;
-    for (int k0 = kbeg; k0 < kend; k0 += GK) {
-        la.store(sA, lane);
-        lb.store(sB, lane);
-        __syncthreads();
-        if (k0 + GK < kend) {  // next stage in flight during the products
-            la.fetch(A, lda, M, K, m0, k0 + GK, kend, lane);
-            lb.fetch(B, ldb, N, K, n0, k0 + GK, kend, lane);
+    for (; k0 < kend; k0 += GW * GK) {
+        la.store(sA[w], lane);
+        lb.store(sB[w], lane);
+        wave_lds_sync();
+        if (k0 + GW * GK < kend) {  // this wave's next stage in flight during the products
+            la.fetch(A, lda, M, K, m0, k0 + GW * GK, kend, lane);
+            lb.fetch(B, ldb, N, K, n0, k0 + GW * GK, kend, lane);
         }
 #pragma unroll
         for (int kk = 0; kk < GK; kk += 16) {
             bf16x4_t a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                a[i] = *reinterpret_cast<const bf16x4_t*>(&sA[16 * i + r][kk + kq]);
-                b[i] = *reinterpret_cast<const bf16x4_t*>(&sB[16 * i + r][kk + kq]);
+                a[i] = *reinterpret_cast<const bf16x4_t*>(&sA[w][16 * i + r][kk + kq]);
+                b[i] = *reinterpret_cast<const bf16x4_t*>(&sB[w][16 * i + r][kk + kq]);
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -181,33 +194,39 @@ __global__ void __launch_bounds__(64) k_gemm_bf16(int M, int N, int K, const uin
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        __syncthreads();
+        wave_lds_sync();
     }
-    // result: lane holds C[row = 4*(lane/16) + q][col = lane%16] of each 16x16 tile
-    float* Zdst = Zout ? Zout + (long)blockIdx.z * M * ldc : nullptr;
+    // lane holds C[row = 4*(lane/16) + q][col = lane%16] of each 16x16 tile
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int gm = m0 + 16 * i + 4 * (lane >> 4) + q;
-                const int gn = n0 + 16 * j + (lane & 15);
-                if (gm >= M || gn >= N) continue;
-                const long o = (long)gm * ldc + gn;
-                float v = acc[i][j][q];
-                if constexpr (EPI == EPI_GELU) {
-                    v += bias[gn];
-                    Zdst[o] = v;
-                    O[o] = f2bf(gelu(v));
-                } else if constexpr (EPI == EPI_LINEAR) {
-                    Zdst[o] = v + bias[gn];
-                } else if constexpr (EPI == EPI_GELU_BACK) {
-                    O[o] = f2bf(v * gelu_grad(Zin[o]));
-                } else {
-                    Zdst[o] = v;
-                }
-            }
+            for (int q = 0; q < 4; ++q) red[w][16 * i + 4 * (lane >> 4) + q][16 * j + (lane & 15)] = acc[i][j][q];
+    __syncthreads();
+    // the waves' partial tiles summed in wave order; one element per thread
+    // and pass, consecutive threads on consecutive columns
+    float* Zdst = Zout ? Zout + (long)blockIdx.z * M * ldc : nullptr;
+    for (int e = threadIdx.x; e < GT * GT; e += 64 * GW) {
+        const int rr = e / GT, cc = e % GT;
+        const int gm = m0 + rr, gn = n0 + cc;
+        if (gm >= M || gn >= N) continue;
+        float v = red[0][rr][cc];
+#pragma unroll
+        for (int q = 1; q < GW; ++q) v += red[q][rr][cc];
+        const long o = (long)gm * ldc + gn;
+        if constexpr (EPI == EPI_GELU) {
+            v += bias[gn];
+            Zdst[o] = v;
+            O[o] = f2bf(gelu(v));
+        } else if constexpr (EPI == EPI_LINEAR) {
+            Zdst[o] = v + bias[gn];
+        } else if constexpr (EPI == EPI_GELU_BACK) {
+            O[o] = f2bf(v * gelu_grad(Zin[o]));
+        } else {
+            Zdst[o] = v;
+        }
+    }
 }
 
 // out[i] = sum over s of part[s*n + i], in split order
@@ -345,11 +364,11 @@ static bmpc_status mlp_forward_impl(bmpc_mlp* net, const float* X, int B, hipStr
         const float* b = net->p + net->boff[l];
         if (l < L - 1) {
             ProfScope ps("mlp_gemm_forward", s);
-            hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_GELU>), grid, dim3(64), 0, s, B, N, K, net->act[l], K, W,
+            hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_GELU>), grid, dim3(64 * GW), 0, s, B, N, K, net->act[l], K, W,
                                N, b, nullptr, net->z[l + 1], net->act[l + 1], N, K);
         } else {
             ProfScope ps("mlp_gemm_forward", s);
-            hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_LINEAR>), grid, dim3(64), 0, s, B, N, K, net->act[l],
+            hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_LINEAR>), grid, dim3(64 * GW), 0, s, B, N, K, net->act[l],
                                K, W, N, b, nullptr, net->z[l + 1], nullptr, N, K);
         }
     }
@@ -382,7 +401,7 @@ static bmpc_status mlp_backward_impl(bmpc_mlp* net, const float* T, int B, hipSt
             dim3 grid((N + GT - 1) / GT, (K + GT - 1) / GT, splits);
             float* dst = splits > 1 ? net->gpart : net->g + net->woff[l];
             ProfScope ps("mlp_gemm_weight_grad", s);
-            hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI_STORE>), grid, dim3(64), 0, s, K, N, B, net->act[l], K,
+            hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI_STORE>), grid, dim3(64 * GW), 0, s, K, N, B, net->act[l], K,
                                net->dz[l + 1], N, nullptr, nullptr, dst, nullptr, N, kchunk);
             if (splits > 1) {
                 const long nel = (long)K * N;
@@ -396,7 +415,7 @@ static bmpc_status mlp_backward_impl(bmpc_mlp* net, const float* T, int B, hipSt
             // dZ_l = (dZ_{l+1} W_l^T) * gelu'(Z_l): (B x N) (N x K)
             ProfScope ps("mlp_gemm_input_grad", s);
             dim3 grid((K + GT - 1) / GT, (B + GT - 1) / GT, 1);
-            hipLaunchKernelGGL((k_gemm_bf16<false, true, EPI_GELU_BACK>), grid, dim3(64), 0, s, B, K, N,
+            hipLaunchKernelGGL((k_gemm_bf16<false, true, EPI_GELU_BACK>), grid, dim3(64 * GW), 0, s, B, K, N,
                                net->dz[l + 1], N, net->pbf + net->woff[l], N, nullptr, net->z[l], nullptr,
                                net->dz[l], K, N);
         }
@@ -586,13 +605,13 @@ BMPC_API bmpc_status bmpc_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint1
     dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, 1);
     const int lda = trans_a ? M : K, ldb = trans_b ? K : N;
     if (!trans_a && !trans_b)
-        hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_STORE>), grid, dim3(64), 0, s, M, N, K, A, lda, B, ldb,
+        hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI_STORE>), grid, dim3(64 * GW), 0, s, M, N, K, A, lda, B, ldb,
                            nullptr, nullptr, C, nullptr, N, K);
     else if (trans_a && !trans_b)
-        hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI_STORE>), grid, dim3(64), 0, s, M, N, K, A, lda, B, ldb,
+        hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI_STORE>), grid, dim3(64 * GW), 0, s, M, N, K, A, lda, B, ldb,
                            nullptr, nullptr, C, nullptr, N, K);
     else if (!trans_a && trans_b)
-        hipLaunchKernelGGL((k_gemm_bf16<false, true, EPI_STORE>), grid, dim3(64), 0, s, M, N, K, A, lda, B, ldb,
+        hipLaunchKernelGGL((k_gemm_bf16<false, true, EPI_STORE>), grid, dim3(64 * GW), 0, s, M, N, K, A, lda, B, ldb,
                            nullptr, nullptr, C, nullptr, N, K);
     else
         return fail(BMPC_ERR_UNSUPPORTED, "both operands transposed is not supported");
