@@ -580,7 +580,7 @@ def run_large_tree(args, torch, L):
                                  for k, v in prof.items()}}
     L.bmpc_lqr_plan_destroy(plan)
     L.bmpc_tree_destroy(tree)
-    # AL iterations of the workgroup solver on this tree
+    # AL iterations on this tree (a single large problem: the whole grid)
     st = L.bmpc_settings_default(max_outer=1, max_inner=5)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     torch.cuda.synchronize()
@@ -594,7 +594,7 @@ def run_large_tree(args, torch, L):
                     f"{N} nodes, 8191 segments); tree LQR of the Gauss-Newton subproblem at the cold start, nx=4, nu=2",
         "algorithmic_bytes_backward": alg["bwd_bytes"], "flops_backward": alg["bwd_flops"],
         "lqr": res,
-        "al_solver_one_workgroup": {"inner_iterations": s["inner_it"],
+        "al_solver_whole_grid": {"inner_iterations": s["inner_it"],
                                     "ms_per_inner_iteration": round(ev[0].elapsed_time(ev[1]) / max(s["inner_it"], 1), 3)},
     }}
 

@@ -65,6 +65,9 @@ enum {
 
 enum { BMPC_LAYOUT_NODE_MAJOR = 0, BMPC_LAYOUT_ELEM_MAJOR = 1 };
 
+/* bmpc_settings.block_size value: one problem solved by the whole grid. */
+enum { BMPC_BLOCK_GRID = -1 };
+
 /* Backward-pass variants of the tree LQR. */
 enum {
     BMPC_RICCATI_AUTO = 0,
@@ -180,7 +183,10 @@ typedef struct {
     double rho0, mu0, armijo_beta;
     int32_t n_alpha, max_outer, max_inner, max_ls_fail, riccati_variant;
     /* threads per problem in batched solves: 64, 128 or 256; 0 = the value
-       chosen by bmpc_batch_tune for the batch, else 256 */
+       chosen by bmpc_batch_tune for the batch, else 256, except that a batch
+       of one problem of at least 16,384 nodes is solved by the whole grid;
+       BMPC_BLOCK_GRID = the whole grid (cooperative launch, level-parallel
+       backward pass; batches of one problem only) */
     int32_t block_size;
     /* cap on inner iterations summed over all outer iterations (0 = none);
        reaching it ends the solve with BMPC_ERR_MAXITER */

@@ -23,6 +23,7 @@ LAYOUT_ELEM_MAJOR = 1
 RICCATI_AUTO = 0
 RICCATI_LEVEL = 1
 RICCATI_SEGSCAN = 2
+BLOCK_GRID = -1
 
 
 class BmpcError(RuntimeError):

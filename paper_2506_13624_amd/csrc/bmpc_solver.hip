@@ -17,6 +17,7 @@
 // walk the stages with a workgroup barrier per stage.  Sums are reduced
 // with a fixed butterfly per wavefront and a fixed-order sum over
 // wavefronts, so results are bitwise reproducible.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -160,15 +161,69 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double* sred)
     __syncthreads();
 }
 
+// Teams of threads that run the solver passes: one workgroup (one problem
+// per workgroup, the batched solver) or the whole grid (one large problem;
+// cooperative launch, so every workgroup is resident and grid-wide
+// synchronisation is safe).  Reductions are deterministic in both: the grid
+// team combines the per-workgroup results in workgroup order.
+template <int BS_>
+struct TeamWG {
+    static constexpr int BS = BS_;
+    static constexpr bool kGrid = false;
+    __device__ static int rank() { return threadIdx.x; }
+    __device__ static int size() { return BS_; }
+    __device__ static void sync() { __syncthreads(); }
+    template <int K, bool MAX>
+    __device__ static void reduce(double (&v)[K], double* sred, double*)
+    {
+        block_reduce<BS_, K, MAX>(v, sred);
+    }
+};
+
+template <int BS_>
+struct TeamGrid {
+    static constexpr int BS = BS_;
+    static constexpr bool kGrid = true;
+    __device__ static int rank() { return blockIdx.x * BS_ + threadIdx.x; }
+    __device__ static int size() { return gridDim.x * BS_; }
+    __device__ static void sync() { cooperative_groups::this_grid().sync(); }
+    // gpart: gridDim.x x K doubles of device memory
+    template <int K, bool MAX>
+    __device__ static void reduce(double (&v)[K], double* sred, double* gpart)
+    {
+        block_reduce<BS_, K, MAX>(v, sred);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < K; ++k) gpart[(long)blockIdx.x * K + k] = v[k];
+        sync();
+        // thread k of every workgroup combines entry k over the workgroups
+        // (same order everywhere), then shares it through LDS
+        if ((int)threadIdx.x < K) {
+            const int k = threadIdx.x;
+            double t = gpart[k];
+            for (int b = 1; b < (int)gridDim.x; ++b) {
+                const double o = gpart[(long)b * K + k];
+                t = MAX ? ((t != t || o != o) ? NAN : fmax(t, o)) : t + o;
+            }
+            sred[k] = t;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = sred[k];
+        __syncthreads();
+        sync();  // partials may be overwritten by the next reduction
+    }
+};
+
 // ---------------------------------------------------------------- passes
 // Linearise dynamics, quadratise L_a; returns this thread's partial L_a and
 // constraint violation.
-template <int BS>
+template <class T>
 __device__ void pass_linearise(const InstDesc& I, double rho, double& La, double& viol)
 {
     La = 0.0;
     viol = 0.0;
-    for (int n = threadIdx.x; n < I.N; n += BS) {
+    for (int n = T::rank(); n < I.N; n += T::size()) {
         const NodeData nd = node_data(I, n);
         double x[BX], u[BU], ye[BG];
         load4(I.x + n * 4, x);
@@ -215,13 +270,13 @@ __device__ void pass_linearise(const InstDesc& I, double rho, double& La, double
 
 // Defects and KKT residual (needs the linearisation of the parents):
 // returns partial max residual and partial sums lam.d, |d|^2.
-template <int BS>
+template <class T>
 __device__ void pass_defects_kkt(const InstDesc& I, double& rk, double& ld, double& dd)
 {
     rk = 0.0;
     ld = 0.0;
     dd = 0.0;
-    for (int n = threadIdx.x; n < I.N; n += BS) {
+    for (int n = T::rank(); n < I.N; n += T::size()) {
         double* w = I.ws + (long)n * W_NODE;
         double lam[BX];
         load4(I.lam + n * 4, lam);
@@ -268,12 +323,12 @@ __device__ void pass_defects_kkt(const InstDesc& I, double& rk, double& ld, doub
 
 // Backward tree Riccati, one stage per barrier.  Returns false (and sets
 // *bad) if some H_n is not positive definite.
-template <int BS>
+template <class T>
 __device__ void pass_riccati(const InstDesc& I, int* bad)
 {
     for (int t = I.T; t >= 0; --t) {
         const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
-        for (int n = n0 + (int)threadIdx.x; n < n1; n += BS) {
+        for (int n = n0 + T::rank(); n < n1; n += T::size()) {
             double* w = I.ws + (long)n * W_NODE;
             const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
             if (c0 == c1) {
@@ -335,7 +390,7 @@ __device__ void pass_riccati(const InstDesc& I, int* bad)
                 w[W_PV + i] = p[i];
             }
         }
-        __syncthreads();
+        T::sync();
     }
 }
 
@@ -551,18 +606,223 @@ __device__ void pass_riccati_segscan(const InstDesc& I, int* bad)
     __syncthreads();
 }
 
-// Forward linear rollout of the deviations (delta x_0 = 0) and the LQR
-// costates lam_hat = P dx + p.
+// ---------------------------------------------------------------- LDS passes
+// For problems whose per-node chain values fit in LDS, the stage-by-stage
+// backward and forward passes keep the values that flow from one stage to
+// the next there (P, p and defect c per node for the backward pass; dx for
+// the forward pass) and fetch each thread's inputs for the next stage from
+// HBM while the current stage is computed.  Same arithmetic as the passes
+// above, so the same results bit for bit.
+constexpr int LN = 28;  // doubles per node: P 16, p 4, c 4, dx 4
+constexpr int LN_P = 0, LN_PV = 16, LN_C = 20, LN_DX = 24;
+
+struct RicPre {
+    StageRegs<BX, BU> st;
+    double A[BX][BX], B[BX][BU];
+};
+
+__device__ __forceinline__ void ric_fetch(const InstDesc& I, int n, RicPre& r)
+{
+    const double* w = I.ws + (long)n * W_NODE;
+    stage_from_ws(w, r.st);
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) r.A[i][j] = w[W_A + i * 4 + j];
+#pragma unroll
+        for (int j = 0; j < BU; ++j) r.B[i][j] = w[W_B + i * 2 + j];
+    }
+}
+
+__device__ __forceinline__ void ric_node_lds(const InstDesc& I, int n, const RicPre& r, double* sn, int* bad)
+{
+    double* me = sn + (long)n * LN;
+    const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+    if (c0 == c1) {
+#pragma unroll
+        for (int i = 0; i < BX; ++i) {
+#pragma unroll
+            for (int j = 0; j < BX; ++j) me[LN_P + i * 4 + j] = r.st.Q[i][j];
+            me[LN_PV + i] = r.st.q[i];
+        }
+        return;
+    }
+    RicAcc<BX, BU> acc;
+    acc.init(r.st);
+    EdgeRegs<BX, BU> ed;
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) ed.A[i][j] = r.A[i][j];
+#pragma unroll
+        for (int j = 0; j < BU; ++j) ed.B[i][j] = r.B[i][j];
+    }
+    for (int j = c0; j < c1; ++j) {
+        const double* cj = sn + (long)j * LN;
+        double P[BX][BX], p[BX];
+#pragma unroll
+        for (int i = 0; i < BX; ++i) {
+#pragma unroll
+            for (int k = 0; k < BX; ++k) P[i][k] = cj[LN_P + i * 4 + k];
+            p[i] = cj[LN_PV + i];
+            ed.c[i] = cj[LN_C + i];
+        }
+        acc.add_child(ed, P, p);
+    }
+    double K[BU][BX], k[BU], P[BX][BX], p[BX];
+    if (!acc.finish(K, k, P, p)) atomicMin(bad, n);
+    double* w = I.ws + (long)n * W_NODE;
+#pragma unroll
+    for (int i = 0; i < BU; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) w[W_K + i * 4 + j] = K[i][j];
+        w[W_KV + i] = k[i];
+    }
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) me[LN_P + i * 4 + j] = P[i][j];
+        me[LN_PV + i] = p[i];
+    }
+}
+
+// Workgroup barrier that orders LDS only: it waits for this wave's LDS
+// operations but not for its outstanding global loads, so the next stage's
+// inputs stay in flight across it.  (A full __syncthreads() would drain
+// them.)  Used only where threads exchange data through LDS.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 template <int BS>
-__device__ void pass_forward(const InstDesc& I)
+__device__ void pass_riccati_lds(const InstDesc& I, int* bad, double* sn)
+{
+    for (int n = threadIdx.x; n < I.N; n += BS) {
+        const double* w = I.ws + (long)n * W_NODE;
+#pragma unroll
+        for (int i = 0; i < BX; ++i) sn[(long)n * LN + LN_C + i] = w[W_C + i];
+    }
+    __syncthreads();
+    for (int t = I.T; t >= 0; --t) {
+        const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
+        for (int n = n0 + (int)threadIdx.x; n < n1; n += BS) {
+            RicPre r;
+            ric_fetch(I, n, r);
+            ric_node_lds(I, n, r, sn, bad);
+        }
+        lds_barrier();
+    }
+    __syncthreads();
+}
+
+struct FwdPre {
+    double K[BU][BX], k[BU], A[BX][BX], B[BX][BU];
+};
+
+__device__ __forceinline__ void fwd_fetch(const InstDesc& I, int n, FwdPre& r)
+{
+    const double* w = I.ws + (long)n * W_NODE;
+#pragma unroll
+    for (int i = 0; i < BU; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) r.K[i][j] = w[W_K + i * 4 + j];
+        r.k[i] = w[W_KV + i];
+    }
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) r.A[i][j] = w[W_A + i * 4 + j];
+#pragma unroll
+        for (int j = 0; j < BU; ++j) r.B[i][j] = w[W_B + i * 2 + j];
+    }
+}
+
+__device__ __forceinline__ void fwd_node_lds(const InstDesc& I, int n, const FwdPre& r, double* sn)
+{
+    double* w = I.ws + (long)n * W_NODE;
+    const double* me = sn + (long)n * LN;
+    double dx[BX];
+#pragma unroll
+    for (int i = 0; i < BX; ++i) dx[i] = me[LN_DX + i];
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+        double acc = me[LN_PV + i];
+#pragma unroll
+        for (int j = 0; j < BX; ++j) acc += me[LN_P + i * 4 + j] * dx[j];
+        w[W_LH + i] = acc;
+        w[W_DX + i] = dx[i];
+    }
+    const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+    double du[BU] = {0.0, 0.0};
+    if (c1 > c0) {
+#pragma unroll
+        for (int i = 0; i < BU; ++i) {
+            double acc = r.k[i];
+#pragma unroll
+            for (int j = 0; j < BX; ++j) acc += r.K[i][j] * dx[j];
+            du[i] = acc;
+        }
+        for (int j = c0; j < c1; ++j) {
+            double* cj = sn + (long)j * LN;
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+                double acc = cj[LN_C + i];
+#pragma unroll
+                for (int k = 0; k < BX; ++k) acc += r.A[i][k] * dx[k];
+#pragma unroll
+                for (int k = 0; k < BU; ++k) acc += r.B[i][k] * du[k];
+                cj[LN_DX + i] = acc;
+            }
+        }
+    }
+    w[W_DU] = du[0];
+    w[W_DU + 1] = du[1];
+}
+
+template <int BS>
+__device__ void pass_forward_lds(const InstDesc& I, double* sn)
 {
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int i = 0; i < BX; ++i) I.ws[W_DX + i] = 0.0;
+        for (int i = 0; i < BX; ++i) sn[LN_DX + i] = 0.0;
+    FwdPre buf[2];
+    if (threadIdx.x == 0) fwd_fetch(I, 0, buf[0]);
     __syncthreads();
+    auto stage = [&](int t, FwdPre& cur, FwdPre& nxt) {
+        const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
+        const int n = n0 + (int)threadIdx.x;
+        if (t < I.T) {
+            const int m = n1 + (int)threadIdx.x;
+            if (m < I.level_off[t + 2]) fwd_fetch(I, m, nxt);
+        }
+        if (n < n1) fwd_node_lds(I, n, cur, sn);
+        for (int e = n + BS; e < n1; e += BS) {
+            FwdPre r;
+            fwd_fetch(I, e, r);
+            fwd_node_lds(I, e, r, sn);
+        }
+        lds_barrier();
+    };
+    for (int t = 0; t <= I.T; t += 2) {
+        stage(t, buf[0], buf[1]);
+        if (t + 1 <= I.T) stage(t + 1, buf[1], buf[0]);
+    }
+    __syncthreads();
+}
+
+// Forward linear rollout of the deviations (delta x_0 = 0) and the LQR
+// costates lam_hat = P dx + p.
+template <class T>
+__device__ void pass_forward(const InstDesc& I)
+{
+    if (T::rank() == 0)
+#pragma unroll
+        for (int i = 0; i < BX; ++i) I.ws[W_DX + i] = 0.0;
+    T::sync();
     for (int t = 0; t <= I.T; ++t) {
         const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
-        for (int n = n0 + (int)threadIdx.x; n < n1; n += BS) {
+        for (int n = n0 + T::rank(); n < n1; n += T::size()) {
             double* w = I.ws + (long)n * W_NODE;
             double dx[BX];
             load4(w + W_DX, dx);
@@ -599,18 +859,18 @@ __device__ void pass_forward(const InstDesc& I)
             w[W_DU] = du[0];
             w[W_DU + 1] = du[1];
         }
-        __syncthreads();
+        T::sync();
     }
 }
 
 // Adjoint sweep lam_leaf = q, lam_n = q_n + A_n^T sum_children lam (makes the
 // state gradient of the Lagrangian vanish at the current point).
-template <int BS>
+template <class T>
 __device__ void pass_adjoint(const InstDesc& I)
 {
     for (int t = I.T; t >= 0; --t) {
         const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
-        for (int n = n0 + (int)threadIdx.x; n < n1; n += BS) {
+        for (int n = n0 + T::rank(); n < n1; n += T::size()) {
             const double* w = I.ws + (long)n * W_NODE;
             const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
             double s[BX] = {0.0, 0.0, 0.0, 0.0};
@@ -626,18 +886,18 @@ __device__ void pass_adjoint(const InstDesc& I)
                 I.lam[n * 4 + i] = acc;
             }
         }
-        __syncthreads();
+        T::sync();
     }
 }
 
 // Start point.  warm bits: 1 = x, u given; 8 = u given, x by rollout from
 // x0; 4 = ye given (clamped at zero); 2 = lam given, otherwise lam from the
 // adjoint sweep at the start.  No bit: cold start u = 0 and exact rollout.
-template <int BS>
+template <class T>
 __device__ void build_start(const InstDesc& I, int warm, double rho)
 {
-    const int tid = threadIdx.x, N = I.N;
-    for (int n = tid; n < N; n += BS) {
+    const int tid = T::rank(), N = I.N;
+    for (int n = tid; n < N; n += T::size()) {
         if (!(warm & (1 | 8)) || I.child_off[n] == I.child_off[n + 1]) {
             I.u[n * 2] = 0.0;
             I.u[n * 2 + 1] = 0.0;
@@ -648,49 +908,49 @@ __device__ void build_start(const InstDesc& I, int warm, double rho)
 #pragma unroll
         for (int s = 0; s < BG; ++s) I.ye[n * BG + s] = (warm & 4) ? fmax(I.ye[n * BG + s], 0.0) : 0.0;
     }
-    __syncthreads();
+    T::sync();
     if ((warm & 8) || !(warm & 1)) {
         for (int t = 1; t <= I.T; ++t) {
             const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
-            for (int n = n0 + tid; n < n1; n += BS) {
+            for (int n = n0 + tid; n < n1; n += T::size()) {
                 const int p = I.parent[n];
                 double xp[BX], up[BU] = {I.u[p * 2], I.u[p * 2 + 1]}, xn[BX];
                 load4(I.x + p * 4, xp);
                 bike_step(I.prm, xp, up, xn);
                 store4(I.x + n * 4, xn);
             }
-            __syncthreads();
+            T::sync();
         }
     }
     if (!(warm & 2)) {
         double La, vi;
-        pass_linearise<BS>(I, rho, La, vi);
-        __syncthreads();
-        pass_adjoint<BS>(I);
+        pass_linearise<T>(I, rho, La, vi);
+        T::sync();
+        pass_adjoint<T>(I);
     }
 }
 
 // Quality of a start point: max(KKT residual, constraint violation), with
 // NaN mapped to +inf.
-template <int BS>
-__device__ double start_measure(const InstDesc& I, double rho, double* sred)
+template <class T>
+__device__ double start_measure(const InstDesc& I, double rho, double* sred, double* gpart)
 {
     double La, vi, rk, ld, dd;
-    pass_linearise<BS>(I, rho, La, vi);
-    __syncthreads();
-    pass_defects_kkt<BS>(I, rk, ld, dd);
+    pass_linearise<T>(I, rho, La, vi);
+    T::sync();
+    pass_defects_kkt<T>(I, rk, ld, dd);
     double mx[2] = {rk, vi};
-    block_reduce<BS, 2, true>(mx, sred);
+    T::template reduce<2, true>(mx, sred, gpart);
     if (!(mx[0] == mx[0]) || !(mx[1] == mx[1])) return INFINITY;
     return fmax(mx[0], mx[1]);
 }
 
 // Save (save = true) the caller's x, u, lam, ye into the node workspace
 // slots of the step (dx, du, costate step, scan scratch), or restore them.
-template <int BS>
+template <class T>
 __device__ void stash_state(const InstDesc& I, bool save)
 {
-    for (int n = threadIdx.x; n < I.N; n += BS) {
+    for (int n = T::rank(); n < I.N; n += T::size()) {
         double* w = I.ws + (long)n * W_NODE;
 #pragma unroll
         for (int i = 0; i < BX; ++i) {
@@ -717,19 +977,21 @@ __device__ void stash_state(const InstDesc& I, bool save)
                 I.ye[n * BG + k] = w[W_S0 + k];
         }
     }
-    __syncthreads();
+    T::sync();
 }
 
 // ---------------------------------------------------------------- solver kernel
-// The whole of Alg. 1 for problem idx, run by one workgroup.
-template <int BS, bool SEGSCAN>
+// The whole of Alg. 1 for problem idx, run by team T (one workgroup or the grid).
+template <class T, bool SEGSCAN>
 __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, int idx, const SolverCfg& cfg,
                                           SolveOut* __restrict__ outs, int* __restrict__ bad_flags,
-                                          double* __restrict__ hist, int hist_cap, double* sred)
+                                          double* __restrict__ hist, int hist_cap, double* sred, double* sn,
+                                          int lds_nodes, double* gpart)
 {
     const InstDesc I = insts[idx];
+    const bool in_lds = !SEGSCAN && !T::kGrid && I.N <= lds_nodes;
     int* bad = bad_flags + idx;
-    const int tid = threadIdx.x;
+    const int tid = T::rank();
     const int N = I.N;
     if (tid == 0) *bad = INT_MAX;
 
@@ -741,28 +1003,28 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
     if (cfg.warm & 16) {
         // guarded start: keep the given start only if it is at least as
         // good as the cold one by max(KKT residual, violation) at rho0
-        stash_state<BS>(I, true);
-        build_start<BS>(I, 0, rho);
-        const double m_cold = start_measure<BS>(I, rho, sred);
-        stash_state<BS>(I, false);
-        build_start<BS>(I, cfg.warm & 15, rho);
-        const double m_given = start_measure<BS>(I, rho, sred);
+        stash_state<T>(I, true);
+        build_start<T>(I, 0, rho);
+        const double m_cold = start_measure<T>(I, rho, sred, gpart);
+        stash_state<T>(I, false);
+        build_start<T>(I, cfg.warm & 15, rho);
+        const double m_given = start_measure<T>(I, rho, sred, gpart);
         if (m_cold < m_given) {
-            build_start<BS>(I, 0, rho);
+            build_start<T>(I, 0, rho);
             start_used = 0;
         }
     } else {
-        build_start<BS>(I, cfg.warm, rho);
+        build_start<T>(I, cfg.warm, rho);
     }
 
     for (outer = 0; outer < cfg.max_outer; ++outer) {
         for (int inner = 0;; ++inner) {
             double La_p, vi_p, rk_p, ld_p, dd_p;
-            pass_linearise<BS>(I, rho, La_p, vi_p);
-            __syncthreads();
-            pass_defects_kkt<BS>(I, rk_p, ld_p, dd_p);
+            pass_linearise<T>(I, rho, La_p, vi_p);
+            T::sync();
+            pass_defects_kkt<T>(I, rk_p, ld_p, dd_p);
             double mx[2] = {rk_p, vi_p};
-            block_reduce<BS, 2, true>(mx, sred);
+            T::template reduce<2, true>(mx, sred, gpart);
             r_kkt = mx[0];
             viol = mx[1];
             if (!(r_kkt == r_kkt)) {
@@ -777,18 +1039,31 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             }
 
             if constexpr (SEGSCAN)
-                pass_riccati_segscan<BS>(I, bad);
-            else
-                pass_riccati<BS>(I, bad);
+                pass_riccati_segscan<T::BS>(I, bad);
+            else if constexpr (!T::kGrid) {
+                if (in_lds)
+                    pass_riccati_lds<T::BS>(I, bad, sn);
+                else
+                    pass_riccati<T>(I, bad);
+            } else {
+                pass_riccati<T>(I, bad);
+            }
             if (__hip_atomic_load(bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != INT_MAX) {
                 status = BMPC_ERR_NOT_PD;
                 goto done;
             }
-            pass_forward<BS>(I);
+            if constexpr (!T::kGrid) {
+                if (in_lds)
+                    pass_forward_lds<T::BS>(I, sn);
+                else
+                    pass_forward<T>(I);
+            } else {
+                pass_forward<T>(I);
+            }
 
             // merit slope pieces and the current merit
             double sm[6] = {0.0, 0.0, 0.0, La_p, ld_p, dd_p};
-            for (int n = tid; n < N; n += BS) {
+            for (int n = tid; n < N; n += T::size()) {
                 const double* w = I.ws + (long)n * W_NODE;
                 double dx[BX];
                 load4(w + W_DX, dx);
@@ -810,7 +1085,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
 #pragma unroll
                     for (int i = 0; i < BX; ++i) sm[2] += (w[W_LH + i] - 2.0 * I.lam[n * 4 + i]) * w[W_C + i];
             }
-            block_reduce<BS, 6, false>(sm, sred);
+            T::template reduce<6, false>(sm, sred, gpart);
             const double gtd = sm[0], dhd = sm[1], lhd = sm[2], La0 = sm[3], ld0 = sm[4], dd0 = sm[5];
             if (dd0 > 0.0) {
                 const double mu_hat = (gtd + lhd + 0.5 * dhd) / dd0;
@@ -824,7 +1099,15 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             double tr[3 * NALPHA_MAX];
 #pragma unroll
             for (int e = 0; e < 3 * NALPHA_MAX; ++e) tr[e] = 0.0;
-            for (int n = tid; n < N; n += BS) {
+            // one (node, step size) pair per thread: ten short rollouts in
+            // parallel instead of ten in a row
+            // (node, step size) pairs while the tree is small against the
+            // workgroup, whole nodes (all step sizes in one thread) otherwise
+            const int per = (N * na <= 16 * T::size()) ? 1 : na;
+            for (int it = tid; it < N * na / per; it += T::size())
+            for (int sub = 0; sub < per; ++sub) {
+                const int n = per == 1 ? it / na : it, ka = per == 1 ? it - n * na : sub;
+                const double alpha = ldexp(1.0, -ka);
                 const double* w = I.ws + (long)n * W_NODE;
                 const NodeData nd = node_data(I, n);
                 double x[BX], u[BU], ye[BG], dx[BX];
@@ -835,36 +1118,38 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
 #pragma unroll
                 for (int s = 0; s < BG; ++s) ye[s] = I.ye[n * BG + s];
                 const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
-                double alpha = 1.0;
+                double xt[BX], ut[BU];
 #pragma unroll
-                for (int ka = 0; ka < NALPHA_MAX; ++ka) {
-                    if (ka < na) {
-                        double xt[BX], ut[BU];
+                for (int i = 0; i < BX; ++i) xt[i] = x[i] + alpha * dx[i];
 #pragma unroll
-                        for (int i = 0; i < BX; ++i) xt[i] = x[i] + alpha * dx[i];
+                for (int i = 0; i < BU; ++i) ut[i] = u[i] + alpha * w[W_DU + i];
+                const double v = node_value(I.prm, nd, xt, ut, ye, rho);
+                double ld = 0.0, dd = 0.0;
+                if (c1 > c0) {
+                    double ft[BX];
+                    bike_step(I.prm, xt, ut, ft);
+                    for (int j = c0; j < c1; ++j) {
+                        const double* wj = I.ws + (long)j * W_NODE;
 #pragma unroll
-                        for (int i = 0; i < BU; ++i) ut[i] = u[i] + alpha * w[W_DU + i];
-                        tr[ka] += node_value(I.prm, nd, xt, ut, ye, rho);
-                        if (c1 > c0) {
-                            double ft[BX];
-                            bike_step(I.prm, xt, ut, ft);
-                            for (int j = c0; j < c1; ++j) {
-                                const double* wj = I.ws + (long)j * W_NODE;
-#pragma unroll
-                                for (int i = 0; i < BX; ++i) {
-                                    const double xj = I.x[j * 4 + i] + alpha * wj[W_DX + i];
-                                    const double lj = I.lam[j * 4 + i] + alpha * (wj[W_LH + i] - I.lam[j * 4 + i]);
-                                    const double d = ft[i] - xj;
-                                    tr[NALPHA_MAX + ka] += lj * d;
-                                    tr[2 * NALPHA_MAX + ka] += d * d;
-                                }
-                            }
+                        for (int i = 0; i < BX; ++i) {
+                            const double xj = I.x[j * 4 + i] + alpha * wj[W_DX + i];
+                            const double lj = I.lam[j * 4 + i] + alpha * (wj[W_LH + i] - I.lam[j * 4 + i]);
+                            const double d = ft[i] - xj;
+                            ld += lj * d;
+                            dd += d * d;
                         }
                     }
-                    alpha *= 0.5;
                 }
+                // accumulate into slot ka without dynamic indexing (keeps tr in registers)
+#pragma unroll
+                for (int q = 0; q < NALPHA_MAX; ++q)
+                    if (q == ka) {
+                        tr[q] += v;
+                        tr[NALPHA_MAX + q] += ld;
+                        tr[2 * NALPHA_MAX + q] += dd;
+                    }
             }
-            block_reduce<BS, 3 * NALPHA_MAX, false>(tr, sred);
+            T::template reduce<3 * NALPHA_MAX, false>(tr, sred, gpart);
             double a_star = -1.0, phi_star = NAN, alpha = 1.0;
             for (int ka = 0; ka < na; ++ka, alpha *= 0.5) {
                 const double phi = tr[ka] + tr[NALPHA_MAX + ka] + 0.5 * mu * tr[2 * NALPHA_MAX + ka];
@@ -884,7 +1169,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             } else {
                 ls_run = 0;
             }
-            for (int n = tid; n < N; n += BS) {
+            for (int n = tid; n < N; n += T::size()) {
                 const double* w = I.ws + (long)n * W_NODE;
 #pragma unroll
                 for (int i = 0; i < BX; ++i) {
@@ -906,12 +1191,12 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                 h[5] = phi_star;
                 ++nhist;
             }
-            __syncthreads();
+            T::sync();
         }
 
         // outer update (BCL)
         if (viol <= eta) {
-            for (int n = tid; n < N; n += BS) {
+            for (int n = tid; n < N; n += T::size()) {
                 const NodeData nd = node_data(I, n);
                 double x[BX], u[BU], g[BG], dist, ex, ey;
                 bool on[BG];
@@ -925,7 +1210,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                     I.ye[n * BG + s] = on[s] ? fmax(0.0, y + rho * g[s]) : 0.0;
                 }
             }
-            __syncthreads();
+            T::sync();
             if (fmax(r_kkt, viol) < cfg.eps_tol) {
                 status = BMPC_OK;
                 ++outer;
@@ -942,7 +1227,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
     }
 
 done:
-    __syncthreads();
+    T::sync();
     if (tid == 0) {
         SolveOut o;
         o.status = status;
@@ -959,7 +1244,7 @@ done:
         o.merit = merit;
         outs[idx] = o;
     }
-    __syncthreads();
+    T::sync();
 }
 
 // Persistent batched solver: every workgroup takes the next problem from a
@@ -971,21 +1256,32 @@ template <int BS, bool SEGSCAN>
 __global__ void __launch_bounds__(BS) k_bmpc_wg(const InstDesc* __restrict__ insts, SolverCfg cfg,
                                                 SolveOut* __restrict__ outs, int* __restrict__ bad_flags,
                                                 double* __restrict__ hist, int hist_cap,
-                                                const int* __restrict__ order, int count, int* queue)
+                                                const int* __restrict__ order, int count, int* queue, int lds_nodes)
 {
     __shared__ double sred[3 * NALPHA_MAX * (BS / 64)];
     __shared__ int s_next;
+    extern __shared__ double s_nodes[];  // lds_nodes x LN
     for (;;) {
         if (threadIdx.x == 0) s_next = atomicAdd(queue, 1);
         __syncthreads();
         const int q = s_next;
         __syncthreads();
         if (q >= count) break;
-        solve_one<BS, SEGSCAN>(insts, order[q], cfg, outs, bad_flags, hist, hist_cap, sred);
+        solve_one<TeamWG<BS>, SEGSCAN>(insts, order[q], cfg, outs, bad_flags, hist, hist_cap, sred, s_nodes,
+                                       lds_nodes, nullptr);
     }
 }
 
 __global__ void k_reset_queue(int* queue) { *queue = 0; }
+
+// One large problem solved by the whole grid (cooperative launch).
+__global__ void __launch_bounds__(256) k_bmpc_grid(const InstDesc* __restrict__ insts, SolverCfg cfg,
+                                                   SolveOut* __restrict__ outs, int* __restrict__ bad_flags,
+                                                   double* __restrict__ hist, int hist_cap, double* gpart)
+{
+    __shared__ double sred[3 * NALPHA_MAX * 4];
+    solve_one<TeamGrid<256>, false>(insts, 0, cfg, outs, bad_flags, hist, hist_cap, sred, nullptr, 0, gpart);
+}
 
 // Linearisation and quadratisation only (row a2), for testing and for
 // callers that bring their own LQR solver.
@@ -994,9 +1290,9 @@ __global__ void __launch_bounds__(BS) k_bmpc_linearise(InstDesc I, double rho, d
 {
     __shared__ double sred[2 * (BS / 64)];
     double La, vi, rk, ld, dd;
-    pass_linearise<BS>(I, rho, La, vi);
+    pass_linearise<TeamWG<BS>>(I, rho, La, vi);
     __syncthreads();
-    pass_defects_kkt<BS>(I, rk, ld, dd);
+    pass_defects_kkt<TeamWG<BS>>(I, rk, ld, dd);
     double mx[2] = {rk, vi};
     block_reduce<BS, 2, true>(mx, sred);
     if (threadIdx.x == 0 && kkt_out) {
@@ -1137,6 +1433,7 @@ struct bmpc_batch {
     int tuned_variant = 0;  // set by bmpc_batch_tune (0 = not tuned)
     int tuned_block = 0;
     int* d_order = nullptr;  // problems by decreasing node count (work queue order)
+    double* d_gpart = nullptr;  // per-workgroup partial sums of the grid solver
     int* d_queue = nullptr;  // next queue position, reset before every solve
 };
 
@@ -1199,7 +1496,7 @@ __global__ void __launch_bounds__(BS) k_start_from_outputs(const InstDesc* __res
 struct WgKernel {
     int block;
     bool segscan;
-    void (*fn)(const InstDesc*, SolverCfg, SolveOut*, int*, double*, int, const int*, int, int*);
+    void (*fn)(const InstDesc*, SolverCfg, SolveOut*, int*, double*, int, const int*, int, int*, int);
     const char* name;
 };
 static const WgKernel kWgKernels[] = {
@@ -1216,6 +1513,28 @@ static const WgKernel* find_wg(int block, bool segscan)
     for (const auto& k : kWgKernels)
         if (k.block == block && k.segscan == segscan) return &k;
     return &kWgKernels[2];
+}
+
+// Dynamic LDS of a solver launch: the per-node chain values of problems up
+// to this size.  A workgroup of 256 threads has a CU to itself (register
+// use), so it takes most of the 160 KB; narrower ones leave room for the
+// other workgroups of the CU.  Requests above the default limit are enabled
+// once per kernel; if that fails the launch stays within 64 KB.
+static size_t solver_lds_bytes(const WgKernel& k)
+{
+    static std::mutex mu;
+    static std::map<const void*, size_t> ok;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = ok.find((const void*)k.fn);
+    if (it != ok.end()) return it->second;
+    size_t want = k.block == 256 ? 144 * 1024 : (k.block == 128 ? 72 * 1024 : 36 * 1024);
+    if (want > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) != hipSuccess) {
+        (void)hipGetLastError();
+        want = 60 * 1024;
+    }
+    ok[(const void*)k.fn] = want;
+    return want;
 }
 
 // Workgroups that fit on the device at once for this kernel (the persistent
@@ -1235,7 +1554,8 @@ static int resident_groups(const WgKernel& k, int count)
         } else {
             int per_cu = 0, cus = 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k.fn, k.block, 0) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k.fn, k.block, solver_lds_bytes(k)) !=
+                    hipSuccess ||
                 per_cu < 1 || cus < 1)
                 return count;
             cap = (long)per_cu * cus;
@@ -1291,12 +1611,41 @@ static bool dalloc(T** p, size_t n)
 // plain kernel launches, so the pair can be captured into a graph).
 static bmpc_status launch_solver(bmpc_batch* b, const WgKernel& k, const SolverCfg& cfg, hipStream_t st)
 {
+    const size_t lds = solver_lds_bytes(k);
     const int grid = resident_groups(k, b->count);
+    const int lds_nodes = (int)(lds / (LN * sizeof(double)));
     ProfScope ps(k.name, st);
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, st, b->d_queue);
-    hipLaunchKernelGGL(k.fn, dim3(grid), dim3(k.block), 0, st, b->d_desc, cfg, b->d_out, b->d_bad, b->d_hist,
-                       b->hist_cap, b->d_order, b->count, b->d_queue);
+    hipLaunchKernelGGL(k.fn, dim3(grid), dim3(k.block), lds, st, b->d_desc, cfg, b->d_out, b->d_bad, b->d_hist,
+                       b->hist_cap, b->d_order, b->count, b->d_queue, lds_nodes);
     BMPC_HIP_TRY(hipGetLastError());
+    return BMPC_OK;
+}
+
+// Problems at least this large, alone in a batch, are solved by the whole
+// grid (cooperative launch) instead of one workgroup.
+constexpr long GRID_MIN_NODES = 16384;
+
+static bmpc_status launch_grid_solver(bmpc_batch* b, const SolverCfg& cfg, hipStream_t st)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    BMPC_HIP_TRY(hipGetDevice(&dev));
+    BMPC_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    BMPC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_bmpc_grid, 256, 0));
+    if (per_cu < 1 || cus < 1) return fail(BMPC_ERR_HIP, "the grid solver does not fit on the device");
+    const int grid = per_cu * cus;
+    if (!b->d_gpart && !dalloc(&b->d_gpart, (size_t)grid * 3 * NALPHA_MAX))
+        return fail(BMPC_ERR_OOM, "device allocation for the grid reductions failed");
+    const InstDesc* desc = b->d_desc;
+    SolverCfg c = cfg;
+    SolveOut* outs = b->d_out;
+    int* bad = b->d_bad;
+    double* hist = b->d_hist;
+    int hist_cap = b->hist_cap;
+    double* gpart = b->d_gpart;
+    void* args[] = {&desc, &c, &outs, &bad, &hist, &hist_cap, &gpart};
+    ProfScope ps("bmpc_solve_grid", st);
+    BMPC_HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bmpc_grid, dim3(grid), dim3(256), args, 0, st));
     return BMPC_OK;
 }
 
@@ -1552,6 +1901,7 @@ BMPC_API void bmpc_batch_destroy(bmpc_batch* b)
 {
     if (!b) return;
     (void)hipFree(b->d_order);
+    (void)hipFree(b->d_gpart);
     (void)hipFree(b->d_queue);
     (void)hipFree(b->d_desc);
     (void)hipFree(b->d_out);
@@ -1571,14 +1921,24 @@ BMPC_API bmpc_status bmpc_batch_launch(bmpc_batch* b, const bmpc_settings* s, in
         s->riccati_variant != BMPC_RICCATI_SEGSCAN)
         return fail(BMPC_ERR_INVALID_ARG, "unknown Riccati variant %d", s->riccati_variant);
     if (warm < 0 || warm > 31) return fail(BMPC_ERR_INVALID_ARG, "warm bits %d outside [0, 31]", warm);
-    if (s->block_size != 0 && s->block_size != 64 && s->block_size != 128 && s->block_size != 256)
-        return fail(BMPC_ERR_INVALID_ARG, "block_size must be 0, 64, 128 or 256");
+    if (s->block_size != 0 && s->block_size != 64 && s->block_size != 128 && s->block_size != 256 &&
+        s->block_size != BMPC_BLOCK_GRID)
+        return fail(BMPC_ERR_INVALID_ARG, "block_size must be 0, 64, 128, 256 or BMPC_BLOCK_GRID");
     int variant = s->riccati_variant, block = s->block_size;
+    hipStream_t st = (hipStream_t)stream;
+    const SolverCfg cfg = to_cfg(*s, warm);
+    if (block == BMPC_BLOCK_GRID) {
+        if (b->count != 1) return fail(BMPC_ERR_INVALID_ARG, "the whole-grid solver takes a batch of one problem");
+        if (variant == BMPC_RICCATI_SEGSCAN)
+            return fail(BMPC_ERR_UNSUPPORTED, "the whole-grid solver uses the level-parallel backward pass");
+        return launch_grid_solver(b, cfg, st);
+    }
+    // a single large problem: the whole grid works on it
+    if (b->count == 1 && b->total_nodes >= GRID_MIN_NODES && variant != BMPC_RICCATI_SEGSCAN && block == 0)
+        return launch_grid_solver(b, cfg, st);
     if (variant == BMPC_RICCATI_AUTO) variant = b->tuned_variant ? b->tuned_variant : BMPC_RICCATI_LEVEL;
     if (block == 0) block = b->tuned_block ? b->tuned_block : 256;
     const WgKernel* k = find_wg(block, variant == BMPC_RICCATI_SEGSCAN);
-    hipStream_t st = (hipStream_t)stream;
-    const SolverCfg cfg = to_cfg(*s, warm);
     return launch_solver(b, *k, cfg, st);
 }
 

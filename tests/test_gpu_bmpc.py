@@ -296,3 +296,41 @@ def test_total_iteration_cap_matches_oracle():
     for i, inst in enumerate(insts):
         _, os_, _ = oracle.solve(oracle.problem_from_instance(inst), oracle.default_settings(max_iter_total=25))
         assert stats[i]["status"] == os_["status"] and stats[i]["inner_it"] == os_["inner_it"] <= 25
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_whole_grid_solver_matches_oracle(seed):
+    """One problem solved by the whole grid (cooperative launch; grid-wide
+    reductions in workgroup order) reaches the oracle's solution with the
+    same status and follows its iteration path."""
+    inst = S.single_bmpc(seed)
+    N = inst.num_nodes
+    pb = Problem(inst)
+    cap = 16
+    b = L.bmpc_batch_create([pb.handle], hist_cap=cap)
+    L.bmpc_batch_launch(b, L.bmpc_settings_default(block_size=L.BLOCK_GRID))
+    gs = L.bmpc_batch_stats(b, 1)[0]
+    h = L.bmpc_batch_history(b, 0, cap)
+    x, u = zeros(N, 4), zeros(N, 2)
+    L.bmpc_batch_state(b, 0, x=x, u=u)
+    torch.cuda.synchronize()
+    L.bmpc_batch_destroy(b)
+    pb.close()
+    print(f"grid solver seed {seed}: status {gs['status']} inner {gs['inner_it']}", flush=True)
+    os_ = _compare(inst, {"x": host(x, (N, 4)), "u": host(u, (N, 2))}, gs)
+    _, _, oh = oracle.solve(oracle.problem_from_instance(inst))
+    k = min(6, len(oh), gs["inner_it"])
+    np.testing.assert_allclose(h[:k, :5], oh[:k, :5], rtol=1e-6)
+    assert abs(gs["inner_it"] - os_["inner_it"]) <= 2 + 0.02 * os_["inner_it"]
+
+
+def test_whole_grid_solver_needs_single_problem():
+    insts = [S.single_bmpc(0), S.single_bmpc(1)]
+    pbs = [Problem(i) for i in insts]
+    b = L.bmpc_batch_create([p.handle for p in pbs])
+    with pytest.raises(L.BmpcError) as e:
+        L.bmpc_batch_launch(b, L.bmpc_settings_default(block_size=L.BLOCK_GRID))
+    assert e.value.status == 1
+    L.bmpc_batch_destroy(b)
+    for p in pbs:
+        p.close()
