@@ -270,8 +270,12 @@ BMPC_API bmpc_status bmpc_linearize(bmpc_problem* problem, const double* x, cons
 
 /* ------------------------------------------------------------------------
  * Batched solve: many independent problems (own trees, own sizes) in one
- * launch, one workgroup per problem; every problem stops on its own
- * convergence.  The batch owns the state of every problem.
+ * launch.  A persistent kernel: each resident workgroup takes the next
+ * problem from a queue (largest first) and solves it start to end, so
+ * results do not depend on the schedule; every problem stops on its own
+ * convergence.  A batch of one large problem is solved by the whole grid
+ * instead (see bmpc_settings.block_size).  The batch owns the state of
+ * every problem.
  * ---------------------------------------------------------------------- */
 /* problems: host array of `count` handles (they must outlive the batch).
    hist_cap > 0 records per inner iteration [outer, r_kkt, alpha, mu, rho,

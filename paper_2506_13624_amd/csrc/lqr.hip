@@ -448,7 +448,9 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
     int4 inf = t.info[n];
     int from = -1;
     bool pref = false;
-    WaveIn<NX, NU, LAY> in;
+    // inputs of the next two nodes of a chain are in flight: node k of a walk
+    // uses buffer k % 2, which is refilled with node k + 2 once consumed
+    WaveIn<NX, NU, LAY> bufA, bufB;
 
     // padding columns of D stay zero
     for (int e = lane; e < NX * NDP; e += 64)
@@ -510,153 +512,165 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
         wave_sync();
     };
 
-    for (;;) {
-        const int c0 = inf.x, c1 = inf.y, par = inf.z, nsib = inf.w;
-        const int4 inf_next = par >= 0 ? t.info[par] : make_int4(0, 0, -1, 0);
-        if (c0 == c1) {
-            Slots<NX * NX> Pv;
-            Slots<NX> pv;
-            Pv.template load<LAY>(a.Q, n, N, lane);
-            pv.template load<LAY>(a.q, n, N, lane);
-            Pv.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
-            pv.each(lane, [&](int e, double v) { sp[e] = v; });
-            for (int e = lane; e < NU * NX; e += 64) a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0;
-            for (int e = lane; e < NU; e += 64) a.k[lidx<LAY>(n, e, NU, N)] = 0.0;
-            if (nsib == 1) {
-                in.load_stage(a, N, par, lane);
-                in.load_edge(a, N, n, lane);
-            }
-            wave_sync();
-        } else {
-            if (!pref) in.load_stage(a, N, n, lane);
-            if (pref) {
-                in.stage_to(sZ, lane);
-                in.edge_to(sD, lane);  // the only child's P is still in sP
-                if (nsib == 1) {
-                    in.load_stage(a, N, par, lane);
-                    in.load_edge(a, N, n, lane);
-                }
-                add_child();
+    // after a leaf or a merge: the parent's inputs into oth and, if the
+    // chain goes on, the grandparent's into cur (free again)
+    auto prefetch_two = [&](WaveIn<NX, NU, LAY>& cur, WaveIn<NX, NU, LAY>& oth, int par, int nsib,
+                            int4 inf_next) {
+        if (nsib != 1) return;
+        oth.load_stage(a, N, par, lane);
+        oth.load_edge(a, N, n, lane);
+        if (inf_next.w == 1 && inf_next.z >= 0) {
+            cur.load_stage(a, N, inf_next.z, lane);
+            cur.load_edge(a, N, par, lane);
+        }
+    };
+    auto step = [&](WaveIn<NX, NU, LAY>& in, WaveIn<NX, NU, LAY>& oth) -> bool {
+            const int c0 = inf.x, c1 = inf.y, par = inf.z, nsib = inf.w;
+            const int4 inf_next = par >= 0 ? t.info[par] : make_int4(0, 0, -1, 0);
+            if (c0 == c1) {
+                Slots<NX * NX> Pv;
+                Slots<NX> pv;
+                Pv.template load<LAY>(a.Q, n, N, lane);
+                pv.template load<LAY>(a.q, n, N, lane);
+                Pv.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
+                pv.each(lane, [&](int e, double v) { sp[e] = v; });
+                for (int e = lane; e < NU * NX; e += 64) a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0;
+                for (int e = lane; e < NU; e += 64) a.k[lidx<LAY>(n, e, NU, N)] = 0.0;
+                prefetch_two(in, oth, par, nsib, inf_next);
+                wave_sync();
             } else {
-                // children two at a time: both edges and both value functions
-                // are requested before either is used
-                for (int j = c0; j < c1; j += 2) {
-                    const bool two = j + 1 < c1;
-                    Slots<NX * NX> Pv0, Pv1;
-                    Slots<NX> pv0, pv1;
-                    WaveIn<NX, NU, LAY> in1;
-                    const bool keep = (c1 - c0 == 1) && from == j;
-                    in.load_edge(a, N, j, lane);
-                    if (!keep) {
-                        Pv0.template load_dev<LAY>(a.P, j, N, lane);
-                        pv0.template load_dev<LAY>(a.p, j, N, lane);
-                    }
-                    if (two) {
-                        in1.load_edge(a, N, j + 1, lane);
-                        Pv1.template load_dev<LAY>(a.P, j + 1, N, lane);
-                        pv1.template load_dev<LAY>(a.p, j + 1, N, lane);
-                    }
-                    if (j == c0) in.stage_to(sZ, lane);  // stage data requested with the first children
-                    wave_sync();
-                    in.edge_to(sD, lane);
-                    if (!keep) {
-                        Pv0.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
-                        pv0.each(lane, [&](int e, double v) { sp[e] = v; });
+                if (!pref) in.load_stage(a, N, n, lane);
+                if (pref) {
+                    in.stage_to(sZ, lane);
+                    in.edge_to(sD, lane);  // the only child's P is still in sP
+                    // the parent's inputs are already in oth; start the grandparent's
+                    if (nsib == 1 && inf_next.w == 1 && inf_next.z >= 0) {
+                        in.load_stage(a, N, inf_next.z, lane);
+                        in.load_edge(a, N, par, lane);
                     }
                     add_child();
-                    if (two) {
-                        in1.edge_to(sD, lane);
-                        Pv1.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
-                        pv1.each(lane, [&](int e, double v) { sp[e] = v; });
+                } else {
+                    // children two at a time: both edges and both value functions
+                    // are requested before either is used
+                    for (int j = c0; j < c1; j += 2) {
+                        const bool two = j + 1 < c1;
+                        Slots<NX * NX> Pv0, Pv1;
+                        Slots<NX> pv0, pv1;
+                        WaveIn<NX, NU, LAY> in1;
+                        const bool keep = (c1 - c0 == 1) && from == j;
+                        in.load_edge(a, N, j, lane);
+                        if (!keep) {
+                            Pv0.template load_dev<LAY>(a.P, j, N, lane);
+                            pv0.template load_dev<LAY>(a.p, j, N, lane);
+                        }
+                        if (two) {
+                            in1.load_edge(a, N, j + 1, lane);
+                            Pv1.template load_dev<LAY>(a.P, j + 1, N, lane);
+                            pv1.template load_dev<LAY>(a.p, j + 1, N, lane);
+                        }
+                        if (j == c0) in.stage_to(sZ, lane);  // stage data requested with the first children
+                        wave_sync();
+                        in.edge_to(sD, lane);
+                        if (!keep) {
+                            Pv0.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
+                            pv0.each(lane, [&](int e, double v) { sp[e] = v; });
+                        }
                         add_child();
+                        if (two) {
+                            in1.edge_to(sD, lane);
+                            Pv1.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
+                            pv1.each(lane, [&](int e, double v) { sp[e] = v; });
+                            add_child();
+                        }
+                    }
+                    prefetch_two(in, oth, par, nsib, inf_next);
+                }
+                // gains: lane i < NX solves column i of K, lane NX solves k
+                if (lane <= NX) {
+                    double L[NU][NU], inv[NU];
+    #pragma unroll
+                    for (int i = 0; i < NU; ++i)
+    #pragma unroll
+                        for (int j = 0; j < NU; ++j) L[i][j] = sZ[NX + i][NX + j];
+                    const bool ok = chol_inplace<NU>(L, inv);
+                    if (!ok && lane == 0) atomicMin(a.bad, n);
+                    double v[NU];
+                    const int col = lane < NX ? lane : NZ;
+    #pragma unroll
+                    for (int i = 0; i < NU; ++i) v[i] = sZ[NX + i][col];
+                    chol_solve<NU>(L, inv, v);
+    #pragma unroll
+                    for (int i = 0; i < NU; ++i) sK[i][lane] = -v[i];
+                }
+                wave_sync();
+                for (int e = lane; e < NU * NX; e += 64)
+                    a.K[lidx<LAY>(n, e, NU * NX, N)] = sK[e / NX][e % NX];
+                for (int e = lane; e < NU; e += 64) a.k[lidx<LAY>(n, e, NU, N)] = sK[e][NX];
+                // P = sym(W + G^T K), p = w + G^T k   (the child's P in sP is no longer needed)
+                constexpr int PS = (NX * NX + 63) / 64, VS = (NX + 63) / 64;
+                double pv[PS], qv[VS];
+    #pragma unroll
+                for (int s = 0; s < PS; ++s) {
+                    const int e = lane + 64 * s;
+                    if (e < NX * NX) {
+                        const int i = e / NX, j = e % NX;
+                        double tij = 0.0, tji = 0.0;
+    #pragma unroll
+                        for (int rr = 0; rr < NU; ++rr) {
+                            tij += sZ[NX + rr][i] * sK[rr][j];
+                            tji += sZ[NX + rr][j] * sK[rr][i];
+                        }
+                        pv[s] = 0.5 * ((sZ[i][j] + tij) + (sZ[j][i] + tji));
                     }
                 }
-                if (nsib == 1) {
-                    in.load_stage(a, N, par, lane);
-                    in.load_edge(a, N, n, lane);
-                }
-            }
-            // gains: lane i < NX solves column i of K, lane NX solves k
-            if (lane <= NX) {
-                double L[NU][NU], inv[NU];
-#pragma unroll
-                for (int i = 0; i < NU; ++i)
-#pragma unroll
-                    for (int j = 0; j < NU; ++j) L[i][j] = sZ[NX + i][NX + j];
-                const bool ok = chol_inplace<NU>(L, inv);
-                if (!ok && lane == 0) atomicMin(a.bad, n);
-                double v[NU];
-                const int col = lane < NX ? lane : NZ;
-#pragma unroll
-                for (int i = 0; i < NU; ++i) v[i] = sZ[NX + i][col];
-                chol_solve<NU>(L, inv, v);
-#pragma unroll
-                for (int i = 0; i < NU; ++i) sK[i][lane] = -v[i];
-            }
-            wave_sync();
-            for (int e = lane; e < NU * NX; e += 64)
-                a.K[lidx<LAY>(n, e, NU * NX, N)] = sK[e / NX][e % NX];
-            for (int e = lane; e < NU; e += 64) a.k[lidx<LAY>(n, e, NU, N)] = sK[e][NX];
-            // P = sym(W + G^T K), p = w + G^T k   (the child's P in sP is no longer needed)
-            constexpr int PS = (NX * NX + 63) / 64, VS = (NX + 63) / 64;
-            double pv[PS], qv[VS];
-#pragma unroll
-            for (int s = 0; s < PS; ++s) {
-                const int e = lane + 64 * s;
-                if (e < NX * NX) {
-                    const int i = e / NX, j = e % NX;
-                    double tij = 0.0, tji = 0.0;
-#pragma unroll
-                    for (int rr = 0; rr < NU; ++rr) {
-                        tij += sZ[NX + rr][i] * sK[rr][j];
-                        tji += sZ[NX + rr][j] * sK[rr][i];
+    #pragma unroll
+                for (int s = 0; s < VS; ++s) {
+                    const int i = lane + 64 * s;
+                    if (i < NX) {
+                        double tt = 0.0;
+    #pragma unroll
+                        for (int rr = 0; rr < NU; ++rr) tt += sZ[NX + rr][i] * sK[rr][NX];
+                        qv[s] = sZ[i][NZ] + tt;
                     }
-                    pv[s] = 0.5 * ((sZ[i][j] + tij) + (sZ[j][i] + tji));
                 }
-            }
-#pragma unroll
-            for (int s = 0; s < VS; ++s) {
-                const int i = lane + 64 * s;
-                if (i < NX) {
-                    double tt = 0.0;
-#pragma unroll
-                    for (int rr = 0; rr < NU; ++rr) tt += sZ[NX + rr][i] * sK[rr][NX];
-                    qv[s] = sZ[i][NZ] + tt;
+                wave_sync();
+    #pragma unroll
+                for (int s = 0; s < PS; ++s) {
+                    const int e = lane + 64 * s;
+                    if (e < NX * NX) sP[e / NX][e % NX] = pv[s];
                 }
+    #pragma unroll
+                for (int s = 0; s < VS; ++s) {
+                    const int i = lane + 64 * s;
+                    if (i < NX) sp[i] = qv[s];
+                }
+                wave_sync();
             }
-            wave_sync();
-#pragma unroll
-            for (int s = 0; s < PS; ++s) {
-                const int e = lane + 64 * s;
-                if (e < NX * NX) sP[e / NX][e % NX] = pv[s];
+            if (nsib > 1) {
+                for (int e = lane; e < NX * NX; e += 64)
+                    st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], sP[e / NX][e % NX]);
+                for (int e = lane; e < NX; e += 64) st_shared_dev(&a.p[lidx<LAY>(n, e, NX, N)], sp[e]);
+            } else {
+                for (int e = lane; e < NX * NX; e += 64) a.P[lidx<LAY>(n, e, NX * NX, N)] = sP[e / NX][e % NX];
+                for (int e = lane; e < NX; e += 64) a.p[lidx<LAY>(n, e, NX, N)] = sp[e];
             }
-#pragma unroll
-            for (int s = 0; s < VS; ++s) {
-                const int i = lane + 64 * s;
-                if (i < NX) sp[i] = qv[s];
+            if (par < 0) return false;
+            pref = nsib == 1;
+            if (nsib > 1) {
+                wait_own_stores();
+                __syncthreads();
+                if (lane == 0) sgo = (atomicAdd(&arrive[par], 1) == nsib - 1);
+                __syncthreads();
+                if (!sgo) return false;
             }
-            wave_sync();
-        }
-        if (nsib > 1) {
-            for (int e = lane; e < NX * NX; e += 64)
-                st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], sP[e / NX][e % NX]);
-            for (int e = lane; e < NX; e += 64) st_shared_dev(&a.p[lidx<LAY>(n, e, NX, N)], sp[e]);
-        } else {
-            for (int e = lane; e < NX * NX; e += 64) a.P[lidx<LAY>(n, e, NX * NX, N)] = sP[e / NX][e % NX];
-            for (int e = lane; e < NX; e += 64) a.p[lidx<LAY>(n, e, NX, N)] = sp[e];
-        }
-        if (par < 0) break;
-        pref = nsib == 1;
-        if (nsib > 1) {
-            wait_own_stores();
-            __syncthreads();
-            if (lane == 0) sgo = (atomicAdd(&arrive[par], 1) == nsib - 1);
-            __syncthreads();
-            if (!sgo) break;
-        }
-        from = n;
-        n = par;
-        inf = inf_next;
+            from = n;
+            n = par;
+            inf = inf_next;
+            return true;
+    };
+    for (;;) {
+        if (!step(bufA, bufB)) break;
+        if (!step(bufB, bufA)) break;
     }
 }
 
