@@ -451,6 +451,10 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
     // inputs of the next two nodes of a chain are in flight: node k of a walk
     // uses buffer k % 2, which is refilled with node k + 2 once consumed
     WaveIn<NX, NU, LAY> bufA, bufB;
+    // a worker reaching a branching node requests the merge's stage data and
+    // first two child edges before it counts itself in (whether or not it
+    // turns out to be the last child), so that they arrive during the count
+    bool merge_pre = false;
 
     // padding columns of D stay zero
     for (int e = lane; e < NX * NDP; e += 64)
@@ -539,7 +543,7 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                 prefetch_two(in, oth, par, nsib, inf_next);
                 wave_sync();
             } else {
-                if (!pref) in.load_stage(a, N, n, lane);
+                if (!pref && !merge_pre) in.load_stage(a, N, n, lane);
                 if (pref) {
                     in.stage_to(sZ, lane);
                     in.edge_to(sD, lane);  // the only child's P is still in sP
@@ -556,15 +560,15 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                         const bool two = j + 1 < c1;
                         Slots<NX * NX> Pv0, Pv1;
                         Slots<NX> pv0, pv1;
-                        WaveIn<NX, NU, LAY> in1;
                         const bool keep = (c1 - c0 == 1) && from == j;
-                        in.load_edge(a, N, j, lane);
+                        const bool pre = merge_pre && j == c0;  // edges already requested
+                        if (!pre) in.load_edge(a, N, j, lane);
                         if (!keep) {
                             Pv0.template load_dev<LAY>(a.P, j, N, lane);
                             pv0.template load_dev<LAY>(a.p, j, N, lane);
                         }
                         if (two) {
-                            in1.load_edge(a, N, j + 1, lane);
+                            if (!pre) oth.load_edge(a, N, j + 1, lane);
                             Pv1.template load_dev<LAY>(a.P, j + 1, N, lane);
                             pv1.template load_dev<LAY>(a.p, j + 1, N, lane);
                         }
@@ -577,12 +581,13 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                         }
                         add_child();
                         if (two) {
-                            in1.edge_to(sD, lane);
+                            oth.edge_to(sD, lane);
                             Pv1.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
                             pv1.each(lane, [&](int e, double v) { sp[e] = v; });
                             add_child();
                         }
                     }
+                    merge_pre = false;
                     prefetch_two(in, oth, par, nsib, inf_next);
                 }
                 // gains: lane i < NX solves column i of K, lane NX solves k
@@ -609,13 +614,13 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                 // P = sym(W + G^T K), p = w + G^T k   (the child's P in sP is no longer needed)
                 constexpr int PS = (NX * NX + 63) / 64, VS = (NX + 63) / 64;
                 double pv[PS], qv[VS];
-    #pragma unroll
+#pragma unroll
                 for (int s = 0; s < PS; ++s) {
                     const int e = lane + 64 * s;
                     if (e < NX * NX) {
                         const int i = e / NX, j = e % NX;
                         double tij = 0.0, tji = 0.0;
-    #pragma unroll
+#pragma unroll
                         for (int rr = 0; rr < NU; ++rr) {
                             tij += sZ[NX + rr][i] * sK[rr][j];
                             tji += sZ[NX + rr][j] * sK[rr][i];
@@ -623,23 +628,23 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                         pv[s] = 0.5 * ((sZ[i][j] + tij) + (sZ[j][i] + tji));
                     }
                 }
-    #pragma unroll
+#pragma unroll
                 for (int s = 0; s < VS; ++s) {
                     const int i = lane + 64 * s;
                     if (i < NX) {
                         double tt = 0.0;
-    #pragma unroll
+#pragma unroll
                         for (int rr = 0; rr < NU; ++rr) tt += sZ[NX + rr][i] * sK[rr][NX];
                         qv[s] = sZ[i][NZ] + tt;
                     }
                 }
                 wave_sync();
-    #pragma unroll
+#pragma unroll
                 for (int s = 0; s < PS; ++s) {
                     const int e = lane + 64 * s;
                     if (e < NX * NX) sP[e / NX][e % NX] = pv[s];
                 }
-    #pragma unroll
+#pragma unroll
                 for (int s = 0; s < VS; ++s) {
                     const int i = lane + 64 * s;
                     if (i < NX) sp[i] = qv[s];
@@ -658,6 +663,13 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
             pref = nsib == 1;
             if (nsib > 1) {
                 wait_own_stores();
+                // requested after the stores have completed (a wait for them
+                // would also wait for these loads); they travel with the count.
+                // The next step runs with (in, oth) = (oth, in) of this one.
+                oth.load_stage(a, N, par, lane);
+                oth.load_edge(a, N, inf_next.x, lane);
+                in.load_edge(a, N, inf_next.x + 1, lane);
+                merge_pre = true;
                 __syncthreads();
                 if (lane == 0) sgo = (atomicAdd(&arrive[par], 1) == nsib - 1);
                 __syncthreads();
