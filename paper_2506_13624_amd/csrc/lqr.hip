@@ -339,19 +339,22 @@ struct Slots {
     __device__ __forceinline__ void load(const double* __restrict__ base, int node, int N, int lane)
     {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int e = lane + 64 * s;
-            v[s] = (e < CNT) ? base[lidx<LAY>(node, e, CNT, N)] : 0.0;
-        }
+        for (int s = 0; s < S; ++s) v[s] = base[lidx<LAY>(node, elem(lane, s), CNT, N)];
     }
     template <int LAY>
     __device__ __forceinline__ void load_dev(const double* base, int node, int N, int lane)
     {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int e = lane + 64 * s;
-            v[s] = (e < CNT) ? ld_shared_dev(&base[lidx<LAY>(node, e, CNT, N)]) : 0.0;
-        }
+        for (int s = 0; s < S; ++s) v[s] = ld_shared_dev(&base[lidx<LAY>(node, elem(lane, s), CNT, N)]);
+    }
+    // Every lane loads in every slot (lanes past the end re-read the last
+    // element, whose copy is never used): the loads then need no branch
+    // around them and no zeroing of their destination, either of which
+    // would make the compiler wait for every load still in flight.
+    static __device__ __forceinline__ int elem(int lane, int s)
+    {
+        const int e = lane + 64 * s;
+        return e < CNT ? e : CNT - 1;
     }
     template <class F>
     __device__ __forceinline__ void each(int lane, F f) const
@@ -597,7 +600,7 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                     for (int i = 0; i < NU; ++i)
     #pragma unroll
                         for (int j = 0; j < NU; ++j) L[i][j] = sZ[NX + i][NX + j];
-                    const bool ok = chol_inplace<NU>(L, inv);
+                    const bool ok = chol_inplace_rsq<NU>(L, inv);
                     if (!ok && lane == 0) atomicMin(a.bad, n);
                     double v[NU];
                     const int col = lane < NX ? lane : NZ;

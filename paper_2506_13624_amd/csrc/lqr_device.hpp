@@ -57,6 +57,46 @@ __device__ __forceinline__ bool chol_inplace(double (&H)[n][n], double (&inv)[n]
     return ok;
 }
 
+// The same factorisation with the reciprocal square roots taken from the
+// hardware estimate (v_rsq_f64) refined by two Newton steps
+// y <- y + y (1 - d y^2) / 2, each of which squares the relative error:
+// a shorter dependent chain than a correctly rounded square root followed by
+// a division, and within a few units in the last place of it.
+__device__ __forceinline__ double rsqrt_refined(double d)
+{
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-d * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+template <int n>
+__device__ __forceinline__ bool chol_inplace_rsq(double (&H)[n][n], double (&inv)[n])
+{
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+        double d = H[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= H[j][k] * H[j][k];
+        ok = ok && (d > 0.0);
+        const double y = rsqrt_refined(d > 0.0 ? d : 1.0);
+        inv[j] = y;
+        H[j][j] = (d > 0.0 ? d : 1.0) * y;
+#pragma unroll
+        for (int i = j + 1; i < n; ++i) {
+            double s = H[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= H[i][k] * H[j][k];
+            H[i][j] = s * y;
+        }
+    }
+    return ok;
+}
+
 // Solve (L L^T) v = v in place, given the reciprocal diagonal.
 template <int n>
 __device__ __forceinline__ void chol_solve(const double (&L)[n][n], const double (&inv)[n], double (&v)[n])
