@@ -449,6 +449,18 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
     const int N = t.N;
     int n = t.leaves[l];
     int4 inf = t.info[n];
+    // The parent's record is requested one step ahead: lane i holds field
+    // i % 4 (a per-lane value, so that the compiler does not move it into
+    // scalar registers, and wait for it, right after the load).
+    auto request_info = [&](int node) -> int {
+        const int f = lane & 3;
+        return node >= 0 ? reinterpret_cast<const int*>(t.info)[4 * node + f] : (f == 2 ? -1 : 0);
+    };
+    auto unpack_info = [&](int v) -> int4 {
+        return make_int4(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 1),
+                         __builtin_amdgcn_readlane(v, 2), __builtin_amdgcn_readlane(v, 3));
+    };
+    int infp = request_info(inf.z);
     int from = -1;
     bool pref = false;
     // inputs of the next two nodes of a chain are in flight: node k of a walk
@@ -533,7 +545,8 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
     };
     auto step = [&](WaveIn<NX, NU, LAY>& in, WaveIn<NX, NU, LAY>& oth) -> bool {
             const int c0 = inf.x, c1 = inf.y, par = inf.z, nsib = inf.w;
-            const int4 inf_next = par >= 0 ? t.info[par] : make_int4(0, 0, -1, 0);
+            const int4 inf_next = unpack_info(infp);
+            const int inf_next2 = request_info(inf_next.z);
             if (c0 == c1) {
                 Slots<NX * NX> Pv;
                 Slots<NX> pv;
@@ -681,6 +694,7 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
             from = n;
             n = par;
             inf = inf_next;
+            infp = inf_next2;
             return true;
     };
     for (;;) {
