@@ -356,16 +356,28 @@ struct Slots {
         const int e = lane + 64 * s;
         return e < CNT ? e : CNT - 1;
     }
+    // Lanes past the end repeat the last element with the value they
+    // loaded for it: a repeated LDS or memory write of the same value.
     template <class F>
     __device__ __forceinline__ void each(int lane, F f) const
     {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int e = lane + 64 * s;
-            if (e < CNT) f(e, v[s]);
-        }
+        for (int s = 0; s < S; ++s) f(elem(lane, s), v[s]);
     }
 };
+
+// f(e) for the CNT elements of a node over the 64 lanes, without branches:
+// lanes past the end repeat the last element (f must write the same value
+// for the same element).
+template <int CNT, class F>
+__device__ __forceinline__ void each_elem(int lane, F f)
+{
+#pragma unroll
+    for (int s = 0; s < (CNT + 63) / 64; ++s) {
+        const int e = lane + 64 * s;
+        f(e < CNT ? e : CNT - 1);
+    }
+}
 
 // Column counts padded to a multiple of 4 so that tiles of 4 columns can be
 // read with 16-byte LDS loads.
@@ -436,7 +448,9 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
 {
     using Dm = WaveDims<NX, NU>;
     constexpr int NZ = Dm::NZ, NDP = Dm::NDP, NQ = Dm::NQ, NZP = Dm::NZP;
-    __shared__ __align__(16) double sD[NX][NDP];   // [A B c 0..] of the current child edge
+    // [A B c 0..] of the current child edge; row NX is the constant
+    // [0 .. 0 1 0 ..] (1 in column NZ) that adds p to the last column of S
+    __shared__ __align__(16) double sD[NX + 1][NDP];
     __shared__ __align__(16) double sP[NX][NX];
     __shared__ __align__(16) double sp[NX];
     __shared__ __align__(16) double sS[NX][NDP];   // P [A B c] + [0 0 p]
@@ -474,6 +488,7 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
     // padding columns of D stay zero
     for (int e = lane; e < NX * NDP; e += 64)
         if (e % NDP >= NZ + 1) sD[e / NDP][e % NDP] = 0.0;
+    for (int e = lane; e < NDP; e += 64) sD[NX][e] = (e == NZ) ? 1.0 : 0.0;
 
     // S = P [A B c] (+p in the last column), tiles of 1 row x 4 columns;
     // then Z += [A B]^T S, tiles of 2 rows x 4 columns
@@ -482,9 +497,11 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
         for (int tt = lane; tt < NX * NQ; tt += 64) {
             const int r = tt / NQ, c4 = 4 * (tt % NQ);
             double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            // k = NX multiplies p by the constant row of D: p is added to
+            // column NZ, exactly, after the sum over k < NX
 #pragma unroll
-            for (int k = 0; k < NX; ++k) {
-                const double pk = sP[r][k];
+            for (int k = 0; k <= NX; ++k) {
+                const double pk = k < NX ? sP[r][k] : sp[r];
                 const double2 d01 = *reinterpret_cast<const double2*>(&sD[k][c4]);
                 const double2 d23 = *reinterpret_cast<const double2*>(&sD[k][c4 + 2]);
                 s0 += pk * d01.x;
@@ -492,11 +509,6 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                 s2 += pk * d23.x;
                 s3 += pk * d23.y;
             }
-            const double pr = sp[r];
-            if (c4 + 0 == NZ) s0 += pr;
-            if (c4 + 1 == NZ) s1 += pr;
-            if (c4 + 2 == NZ) s2 += pr;
-            if (c4 + 3 == NZ) s3 += pr;
             *reinterpret_cast<double2*>(&sS[r][c4]) = make_double2(s0, s1);
             *reinterpret_cast<double2*>(&sS[r][c4 + 2]) = make_double2(s2, s3);
         }
@@ -518,13 +530,22 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                 z[1][2] += dr.y * s23.x;
                 z[1][3] += dr.y * s23.y;
             }
+            // whole 16-byte pairs, padding columns included (never read):
+            // a store under a per-element condition lets the compiler sink
+            // each element's sum into its own branch and run the eight sums
+            // one after another
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int r = r0 + i;
-                if (r < NZ) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (c4 + j <= NZ) sZ[r][c4 + j] += z[i][j];
+                if (NZP == NZ || r < NZ) {
+                    double2* zr = reinterpret_cast<double2*>(&sZ[r][c4]);
+                    double2 z01 = zr[0], z23 = zr[1];
+                    z01.x += z[i][0];
+                    z01.y += z[i][1];
+                    z23.x += z[i][2];
+                    z23.y += z[i][3];
+                    zr[0] = z01;
+                    zr[1] = z23;
                 }
             }
         }
@@ -554,8 +575,8 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                 pv.template load<LAY>(a.q, n, N, lane);
                 Pv.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
                 pv.each(lane, [&](int e, double v) { sp[e] = v; });
-                for (int e = lane; e < NU * NX; e += 64) a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0;
-                for (int e = lane; e < NU; e += 64) a.k[lidx<LAY>(n, e, NU, N)] = 0.0;
+                each_elem<NU * NX>(lane, [&](int e) { a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0; });
+                each_elem<NU>(lane, [&](int e) { a.k[lidx<LAY>(n, e, NU, N)] = 0.0; });
                 prefetch_two(in, oth, par, nsib, inf_next);
                 wave_sync();
             } else {
@@ -624,56 +645,55 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                     for (int i = 0; i < NU; ++i) sK[i][lane] = -v[i];
                 }
                 wave_sync();
-                for (int e = lane; e < NU * NX; e += 64)
-                    a.K[lidx<LAY>(n, e, NU * NX, N)] = sK[e / NX][e % NX];
-                for (int e = lane; e < NU; e += 64) a.k[lidx<LAY>(n, e, NU, N)] = sK[e][NX];
+                each_elem<NU * NX>(lane, [&](int e) { a.K[lidx<LAY>(n, e, NU * NX, N)] = sK[e / NX][e % NX]; });
+                each_elem<NU>(lane, [&](int e) { a.k[lidx<LAY>(n, e, NU, N)] = sK[e][NX]; });
                 // P = sym(W + G^T K), p = w + G^T k   (the child's P in sP is no longer needed)
                 constexpr int PS = (NX * NX + 63) / 64, VS = (NX + 63) / 64;
                 double pv[PS], qv[VS];
+                // every lane computes (lanes past the end repeat the last
+                // element), so that the slots' sums interleave
 #pragma unroll
                 for (int s = 0; s < PS; ++s) {
-                    const int e = lane + 64 * s;
-                    if (e < NX * NX) {
-                        const int i = e / NX, j = e % NX;
-                        double tij = 0.0, tji = 0.0;
+                    const int e0 = lane + 64 * s;
+                    const int e = e0 < NX * NX ? e0 : NX * NX - 1;
+                    const int i = e / NX, j = e % NX;
+                    double tij = 0.0, tji = 0.0;
 #pragma unroll
-                        for (int rr = 0; rr < NU; ++rr) {
-                            tij += sZ[NX + rr][i] * sK[rr][j];
-                            tji += sZ[NX + rr][j] * sK[rr][i];
-                        }
-                        pv[s] = 0.5 * ((sZ[i][j] + tij) + (sZ[j][i] + tji));
+                    for (int rr = 0; rr < NU; ++rr) {
+                        tij += sZ[NX + rr][i] * sK[rr][j];
+                        tji += sZ[NX + rr][j] * sK[rr][i];
                     }
+                    pv[s] = 0.5 * ((sZ[i][j] + tij) + (sZ[j][i] + tji));
                 }
 #pragma unroll
                 for (int s = 0; s < VS; ++s) {
-                    const int i = lane + 64 * s;
-                    if (i < NX) {
-                        double tt = 0.0;
+                    const int i0 = lane + 64 * s;
+                    const int i = i0 < NX ? i0 : NX - 1;
+                    double tt = 0.0;
 #pragma unroll
-                        for (int rr = 0; rr < NU; ++rr) tt += sZ[NX + rr][i] * sK[rr][NX];
-                        qv[s] = sZ[i][NZ] + tt;
-                    }
+                    for (int rr = 0; rr < NU; ++rr) tt += sZ[NX + rr][i] * sK[rr][NX];
+                    qv[s] = sZ[i][NZ] + tt;
                 }
                 wave_sync();
 #pragma unroll
                 for (int s = 0; s < PS; ++s) {
-                    const int e = lane + 64 * s;
-                    if (e < NX * NX) sP[e / NX][e % NX] = pv[s];
+                    const int e0 = lane + 64 * s;
+                    const int e = e0 < NX * NX ? e0 : NX * NX - 1;
+                    sP[e / NX][e % NX] = pv[s];
                 }
 #pragma unroll
                 for (int s = 0; s < VS; ++s) {
-                    const int i = lane + 64 * s;
-                    if (i < NX) sp[i] = qv[s];
+                    const int i0 = lane + 64 * s;
+                    sp[i0 < NX ? i0 : NX - 1] = qv[s];
                 }
                 wave_sync();
             }
             if (nsib > 1) {
-                for (int e = lane; e < NX * NX; e += 64)
-                    st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], sP[e / NX][e % NX]);
-                for (int e = lane; e < NX; e += 64) st_shared_dev(&a.p[lidx<LAY>(n, e, NX, N)], sp[e]);
+                each_elem<NX * NX>(lane, [&](int e) { st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], sP[e / NX][e % NX]); });
+                each_elem<NX>(lane, [&](int e) { st_shared_dev(&a.p[lidx<LAY>(n, e, NX, N)], sp[e]); });
             } else {
-                for (int e = lane; e < NX * NX; e += 64) a.P[lidx<LAY>(n, e, NX * NX, N)] = sP[e / NX][e % NX];
-                for (int e = lane; e < NX; e += 64) a.p[lidx<LAY>(n, e, NX, N)] = sp[e];
+                each_elem<NX * NX>(lane, [&](int e) { a.P[lidx<LAY>(n, e, NX * NX, N)] = sP[e / NX][e % NX]; });
+                each_elem<NX>(lane, [&](int e) { a.p[lidx<LAY>(n, e, NX, N)] = sp[e]; });
             }
             if (par < 0) return false;
             pref = nsib == 1;
