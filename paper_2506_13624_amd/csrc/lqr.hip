@@ -455,7 +455,7 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
     __shared__ __align__(16) double sp[NX];
     __shared__ __align__(16) double sS[NX][NDP];   // P [A B c] + [0 0 p]
     __shared__ __align__(16) double sZ[NZ][NDP];   // [[W . w],[G H g]]
-    __shared__ __align__(16) double sK[NU][NX + 1];
+    __shared__ __align__(16) double sGh[NU][NX + 1];  // L^-1 [G g], L L^T = H
     __shared__ int sgo;
 
     const int l = blockIdx.x;
@@ -515,6 +515,15 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
         wave_sync();
         for (int tt = lane; tt < (NZP / 2) * NQ; tt += 64) {
             const int r0 = 2 * (tt / NQ), c4 = 4 * (tt % NQ);
+            // the tile's current Z, requested before the sums
+            double2 old[2][2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int r = (NZP == NZ || r0 + i < NZ) ? r0 + i : NZ - 1;
+                const double2* zr = reinterpret_cast<const double2*>(&sZ[r][c4]);
+                old[i][0] = zr[0];
+                old[i][1] = zr[1];
+            }
             double z[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
             for (int k = 0; k < NX; ++k) {
@@ -539,7 +548,7 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                 const int r = r0 + i;
                 if (NZP == NZ || r < NZ) {
                     double2* zr = reinterpret_cast<double2*>(&sZ[r][c4]);
-                    double2 z01 = zr[0], z23 = zr[1];
+                    double2 z01 = old[i][0], z23 = old[i][1];
                     z01.x += z[i][0];
                     z01.y += z[i][1];
                     z23.x += z[i][2];
@@ -627,73 +636,92 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
                     merge_pre = false;
                     prefetch_two(in, oth, par, nsib, inf_next);
                 }
-                // gains: lane i < NX solves column i of K, lane NX solves k
-                if (lane <= NX) {
+                // Gains with H = L L^T: every lane factors H; lane i < NX
+                // takes column i of G, the others the column g.  With
+                // Gh = L^-1 [G g]:  [K k] = -L^-T Gh,  G^T K = -Gh^T Gh and
+                // G^T k = -Gh^T gh, so P and p need only Gh, and K, k go to
+                // memory straight from the lanes' registers.
+                {
                     double L[NU][NU], inv[NU];
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < NU; ++i)
-    #pragma unroll
+#pragma unroll
                         for (int j = 0; j < NU; ++j) L[i][j] = sZ[NX + i][NX + j];
                     const bool ok = chol_inplace_rsq<NU>(L, inv);
                     if (!ok && lane == 0) atomicMin(a.bad, n);
-                    double v[NU];
                     const int col = lane < NX ? lane : NZ;
-    #pragma unroll
+                    const int gcol = lane < NX ? lane : NX;
+                    double v[NU];
+#pragma unroll
                     for (int i = 0; i < NU; ++i) v[i] = sZ[NX + i][col];
-                    chol_solve<NU>(L, inv, v);
-    #pragma unroll
-                    for (int i = 0; i < NU; ++i) sK[i][lane] = -v[i];
+                    chol_fwd<NU>(L, inv, v);
+#pragma unroll
+                    for (int i = 0; i < NU; ++i) sGh[i][gcol] = v[i];
+                    chol_bwd<NU>(L, inv, v);
+#pragma unroll
+                    for (int i = 0; i < NU; ++i) {
+                        double* dst = lane < NX ? &a.K[lidx<LAY>(n, i * NX + lane, NU * NX, N)]
+                                                : &a.k[lidx<LAY>(n, i, NU, N)];
+                        *dst = -v[i];
+                    }
                 }
                 wave_sync();
-                each_elem<NU * NX>(lane, [&](int e) { a.K[lidx<LAY>(n, e, NU * NX, N)] = sK[e / NX][e % NX]; });
-                each_elem<NU>(lane, [&](int e) { a.k[lidx<LAY>(n, e, NU, N)] = sK[e][NX]; });
-                // P = sym(W + G^T K), p = w + G^T k   (the child's P in sP is no longer needed)
-                constexpr int PS = (NX * NX + 63) / 64, VS = (NX + 63) / 64;
-                double pv[PS], qv[VS];
+                // P = (W + W^T)/2 - Gh^T Gh (exactly symmetric), p = w - Gh^T gh;
                 // every lane computes (lanes past the end repeat the last
                 // element), so that the slots' sums interleave
+                constexpr int PS = (NX * NX + 63) / 64, VS = (NX + 63) / 64;
+                double pv[PS], qv[VS];
 #pragma unroll
                 for (int s = 0; s < PS; ++s) {
                     const int e0 = lane + 64 * s;
                     const int e = e0 < NX * NX ? e0 : NX * NX - 1;
                     const int i = e / NX, j = e % NX;
-                    double tij = 0.0, tji = 0.0;
+                    double t = 0.0;
 #pragma unroll
-                    for (int rr = 0; rr < NU; ++rr) {
-                        tij += sZ[NX + rr][i] * sK[rr][j];
-                        tji += sZ[NX + rr][j] * sK[rr][i];
-                    }
-                    pv[s] = 0.5 * ((sZ[i][j] + tij) + (sZ[j][i] + tji));
+                    for (int rr = 0; rr < NU; ++rr) t = fma(sGh[rr][i], sGh[rr][j], t);
+                    pv[s] = 0.5 * (sZ[i][j] + sZ[j][i]) - t;
                 }
 #pragma unroll
                 for (int s = 0; s < VS; ++s) {
                     const int i0 = lane + 64 * s;
                     const int i = i0 < NX ? i0 : NX - 1;
-                    double tt = 0.0;
+                    double t = 0.0;
 #pragma unroll
-                    for (int rr = 0; rr < NU; ++rr) tt += sZ[NX + rr][i] * sK[rr][NX];
-                    qv[s] = sZ[i][NZ] + tt;
+                    for (int rr = 0; rr < NU; ++rr) t = fma(sGh[rr][i], sGh[rr][NX], t);
+                    qv[s] = sZ[i][NZ] - t;
                 }
-                wave_sync();
+                // (the child's P in sP was last read by the products)
 #pragma unroll
                 for (int s = 0; s < PS; ++s) {
                     const int e0 = lane + 64 * s;
                     const int e = e0 < NX * NX ? e0 : NX * NX - 1;
                     sP[e / NX][e % NX] = pv[s];
+                    if (nsib > 1)
+                        st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], pv[s]);
+                    else
+                        a.P[lidx<LAY>(n, e, NX * NX, N)] = pv[s];
                 }
 #pragma unroll
                 for (int s = 0; s < VS; ++s) {
                     const int i0 = lane + 64 * s;
-                    sp[i0 < NX ? i0 : NX - 1] = qv[s];
+                    const int i = i0 < NX ? i0 : NX - 1;
+                    sp[i] = qv[s];
+                    if (nsib > 1)
+                        st_shared_dev(&a.p[lidx<LAY>(n, i, NX, N)], qv[s]);
+                    else
+                        a.p[lidx<LAY>(n, i, NX, N)] = qv[s];
                 }
                 wave_sync();
             }
-            if (nsib > 1) {
-                each_elem<NX * NX>(lane, [&](int e) { st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], sP[e / NX][e % NX]); });
-                each_elem<NX>(lane, [&](int e) { st_shared_dev(&a.p[lidx<LAY>(n, e, NX, N)], sp[e]); });
-            } else {
-                each_elem<NX * NX>(lane, [&](int e) { a.P[lidx<LAY>(n, e, NX * NX, N)] = sP[e / NX][e % NX]; });
-                each_elem<NX>(lane, [&](int e) { a.p[lidx<LAY>(n, e, NX, N)] = sp[e]; });
+            if (c0 == c1) {
+                // leaf: P = Q_f, p = q_f, already in sP, sp
+                if (nsib > 1) {
+                    each_elem<NX * NX>(lane, [&](int e) { st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], sP[e / NX][e % NX]); });
+                    each_elem<NX>(lane, [&](int e) { st_shared_dev(&a.p[lidx<LAY>(n, e, NX, N)], sp[e]); });
+                } else {
+                    each_elem<NX * NX>(lane, [&](int e) { a.P[lidx<LAY>(n, e, NX * NX, N)] = sP[e / NX][e % NX]; });
+                    each_elem<NX>(lane, [&](int e) { a.p[lidx<LAY>(n, e, NX, N)] = sp[e]; });
+                }
             }
             if (par < 0) return false;
             pref = nsib == 1;

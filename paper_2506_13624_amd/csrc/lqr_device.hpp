@@ -97,6 +97,30 @@ __device__ __forceinline__ bool chol_inplace_rsq(double (&H)[n][n], double (&inv
     return ok;
 }
 
+// The two halves of chol_solve: v <- L^-1 v and v <- L^-T v.
+template <int n>
+__device__ __forceinline__ void chol_fwd(const double (&L)[n][n], const double (&inv)[n], double (&v)[n])
+{
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+        double s = v[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[i][k] * v[k];
+        v[i] = s * inv[i];
+    }
+}
+template <int n>
+__device__ __forceinline__ void chol_bwd(const double (&L)[n][n], const double (&inv)[n], double (&v)[n])
+{
+#pragma unroll
+    for (int i = n - 1; i >= 0; --i) {
+        double s = v[i];
+#pragma unroll
+        for (int k = i + 1; k < n; ++k) s -= L[k][i] * v[k];
+        v[i] = s * inv[i];
+    }
+}
+
 // Solve (L L^T) v = v in place, given the reciprocal diagonal.
 template <int n>
 __device__ __forceinline__ void chol_solve(const double (&L)[n][n], const double (&inv)[n], double (&v)[n])
