@@ -434,6 +434,8 @@ struct WaveIn {
     }
 };
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 // Single-wavefront workgroups: LDS accesses of one wavefront complete in
 // issue order, so ordering them only needs a compiler-level fence.
 __device__ __forceinline__ void wave_sync()
@@ -492,7 +494,57 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
 
     // S = P [A B c] (+p in the last column), tiles of 1 row x 4 columns;
     // then Z += [A B]^T S, tiles of 2 rows x 4 columns
+    // With NZ = 16 (nx + nu = 16) the products run on the FP64 matrix
+    // cores (v_mfma_f64_16x16x4, k = 4 per call):
+    //   S  = P [A B]           (rows >= NX of the A operand are zero)
+    //   S' = P [c 0 ..] + [p 0 ..]
+    //   Z  += [A B]^T S,  Z[:, NZ] += [A B]^T S'[:, 0]
+    // Lane l holds A operand entry (l % 16, l / 16), B operand entry
+    // (l / 16, l % 16) and result entries (l / 16 + 4 v, l % 16), v < 4: the
+    // result of S in element v is exactly the B operand of the Z product
+    // for its k-block v, so S never leaves the registers, and [A B] serves
+    // as the B operand of S and the A operand of Z.
+    auto add_child_mfma = [&]() {
+        wave_sync();
+        const int li = lane & 15, lk = lane >> 4;
+        double d[3], pa[3], cb[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            d[m] = sD[4 * m + lk][li];
+            pa[m] = li < NX ? sP[li][4 * m + lk] : 0.0;
+            cb[m] = li == 0 ? sD[4 * m + lk][NZ] : 0.0;
+        }
+        f64x4 sm = {0.0, 0.0, 0.0, 0.0}, sc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sc[v] = (li == 0 && lk + 4 * v < NX) ? sp[lk + 4 * v] : 0.0;
+        f64x4 zm, zc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            zm[v] = sZ[lk + 4 * v][li];
+            zc[v] = li == 0 ? sZ[lk + 4 * v][NZ] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            sm = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[m], d[m], sm, 0, 0, 0);
+            sc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[m], cb[m], sc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            zm = __builtin_amdgcn_mfma_f64_16x16x4f64(d[m], sm[m], zm, 0, 0, 0);
+            zc = __builtin_amdgcn_mfma_f64_16x16x4f64(d[m], sc[m], zc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            sZ[lk + 4 * v][li] = zm[v];
+            if (li == 0) sZ[lk + 4 * v][NZ] = zc[v];
+        }
+        wave_sync();
+    };
     auto add_child = [&]() {
+        if constexpr (NZ == 16) {
+            add_child_mfma();
+            return;
+        }
         wave_sync();
         for (int tt = lane; tt < NX * NQ; tt += 64) {
             const int r = tt / NQ, c4 = 4 * (tt % NQ);
