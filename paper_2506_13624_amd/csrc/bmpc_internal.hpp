@@ -49,6 +49,7 @@ struct TreeDev {
     const int* leaf_stage;// num_leaves
     const int* path;      // (depth+1) x num_leaves: node at stage t on the path of leaf l
     const int* first_leaf;// N: smallest leaf index below n (the node's designated writer)
+    const int* write_from;// num_leaves: path l writes the nodes of stages >= write_from[l]
     // segment scan structure
     int num_segments;
     const int* seg_start; // S: first (top) node of segment s
@@ -64,7 +65,7 @@ struct TreeDev {
 };
 
 struct HostTree {
-    std::vector<int> parent, child_off, stage, leaves, leaf_stage, path, first_leaf;
+    std::vector<int> parent, child_off, stage, leaves, leaf_stage, path, first_leaf, write_from;
     std::vector<int4> info;
     std::vector<int> level_off;
     std::vector<int> seg_start, seg_end, seg_len, seg_of, seg_pos, seg_nodes, seg_off, seg_depth;

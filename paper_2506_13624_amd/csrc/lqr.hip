@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <utility>
 
 #include "bmpc_internal.hpp"
 #include "cvf_device.hpp"
@@ -806,87 +807,155 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
 // ------------------------------------------------------------------------
 // forward rollout: G lanes per root-to-leaf path, inputs D steps ahead
 // ------------------------------------------------------------------------
+// Value of lane j of each row of 16 lanes, for every lane of the row
+// (one DPP move, row_newbcast, instead of a trip through the LDS crossbar).
+template <int J>
+__device__ __forceinline__ double row_bcast(double v)
+{
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xf, 0xf, false);
+}
+template <int J>
+__device__ __forceinline__ int row_bcast_int(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x150 + J, 0xf, 0xf, false);
+}
+// lane J of the group of G lanes that starts at lane base
+template <int G, int J>
+__device__ __forceinline__ double group_value(double v, int base)
+{
+    if constexpr (G == 16)
+        return row_bcast<J>(v);
+    else
+        return __shfl(v, base + J, 64);
+}
+template <int G, int J>
+__device__ __forceinline__ int group_value_int(int v, int base)
+{
+    if constexpr (G == 16)
+        return row_bcast_int<J>(v);
+    else
+        return __shfl(v, base + J, 64);
+}
+template <int G, int... J>
+__device__ __forceinline__ void group_gather(double v, int base, double* out, std::integer_sequence<int, J...>)
+{
+    ((out[J] = group_value<G, J>(v, base)), ...);
+}
+template <class F, int... K>
+__device__ __forceinline__ void unroll_impl(F&& f, std::integer_sequence<int, K...>)
+{
+    (f(std::integral_constant<int, K>{}), ...);
+}
+template <int CNT, class F>
+__device__ __forceinline__ void unroll(F&& f)
+{
+    unroll_impl(f, std::make_integer_sequence<int, CNT>{});
+}
+
+// One step of a path: lane g < NX holds row g of [A B c] of the edge into
+// the next node; lane NX + i holds row i of [K k] of the node (lanes past
+// NX + NU repeat the last row).  Both roles evaluate r = w . x + c0, which is
+// A x + c on the first lanes and u = K x + k on the others.
 template <int NX, int NU>
-struct FwdStep {
-    int n, m;    // node of this step and the next node on the path (-1: none)
-    int writer;  // this path writes node n
-    double K[NX], k, A[NX], B[NU], c;
+struct FwdRow {
+    double w[NX], b[NU], c0;
 };
 
 template <int NX, int NU, int LAY>
-__device__ __forceinline__ void fwd_fill(const TreeDev& t, const LqrArgs& a, int path, int last, int s,
-                                         int g, FwdStep<NX, NU>& f)
+__device__ __forceinline__ void fwd_row_fill(const LqrArgs& a, int N, int n, int m, int g, FwdRow<NX, NU>& f)
 {
-    const int N = t.N, Z = t.num_leaves;
-    f.n = s <= last ? t.path[(long)s * Z + path] : -1;
-    f.m = s < last ? t.path[(long)(s + 1) * Z + path] : -1;
-    f.writer = f.n >= 0 ? (t.first_leaf[f.n] == path) : 0;
-    if (f.m >= 0) {
-        if (g < NU) {
+    // the last step of a path needs no inputs, and stages past its end
+    // none at all: those read the entries of node n, or of the root, which
+    // are in bounds, so that the loads need no branch
+    const int nn = n >= 0 ? n : 0;
+    const int me = m >= 0 ? m : nn;
+    const bool krow = g >= NX;
+    const int i = krow ? (g - NX < NU ? g - NX : NU - 1) : g;
+    const double* wp = krow ? a.K : a.A;
+    const int wn = krow ? nn : me, wsz = krow ? NU * NX : NX * NX;
 #pragma unroll
-            for (int j = 0; j < NX; ++j) f.K[j] = a.K[lidx<LAY>(f.n, g * NX + j, NU * NX, N)];
-            f.k = a.k[lidx<LAY>(f.n, g, NU, N)];
-        }
-        if (g < NX) {
+    for (int j = 0; j < NX; ++j) f.w[j] = wp[lidx<LAY>(wn, i * NX + j, wsz, N)];
+    const int ib = krow ? 0 : i;
 #pragma unroll
-            for (int j = 0; j < NX; ++j) f.A[j] = a.A[lidx<LAY>(f.m, g * NX + j, NX * NX, N)];
-#pragma unroll
-            for (int j = 0; j < NU; ++j) f.B[j] = a.B[lidx<LAY>(f.m, g * NU + j, NX * NU, N)];
-            f.c = a.c[lidx<LAY>(f.m, g, NX, N)];
-        }
-    }
+    for (int j = 0; j < NU; ++j) f.b[j] = a.B[lidx<LAY>(me, ib * NU + j, NX * NU, N)];
+    f.c0 = krow ? a.k[lidx<LAY>(nn, i, NU, N)] : a.c[lidx<LAY>(me, i, NX, N)];
 }
 
 template <int NX, int NU, int LAY, int G, int D>
 __global__ void __launch_bounds__(64) k_fwd_rows(TreeDev t, LqrArgs a)
 {
-    static_assert(G >= NX && G >= NU && 64 % G == 0, "group must cover the rows");
+    static_assert(NX + NU <= G && 64 % G == 0 && G % D == 0, "group must hold the rows of [A B c] and [K k]");
     const int tid = blockIdx.x * 64 + threadIdx.x;
     const int path = tid / G;
     const int g = tid % G;
     const int base = (int)threadIdx.x - g;
-    const int N = t.N;
-    if (path >= t.num_leaves) return;  // whole group leaves together
+    const int N = t.N, Z = t.num_leaves;
+    if (path >= Z) return;  // whole group leaves together
     const int last = t.leaf_stage[path];
-    FwdStep<NX, NU> ring[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) fwd_fill<NX, NU, LAY>(t, a, path, last, d, g, ring[d]);
+    const int wfrom = t.write_from[path];
+    // node ids, one block of G stages per register: lane g of the group
+    // holds the node at stage s0 + g; two blocks are held and the next one
+    // is requested a block ahead
+    auto ids = [&](int s0) -> int {
+        const int s = s0 + g;
+        return s <= last ? t.path[(long)s * Z + path] : -1;
+    };
+    int blk0 = ids(0), blk1 = ids(G);
+    FwdRow<NX, NU> ring[D];
+    // node at stage s0 + K (K a constant, K < 2G) of the blocks held
+    auto node_at = [&](auto kc) -> int {
+        constexpr int K = decltype(kc)::value;
+        if constexpr (K < G)
+            return group_value_int<G, K>(blk0, base);
+        else
+            return group_value_int<G, K - G>(blk1, base);
+    };
+    unroll<D>([&](auto dc) {
+        constexpr int d = decltype(dc)::value;
+        fwd_row_fill<NX, NU, LAY>(a, N, node_at(std::integral_constant<int, d>{}),
+                                  node_at(std::integral_constant<int, d + 1>{}), g, ring[d]);
+    });
     double xg = g < NX ? a.x0[g] : 0.0;
-    for (int s0 = 0; s0 <= last; s0 += D) {
+    for (int s0 = 0; s0 <= last; s0 += G) {
+        const int blk2 = ids(s0 + 2 * G);
+        unroll<G>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int s = s0 + k;
+            // no branch in a step except around the stores: a value that is
+            // kept on one side of a branch and loaded on the other would be
+            // merged by a copy, and the copy waits for every load in flight
+            const bool live = s <= last, fin = s == last;
+            FwdRow<NX, NU>& f = ring[k % D];
+            const int n = node_at(std::integral_constant<int, k>{});
+            const bool writer = live && s >= wfrom;
+            double xs[NX];
+            group_gather<G>(xg, base, xs, std::make_integer_sequence<int, NX>{});
+            if (writer && g < NX) a.x[lidx<LAY>(n, g, NX, N)] = xg;
+            double r = f.c0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const int s = s0 + d;
-            if (s <= last) {
-                const FwdStep<NX, NU>& f = ring[d];
-                double xs[NX];
+            for (int j = 0; j < NX; ++j) r += f.w[j] * xs[j];
+            if (writer && g >= NX && g < NX + NU) a.u[lidx<LAY>(n, g - NX, NU, N)] = fin ? 0.0 : r;
+            double us[NU];
+            unroll<NU>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                us[i] = group_value<G, NX + i>(r, base);
+            });
 #pragma unroll
-                for (int j = 0; j < NX; ++j) xs[j] = __shfl(xg, base + j, 64);
-                if (f.writer && g < NX) a.x[lidx<LAY>(f.n, g, NX, N)] = xg;
-                if (s == last) {
-                    if (f.writer && g < NU) a.u[lidx<LAY>(f.n, g, NU, N)] = 0.0;
-                } else {
-                    double ug = 0.0;
-                    if (g < NU) {
-                        ug = f.k;
-#pragma unroll
-                        for (int j = 0; j < NX; ++j) ug += f.K[j] * xs[j];
-                        if (f.writer) a.u[lidx<LAY>(f.n, g, NU, N)] = ug;
-                    }
-                    double us[NU];
-#pragma unroll
-                    for (int j = 0; j < NU; ++j) us[j] = __shfl(ug, base + j, 64);
-                    if (g < NX) {
-                        double acc = f.c;
-#pragma unroll
-                        for (int j = 0; j < NX; ++j) acc += f.A[j] * xs[j];
-#pragma unroll
-                        for (int j = 0; j < NU; ++j) acc += f.B[j] * us[j];
-                        xg = acc;
-                    }
-                }
-                fwd_fill<NX, NU, LAY>(t, a, path, last, s + D, g, ring[d]);
+            for (int j = 0; j < NU; ++j) r += f.b[j] * us[j];
+            xg = (live && !fin) ? r : xg;
+            // refill with the inputs of stage s + D
+            if constexpr (k + D + 1 < 2 * G) {
+                fwd_row_fill<NX, NU, LAY>(a, N, node_at(std::integral_constant<int, k + D>{}),
+                                          node_at(std::integral_constant<int, k + D + 1>{}), g, f);
+            } else {
+                // stage s + D + 1 lies in the block after next
+                const int n1 = node_at(std::integral_constant<int, k + D>{});
+                const int n2 = group_value_int<G, k + D + 1 - 2 * G>(blk2, base);
+                fwd_row_fill<NX, NU, LAY>(a, N, n1, n2, g, f);
             }
-        }
+        });
+        blk0 = blk1;
+        blk1 = blk2;
     }
 }
 
@@ -933,8 +1002,8 @@ struct LqrKernels {
 template <int NX, int NU, int LAY, bool LANE>
 static LqrKernels make_k()
 {
-    constexpr int G = NX <= 4 ? 4 : (NX <= 8 ? 8 : 16);
-    LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, nullptr, k_fwd_rows<NX, NU, LAY, G, 3>,
+    constexpr int G = NX + NU <= 4 ? 4 : (NX + NU <= 8 ? 8 : 16);
+    LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, nullptr, k_fwd_rows<NX, NU, LAY, G, 4>,
                  k_costate<NX, LAY>};
     if constexpr (LANE) k.bwd_lane = k_bwd_lane<NX, NU, LAY>;
     if constexpr (NX <= 4) k.bwd_seg = k_bwd_seg<NX, NU, LAY>;

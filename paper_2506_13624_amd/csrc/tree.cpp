@@ -79,6 +79,15 @@ static bmpc_status analyse(const int32_t* parent, int32_t N, HostTree& h)
     h.path.assign((size_t)(h.depth + 1) * Z, -1);
     for (int l = 0; l < Z; ++l)
         for (int n = h.leaves[l]; n >= 0; n = parent[n]) h.path[(size_t)h.stage[n] * Z + l] = n;
+    // a path is the designated writer of a node exactly when it is the
+    // smallest leaf below it; going up from the leaf, that holds for an
+    // unbroken run of ancestors, so one stage per path describes it
+    h.write_from.resize(Z);
+    for (int l = 0; l < Z; ++l) {
+        int n = h.leaves[l];
+        while (parent[n] >= 0 && h.first_leaf[parent[n]] == l) n = parent[n];
+        h.write_from[l] = h.stage[n];
+    }
 
     // maximal unbranched segments: start at the root or at a child of a node
     // with >= 2 children; continue through single-child nodes
@@ -146,7 +155,7 @@ bmpc_status tree_on_device(bmpc_tree* t)
     bmpc_status st;
 #define UP(field) \
     if ((st = upload(t, h.field, &d.field)) != BMPC_OK) return st;
-    UP(parent) UP(child_off) UP(info) UP(stage) UP(level_off) UP(leaves) UP(leaf_stage) UP(path) UP(first_leaf)
+    UP(parent) UP(child_off) UP(info) UP(stage) UP(level_off) UP(leaves) UP(leaf_stage) UP(path) UP(first_leaf) UP(write_from)
     UP(seg_start) UP(seg_end) UP(seg_len) UP(seg_of) UP(seg_pos) UP(seg_nodes) UP(seg_off) UP(seg_depth)
 #undef UP
     t->on_device = true;
