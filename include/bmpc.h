@@ -420,6 +420,10 @@ BMPC_API void bmpc_graph_destroy(bmpc_graph* graph);
  * ---------------------------------------------------------------------- */
 /* Enable (on != 0) or disable timing; clears the accumulated totals. */
 BMPC_API bmpc_status bmpc_profile_enable(int32_t on);
+/* Restrict timing to the launches whose kernel name equals `name` (host
+   string, copied; NULL or "" times every launch again), so that a run can
+   time its dominant kernel without the event gaps around the others. */
+BMPC_API bmpc_status bmpc_profile_only(const char* name);
 /* Waits for the recorded events and returns the number of distinct kernel
    names timed since the last read; fills up to `cap` entries: names
    (host, 64 bytes per entry, NUL-terminated), total_ms (host, summed event

@@ -65,6 +65,7 @@ _sig("bmpc_lqr_solve", _i32, [_vp] + [_vp] * 16 + [_i32, _vp])
 _sig("bmpc_lqr_check", _i32, [_vp, _pi32, _vp])
 _sig("bmpc_profile_enable", _i32, [_i32])
 _sig("bmpc_profile_read", _i32, [C.c_char_p, _pd, _pi32, _i32])
+_sig("bmpc_profile_only", _i32, [C.c_char_p])
 
 
 def check(status):
@@ -171,6 +172,10 @@ def bmpc_lqr_check(plan, stream=None):
 
 def bmpc_profile_enable(on=True):
     check(lib.bmpc_profile_enable(1 if on else 0))
+
+
+def bmpc_profile_only(name=None):
+    check(lib.bmpc_profile_only(name.encode() if name else None))
 
 
 def bmpc_profile_read(cap=64):

@@ -25,6 +25,7 @@ bool g_on = false;
 std::vector<hipEvent_t> g_pool;
 std::vector<Rec> g_pending;
 std::map<std::string, std::pair<double, int>> g_tot;
+std::string g_only;  // empty: every launch
 
 hipEvent_t take_event()
 {
@@ -64,6 +65,7 @@ ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), s_(s)
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_only.empty() && g_only != name) return;
     a_ = take_event();
     if (a_) (void)hipEventRecord(a_, s_);
 }
@@ -89,6 +91,13 @@ BMPC_API bmpc_status bmpc_profile_enable(int32_t on)
     resolve_locked();
     g_tot.clear();
     g_on = on != 0;
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_profile_only(const char* name)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_only = name ? name : "";
     return BMPC_OK;
 }
 
