@@ -1002,7 +1002,8 @@ struct LqrKernels {
 template <int NX, int NU, int LAY, bool LANE>
 static LqrKernels make_k()
 {
-    constexpr int G = NX + NU <= 4 ? 4 : (NX + NU <= 8 ? 8 : 16);
+    // rows of 16 lanes: the broadcasts inside a group are DPP row moves
+    constexpr int G = 16;
     LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, nullptr, k_fwd_rows<NX, NU, LAY, G, 4>,
                  k_costate<NX, LAY>};
     if constexpr (LANE) k.bwd_lane = k_bwd_lane<NX, NU, LAY>;
