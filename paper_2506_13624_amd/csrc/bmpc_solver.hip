@@ -323,71 +323,99 @@ __device__ void pass_defects_kkt(const InstDesc& I, double& rk, double& ld, doub
 
 // Backward tree Riccati, one stage per barrier.  Returns false (and sets
 // *bad) if some H_n is not positive definite.
+// One node of the backward pass: gains and value function from its stage
+// data and its children's value functions (workspace rows).
+__device__ __forceinline__ void ric_node_ws(const InstDesc& I, int n, int* bad)
+{
+    double* w = I.ws + (long)n * W_NODE;
+    const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+    if (c0 == c1) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) w[W_P + e] = w[W_Q + e];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[W_PV + e] = w[W_QV + e];
+        return;
+    }
+    StageRegs<BX, BU> st;
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) st.Q[i][j] = w[W_Q + i * 4 + j];
+        st.q[i] = w[W_QV + i];
+    }
+#pragma unroll
+    for (int i = 0; i < BU; ++i) {
+#pragma unroll
+        for (int j = 0; j < BU; ++j) st.R[i][j] = w[W_R + i * 2 + j];
+#pragma unroll
+        for (int j = 0; j < BX; ++j) st.M[i][j] = 0.0;
+        st.r[i] = w[W_RV + i];
+    }
+    RicAcc<BX, BU> acc;
+    acc.init(st);
+    EdgeRegs<BX, BU> ed;
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) ed.A[i][j] = w[W_A + i * 4 + j];
+#pragma unroll
+        for (int j = 0; j < BU; ++j) ed.B[i][j] = w[W_B + i * 2 + j];
+    }
+    for (int j = c0; j < c1; ++j) {
+        const double* wj = I.ws + (long)j * W_NODE;
+        double P[BX][BX], p[BX];
+#pragma unroll
+        for (int i = 0; i < BX; ++i) {
+#pragma unroll
+            for (int k = 0; k < BX; ++k) P[i][k] = wj[W_P + i * 4 + k];
+            p[i] = wj[W_PV + i];
+            ed.c[i] = wj[W_C + i];
+        }
+        acc.add_child(ed, P, p);
+    }
+    double K[BU][BX], k[BU], P[BX][BX], p[BX];
+    if (!acc.finish(K, k, P, p)) atomicMin(bad, n);
+#pragma unroll
+    for (int i = 0; i < BU; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) w[W_K + i * 4 + j] = K[i][j];
+        w[W_KV + i] = k[i];
+    }
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) w[W_P + i * 4 + j] = P[i][j];
+        w[W_PV + i] = p[i];
+    }
+}
+
 template <class T>
 __device__ void pass_riccati(const InstDesc& I, int* bad)
 {
     for (int t = I.T; t >= 0; --t) {
         const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
-        for (int n = n0 + T::rank(); n < n1; n += T::size()) {
-            double* w = I.ws + (long)n * W_NODE;
-            const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
-            if (c0 == c1) {
-#pragma unroll
-                for (int e = 0; e < 16; ++e) w[W_P + e] = w[W_Q + e];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) w[W_PV + e] = w[W_QV + e];
-                continue;
-            }
-            StageRegs<BX, BU> st;
-#pragma unroll
-            for (int i = 0; i < BX; ++i) {
-#pragma unroll
-                for (int j = 0; j < BX; ++j) st.Q[i][j] = w[W_Q + i * 4 + j];
-                st.q[i] = w[W_QV + i];
-            }
-#pragma unroll
-            for (int i = 0; i < BU; ++i) {
-#pragma unroll
-                for (int j = 0; j < BU; ++j) st.R[i][j] = w[W_R + i * 2 + j];
-#pragma unroll
-                for (int j = 0; j < BX; ++j) st.M[i][j] = 0.0;
-                st.r[i] = w[W_RV + i];
-            }
-            RicAcc<BX, BU> acc;
-            acc.init(st);
-            EdgeRegs<BX, BU> ed;
-#pragma unroll
-            for (int i = 0; i < BX; ++i) {
-#pragma unroll
-                for (int j = 0; j < BX; ++j) ed.A[i][j] = w[W_A + i * 4 + j];
-#pragma unroll
-                for (int j = 0; j < BU; ++j) ed.B[i][j] = w[W_B + i * 2 + j];
-            }
-            for (int j = c0; j < c1; ++j) {
-                const double* wj = I.ws + (long)j * W_NODE;
-                double P[BX][BX], p[BX];
-#pragma unroll
-                for (int i = 0; i < BX; ++i) {
-#pragma unroll
-                    for (int k = 0; k < BX; ++k) P[i][k] = wj[W_P + i * 4 + k];
-                    p[i] = wj[W_PV + i];
-                    ed.c[i] = wj[W_C + i];
-                }
-                acc.add_child(ed, P, p);
-            }
-            double K[BU][BX], k[BU], P[BX][BX], p[BX];
-            if (!acc.finish(K, k, P, p)) atomicMin(bad, n);
-#pragma unroll
-            for (int i = 0; i < BU; ++i) {
-#pragma unroll
-                for (int j = 0; j < BX; ++j) w[W_K + i * 4 + j] = K[i][j];
-                w[W_KV + i] = k[i];
-            }
-#pragma unroll
-            for (int i = 0; i < BX; ++i) {
-#pragma unroll
-                for (int j = 0; j < BX; ++j) w[W_P + i * 4 + j] = P[i][j];
-                w[W_PV + i] = p[i];
+        for (int n = n0 + T::rank(); n < n1; n += T::size()) ric_node_ws(I, n, bad);
+        T::sync();
+    }
+}
+
+// The same backward pass by segment depth: one thread walks a maximal
+// unbranched segment from its bottom node (a leaf, or a branching node
+// whose children start deeper segments, done in an earlier round) up to
+// its top, so a round of the whole team covers a segment depth instead
+// of a stage: on a tree that branches every few stages far fewer team
+// barriers, and the same operations per node, so the same results.
+template <class T>
+__device__ void pass_riccati_seg(const InstDesc& I, int* bad)
+{
+    for (int d = I.max_seg_depth; d >= 0; --d) {
+        for (int n = T::rank(); n < I.N; n += T::size()) {
+            const int s = I.seg_of[n];
+            if (I.seg_end[s] != n || I.seg_depth[s] != d) continue;
+            const int top = I.seg_nodes[I.seg_off[s]];
+            for (int m = n;; m = I.parent[m]) {
+                ric_node_ws(I, m, bad);
+                if (m == top) break;
             }
         }
         T::sync();
@@ -813,6 +841,47 @@ __device__ void pass_forward_lds(const InstDesc& I, double* sn)
 
 // Forward linear rollout of the deviations (delta x_0 = 0) and the LQR
 // costates lam_hat = P dx + p.
+// One node of the forward pass: costate estimate, control step and the
+// state steps of its children.
+__device__ __forceinline__ void fwd_node_ws(const InstDesc& I, int n)
+{
+    double* w = I.ws + (long)n * W_NODE;
+    double dx[BX];
+    load4(w + W_DX, dx);
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+        double acc = w[W_PV + i];
+#pragma unroll
+        for (int j = 0; j < BX; ++j) acc += w[W_P + i * 4 + j] * dx[j];
+        w[W_LH + i] = acc;
+    }
+    const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+    double du[BU] = {0.0, 0.0};
+    if (c1 > c0) {
+#pragma unroll
+        for (int i = 0; i < BU; ++i) {
+            double acc = w[W_KV + i];
+#pragma unroll
+            for (int j = 0; j < BX; ++j) acc += w[W_K + i * 4 + j] * dx[j];
+            du[i] = acc;
+        }
+        for (int j = c0; j < c1; ++j) {
+            double* wj = I.ws + (long)j * W_NODE;
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+                double acc = wj[W_C + i];
+#pragma unroll
+                for (int k = 0; k < BX; ++k) acc += w[W_A + i * 4 + k] * dx[k];
+#pragma unroll
+                for (int k = 0; k < BU; ++k) acc += w[W_B + i * 2 + k] * du[k];
+                wj[W_DX + i] = acc;
+            }
+        }
+    }
+    w[W_DU] = du[0];
+    w[W_DU + 1] = du[1];
+}
+
 template <class T>
 __device__ void pass_forward(const InstDesc& I)
 {
@@ -822,42 +891,27 @@ __device__ void pass_forward(const InstDesc& I)
     T::sync();
     for (int t = 0; t <= I.T; ++t) {
         const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
-        for (int n = n0 + T::rank(); n < n1; n += T::size()) {
-            double* w = I.ws + (long)n * W_NODE;
-            double dx[BX];
-            load4(w + W_DX, dx);
+        for (int n = n0 + T::rank(); n < n1; n += T::size()) fwd_node_ws(I, n);
+        T::sync();
+    }
+}
+
+// The forward pass by segment depth: one thread walks a segment from its
+// top down (each node sets its children's state steps, read next by the
+// same thread or, for the tops of deeper segments, in a later round).
+template <class T>
+__device__ void pass_forward_seg(const InstDesc& I)
+{
+    if (T::rank() == 0)
 #pragma unroll
-            for (int i = 0; i < BX; ++i) {
-                double acc = w[W_PV + i];
-#pragma unroll
-                for (int j = 0; j < BX; ++j) acc += w[W_P + i * 4 + j] * dx[j];
-                w[W_LH + i] = acc;
-            }
-            const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
-            double du[BU] = {0.0, 0.0};
-            if (c1 > c0) {
-#pragma unroll
-                for (int i = 0; i < BU; ++i) {
-                    double acc = w[W_KV + i];
-#pragma unroll
-                    for (int j = 0; j < BX; ++j) acc += w[W_K + i * 4 + j] * dx[j];
-                    du[i] = acc;
-                }
-                for (int j = c0; j < c1; ++j) {
-                    double* wj = I.ws + (long)j * W_NODE;
-#pragma unroll
-                    for (int i = 0; i < BX; ++i) {
-                        double acc = wj[W_C + i];
-#pragma unroll
-                        for (int k = 0; k < BX; ++k) acc += w[W_A + i * 4 + k] * dx[k];
-#pragma unroll
-                        for (int k = 0; k < BU; ++k) acc += w[W_B + i * 2 + k] * du[k];
-                        wj[W_DX + i] = acc;
-                    }
-                }
-            }
-            w[W_DU] = du[0];
-            w[W_DU + 1] = du[1];
+        for (int i = 0; i < BX; ++i) I.ws[W_DX + i] = 0.0;
+    T::sync();
+    for (int d = 0; d <= I.max_seg_depth; ++d) {
+        for (int n = T::rank(); n < I.N; n += T::size()) {
+            const int s = I.seg_of[n];
+            if (I.seg_pos[n] != 0 || I.seg_depth[s] != d) continue;
+            const int off = I.seg_off[s], len = I.seg_len[s];
+            for (int q = 0; q < len; ++q) fwd_node_ws(I, I.seg_nodes[off + q]);
         }
         T::sync();
     }
@@ -1046,7 +1100,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                 else
                     pass_riccati<T>(I, bad);
             } else {
-                pass_riccati<T>(I, bad);
+                pass_riccati_seg<T>(I, bad);
             }
             if (__hip_atomic_load(bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != INT_MAX) {
                 status = BMPC_ERR_NOT_PD;
@@ -1058,7 +1112,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                 else
                     pass_forward<T>(I);
             } else {
-                pass_forward<T>(I);
+                pass_forward_seg<T>(I);
             }
 
             // merit slope pieces and the current merit
