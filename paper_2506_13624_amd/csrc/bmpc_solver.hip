@@ -196,21 +196,23 @@ struct TeamGrid {
 #pragma unroll
             for (int k = 0; k < K; ++k) gpart[(long)blockIdx.x * K + k] = v[k];
         sync();
-        // thread k of every workgroup combines entry k over the workgroups
-        // (same order everywhere), then shares it through LDS
-        if ((int)threadIdx.x < K) {
-            const int k = threadIdx.x;
-            double t = gpart[k];
-            for (int b = 1; b < (int)gridDim.x; ++b) {
-                const double o = gpart[(long)b * K + k];
-                t = MAX ? ((t != t || o != o) ? NAN : fmax(t, o)) : t + o;
-            }
-            sred[k] = t;
-        }
-        __syncthreads();
+        // every workgroup combines the per-workgroup results the same way:
+        // thread t takes workgroups t, t + BS, ... in order, then the
+        // workgroup's fixed reduction tree; so all of them hold the same
+        // value, and no thread walks all workgroups alone
+        double w[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = sred[k];
-        __syncthreads();
+        for (int k = 0; k < K; ++k) w[k] = MAX ? -INFINITY : 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += BS_) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double o = gpart[(long)b * K + k];
+                w[k] = MAX ? ((w[k] != w[k] || o != o) ? NAN : fmax(w[k], o)) : w[k] + o;
+            }
+        }
+        block_reduce<BS_, K, MAX>(w, sred);
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = w[k];
         sync();  // partials may be overwritten by the next reduction
     }
 };
