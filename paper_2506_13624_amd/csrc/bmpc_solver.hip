@@ -899,8 +899,50 @@ __device__ void pass_forward(const InstDesc& I)
 }
 
 // The forward pass by segment depth: one thread walks a segment from its
-// top down (each node sets its children's state steps, read next by the
-// same thread or, for the tops of deeper segments, in a later round).
+// top down.  The walk keeps the state step in registers and has the next
+// node's K, k, A, B and defect c in flight while a node is computed.  The
+// costate estimates lam_hat = P dx + p, which nothing in the walk needs, are
+// left to the caller's next node-parallel sweep (lam_hat_ws).  The same
+// operations per node as fwd_node_ws, so the same results.
+__device__ __forceinline__ void lam_hat_ws(const InstDesc& I, int n)
+{
+    double* w = I.ws + (long)n * W_NODE;
+    double dx[BX];
+    load4(w + W_DX, dx);
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+        double acc = w[W_PV + i];
+#pragma unroll
+        for (int j = 0; j < BX; ++j) acc += w[W_P + i * 4 + j] * dx[j];
+        w[W_LH + i] = acc;
+    }
+}
+
+struct FwdWalkIn {
+    double K[BU][BX], k[BU], A[BX][BX], B[BX][BU], c[BX];
+    int c0, c1;
+};
+__device__ __forceinline__ void fwd_walk_load(const InstDesc& I, int n, FwdWalkIn& r)
+{
+    const double* w = I.ws + (long)n * W_NODE;
+    r.c0 = I.child_off[n];
+    r.c1 = I.child_off[n + 1];
+#pragma unroll
+    for (int i = 0; i < BU; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) r.K[i][j] = w[W_K + i * 4 + j];
+        r.k[i] = w[W_KV + i];
+    }
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) r.A[i][j] = w[W_A + i * 4 + j];
+#pragma unroll
+        for (int j = 0; j < BU; ++j) r.B[i][j] = w[W_B + i * 2 + j];
+        r.c[i] = w[W_C + i];
+    }
+}
+
 template <class T>
 __device__ void pass_forward_seg(const InstDesc& I)
 {
@@ -913,7 +955,62 @@ __device__ void pass_forward_seg(const InstDesc& I)
             const int s = I.seg_of[n];
             if (I.seg_pos[n] != 0 || I.seg_depth[s] != d) continue;
             const int off = I.seg_off[s], len = I.seg_len[s];
-            for (int q = 0; q < len; ++q) fwd_node_ws(I, I.seg_nodes[off + q]);
+            FwdWalkIn cur, nxt;
+            fwd_walk_load(I, n, cur);
+            double dx[BX];
+            load4(I.ws + (long)n * W_NODE + W_DX, dx);
+            // node ids of the walk: this step's, the next one's (its inputs
+            // are requested now) and the one after (requested a step ahead)
+            int m = n, m1 = len > 1 ? I.seg_nodes[off + 1] : -1;
+            for (int q = 0; q < len; ++q) {
+                const bool more = q + 1 < len;
+                const int m2 = q + 2 < len ? I.seg_nodes[off + q + 2] : -1;
+                if (more) fwd_walk_load(I, m1, nxt);
+                double* w = I.ws + (long)m * W_NODE;
+#pragma unroll
+                for (int i = 0; i < BX; ++i) w[W_DX + i] = dx[i];
+                const int c0 = cur.c0, c1 = cur.c1;
+                double du[BU] = {0.0, 0.0};
+                double dxn[BX] = {0.0, 0.0, 0.0, 0.0};
+                if (c1 > c0) {
+#pragma unroll
+                    for (int i = 0; i < BU; ++i) {
+                        double acc = cur.k[i];
+#pragma unroll
+                        for (int j = 0; j < BX; ++j) acc += cur.K[i][j] * dx[j];
+                        du[i] = acc;
+                    }
+                    for (int j = c0; j < c1; ++j) {
+                        double* wj = I.ws + (long)j * W_NODE;
+                        // the only child is the next node of the walk: its
+                        // defect is in flight with its other inputs
+                        double cj[BX];
+                        if (more) {
+#pragma unroll
+                            for (int i = 0; i < BX; ++i) cj[i] = nxt.c[i];
+                        } else {
+                            load4(wj + W_C, cj);
+                        }
+#pragma unroll
+                        for (int i = 0; i < BX; ++i) {
+                            double acc = cj[i];
+#pragma unroll
+                            for (int k = 0; k < BX; ++k) acc += cur.A[i][k] * dx[k];
+#pragma unroll
+                            for (int k = 0; k < BU; ++k) acc += cur.B[i][k] * du[k];
+                            dxn[i] = acc;
+                            if (!more) wj[W_DX + i] = acc;
+                        }
+                    }
+                }
+                w[W_DU] = du[0];
+                w[W_DU + 1] = du[1];
+#pragma unroll
+                for (int i = 0; i < BX; ++i) dx[i] = dxn[i];
+                cur = nxt;
+                m = m1;
+                m1 = m2;
+            }
         }
         T::sync();
     }
@@ -1120,6 +1217,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             // merit slope pieces and the current merit
             double sm[6] = {0.0, 0.0, 0.0, La_p, ld_p, dd_p};
             for (int n = tid; n < N; n += T::size()) {
+                if constexpr (T::kGrid) lam_hat_ws(I, n);  // left by the segment walk
                 const double* w = I.ws + (long)n * W_NODE;
                 double dx[BX];
                 load4(w + W_DX, dx);
