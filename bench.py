@@ -220,6 +220,40 @@ def run_lqr(args, torch, L):
         "roofline": roofline,
     }
     L.bmpc_lqr_plan_destroy(plan)
+
+    # Independent solves on several streams at once (reported beside
+    # `value`, which is the one-solve-at-a-time rate): one solve of this tree
+    # is bound by its dependency depth and leaves most of the GPU idle.
+    conc = {}
+    for n_str in (2, 4, 8):
+        plans = [L.bmpc_lqr_plan_create(tree, nx, nu, layout) for _ in range(n_str)]
+        streams = [torch.cuda.Stream() for _ in range(n_str)]
+        # each stream has its own output arrays
+        outs = [[empty((N, nx)), empty((N, nu)), empty((N, nx)), empty((N, nu, nx)), empty((N, nu)),
+                 empty((N, nx, nx)), empty((N, nx))] for _ in range(n_str)]
+
+        def cstep(i):
+            k = i % n_str
+            d = dev[i % n_inst]
+            L.bmpc_lqr_solve(plans[k], d["A"], d["B"], d["c"], d["Q"], d["R"], d["M"], d["q"], d["r"],
+                             d["x0"], *outs[k], variant=L.RICCATI_LEVEL, stream=streams[k])
+        for i in range(args.warmup):
+            cstep(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            cstep(i)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        for k in range(n_str):
+            st, bad = L.bmpc_lqr_check(plans[k], stream=streams[k])
+            if st != 0:
+                raise RuntimeError(f"concurrent LQR solve failed (status {st}, node {bad})")
+            L.bmpc_lqr_plan_destroy(plans[k])
+        conc[f"{n_str}_streams"] = {"solves": args.steps, "seconds": round(el, 5),
+                                    "nodes_per_s": round(N * args.steps / el, 1),
+                                    "backward_bytes_GBps": round(alg["bwd_bytes"] * args.steps / el / 1e9, 2)}
+    out["concurrent_independent_solves"] = conc
     L.bmpc_tree_destroy(tree)
     return out, insts[0]
 
