@@ -215,3 +215,30 @@ def test_lqr_segment_scan_not_positive_definite_reports_node():
     inst.B[8] = 0.0
     g, st, bad = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR, variant=L.RICCATI_SEGSCAN)
     assert st == 3 and bad == 5
+
+
+def test_kernel_timing_can_be_restricted_to_one_kernel():
+    """bmpc_profile_only: only the named kernel's launches are bracketed by
+    event pairs; the results of the solve are unaffected."""
+    inst = S.lqr_microbench(0)
+    ref = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR)
+    L.bmpc_profile_only("lqr_forward_paths")
+    L.bmpc_profile_enable(True)
+    try:
+        got = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR)
+        prof = L.bmpc_profile_read()
+    finally:
+        L.bmpc_profile_enable(False)
+        L.bmpc_profile_only(None)
+    assert set(prof) == {"lqr_forward_paths"} and prof["lqr_forward_paths"][1] == 1
+    assert prof["lqr_forward_paths"][0] > 0.0
+    for k in ref[0]:
+        assert np.array_equal(ref[0][k], got[0][k]), k
+    # with the restriction lifted every kernel of the solve is timed again
+    L.bmpc_profile_enable(True)
+    try:
+        gpu_lqr(inst, L.LAYOUT_NODE_MAJOR)
+        prof = L.bmpc_profile_read()
+    finally:
+        L.bmpc_profile_enable(False)
+    assert {"lqr_backward_level_wave", "lqr_forward_paths", "lqr_costate"} <= set(prof)
