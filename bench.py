@@ -65,6 +65,10 @@ def lqr_algorithmic(parent, nx, nu):
             "fwd_flops": fwd_flops}
 
 
+SOLVER_SRCS = ["paper_2506_13624_amd/csrc/bmpc_solver.hip", "paper_2506_13624_amd/csrc/bmpc_device.hpp",
+               "paper_2506_13624_amd/csrc/lqr_device.hpp", "paper_2506_13624_amd/csrc/cvf_device.hpp"]
+
+
 def source_digest(paths):
     h = hashlib.sha256()
     for p in paths:
@@ -570,8 +574,9 @@ def run_warmstart(args, torch, L):
 def run_large_tree(args, torch, L):
     """Tree LQR on the 4096-scenario bicycle tree (122,871 nodes): the Gauss-
     Newton LQR subproblem at the cold start, level-parallel vs segment-scan
-    backward; plus the time per AL inner iteration of the batched solver
-    (one workgroup) on this tree."""
+    backward; plus the time per AL inner iteration of the whole-grid solver
+    on this tree, with its measured HBM traffic per iteration when the
+    committed counter summary matches the solver sources."""
     import bmpc_synth as S
     from paper_2506_13624_amd.bicycle import Problem
 
@@ -584,7 +589,13 @@ def run_large_tree(args, torch, L):
     u = torch.zeros(N * 2, dtype=torch.float64, device="cuda")
     lam = torch.zeros(N * 4, dtype=torch.float64, device="cuda")
     ye = torch.zeros(N * 5, dtype=torch.float64, device="cuda")
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev0[0].record()
     L.bmpc_solve(pb.handle, st0, 0, x, u, lam, ye)  # cold start only (rollout + adjoint)
+    ev0[1].record()
+    torch.cuda.synchronize()
+    start_ms = ev0[0].elapsed_time(ev0[1])
     A, B, c, Q, R, q, r = (torch.zeros(N * k, dtype=torch.float64, device="cuda") for k in (16, 8, 4, 16, 4, 4, 2))
     L.bmpc_linearize(pb.handle, x, u, lam, ye, 100.0, A, B, c, Q, R, q, r)
     # the LQR takes the step Jacobians on the edge into each child
@@ -633,13 +644,28 @@ def run_large_tree(args, torch, L):
     ev[1].record()
     torch.cuda.synchronize()
     pb.close()
+    n_it = max(s["inner_it"], 1)
+    ms_all = ev[0].elapsed_time(ev[1])
+    # per inner iteration: the launch with five inner iterations less the
+    # launch that only builds the cold start
+    ms_it = (ms_all - start_ms) / n_it
+    al = {"inner_iterations": s["inner_it"], "ms_launch": round(ms_all, 3), "ms_start_only_launch": round(start_ms, 3),
+          "ms_per_inner_iteration": round(ms_it, 3)}
+    # measured HBM traffic of the same two launches (rocprofv3 FETCH_SIZE +
+    # WRITE_SIZE, profiles/), while the solver sources are unchanged
+    tb = measured_traffic("bmpc_solve_grid_5_inner", SOLVER_SRCS)
+    t0 = measured_traffic("bmpc_solve_grid_start_only", SOLVER_SRCS)
+    if tb is not None and t0 is not None and s["inner_it"] == 5:
+        per_it = (tb - t0) / 5
+        gbps = per_it / (ms_it * 1e-3) / 1e9
+        al.update({"hbm_bytes_per_inner_iteration": round(per_it), "hbm_GBps": round(gbps, 2),
+                   "hbm_frac": round(gbps / HBM_PEAK_GBS, 5)})
     return {"large_tree": {
         "workload": "bicycle tree, horizon 80, binary branching every 5 stages to stage 55 (4096 scenarios, "
                     f"{N} nodes, 8191 segments); tree LQR of the Gauss-Newton subproblem at the cold start, nx=4, nu=2",
         "algorithmic_bytes_backward": alg["bwd_bytes"], "flops_backward": alg["bwd_flops"],
         "lqr": res,
-        "al_solver_whole_grid": {"inner_iterations": s["inner_it"],
-                                    "ms_per_inner_iteration": round(ev[0].elapsed_time(ev[1]) / max(s["inner_it"], 1), 3)},
+        "al_solver_whole_grid": al,
     }}
 
 
@@ -655,6 +681,8 @@ def main():
     ap.add_argument("--skip-bmpc", action="store_true")
     ap.add_argument("--skip-warmstart", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
+    ap.add_argument("--only-large", action="store_true",
+                    help="only the 4096-scenario tree section, printed on its own (for counter runs)")
     ap.add_argument("--ws-train", type=int, default=200000, help="training instances of the learned warm start")
     ap.add_argument("--ws-steps", type=int, default=3000, help="training steps (batch 1024)")
     ap.add_argument("--ws-test", type=int, default=8192, help="test problems of the learned warm start")
@@ -670,6 +698,17 @@ def main():
         print(json.dumps({"error": "no HIP device visible"}))
         sys.exit(1)
     from paper_2506_13624_amd import _lib as L
+
+    if args.only_large:
+        if args.calib_copy:
+            nbytes = 512 * 2 ** 20
+            src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            del src
+        progress("large tree")
+        print(json.dumps(run_large_tree(args, torch, L)), flush=True)
+        return
 
     progress("tree-Riccati microbenchmark")
     out, inst = run_lqr(args, torch, L)
