@@ -185,6 +185,10 @@ struct TeamGrid {
     static constexpr int BS = BS_;
     static constexpr bool kGrid = true;
     __device__ static int rank() { return blockIdx.x * BS_ + threadIdx.x; }
+    // a rank whose neighbours are in different workgroups: work that falls
+    // on a contiguous range of node ids (one stage of the tree) is spread
+    // over all CUs instead of a few
+    __device__ static int rank_spread() { return threadIdx.x * gridDim.x + blockIdx.x; }
     __device__ static int size() { return gridDim.x * BS_; }
     __device__ static void sync() { cooperative_groups::this_grid().sync(); }
     // gpart: gridDim.x x K doubles of device memory
@@ -411,7 +415,7 @@ template <class T>
 __device__ void pass_riccati_seg(const InstDesc& I, int* bad)
 {
     for (int d = I.max_seg_depth; d >= 0; --d) {
-        for (int n = T::rank(); n < I.N; n += T::size()) {
+        for (int n = T::rank_spread(); n < I.N; n += T::size()) {
             const int s = I.seg_of[n];
             if (I.seg_end[s] != n || I.seg_depth[s] != d) continue;
             const int top = I.seg_nodes[I.seg_off[s]];
@@ -951,7 +955,7 @@ __device__ void pass_forward_seg(const InstDesc& I)
         for (int i = 0; i < BX; ++i) I.ws[W_DX + i] = 0.0;
     T::sync();
     for (int d = 0; d <= I.max_seg_depth; ++d) {
-        for (int n = T::rank(); n < I.N; n += T::size()) {
+        for (int n = T::rank_spread(); n < I.N; n += T::size()) {
             const int s = I.seg_of[n];
             if (I.seg_pos[n] != 0 || I.seg_depth[s] != d) continue;
             const int off = I.seg_off[s], len = I.seg_len[s];
