@@ -589,13 +589,7 @@ def run_large_tree(args, torch, L):
     u = torch.zeros(N * 2, dtype=torch.float64, device="cuda")
     lam = torch.zeros(N * 4, dtype=torch.float64, device="cuda")
     ye = torch.zeros(N * 5, dtype=torch.float64, device="cuda")
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    torch.cuda.synchronize()
-    ev0[0].record()
     L.bmpc_solve(pb.handle, st0, 0, x, u, lam, ye)  # cold start only (rollout + adjoint)
-    ev0[1].record()
-    torch.cuda.synchronize()
-    start_ms = ev0[0].elapsed_time(ev0[1])
     A, B, c, Q, R, q, r = (torch.zeros(N * k, dtype=torch.float64, device="cuda") for k in (16, 8, 4, 16, 4, 4, 2))
     L.bmpc_linearize(pb.handle, x, u, lam, ye, 100.0, A, B, c, Q, R, q, r)
     # the LQR takes the step Jacobians on the edge into each child
@@ -635,7 +629,16 @@ def run_large_tree(args, torch, L):
                                  for k, v in prof.items()}}
     L.bmpc_lqr_plan_destroy(plan)
     L.bmpc_tree_destroy(tree)
-    # AL iterations on this tree (a single large problem: the whole grid)
+    # AL iterations on this tree (a single large problem: the whole grid);
+    # the launch that only builds the cold start is timed again here, after
+    # the first launch of the kernel above
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev0[0].record()
+    L.bmpc_solve(pb.handle, st0, 0, x, u, lam, ye)
+    ev0[1].record()
+    torch.cuda.synchronize()
+    start_ms = ev0[0].elapsed_time(ev0[1])
     st = L.bmpc_settings_default(max_outer=1, max_inner=5)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     torch.cuda.synchronize()

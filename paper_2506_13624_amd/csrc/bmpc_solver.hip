@@ -1309,12 +1309,19 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             }
             T::template reduce<3 * NALPHA_MAX, false>(tr, sred, gpart);
             double a_star = -1.0, phi_star = NAN, alpha = 1.0;
-            for (int ka = 0; ka < na; ++ka, alpha *= 0.5) {
-                const double phi = tr[ka] + tr[NALPHA_MAX + ka] + 0.5 * mu * tr[2 * NALPHA_MAX + ka];
-                if (a_star < 0.0 && phi <= phi0 + cfg.beta * alpha * dphi0) {
-                    a_star = alpha;
-                    phi_star = phi;
+            // constant indices only, so that tr stays in registers (a loop
+            // bounded by na would index it at run time and move it to
+            // scratch memory, for the accumulation above as well)
+#pragma unroll
+            for (int ka = 0; ka < NALPHA_MAX; ++ka) {
+                if (ka < na) {
+                    const double phi = tr[ka] + tr[NALPHA_MAX + ka] + 0.5 * mu * tr[2 * NALPHA_MAX + ka];
+                    if (a_star < 0.0 && phi <= phi0 + cfg.beta * alpha * dphi0) {
+                        a_star = alpha;
+                        phi_star = phi;
+                    }
                 }
+                alpha *= 0.5;
             }
             if (a_star < 0.0) {
                 ++ls_fail;
