@@ -1022,27 +1022,46 @@ __device__ void pass_forward_seg(const InstDesc& I)
 
 // Adjoint sweep lam_leaf = q, lam_n = q_n + A_n^T sum_children lam (makes the
 // state gradient of the Lagrangian vanish at the current point).
+__device__ __forceinline__ void adjoint_node(const InstDesc& I, int n)
+{
+    const double* w = I.ws + (long)n * W_NODE;
+    const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+    double s[BX] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = c0; j < c1; ++j)
+#pragma unroll
+        for (int i = 0; i < BX; ++i) s[i] += I.lam[j * 4 + i];
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+        double acc = w[W_QV + i];
+        if (c1 > c0)
+#pragma unroll
+            for (int k = 0; k < BX; ++k) acc += w[W_A + k * 4 + i] * s[k];
+        I.lam[n * 4 + i] = acc;
+    }
+}
+
 template <class T>
 __device__ void pass_adjoint(const InstDesc& I)
 {
+    if constexpr (T::kGrid) {
+        // by segment depth, each segment walked bottom-up by one thread
+        for (int d = I.max_seg_depth; d >= 0; --d) {
+            for (int n = T::rank_spread(); n < I.N; n += T::size()) {
+                const int s = I.seg_of[n];
+                if (I.seg_end[s] != n || I.seg_depth[s] != d) continue;
+                const int top = I.seg_nodes[I.seg_off[s]];
+                for (int m = n;; m = I.parent[m]) {
+                    adjoint_node(I, m);
+                    if (m == top) break;
+                }
+            }
+            T::sync();
+        }
+        return;
+    }
     for (int t = I.T; t >= 0; --t) {
         const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
-        for (int n = n0 + T::rank(); n < n1; n += T::size()) {
-            const double* w = I.ws + (long)n * W_NODE;
-            const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
-            double s[BX] = {0.0, 0.0, 0.0, 0.0};
-            for (int j = c0; j < c1; ++j)
-#pragma unroll
-                for (int i = 0; i < BX; ++i) s[i] += I.lam[j * 4 + i];
-#pragma unroll
-            for (int i = 0; i < BX; ++i) {
-                double acc = w[W_QV + i];
-                if (c1 > c0)
-#pragma unroll
-                    for (int k = 0; k < BX; ++k) acc += w[W_A + k * 4 + i] * s[k];
-                I.lam[n * 4 + i] = acc;
-            }
-        }
+        for (int n = n0 + T::rank(); n < n1; n += T::size()) adjoint_node(I, n);
         T::sync();
     }
 }
@@ -1067,16 +1086,33 @@ __device__ void build_start(const InstDesc& I, int warm, double rho)
     }
     T::sync();
     if ((warm & 8) || !(warm & 1)) {
-        for (int t = 1; t <= I.T; ++t) {
-            const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
-            for (int n = n0 + tid; n < n1; n += T::size()) {
-                const int p = I.parent[n];
-                double xp[BX], up[BU] = {I.u[p * 2], I.u[p * 2 + 1]}, xn[BX];
-                load4(I.x + p * 4, xp);
-                bike_step(I.prm, xp, up, xn);
-                store4(I.x + n * 4, xn);
+        auto roll = [&](int n) {
+            const int p = I.parent[n];
+            double xp[BX], up[BU] = {I.u[p * 2], I.u[p * 2 + 1]}, xn[BX];
+            load4(I.x + p * 4, xp);
+            bike_step(I.prm, xp, up, xn);
+            store4(I.x + n * 4, xn);
+        };
+        if constexpr (T::kGrid) {
+            // by segment depth, each segment walked top-down by one thread
+            for (int d = 0; d <= I.max_seg_depth; ++d) {
+                for (int n = T::rank_spread(); n < N; n += T::size()) {
+                    const int s = I.seg_of[n];
+                    if (I.seg_pos[n] != 0 || I.seg_depth[s] != d) continue;
+                    const int off = I.seg_off[s], len = I.seg_len[s];
+                    for (int q = 0; q < len; ++q) {
+                        const int m = I.seg_nodes[off + q];
+                        if (m != 0) roll(m);
+                    }
+                }
+                T::sync();
             }
-            T::sync();
+        } else {
+            for (int t = 1; t <= I.T; ++t) {
+                const int n0 = I.level_off[t], n1 = I.level_off[t + 1];
+                for (int n = n0 + tid; n < n1; n += T::size()) roll(n);
+                T::sync();
+            }
         }
     }
     if (!(warm & 2)) {
