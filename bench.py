@@ -229,7 +229,7 @@ def run_lqr(args, torch, L):
     # `value`, which is the one-solve-at-a-time rate): one solve of this tree
     # is bound by its dependency depth and leaves most of the GPU idle.
     conc = {}
-    for n_str in (2, 4, 8):
+    for n_str in (() if args.no_concurrent else (2, 4, 8)):
         plans = [L.bmpc_lqr_plan_create(tree, nx, nu, layout) for _ in range(n_str)]
         streams = [torch.cuda.Stream() for _ in range(n_str)]
         # each stream has its own output arrays
@@ -257,7 +257,8 @@ def run_lqr(args, torch, L):
         conc[f"{n_str}_streams"] = {"solves": args.steps, "seconds": round(el, 5),
                                     "nodes_per_s": round(N * args.steps / el, 1),
                                     "backward_bytes_GBps": round(alg["bwd_bytes"] * args.steps / el / 1e9, 2)}
-    out["concurrent_independent_solves"] = conc
+    if conc:
+        out["concurrent_independent_solves"] = conc
     L.bmpc_tree_destroy(tree)
     return out, insts[0]
 
@@ -684,6 +685,8 @@ def main():
     ap.add_argument("--skip-bmpc", action="store_true")
     ap.add_argument("--skip-warmstart", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the independent solves on several streams (for per-kernel profiles)")
     ap.add_argument("--only-large", action="store_true",
                     help="only the 4096-scenario tree section, printed on its own (for counter runs)")
     ap.add_argument("--ws-train", type=int, default=200000, help="training instances of the learned warm start")
