@@ -646,9 +646,54 @@ __device__ void pass_riccati_segscan(const InstDesc& I, int* bad)
 // the next there (P, p and defect c per node for the backward pass; dx for
 // the forward pass) and fetch each thread's inputs for the next stage from
 // HBM while the current stage is computed.  Same arithmetic as the passes
-// above, so the same results bit for bit.
-constexpr int LN = 28;  // doubles per node: P 16, p 4, c 4, dx 4
-constexpr int LN_P = 0, LN_PV = 16, LN_C = 20, LN_DX = 24;
+// above, so the same results bit for bit.  Each row also holds the node's
+// child range, written once per problem, so that a stage reads no topology
+// from global memory, and the forward pass's control step, so that a stage
+// writes no global memory either (the results of either pass go to the
+// workspace in one sweep over all nodes after it).  The backward pass keeps
+// the gains K (8) and k (2) in four slots of their own plus the dx and du
+// slots, which the forward pass fills only after that sweep.
+constexpr int LN = 35;  // doubles per node: P 16, p 4, c 4, dx 4, child range, du 2, gains 4
+constexpr int LN_P = 0, LN_PV = 16, LN_C = 20, LN_DX = 24, LN_CH = 28, LN_DU = 29, LN_G = 31;
+// LDS slot of gain entry e (K row-major, then k)
+__device__ __forceinline__ constexpr int lds_gain_slot(int e)
+{
+    return e < 4 ? LN_G + e : (e < 8 ? LN_DX + e - 4 : LN_DU + e - 8);
+}
+
+// child range [first, end) of node n, as kept in its LDS row
+__device__ __forceinline__ int2 lds_children(const double* sn, int n)
+{
+    return *reinterpret_cast<const int2*>(sn + (long)n * LN + LN_CH);
+}
+
+template <class T>
+__device__ void lds_topology(const InstDesc& I, double* sn)
+{
+    for (int n = T::rank(); n < I.N; n += T::size())
+        *reinterpret_cast<int2*>(sn + (long)n * LN + LN_CH) = make_int2(I.child_off[n], I.child_off[n + 1]);
+    T::sync();
+}
+
+// After a backward pass that left the value functions in the workspace (the
+// segment scan): copy P, p and the defect c of every node into its LDS row,
+// all nodes at once, for the LDS forward pass.
+template <int BS>
+__device__ void lds_from_ws(const InstDesc& I, double* sn)
+{
+    for (int n = threadIdx.x; n < I.N; n += BS) {
+        const double* w = I.ws + (long)n * W_NODE;
+        double* me = sn + (long)n * LN;
+#pragma unroll
+        for (int e = 0; e < BX * BX; ++e) me[LN_P + e] = w[W_P + e];
+#pragma unroll
+        for (int i = 0; i < BX; ++i) {
+            me[LN_PV + i] = w[W_PV + i];
+            me[LN_C + i] = w[W_C + i];
+        }
+    }
+    __syncthreads();
+}
 
 struct RicPre {
     StageRegs<BX, BU> st;
@@ -671,7 +716,8 @@ __device__ __forceinline__ void ric_fetch(const InstDesc& I, int n, RicPre& r)
 __device__ __forceinline__ void ric_node_lds(const InstDesc& I, int n, const RicPre& r, double* sn, int* bad)
 {
     double* me = sn + (long)n * LN;
-    const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+    const int2 ch = lds_children(sn, n);
+    const int c0 = ch.x, c1 = ch.y;
     if (c0 == c1) {
 #pragma unroll
         for (int i = 0; i < BX; ++i) {
@@ -705,12 +751,11 @@ __device__ __forceinline__ void ric_node_lds(const InstDesc& I, int n, const Ric
     }
     double K[BU][BX], k[BU], P[BX][BX], p[BX];
     if (!acc.finish(K, k, P, p)) atomicMin(bad, n);
-    double* w = I.ws + (long)n * W_NODE;
 #pragma unroll
     for (int i = 0; i < BU; ++i) {
 #pragma unroll
-        for (int j = 0; j < BX; ++j) w[W_K + i * 4 + j] = K[i][j];
-        w[W_KV + i] = k[i];
+        for (int j = 0; j < BX; ++j) me[lds_gain_slot(i * 4 + j)] = K[i][j];
+        me[lds_gain_slot(8 + i)] = k[i];
     }
 #pragma unroll
     for (int i = 0; i < BX; ++i) {
@@ -748,6 +793,18 @@ __device__ void pass_riccati_lds(const InstDesc& I, int* bad, double* sn)
         lds_barrier();
     }
     __syncthreads();
+    // gains to the workspace, where the forward pass fetches them
+    for (int n = threadIdx.x; n < I.N; n += BS) {
+        const int2 ch = lds_children(sn, n);
+        if (ch.x == ch.y) continue;
+        const double* me = sn + (long)n * LN;
+        double* w = I.ws + (long)n * W_NODE;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[W_K + e] = me[lds_gain_slot(e)];
+        w[W_KV] = me[lds_gain_slot(8)];
+        w[W_KV + 1] = me[lds_gain_slot(9)];
+    }
+    __syncthreads();
 }
 
 struct FwdPre {
@@ -772,22 +829,14 @@ __device__ __forceinline__ void fwd_fetch(const InstDesc& I, int n, FwdPre& r)
     }
 }
 
-__device__ __forceinline__ void fwd_node_lds(const InstDesc& I, int n, const FwdPre& r, double* sn)
+__device__ __forceinline__ void fwd_node_lds(int n, const FwdPre& r, double* sn)
 {
-    double* w = I.ws + (long)n * W_NODE;
-    const double* me = sn + (long)n * LN;
+    double* me = sn + (long)n * LN;
     double dx[BX];
 #pragma unroll
     for (int i = 0; i < BX; ++i) dx[i] = me[LN_DX + i];
-#pragma unroll
-    for (int i = 0; i < BX; ++i) {
-        double acc = me[LN_PV + i];
-#pragma unroll
-        for (int j = 0; j < BX; ++j) acc += me[LN_P + i * 4 + j] * dx[j];
-        w[W_LH + i] = acc;
-        w[W_DX + i] = dx[i];
-    }
-    const int c0 = I.child_off[n], c1 = I.child_off[n + 1];
+    const int2 ch = lds_children(sn, n);
+    const int c0 = ch.x, c1 = ch.y;
     double du[BU] = {0.0, 0.0};
     if (c1 > c0) {
 #pragma unroll
@@ -810,8 +859,29 @@ __device__ __forceinline__ void fwd_node_lds(const InstDesc& I, int n, const Fwd
             }
         }
     }
-    w[W_DU] = du[0];
-    w[W_DU + 1] = du[1];
+    me[LN_DU] = du[0];
+    me[LN_DU + 1] = du[1];
+}
+
+// Forward results of one node from its LDS row to the workspace: the LQR
+// costate estimate P dx + p, dx and du.
+__device__ __forceinline__ void fwd_store_lds(const InstDesc& I, int n, const double* sn)
+{
+    double* w = I.ws + (long)n * W_NODE;
+    const double* me = sn + (long)n * LN;
+    double dx[BX];
+#pragma unroll
+    for (int i = 0; i < BX; ++i) dx[i] = me[LN_DX + i];
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+        double acc = me[LN_PV + i];
+#pragma unroll
+        for (int j = 0; j < BX; ++j) acc += me[LN_P + i * 4 + j] * dx[j];
+        w[W_LH + i] = acc;
+        w[W_DX + i] = dx[i];
+    }
+    w[W_DU] = me[LN_DU];
+    w[W_DU + 1] = me[LN_DU + 1];
 }
 
 template <int BS>
@@ -830,11 +900,11 @@ __device__ void pass_forward_lds(const InstDesc& I, double* sn)
             const int m = n1 + (int)threadIdx.x;
             if (m < I.level_off[t + 2]) fwd_fetch(I, m, nxt);
         }
-        if (n < n1) fwd_node_lds(I, n, cur, sn);
+        if (n < n1) fwd_node_lds(n, cur, sn);
         for (int e = n + BS; e < n1; e += BS) {
             FwdPre r;
             fwd_fetch(I, e, r);
-            fwd_node_lds(I, e, r, sn);
+            fwd_node_lds(e, r, sn);
         }
         lds_barrier();
     };
@@ -842,6 +912,8 @@ __device__ void pass_forward_lds(const InstDesc& I, double* sn)
         stage(t, buf[0], buf[1]);
         if (t + 1 <= I.T) stage(t + 1, buf[1], buf[0]);
     }
+    __syncthreads();
+    for (int n = threadIdx.x; n < I.N; n += BS) fwd_store_lds(I, n, sn);
     __syncthreads();
 }
 
@@ -1182,11 +1254,16 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                                           int lds_nodes, double* gpart)
 {
     const InstDesc I = insts[idx];
-    const bool in_lds = !SEGSCAN && !T::kGrid && I.N <= lds_nodes;
+    // the per-node chain values fit in LDS: the stage-by-stage passes run
+    // there (both with the level backward, the forward one after the
+    // segment scan)
+    const bool fits = !T::kGrid && I.N <= lds_nodes;
+    const bool in_lds = fits && !SEGSCAN;
     int* bad = bad_flags + idx;
     const int tid = T::rank();
     const int N = I.N;
     if (tid == 0) *bad = INT_MAX;
+    if (fits) lds_topology<T>(I, sn);
 
     double rho = cfg.rho0, mu = cfg.mu0, omega = cfg.omega0, eta = cfg.eta0;
     double r_kkt = INFINITY, viol = INFINITY, merit = 0.0;
@@ -1246,10 +1323,12 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                 goto done;
             }
             if constexpr (!T::kGrid) {
-                if (in_lds)
+                if (fits) {
+                    if (SEGSCAN) lds_from_ws<T::BS>(I, sn);
                     pass_forward_lds<T::BS>(I, sn);
-                else
+                } else {
                     pass_forward<T>(I);
+                }
             } else {
                 pass_forward_seg<T>(I);
             }
