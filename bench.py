@@ -301,6 +301,20 @@ def cpu_baseline_bmpc(insts, budget_s=10.0):
                       f"({conv} converged) in {el:.1f} s, one instance per process on {cores} cores"}
 
 
+def slowest(stats, insts):
+    i = int(np.argmax([x["inner_it"] for x in stats]))
+    return {"instance": i, "nodes": int(insts[i].num_nodes), "inner_it": int(stats[i]["inner_it"]),
+            "status": int(stats[i]["status"])}
+
+
+def not_converged(stats):
+    out = {}
+    for x in stats:
+        if x["status"] != 0:
+            out[str(x["status"])] = out.get(str(x["status"]), 0) + 1
+    return out
+
+
 def run_bmpc(args, torch, L):
     import bmpc_synth as S
     from paper_2506_13624_amd.bicycle import Problem
@@ -437,7 +451,10 @@ def run_bmpc(args, torch, L):
                       "candidates_ms": {f"{'segment_scan' if v == L.RICCATI_SEGSCAN else 'level'}/{blk}": round(t, 3)
                                         for (v, blk), t in cand.items()}},
         "cold_tuned": {"ms": round(ms_tuned, 3), "converged": conv(s_tuned), "mean_inner_it": mean_it(s_tuned),
-                       "solves_per_s": round(conv(s_tuned) / (ms_tuned / 1e3), 1)},
+                       "solves_per_s": round(conv(s_tuned) / (ms_tuned / 1e3), 1),
+                       # the launch ends with its longest-running problem
+                       "most_iterations": slowest(s_tuned, insts),
+                       "not_converged_by_status": not_converged(s_tuned)},
         "cold_tuned_cap_200_iterations": {"ms": round(ms_cap, 3), "converged": conv(s_cap),
                                           "mean_inner_it": mean_it(s_cap),
                                           "solves_per_s": round(conv(s_cap) / (ms_cap / 1e3), 1)},
