@@ -1247,13 +1247,53 @@ __device__ void stash_state(const InstDesc& I, bool save)
 
 // ---------------------------------------------------------------- solver kernel
 // The whole of Alg. 1 for problem idx, run by team T (one workgroup or the grid).
+// The descriptor's pointers all address global memory, but the compiler
+// cannot tell that from a pointer loaded from memory and reaches them with
+// flat instructions, which count against the LDS counter as well (so every
+// wait for an LDS operation also waits for them).  Each pointer is passed
+// through an empty asm statement as a global-address-space pointer and
+// converted back, so that the compiler knows where it points and uses
+// global loads and stores.
+template <class P>
+__device__ __forceinline__ P* as_global(P* p)
+{
+    __attribute__((address_space(1))) P* g = (__attribute__((address_space(1))) P*)p;
+    asm volatile("" : "+s"(g));
+    return (P*)g;
+}
+
+__device__ __forceinline__ InstDesc global_view(InstDesc d)
+{
+    d.parent = as_global(d.parent);
+    d.child_off = as_global(d.child_off);
+    d.level_off = as_global(d.level_off);
+    d.weight = as_global(d.weight);
+    d.ref = as_global(d.ref);
+    d.obs = as_global(d.obs);
+    d.has_obs = as_global(d.has_obs);
+    d.x0 = as_global(d.x0);
+    d.x = as_global(d.x);
+    d.u = as_global(d.u);
+    d.lam = as_global(d.lam);
+    d.ye = as_global(d.ye);
+    d.ws = as_global(d.ws);
+    d.seg_of = as_global(d.seg_of);
+    d.seg_pos = as_global(d.seg_pos);
+    d.seg_len = as_global(d.seg_len);
+    d.seg_nodes = as_global(d.seg_nodes);
+    d.seg_off = as_global(d.seg_off);
+    d.seg_end = as_global(d.seg_end);
+    d.seg_depth = as_global(d.seg_depth);
+    return d;
+}
+
 template <class T, bool SEGSCAN>
 __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, int idx, const SolverCfg& cfg,
                                           SolveOut* __restrict__ outs, int* __restrict__ bad_flags,
                                           double* __restrict__ hist, int hist_cap, double* sred, double* sn,
                                           int lds_nodes, double* gpart)
 {
-    const InstDesc I = insts[idx];
+    const InstDesc I = global_view(insts[idx]);
     // the per-node chain values fit in LDS: the stage-by-stage passes run
     // there (both with the level backward, the forward one after the
     // segment scan)
