@@ -74,7 +74,7 @@ class Settings(C.Structure):
                 ("a_eta", C.c_double), ("b_eta", C.c_double), ("rho0", C.c_double),
                 ("mu0", C.c_double), ("armijo_beta", C.c_double), ("n_alpha", C.c_int),
                 ("max_outer", C.c_int), ("max_inner", C.c_int), ("max_ls_fail", C.c_int),
-                ("max_iter_total", C.c_int)]
+                ("max_iter_total", C.c_int), ("ls_rounds", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -105,6 +105,9 @@ def _declare(L):
         getattr(L, name).argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_double]
     L.orc_merit.restype = C.c_double
     L.orc_merit.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, C.c_double, C.c_double]
+    L.orc_direction.restype = C.c_int
+    L.orc_direction.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, C.c_double, C.c_double,
+                                _dp, _dp, _dp, _dp]
     L.orc_kkt.restype = C.c_double
     L.orc_kkt.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, C.c_double]
     L.orc_adjoint.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_double, _dp]
@@ -335,6 +338,21 @@ def merit(pb, x, u, lam, ye, rho, mu):
 
 def kkt(pb, x, u, lam, ye, rho):
     return lib().orc_kkt(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(lam)), _d(_f64(ye)), rho)
+
+
+def direction(pb, x, u, lam, ye, rho, mu):
+    """One search direction at (x, u, lam): the tree-LQR step and the merit
+    slope pieces.  Returns (dx, du, lam_hat, dict) with the dict holding
+    gtd, dhd, lhd, dd, mu_hat, mu, dphi0, phi0."""
+    N = pb.N
+    dx, du, lh = np.zeros((N, 4)), np.zeros((N, 2)), np.zeros((N, 4))
+    out = np.zeros(8)
+    st = lib().orc_direction(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(lam)), _d(_f64(ye)), rho, mu,
+                             _d(dx), _d(du), _d(lh), _d(out))
+    if st != 0:
+        raise OracleError(st)
+    keys = ("gtd", "dhd", "lhd", "dd", "mu_hat", "mu", "dphi0", "phi0")
+    return dx, du, lh, dict(zip(keys, out.tolist()))
 
 
 def violation(pb, x, u, ye, rho):

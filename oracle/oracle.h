@@ -72,6 +72,7 @@ typedef struct {
     double rho0, mu0, armijo_beta;
     int n_alpha, max_outer, max_inner, max_ls_fail;
     int max_iter_total; /* cap on inner iterations over all outer ones, 0 = none */
+    int ls_rounds;      /* backtracking rounds of n_alpha step sizes each */
 } orc_settings;
 
 typedef struct {
@@ -103,6 +104,15 @@ double orc_merit(const orc_problem* pb, const double* x, const double* u, const 
                  const double* ye, double rho, double mu);
 double orc_kkt(const orc_problem* pb, const double* x, const double* u, const double* lam,
                const double* ye, double rho);
+/* One search direction and the slope of the merit along it: the tree LQR
+ * step (dx, du, lh) at the given point, then with J_d dz = -d,
+ *   out[0] = g^T dz, out[1] = dz^T H dz, out[2] = (lh - 2 lam)^T d,
+ *   out[3] = d^T d, out[4] = mu_hat (0 if d = 0), out[5] = mu after the
+ *   update, out[6] = phi'(0) at that mu, out[7] = phi(0) at that mu.
+ * Returns the LQR status. */
+int orc_direction(const orc_problem* pb, const double* x, const double* u, const double* lam,
+                  const double* ye, double rho, double mu, double* dx, double* du, double* lh,
+                  double* out);
 double orc_violation(const orc_problem* pb, const double* x, const double* u,
                      const double* ye, double rho);
 void orc_adjoint(const orc_problem* pb, const double* x, const double* u,

@@ -29,6 +29,7 @@
 #define NX ORC_NX
 #define NU ORC_NU
 #define NG ORC_NG
+#define HALF_PI 1.5707963267948966
 
 void orc_settings_default(orc_settings* s)
 {
@@ -48,6 +49,7 @@ void orc_settings_default(orc_settings* s)
     s->max_inner = 100;
     s->max_ls_fail = 3;
     s->max_iter_total = 0;
+    s->ls_rounds = 3;
 }
 
 /* ------------------------------------------------------------------------
@@ -318,10 +320,23 @@ static void defect(const orc_problem* pb, int j, const double* x, const double* 
 }
 
 /* Merit of eq. merit with J := L_a:  phi = L_a + lam^T d + mu/2 d^T d */
+/* The kinematic bicycle is defined for steering angles inside (-pi/2, pi/2):
+ * tan has its pole at pi/2 and past it the yaw rate changes sign.  A trial
+ * point outside that domain is not a point of the problem; its merit is +inf,
+ * so the sufficient-decrease test rejects it and the search backtracks. */
+static int in_model_domain(const orc_problem* pb, const int* nch, const double* u)
+{
+    if (pb->model.model != 0) return 1;
+    for (int n = 0; n < pb->N; ++n)
+        if (nch[n] > 0 && !(fabs(u[n * NU + 1]) < HALF_PI)) return 0;
+    return 1;
+}
+
 static double merit_impl(const orc_problem* pb, const int* nch, const double* x,
                          const double* u, const double* lam, const double* ye, double rho,
                          double mu)
 {
+    if (!in_model_domain(pb, nch, u)) return INFINITY;
     double v = aug_lag(pb, nch, x, u, ye, rho);
     double ld = 0.0, dd = 0.0;
     for (int j = 1; j < pb->N; ++j) {
@@ -470,6 +485,94 @@ static double start_measure(const orc_problem* pb, const double* x, const double
     return k > v ? k : v;
 }
 
+/* Linearise the dynamics and quadratise L_a at (x, u) (Gauss-Newton, Sec.
+ * IV-A), solve the tree LQR in the deviations with delta x_0 = 0, and form
+ * the merit's slope along the step.  The step satisfies J_d dz = -d, so with
+ * lambda(alpha) = lambda + alpha (lh - lambda),
+ *   phi'(0) = g^T dz + (lh - lambda)^T d + lambda^T J_d dz + mu d^T J_d dz
+ *           = g^T dz + (lh - 2 lambda)^T d - mu ||d||^2.
+ * Adaptive mu (Gill et al., cited in Sec. IV-A): the slope must not exceed
+ * -1/2 dz^T H dz; mu_hat is the mu at which it equals that bound, and a mu
+ * below mu_hat is raised to max(mu_hat, 2 mu).  sl receives g^T dz, dz^T H dz,
+ * (lh - 2 lambda)^T d, ||d||^2, mu_hat, the new mu, phi'(0) and phi(0). */
+static int direction_step(const orc_problem* pb, const int* nch, const double* x,
+                          const double* u, const double* lam, const double* ye, double rho,
+                          double mu, double* A, double* B, double* c, double* Q, double* R,
+                          double* M, double* q, double* r, double* dx, double* du, double* lh,
+                          double* K, double* kk, double* P, double* p, int* bad, double* sl)
+{
+    const int N = pb->N;
+    const double zero_x[NX] = {0, 0, 0, 0};
+    for (int n = 0; n < N; ++n) {
+        node_terms_impl(pb, n, nch[n] == 0, x + n * NX, u + n * NU, ye + n * NG, rho, NULL,
+                        q + n * NX, r + n * NU, Q + n * NX * NX, R + n * NU * NU);
+        memset(M + n * NU * NX, 0, sizeof(double) * NU * NX);
+        if (n > 0) defect(pb, n, x, u, c + n * NX, A + n * NX * NX, B + n * NX * NU);
+    }
+    const int lst = orc_tree_lqr(N, NX, NU, pb->parent, A, B, c, Q, R, M, q, r, zero_x, dx,
+                                 du, lh, K, kk, P, p, bad);
+    if (lst != ORC_OK) return lst;
+    double gtd = 0.0, dhd = 0.0, ld = 0.0, dd = 0.0;
+    for (int n = 0; n < N; ++n) {
+        const double* Qn = Q + n * NX * NX;
+        const double* Rn = R + n * NU * NU;
+        for (int a = 0; a < NX; ++a) {
+            gtd += q[n * NX + a] * dx[n * NX + a];
+            for (int b = 0; b < NX; ++b) dhd += dx[n * NX + a] * Qn[a * NX + b] * dx[n * NX + b];
+        }
+        if (nch[n] > 0)
+            for (int a = 0; a < NU; ++a) {
+                gtd += r[n * NU + a] * du[n * NU + a];
+                for (int b = 0; b < NU; ++b) dhd += du[n * NU + a] * Rn[a * NU + b] * du[n * NU + b];
+            }
+        if (n > 0)
+            for (int a = 0; a < NX; ++a) {
+                ld += (lh[n * NX + a] - 2.0 * lam[n * NX + a]) * c[n * NX + a];
+                dd += c[n * NX + a] * c[n * NX + a];
+            }
+    }
+    double mu_hat = 0.0;
+    if (dd > 0.0) {
+        mu_hat = (gtd + ld + 0.5 * dhd) / dd;
+        if (mu < mu_hat) mu = fmax(mu_hat, 2.0 * mu);
+    }
+    sl[0] = gtd;
+    sl[1] = dhd;
+    sl[2] = ld;
+    sl[3] = dd;
+    sl[4] = mu_hat;
+    sl[5] = mu;
+    sl[6] = gtd + ld - mu * dd;
+    sl[7] = merit_impl(pb, nch, x, u, lam, ye, rho, mu);
+    return ORC_OK;
+}
+
+int orc_direction(const orc_problem* pb, const double* x, const double* u, const double* lam,
+                  const double* ye, double rho, double mu, double* dx, double* du, double* lh,
+                  double* out)
+{
+    const int N = pb->N;
+    int* nch = child_counts(pb);
+    double* A = calloc((size_t)N * NX * NX, sizeof(double));
+    double* B = calloc((size_t)N * NX * NU, sizeof(double));
+    double* c = calloc((size_t)N * NX, sizeof(double));
+    double* Q = calloc((size_t)N * NX * NX, sizeof(double));
+    double* R = calloc((size_t)N * NU * NU, sizeof(double));
+    double* M = calloc((size_t)N * NU * NX, sizeof(double));
+    double* q = calloc((size_t)N * NX, sizeof(double));
+    double* r = calloc((size_t)N * NU, sizeof(double));
+    double* K = calloc((size_t)N * NU * NX, sizeof(double));
+    double* kk = calloc((size_t)N * NU, sizeof(double));
+    double* P = calloc((size_t)N * NX * NX, sizeof(double));
+    double* p = calloc((size_t)N * NX, sizeof(double));
+    int bad = -1;
+    const int st = direction_step(pb, nch, x, u, lam, ye, rho, mu, A, B, c, Q, R, M, q, r, dx,
+                                  du, lh, K, kk, P, p, &bad, out);
+    free(nch); free(A); free(B); free(c); free(Q); free(R); free(M); free(q); free(r);
+    free(K); free(kk); free(P); free(p);
+    return st;
+}
+
 /* ------------------------------------------------------------------------
  * AL multiple-shooting iLQR (Sec. IV, Alg. 1).
  * ---------------------------------------------------------------------- */
@@ -501,7 +604,6 @@ int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm, doub
     double* xt = calloc((size_t)N * nx, sizeof(double));
     double* ut = calloc((size_t)N * nu, sizeof(double));
     double* lt = calloc((size_t)N * nx, sizeof(double));
-    double zero_x[NX] = {0, 0, 0, 0};
     int status = ORC_ERR_MAXITER;
     int bad = -1, nhist = 0;
 
@@ -544,12 +646,6 @@ int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm, doub
 
     for (outer = 0; outer < st->max_outer; ++outer) {
         for (int inner = 0;; ++inner) {
-            /* linearise dynamics and quadratise L_a at (x, u) */
-            for (int n = 0; n < N; ++n) {
-                node_terms_impl(pb, n, nch[n] == 0, x + n * NX, u + n * NU, ye + n * NG, rho,
-                                NULL, q + n * NX, r + n * NU, Q + n * NX * NX, R + n * NU * NU);
-                if (n > 0) defect(pb, n, x, u, c + n * NX, A + n * NX * NX, B + n * NX * NU);
-            }
             r_kkt = orc_kkt(pb, x, u, lam, ye, rho);
             if (!isfinite(r_kkt)) {
                 status = ORC_ERR_NONFINITE;
@@ -562,56 +658,35 @@ int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm, doub
                 goto done;
             }
 
-            /* search direction: tree LQR in the deviations, delta x_0 = 0 */
-            int lst = orc_tree_lqr(N, NX, NU, pb->parent, A, B, c, Q, R, M, q, r, zero_x, dx,
-                                   du, lh, K, kk, P, p, &bad);
+            /* search direction, merit slope and the adaptive mu */
+            double sl[8];
+            int lst = direction_step(pb, nch, x, u, lam, ye, rho, mu, A, B, c, Q, R, M, q, r,
+                                     dx, du, lh, K, kk, P, p, &bad, sl);
             if (lst != ORC_OK) {
                 status = lst;
                 goto done;
             }
-            /* merit slope and adaptive mu (Gill et al.): require
-             * phi'(0) <= -1/2 dz^T H dz, using J_d dz = -d for the LQR step */
-            double gtd = 0.0, dhd = 0.0, ld = 0.0, dd = 0.0;
-            for (int n = 0; n < N; ++n) {
-                const double* Qn = Q + n * NX * NX;
-                const double* Rn = R + n * NU * NU;
-                for (int a = 0; a < NX; ++a) {
-                    gtd += q[n * NX + a] * dx[n * NX + a];
-                    for (int b = 0; b < NX; ++b)
-                        dhd += dx[n * NX + a] * Qn[a * NX + b] * dx[n * NX + b];
-                }
-                if (nch[n] > 0)
-                    for (int a = 0; a < NU; ++a) {
-                        gtd += r[n * NU + a] * du[n * NU + a];
-                        for (int b = 0; b < NU; ++b)
-                            dhd += du[n * NU + a] * Rn[a * NU + b] * du[n * NU + b];
-                    }
-                if (n > 0)
-                    for (int a = 0; a < NX; ++a) {
-                        ld += (lh[n * NX + a] - 2.0 * lam[n * NX + a]) * c[n * NX + a];
-                        dd += c[n * NX + a] * c[n * NX + a];
-                    }
-            }
-            if (dd > 0.0) {
-                const double mu_hat = (gtd + ld + 0.5 * dhd) / dd;
-                if (mu < mu_hat) mu = fmax(mu_hat, 2.0 * mu);
-            }
-            const double phi0 = merit_impl(pb, nch, x, u, lam, ye, rho, mu);
-            const double dphi0 = gtd + ld - mu * dd;
+            mu = sl[5];
+            const double dphi0 = sl[6], phi0 = sl[7];
 
-            /* all trial step sizes, then the largest accepted one */
+            /* backtracking (Sec. IV-A): each round evaluates n_alpha trial step
+             * sizes 2^-k and keeps the largest accepted one; a further round
+             * of smaller steps runs only when a round accepts none */
             double alpha_acc = -1.0, phi_acc = phi0;
-            double alpha = 1.0;
-            for (int ka = 0; ka < st->n_alpha; ++ka, alpha *= 0.5) {
-                for (size_t e = 0; e < (size_t)N * nx; ++e) {
-                    xt[e] = x[e] + alpha * dx[e];
-                    lt[e] = lam[e] + alpha * (lh[e] - lam[e]);
-                }
-                for (size_t e = 0; e < (size_t)N * nu; ++e) ut[e] = u[e] + alpha * du[e];
-                const double phi = merit_impl(pb, nch, xt, ut, lt, ye, rho, mu);
-                if (phi <= phi0 + st->armijo_beta * alpha * dphi0 && alpha > alpha_acc) {
-                    alpha_acc = alpha;
-                    phi_acc = phi;
+            const int rounds = st->ls_rounds > 0 ? st->ls_rounds : 1;
+            for (int rd = 0; rd < rounds && alpha_acc < 0.0; ++rd) {
+                double alpha = ldexp(1.0, -rd * st->n_alpha);
+                for (int ka = 0; ka < st->n_alpha; ++ka, alpha *= 0.5) {
+                    for (size_t e = 0; e < (size_t)N * nx; ++e) {
+                        xt[e] = x[e] + alpha * dx[e];
+                        lt[e] = lam[e] + alpha * (lh[e] - lam[e]);
+                    }
+                    for (size_t e = 0; e < (size_t)N * nu; ++e) ut[e] = u[e] + alpha * du[e];
+                    const double phi = merit_impl(pb, nch, xt, ut, lt, ye, rho, mu);
+                    if (phi <= phi0 + st->armijo_beta * alpha * dphi0 && alpha > alpha_acc) {
+                        alpha_acc = alpha;
+                        phi_acc = phi;
+                    }
                 }
             }
             if (alpha_acc < 0.0) {
@@ -621,7 +696,7 @@ int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm, doub
                     status = ORC_ERR_LINESEARCH;
                     goto done;
                 }
-                alpha_acc = ldexp(1.0, -(st->n_alpha - 1));
+                alpha_acc = ldexp(1.0, -(rounds * st->n_alpha - 1));
                 phi_acc = NAN;
             } else {
                 ls_fail_run = 0;
@@ -666,7 +741,11 @@ int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm, doub
             omega = st->omega0 / pow(rho, st->a_omega);
             eta = st->eta0 / pow(rho, st->a_eta);
         }
+        /* Alg. 1 floors omega at eps_tol; eta gets the same floor: the stopping
+         * test only asks c < eps_tol, and a smaller eta would raise rho for a
+         * violation that already meets it */
         omega = fmax(omega, st->eps_tol);
+        eta = fmax(eta, st->eps_tol);
     }
 
 done:
