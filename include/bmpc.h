@@ -176,8 +176,11 @@ typedef struct {
 /* Parameters of the AL outer loop and iLQR inner loop (Alg. 1).  Defaults
    from bmpc_settings_default: eps_tol 1e-6, tau 100, omega0 1, eta0 0.1,
    a_omega = b_omega = 1, a_eta 0.1, b_eta 0.9, rho0 100, mu0 100, Armijo
-   constant 1e-4, n_alpha 10 step sizes 2^0 .. 2^-9, max_outer 50, max_inner
-   100 (per outer iteration), max_ls_fail 3 consecutive line-search failures. */
+   constant 1e-4, n_alpha 10 step sizes 2^0 .. 2^-9 per backtracking round,
+   ls_rounds 3, max_outer 50, max_inner 100 (per outer iteration),
+   max_ls_fail 3 consecutive line-search failures.  The merit of a trial
+   point whose steering angle leaves (-pi/2, pi/2), where the bicycle model is
+   undefined, is +inf.  Tolerances omega and eta are floored at eps_tol. */
 typedef struct {
     double eps_tol, tau, omega0, eta0, a_omega, b_omega, a_eta, b_eta;
     double rho0, mu0, armijo_beta;
@@ -191,6 +194,12 @@ typedef struct {
     /* cap on inner iterations summed over all outer iterations (0 = none);
        reaching it ends the solve with BMPC_ERR_MAXITER */
     int32_t max_iter_total;
+    /* backtracking rounds of the line search (Sec. IV-A), 1 .. 8: round k
+       tries the n_alpha step sizes 2^-(k n_alpha) .. 2^-(k n_alpha + n_alpha
+       - 1) and runs only when round k - 1 accepted none; if no round accepts
+       a step, the step 2^-(ls_rounds n_alpha - 1) is taken and counted as a
+       line-search failure */
+    int32_t ls_rounds;
 } bmpc_settings;
 
 /* Result of one solve.  r_kkt: last KKT residual of the relaxed problem

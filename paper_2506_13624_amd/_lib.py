@@ -74,15 +74,56 @@ def check(status):
     return status
 
 
-def dptr(t):
-    """Device pointer of a torch tensor (None -> NULL)."""
+def dptr(t, dtype=None, numel=None, name="array"):
+    """Device pointer of a torch tensor (None -> NULL).  With ``dtype`` and
+    ``numel`` the tensor must have that element type and hold at least that
+    many elements: the kernels trust the sizes the library derives from its
+    handles, so a short or mistyped array would be read past its end."""
     if t is None:
         return None
+    _check_only(t, dtype, numel, name)
     if not t.is_cuda:
-        raise ValueError("device array expected (torch tensor on a HIP device)")
+        raise ValueError(f"{name}: device array expected (torch tensor on a HIP device)")
     if not t.is_contiguous():
-        raise ValueError("device array must be contiguous")
+        raise ValueError(f"{name}: device array must be contiguous")
     return _vp(t.data_ptr())
+
+
+def _dptrs(specs):
+    """dptr over (tensor, dtype, numel, name) tuples, checking the types and
+    sizes of all of them before the device placement of any."""
+    for t, dtype, numel, name in specs:
+        if t is not None:
+            _check_only(t, dtype, numel, name)
+    return [dptr(t, dtype, numel, name) for t, dtype, numel, name in specs]
+
+
+def _check_only(t, dtype, numel, name):
+    if dtype is not None and t.dtype != _torch_dtype(dtype):
+        raise ValueError(f"{name}: element type {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, at least {numel} expected")
+
+
+def _torch_dtype(name):
+    import torch
+    return {"float64": torch.float64, "float32": torch.float32, "int16": torch.int16,
+            "bfloat16": torch.bfloat16}[name]
+
+
+def _bf16_ptr(t, numel, name):
+    """BF16 bit patterns: int16 or bfloat16 tensors."""
+    if t is not None and t.dtype == _torch_dtype("bfloat16"):
+        return dptr(t, "bfloat16", numel, name)
+    return dptr(t, "int16", numel, name)
+
+
+# sizes behind the opaque handles, for the argument checks of dptr
+_dims = {}
+
+
+def _key(h):
+    return h.value if isinstance(h, _vp) else int(h)
 
 
 def _hi32(a):
@@ -151,16 +192,23 @@ def bmpc_lqr_supported(nx, nu, variant=RICCATI_AUTO):
 def bmpc_lqr_plan_create(tree, nx, nu, layout):
     h = _vp()
     check(lib.bmpc_lqr_plan_create(tree, nx, nu, layout, C.byref(h)))
+    _dims[_key(h)] = (bmpc_tree_info(tree)["num_nodes"], nx, nu)
     return h
 
 
 def bmpc_lqr_plan_destroy(h):
+    _dims.pop(_key(h), None)
     lib.bmpc_lqr_plan_destroy(h)
 
 
 def bmpc_lqr_solve(plan, A, B, c, Q, R, M, q, r, x0, x, u, lam, K=None, k=None, P=None, p=None,
                    variant=RICCATI_AUTO, stream=None):
-    args = [dptr(v) for v in (A, B, c, Q, R, M, q, r, x0, x, u, lam, K, k, P, p)]
+    N, n, m = _dims[_key(plan)]
+    sizes = (("A", N * n * n), ("B", N * n * m), ("c", N * n), ("Q", N * n * n), ("R", N * m * m),
+             ("M", N * m * n), ("q", N * n), ("r", N * m), ("x0", n), ("x", N * n), ("u", N * m),
+             ("lam", N * n), ("K", N * m * n), ("k", N * m), ("P", N * n * n), ("p", N * n))
+    args = _dptrs([(v, "float64", cnt, nm) for v, (nm, cnt) in zip((A, B, c, Q, R, M, q, r, x0, x, u, lam, K, k,
+                                                                     P, p), sizes)])
     check(lib.bmpc_lqr_solve(plan, *args, variant, stream_ptr(stream)))
 
 
@@ -209,7 +257,7 @@ class bmpc_settings(C.Structure):
                 ("mu0", C.c_double), ("armijo_beta", C.c_double), ("n_alpha", C.c_int32),
                 ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("max_ls_fail", C.c_int32),
                 ("riccati_variant", C.c_int32), ("block_size", C.c_int32),
-                ("max_iter_total", C.c_int32)]
+                ("max_iter_total", C.c_int32), ("ls_rounds", C.c_int32)]
 
 
 class bmpc_stats(C.Structure):
@@ -279,10 +327,12 @@ def bmpc_problem_create(tree, prm, node_weight, node_ref, node_obs, has_obs, x0)
     x, xp = _hf64(x0)
     out = _vp()
     check(lib.bmpc_problem_create(tree, C.byref(prm), wp, rp, op, hp, xp, C.byref(out)))
+    _dims[_key(out)] = bmpc_tree_info(tree)["num_nodes"]
     return out
 
 
 def bmpc_problem_destroy(h):
+    _dims.pop(_key(h), None)
     lib.bmpc_problem_destroy(h)
 
 
@@ -316,8 +366,9 @@ def bmpc_solve(problem, settings, warm, x, u, lam, ye, stream=None, raise_on_sta
     """x, u, lam, ye: device tensors (node-major).  Returns the stats dict;
     the solver's own status is reported in stats['status']."""
     st = bmpc_stats()
-    status = lib.bmpc_solve(problem, C.byref(settings), warm, dptr(x), dptr(u), dptr(lam), dptr(ye),
-                            C.byref(st), stream_ptr(stream))
+    N = _dims[_key(problem)]
+    status = lib.bmpc_solve(problem, C.byref(settings), warm, *_state_ptrs(N, x, u, lam, ye), C.byref(st),
+                            stream_ptr(stream))
     if raise_on_status:
         check(status)
     elif status not in (0, 3, 4, 5, 6):
@@ -327,8 +378,11 @@ def bmpc_solve(problem, settings, warm, x, u, lam, ye, stream=None, raise_on_sta
 
 def bmpc_linearize(problem, x, u, lam, ye, rho, A, B, c, Q, R, q, r, stream=None):
     kv = np.zeros(2)
-    check(lib.bmpc_linearize(problem, dptr(x), dptr(u), dptr(lam), dptr(ye), rho, dptr(A), dptr(B),
-                             dptr(c), dptr(Q), dptr(R), dptr(q), dptr(r), kv.ctypes.data_as(_pd),
+    N = _dims[_key(problem)]
+    f = _dptrs([(v, "float64", N * w, nm) for v, w, nm in
+         ((x, 4, "x"), (u, 2, "u"), (lam, 4, "lam"), (ye, 5, "ye"), (A, 16, "A"), (B, 8, "B"), (c, 4, "c"),
+          (Q, 16, "Q"), (R, 4, "R"), (q, 4, "q"), (r, 2, "r"))])
+    check(lib.bmpc_linearize(problem, f[0], f[1], f[2], f[3], rho, *f[4:], kv.ctypes.data_as(_pd),
                              stream_ptr(stream)))
     return float(kv[0]), float(kv[1])
 
@@ -337,10 +391,12 @@ def bmpc_batch_create(problems, hist_cap=0):
     arr = (_vp * len(problems))(*[p.value if isinstance(p, _vp) else p for p in problems])
     out = _vp()
     check(lib.bmpc_batch_create(arr, len(problems), hist_cap, C.byref(out)))
+    _dims[_key(out)] = [_dims[_key(p)] for p in problems]
     return out
 
 
 def bmpc_batch_destroy(h):
+    _dims.pop(_key(h), None)
     lib.bmpc_batch_destroy(h)
 
 
@@ -354,13 +410,22 @@ def bmpc_batch_stats(batch, count, stream=None):
     return [a.as_dict() for a in arr]
 
 
+def _state_ptrs(N, x, u, lam, ye):
+    return _dptrs([(v, "float64", N * w, nm) for v, w, nm in ((x, 4, "x"), (u, 2, "u"), (lam, 4, "lam"),
+                                                               (ye, 5, "ye"))])
+
+
 def bmpc_batch_state(batch, i, x=None, u=None, lam=None, ye=None, into_batch=False, stream=None):
-    check(lib.bmpc_batch_state(batch, i, dptr(x), dptr(u), dptr(lam), dptr(ye), 1 if into_batch else 0,
+    sizes = _dims[_key(batch)]
+    if not 0 <= i < len(sizes):
+        raise ValueError(f"problem index {i} outside the batch of {len(sizes)}")
+    check(lib.bmpc_batch_state(batch, i, *_state_ptrs(sizes[i], x, u, lam, ye), 1 if into_batch else 0,
                                stream_ptr(stream)))
 
 
 def bmpc_batch_state_all(batch, x=None, u=None, lam=None, ye=None, into_batch=False, stream=None):
-    check(lib.bmpc_batch_state_all(batch, dptr(x), dptr(u), dptr(lam), dptr(ye), 1 if into_batch else 0,
+    T = sum(_dims[_key(batch)])
+    check(lib.bmpc_batch_state_all(batch, *_state_ptrs(T, x, u, lam, ye), 1 if into_batch else 0,
                                    stream_ptr(stream)))
 
 
@@ -376,7 +441,8 @@ def bmpc_batch_history(batch, i, hist_cap, stream=None):
 
 def bmpc_batch_start_from_network(batch, Y, rows, width, stream=None):
     """Y: float32 device tensor (rows x width)."""
-    check(lib.bmpc_batch_start_from_network(batch, dptr(Y), rows, width, stream_ptr(stream)))
+    check(lib.bmpc_batch_start_from_network(batch, dptr(Y, "float32", rows * width, "Y"), rows, width,
+                                            stream_ptr(stream)))
 
 
 def bmpc_batch_shift(batch, stream=None):
@@ -409,10 +475,12 @@ def bmpc_mlp_create(widths, max_batch):
     w, pw = _hi32(widths)
     out = _vp()
     check(lib.bmpc_mlp_create(pw, len(w) - 1, max_batch, C.byref(out)))
+    _dims[_key(out)] = (int(w[0]), int(w[-1]))
     return out
 
 
 def bmpc_mlp_destroy(h):
+    _dims.pop(_key(h), None)
     lib.bmpc_mlp_destroy(h)
 
 
@@ -441,28 +509,38 @@ def bmpc_mlp_get_params(h):
 
 def bmpc_mlp_forward(h, X, Y, stream=None):
     """X (B, w_0) and Y (B, w_L): float32 device tensors."""
-    check(lib.bmpc_mlp_forward(h, dptr(X), X.shape[0], dptr(Y), stream_ptr(stream)))
+    w0, wl = _dims[_key(h)]
+    B = X.shape[0]
+    px, py = _dptrs([(X, "float32", B * w0, "X"), (Y, "float32", B * wl, "Y")])
+    check(lib.bmpc_mlp_forward(h, px, B, py, stream_ptr(stream)))
 
 
 def bmpc_mlp_gradients(h, X, T, stream=None):
     g = np.zeros(bmpc_mlp_num_params(h), dtype=np.float32)
     loss = np.zeros(1, dtype=np.float32)
-    check(lib.bmpc_mlp_gradients(h, dptr(X), dptr(T), X.shape[0], g.ctypes.data_as(_pf32),
+    w0, wl = _dims[_key(h)]
+    B = X.shape[0]
+    px, pt = _dptrs([(X, "float32", B * w0, "X"), (T, "float32", B * wl, "T")])
+    check(lib.bmpc_mlp_gradients(h, px, pt, B,
+                                 g.ctypes.data_as(_pf32),
                                  loss.ctypes.data_as(_pf32), stream_ptr(stream)))
     return float(loss[0]), g
 
 
 def bmpc_mlp_train_step(h, X, T, lr, want_loss=True, stream=None):
     loss = np.zeros(1, dtype=np.float32)
-    check(lib.bmpc_mlp_train_step(h, dptr(X), dptr(T), X.shape[0], lr,
+    w0, wl = _dims[_key(h)]
+    B = X.shape[0]
+    px, pt = _dptrs([(X, "float32", B * w0, "X"), (T, "float32", B * wl, "T")])
+    check(lib.bmpc_mlp_train_step(h, px, pt, B, lr,
                                   loss.ctypes.data_as(_pf32) if want_loss else None, stream_ptr(stream)))
     return float(loss[0]) if want_loss else None
 
 
 def bmpc_gemm_bf16(M, N, K, A, trans_a, B, trans_b, C_out, stream=None):
     """A, B: int16/bfloat16 device tensors holding BF16 bit patterns; C_out float32."""
-    check(lib.bmpc_gemm_bf16(M, N, K, dptr(A), int(trans_a), dptr(B), int(trans_b), dptr(C_out),
-                             stream_ptr(stream)))
+    check(lib.bmpc_gemm_bf16(M, N, K, _bf16_ptr(A, M * K, "A"), int(trans_a), _bf16_ptr(B, K * N, "B"),
+                             int(trans_b), dptr(C_out, "float32", M * N, "C"), stream_ptr(stream)))
 
 
 # ----------------------------------------------------------------------------

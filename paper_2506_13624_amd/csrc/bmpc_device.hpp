@@ -139,6 +139,14 @@ __device__ __forceinline__ void node_constraints(const BikeParams& P, const Node
     g[4] = P.obs_r - dist;
 }
 
+// The kinematic bicycle is defined for steering angles inside (-pi/2, pi/2):
+// tan(delta) has its pole at pi/2 and past it the yaw rate changes sign.  A
+// point with a control outside is not a point of the problem (merit +inf).
+__device__ __forceinline__ bool steer_in_domain(const double (&u)[BU])
+{
+    return fabs(u[1]) < 1.5707963267948966;
+}
+
 // Value of the node's augmented objective
 //   w * (1/2 |x - ref|_Q^2 + 1/2 |u|_R^2) + rho/2 sum_active max(0, g + y/rho)^2.
 __device__ __forceinline__ double node_value(const BikeParams& P, const NodeData& nd, const double (&x)[BX],

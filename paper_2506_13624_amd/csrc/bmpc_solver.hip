@@ -37,6 +37,7 @@
 namespace bmpc {
 
 constexpr int NALPHA_MAX = 12;
+constexpr int LS_ROUNDS_MAX = 8;
 
 // Workspace arrays per instance (node-major, doubles per node)
 enum WsOff : int {
@@ -89,7 +90,7 @@ struct InstDesc {
 
 struct SolverCfg {
     double eps_tol, tau, omega0, eta0, a_omega, b_omega, a_eta, b_eta, rho0, mu0, beta;
-    int n_alpha, max_outer, max_inner, max_ls_fail, max_total;
+    int n_alpha, max_outer, max_inner, max_ls_fail, max_total, ls_rounds;
     int warm;  // bits: 1 x,u given, 2 lam given, 4 ye given, 8 u given (x rolled out), 16 guarded
 };
 
@@ -239,6 +240,7 @@ __device__ void pass_linearise(const InstDesc& I, double rho, double& La, double
         for (int s = 0; s < BG; ++s) ye[s] = I.ye[n * BG + s];
         double q[BX], r[BU], Qh[BX][BX], Rh[BU][BU];
         La += node_quad(I.prm, nd, x, u, ye, rho, q, r, Qh, Rh);
+        if (!nd.leaf && !steer_in_domain(u)) La = INFINITY;
         double* w = I.ws + (long)n * W_NODE;
 #pragma unroll
         for (int i = 0; i < BX; ++i) {
@@ -259,7 +261,7 @@ __device__ void pass_linearise(const InstDesc& I, double rho, double& La, double
         for (int s = 0; s < BG; ++s)
             if (on[s]) {
                 const double c = fabs(fmax(g[s], -ye[s] / rho));
-                viol = (c != c) ? NAN : fmax(viol, c);
+                viol = (viol != viol || c != c) ? NAN : fmax(viol, c);
             }
         double xn[BX] = {0.0, 0.0, 0.0, 0.0}, A[BX][BX] = {}, B[BX][BU] = {};
         if (!nd.leaf) bike_step_jac(I.prm, x, u, xn, A, B);
@@ -294,7 +296,7 @@ __device__ void pass_defects_kkt(const InstDesc& I, double& rk, double& ld, doub
                 w[W_C + i] = d;
                 ld += lam[i] * d;
                 dd += d * d;
-                rk = (d != d) ? NAN : fmax(rk, fabs(d));
+                rk = (rk != rk || d != d) ? NAN : fmax(rk, fabs(d));
             }
         } else {
 #pragma unroll
@@ -312,7 +314,7 @@ __device__ void pass_defects_kkt(const InstDesc& I, double& rk, double& ld, doub
                 if (c1 > c0)
 #pragma unroll
                     for (int k = 0; k < BX; ++k) gx += w[W_A + k * 4 + i] * s[k];
-                rk = (gx != gx) ? NAN : fmax(rk, fabs(gx));
+                rk = (rk != rk || gx != gx) ? NAN : fmax(rk, fabs(gx));
             }
         }
         if (c1 > c0) {
@@ -321,7 +323,7 @@ __device__ void pass_defects_kkt(const InstDesc& I, double& rk, double& ld, doub
                 double gu = w[W_RV + i];
 #pragma unroll
                 for (int k = 0; k < BX; ++k) gu += w[W_B + k * 2 + i] * s[k];
-                rk = (gu != gu) ? NAN : fmax(rk, fabs(gu));
+                rk = (rk != rk || gu != gu) ? NAN : fmax(rk, fabs(gu));
             }
         }
     }
@@ -1407,8 +1409,14 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             const double phi0 = La0 + ld0 + 0.5 * mu * dd0;
             const double dphi0 = gtd + lhd - mu * dd0;
 
-            // merit at every trial step size
+            // backtracking (Sec. IV-A): a round evaluates the merit at na
+            // step sizes 2^-k0 ... 2^-(k0+na-1) and keeps the largest accepted
+            // one; a further round of smaller steps runs only when a round
+            // accepts none
             const int na = cfg.n_alpha;
+            double a_star = -1.0, phi_star = NAN;
+            for (int rd = 0; rd < cfg.ls_rounds && a_star < 0.0; ++rd) {
+            const int k0 = rd * na;
             double tr[3 * NALPHA_MAX];
 #pragma unroll
             for (int e = 0; e < 3 * NALPHA_MAX; ++e) tr[e] = 0.0;
@@ -1420,7 +1428,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             for (int it = tid; it < N * na / per; it += T::size())
             for (int sub = 0; sub < per; ++sub) {
                 const int n = per == 1 ? it / na : it, ka = per == 1 ? it - n * na : sub;
-                const double alpha = ldexp(1.0, -ka);
+                const double alpha = ldexp(1.0, -(k0 + ka));
                 const double* w = I.ws + (long)n * W_NODE;
                 const NodeData nd = node_data(I, n);
                 double x[BX], u[BU], ye[BG], dx[BX];
@@ -1436,7 +1444,9 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                 for (int i = 0; i < BX; ++i) xt[i] = x[i] + alpha * dx[i];
 #pragma unroll
                 for (int i = 0; i < BU; ++i) ut[i] = u[i] + alpha * w[W_DU + i];
-                const double v = node_value(I.prm, nd, xt, ut, ye, rho);
+                // outside the model's domain the trial point has merit +inf
+                const double v = (c1 > c0 && !steer_in_domain(ut)) ? INFINITY
+                                                                   : node_value(I.prm, nd, xt, ut, ye, rho);
                 double ld = 0.0, dd = 0.0;
                 if (c1 > c0) {
                     double ft[BX];
@@ -1463,7 +1473,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                     }
             }
             T::template reduce<3 * NALPHA_MAX, false>(tr, sred, gpart);
-            double a_star = -1.0, phi_star = NAN, alpha = 1.0;
+            double alpha = ldexp(1.0, -k0);
             // constant indices only, so that tr stays in registers (a loop
             // bounded by na would index it at run time and move it to
             // scratch memory, for the accumulation above as well)
@@ -1478,13 +1488,14 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                 }
                 alpha *= 0.5;
             }
+            }
             if (a_star < 0.0) {
                 ++ls_fail;
                 if (++ls_run >= cfg.max_ls_fail) {
                     status = BMPC_ERR_LINESEARCH;
                     goto done;
                 }
-                a_star = ldexp(1.0, -(na - 1));
+                a_star = ldexp(1.0, -(cfg.ls_rounds * na - 1));
                 phi_star = NAN;
             } else {
                 ls_run = 0;
@@ -1543,7 +1554,10 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             omega = cfg.omega0 / pow(rho, cfg.a_omega);
             eta = cfg.eta0 / pow(rho, cfg.a_eta);
         }
+        // Alg. 1 floors omega at eps_tol; eta gets the same floor, since the
+        // stopping test asks only viol < eps_tol
         omega = fmax(omega, cfg.eps_tol);
+        eta = fmax(eta, cfg.eps_tol);
     }
 
 done:
@@ -1917,6 +1931,7 @@ static SolverCfg to_cfg(const bmpc_settings& s, int warm)
     c.max_inner = s.max_inner;
     c.max_total = s.max_iter_total;
     c.max_ls_fail = s.max_ls_fail;
+    c.ls_rounds = s.ls_rounds;
     c.warm = warm;
     return c;
 }
@@ -1992,6 +2007,7 @@ BMPC_API void bmpc_settings_default(bmpc_settings* s)
     s->riccati_variant = BMPC_RICCATI_AUTO;
     s->block_size = 0;
     s->max_iter_total = 0;
+    s->ls_rounds = 3;
 }
 
 BMPC_API void bmpc_bicycle_default(bmpc_bicycle_params* p)
@@ -2237,6 +2253,8 @@ BMPC_API bmpc_status bmpc_batch_launch(bmpc_batch* b, const bmpc_settings* s, in
     if (!b || !s) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
     if (s->n_alpha < 1 || s->n_alpha > NALPHA_MAX)
         return fail(BMPC_ERR_INVALID_ARG, "n_alpha must be in [1, %d]", NALPHA_MAX);
+    if (s->ls_rounds < 1 || s->ls_rounds > LS_ROUNDS_MAX)
+        return fail(BMPC_ERR_INVALID_ARG, "ls_rounds must be in [1, %d]", LS_ROUNDS_MAX);
     if (s->riccati_variant != BMPC_RICCATI_AUTO && s->riccati_variant != BMPC_RICCATI_LEVEL &&
         s->riccati_variant != BMPC_RICCATI_SEGSCAN)
         return fail(BMPC_ERR_INVALID_ARG, "unknown Riccati variant %d", s->riccati_variant);
@@ -2270,6 +2288,8 @@ BMPC_API bmpc_status bmpc_batch_tune(bmpc_batch* b, const bmpc_settings* s, int3
     if (warm < 0 || warm > 31) return fail(BMPC_ERR_INVALID_ARG, "warm bits %d outside [0, 31]", warm);
     if (s->n_alpha < 1 || s->n_alpha > NALPHA_MAX)
         return fail(BMPC_ERR_INVALID_ARG, "n_alpha must be in [1, %d]", NALPHA_MAX);
+    if (s->ls_rounds < 1 || s->ls_rounds > LS_ROUNDS_MAX)
+        return fail(BMPC_ERR_INVALID_ARG, "ls_rounds must be in [1, %d]", LS_ROUNDS_MAX);
     hipStream_t st = (hipStream_t)stream;
     const size_t bytes = sizeof(double) * (size_t)b->total_nodes * 15;
     double* saved = nullptr;

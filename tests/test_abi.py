@@ -81,3 +81,47 @@ def test_supported_dimensions_reported(L):
     assert L.bmpc_lqr_supported(4, 2)
     assert L.bmpc_lqr_supported(12, 4)
     assert not L.bmpc_lqr_supported(5, 5)
+
+
+def test_binding_rejects_mistyped_or_short_arrays_before_the_call(L):
+    """Every device array passed through the binding is checked against the
+    sizes behind its handle (element type, element count) before the C call,
+    so no kernel can read past a short or mistyped buffer.  Host tensors are
+    enough here: the checks come first."""
+    import torch
+    N, n, m = 10, 3, 2
+    fake = ctypes.c_void_p(0x1000)
+    L._dims[L._key(fake)] = (N, n, m)
+    try:
+        good = {k: torch.zeros(N * w, dtype=torch.float64) for k, w in
+                (("A", n * n), ("B", n * m), ("c", n), ("Q", n * n), ("R", m * m), ("M", m * n), ("q", n),
+                 ("r", m), ("x", n), ("u", m), ("lam", n))}
+        x0 = torch.zeros(n, dtype=torch.float64)
+        args = lambda d: (d["A"], d["B"], d["c"], d["Q"], d["R"], d["M"], d["q"], d["r"], x0, d["x"],
+                          d["u"], d["lam"])
+        bad = dict(good, B=torch.zeros(N * n * m, dtype=torch.float32))
+        with pytest.raises(ValueError, match="element type"):
+            L.bmpc_lqr_solve(fake, *args(bad))
+        bad = dict(good, Q=torch.zeros(N * n * n - 1, dtype=torch.float64))
+        with pytest.raises(ValueError, match="at least"):
+            L.bmpc_lqr_solve(fake, *args(bad))
+        # right types and sizes: only the device check is left
+        with pytest.raises(ValueError, match="device array expected"):
+            L.bmpc_lqr_solve(fake, *args(good))
+        # a problem of N nodes: state arrays N x 4, N x 2, N x 4, N x 5
+        L._dims[L._key(fake)] = N
+        st = L.bmpc_settings_default()
+        with pytest.raises(ValueError, match="ye"):
+            L.bmpc_solve(fake, st, 0, torch.zeros(N * 4, dtype=torch.float64),
+                         torch.zeros(N * 2, dtype=torch.float64), torch.zeros(N * 4, dtype=torch.float64),
+                         torch.zeros(N * 4, dtype=torch.float64))
+        # a network with 4 inputs and 2 outputs
+        L._dims[L._key(fake)] = (4, 2)
+        with pytest.raises(ValueError, match="element type"):
+            L.bmpc_mlp_forward(fake, torch.zeros((3, 4), dtype=torch.float64),
+                               torch.zeros(6, dtype=torch.float32))
+        with pytest.raises(ValueError, match="at least"):
+            L.bmpc_mlp_forward(fake, torch.zeros((3, 4), dtype=torch.float32),
+                               torch.zeros(5, dtype=torch.float32))
+    finally:
+        L._dims.pop(L._key(fake), None)
