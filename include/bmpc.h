@@ -277,6 +277,24 @@ BMPC_API bmpc_status bmpc_linearize(bmpc_problem* problem, const double* x, cons
                                     double* c, double* Q, double* R, double* q, double* r, double* kkt_viol,
                                     void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   linearisation as bmpc_linearize, with its workspace rows in a fixed
+   library-owned array of BMPC_NOALLOC_MAX_NODES rows per GPU (3.4 MB, held
+   until the process ends) instead of memory allocated for the problem.
+   The call allocates nothing.  Arguments as in bmpc_linearize, except
+   kkt_viol: a DEVICE pointer (2 doubles, nullable) written by the kernel,
+   so the call is always asynchronous on `stream`.  A problem of more than
+   BMPC_NOALLOC_MAX_NODES nodes -> BMPC_ERR_INVALID_ARG.  Every call on one
+   GPU uses that GPU's one array: calls that overlap on a GPU (different
+   streams, or different host threads) race, and the array keeps the last
+   call's contents. */
+#define BMPC_NOALLOC_MAX_NODES 2048
+BMPC_API bmpc_status bmpc_linearize_noalloc(const bmpc_problem* problem, const double* x, const double* u,
+                                            const double* lam, const double* ye, double rho, double* A,
+                                            double* B, double* c, double* Q, double* R, double* q, double* r,
+                                            double* kkt_viol, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched solve: many independent problems (own trees, own sizes) in one
  * launch.  A persistent kernel: each resident workgroup takes the next

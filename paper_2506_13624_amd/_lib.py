@@ -286,6 +286,8 @@ _sig("bmpc_problem_set_x0", _i32, [_vp, _pd])
 _sig("bmpc_solve", _i32, [_vp, C.POINTER(bmpc_settings), _i32, _vp, _vp, _vp, _vp,
                           C.POINTER(bmpc_stats), _vp])
 _sig("bmpc_linearize", _i32, [_vp, _vp, _vp, _vp, _vp, C.c_double] + [_vp] * 7 + [_pd, _vp])
+_sig("bmpc_linearize_noalloc", _i32, [_vp, _vp, _vp, _vp, _vp, C.c_double] + [_vp] * 8 + [_vp])
+NOALLOC_MAX_NODES = 2048
 _sig("bmpc_batch_create", _i32, [C.POINTER(_vp), _i32, _i32, C.POINTER(_vp)])
 _sig("bmpc_batch_destroy", None, [_vp])
 _sig("bmpc_batch_launch", _i32, [_vp, C.POINTER(bmpc_settings), _i32, _vp])
@@ -385,6 +387,18 @@ def bmpc_linearize(problem, x, u, lam, ye, rho, A, B, c, Q, R, q, r, stream=None
     check(lib.bmpc_linearize(problem, f[0], f[1], f[2], f[3], rho, *f[4:], kv.ctypes.data_as(_pd),
                              stream_ptr(stream)))
     return float(kv[0]), float(kv[1])
+
+
+def bmpc_linearize_noalloc(problem, x, u, lam, ye, rho, A, B, c, Q, R, q, r, kkt_viol=None, stream=None):
+    """As bmpc_linearize, with the library's fixed workspace (no device
+    allocation); kkt_viol: float64 device tensor of 2 entries or None.
+    Asynchronous."""
+    N = _dims[_key(problem)]
+    f = _dptrs([(v, "float64", N * w, nm) for v, w, nm in
+                ((x, 4, "x"), (u, 2, "u"), (lam, 4, "lam"), (ye, 5, "ye"), (A, 16, "A"), (B, 8, "B"),
+                 (c, 4, "c"), (Q, 16, "Q"), (R, 4, "R"), (q, 4, "q"), (r, 2, "r"))]
+               + [(kkt_viol, "float64", 2, "kkt_viol")])
+    check(lib.bmpc_linearize_noalloc(problem, f[0], f[1], f[2], f[3], rho, *f[4:], stream_ptr(stream)))
 
 
 def bmpc_batch_create(problems, hist_cap=0):

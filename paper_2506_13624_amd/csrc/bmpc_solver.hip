@@ -2492,6 +2492,43 @@ BMPC_API bmpc_status bmpc_solve(bmpc_problem* p, const bmpc_settings* s, int32_t
     return BMPC_OK;
 }
 
+}  // extern "C"
+
+// Workspace rows of bmpc_linearize_noalloc: one file-scope device array per
+// GPU, NOALLOC_MAX_NODES rows of W_NODE doubles (3.4 MB), held until the
+// process ends.  Host code never uses the array's name as an address: the
+// device address of each GPU's copy is looked up once with that device
+// current and kept per device.
+constexpr int NOALLOC_MAX_NODES = BMPC_NOALLOC_MAX_NODES;
+static __device__ __align__(256) double scratch[(size_t)NOALLOC_MAX_NODES * W_NODE];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of this GPU's scratch array (looked up on the first call
+// on the device, with it current).
+static bmpc_status scratch_for_current_device(double** out)
+{
+    int dev = 0;
+    BMPC_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(BMPC_ERR_UNSUPPORTED, "device %d beyond the %d devices with a scratch array", dev,
+                    NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(BMPC_ERR_HIP, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return BMPC_OK;
+}
+
+extern "C" {
+
 BMPC_API bmpc_status bmpc_linearize(bmpc_problem* p, const double* x, const double* u, const double* lam,
                                     const double* ye, double rho, double* A, double* B, double* c, double* Q,
                                     double* R, double* q, double* r, double* kkt_viol, void* stream)
@@ -2531,6 +2568,58 @@ BMPC_API bmpc_status bmpc_linearize(bmpc_problem* p, const double* x, const doub
         BMPC_HIP_TRY(hipStreamSynchronize(sm));
         (void)hipFree(kk);
     }
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_linearize_noalloc(const bmpc_problem* p, const double* x, const double* u,
+                                            const double* lam, const double* ye, double rho, double* A, double* B,
+                                            double* c, double* Q, double* R, double* q, double* r,
+                                            double* kkt_viol, void* stream)
+{
+    if (!p || !x || !u || !lam || !ye || !A || !B || !c || !Q || !R || !q || !r)
+        return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    if (!(rho > 0.0)) return fail(BMPC_ERR_INVALID_ARG, "rho must be positive");
+    if (p->N > NOALLOC_MAX_NODES)
+        return fail(BMPC_ERR_INVALID_ARG, "problem of %d nodes exceeds the %d nodes of the fixed workspace", p->N,
+                    NOALLOC_MAX_NODES);
+    double* ws = nullptr;
+    bmpc_status st = scratch_for_current_device(&ws);
+    if (st != BMPC_OK) return st;
+    // the problem's own device data; the point and the workspace rows are
+    // the caller's arrays and the scratch array (the kernel only reads x, u,
+    // lam, ye)
+    InstDesc d{};
+    d.N = p->N;
+    d.T = p->tree->h.depth;
+    d.parent = p->tree->d.parent;
+    d.child_off = p->tree->d.child_off;
+    d.level_off = p->tree->d.level_off;
+    d.weight = p->d_weight;
+    d.ref = p->d_ref;
+    d.obs = p->d_obs;
+    d.has_obs = p->d_has;
+    d.x0 = p->d_x0;
+    d.prm = to_dev(p->prm);
+    d.x = const_cast<double*>(x);
+    d.u = const_cast<double*>(u);
+    d.lam = const_cast<double*>(lam);
+    d.ye = const_cast<double*>(ye);
+    d.ws = ws;
+    hipStream_t sm = (hipStream_t)stream;
+    {
+        ProfScope ps("bmpc_linearise", sm);
+        hipLaunchKernelGGL(k_bmpc_linearise<256>, dim3(1), dim3(256), 0, sm, d, rho, kkt_viol);
+    }
+    BMPC_HIP_TRY(hipGetLastError());
+    const size_t N = d.N;
+    const size_t pitch = sizeof(double) * W_NODE;
+    struct {
+        double* dst;
+        int off, w;
+    } parts[7] = {{A, W_A, 16}, {B, W_B, 8}, {c, W_C, 4}, {Q, W_Q, 16}, {R, W_R, 4}, {q, W_QV, 4}, {r, W_RV, 2}};
+    for (auto& pt : parts)
+        BMPC_HIP_TRY(hipMemcpy2DAsync(pt.dst, sizeof(double) * pt.w, ws + pt.off, pitch, sizeof(double) * pt.w, N,
+                                      hipMemcpyDeviceToDevice, sm));
     return BMPC_OK;
 }
 
