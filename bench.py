@@ -65,6 +65,44 @@ def lqr_algorithmic(parent, nx, nu):
             "fwd_flops": fwd_flops}
 
 
+def lqr_solve_algorithmic_bytes(parent, nx, nu):
+    """Algorithmic bytes of one tree-LQR solve with no intermediate stored:
+    every input read once (A, B, c per edge; Q, R, q, r per control node;
+    Q_f, q_f per leaf) and x, u, lam written once.  Returns (bytes read by
+    the backward pass, bytes of the whole solve).  For nx = 12, nu = 4 that
+    is 1,632 B per edge, 1,408 B per control node and 1,248 B per leaf read,
+    24.7 MB and 26.5 MB for the 8,185-node tree."""
+    N = len(parent)
+    nch = np.bincount(parent[1:], minlength=N)
+    ctrl = int((nch > 0).sum())
+    leaves = N - ctrl
+    n, m, d = nx, nu, 8
+    reads = d * ((N - 1) * (n * n + n * m + n) + ctrl * (n * n + m * m + n + m) + leaves * (n * n + n))
+    writes = d * (N * 2 * n + ctrl * m)
+    return reads, reads + writes
+
+
+def host_info():
+    """Host cores, CPU model and clock, as the kernel reports them."""
+    model, mhz = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and model == "unknown":
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("cpu MHz") and mhz is None:
+                    mhz = float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "cpu_mhz": mhz}
+
+
+def baseline_cores():
+    """Worker count for the CPU baselines: every host core, at most 16 (the
+    host share of one GPU)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 SOLVER_SRCS = ["paper_2506_13624_amd/csrc/bmpc_solver.hip", "paper_2506_13624_amd/csrc/bmpc_device.hpp",
                "paper_2506_13624_amd/csrc/lqr_device.hpp", "paper_2506_13624_amd/csrc/cvf_device.hpp"]
 
@@ -92,20 +130,35 @@ def measured_traffic(kernel, srcs):
 
 
 def cpu_baseline_lqr(inst, budget_s=10.0):
+    """The oracle's serial tree Riccati (built -O3 -march=native for this
+    host), independent solves of the same tree on every host core (one per
+    thread; the C oracle runs outside the interpreter lock), for about
+    budget_s seconds."""
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
+    oracle.use_native_build()
+    cores = baseline_cores()
     oracle.tree_lqr_inst(inst)  # warm
+    t1 = time.perf_counter()
+    oracle.tree_lqr_inst(inst)
+    one_core = time.perf_counter() - t1
+
+    def worker(_):
+        k = 0
+        while time.perf_counter() - t0 < budget_s:
+            oracle.tree_lqr_inst(inst)
+            k += 1
+        return k
     t0 = time.perf_counter()
-    n = 0
-    while True:
-        oracle.tree_lqr_inst(inst)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
+    with ThreadPoolExecutor(cores) as ex:
+        n = sum(ex.map(worker, range(cores)))
+    el = time.perf_counter() - t0
     N = len(inst.parent)
-    return {"value": N * n / el, "unit": "tree-Riccati nodes/s", "cores": 1, "kind": "oracle",
+    return {"value": N * n / el, "unit": "tree-Riccati nodes/s", "cores": cores, "kind": "oracle",
+            "one_core_nodes_per_s": round(N / one_core, 1), "build": "gcc -O3 -march=native",
+            "host": host_info(),
             "sample": f"{n} serial tree-Riccati solves (backward + forward) of the nx=12, nu=4, "
-                      f"8,185-node tree in {el:.1f} s on one host core"}
+                      f"8,185-node tree in {el:.1f} s, one solve per thread on {cores} host cores"}
 
 
 def run_lqr(args, torch, L):
@@ -196,12 +249,15 @@ def run_lqr(args, torch, L):
     fwd_avg_s = fwd_ms / fwd_n / 1e3
     srcs = ["paper_2506_13624_amd/csrc/lqr.hip", "paper_2506_13624_amd/csrc/lqr_device.hpp",
             "paper_2506_13624_amd/csrc/cvf_device.hpp"]
-    achieved = alg["bwd_bytes"] / bwd_avg_s / 1e9
+    bwd_reads, solve_bytes = lqr_solve_algorithmic_bytes(par, nx, nu)
+    achieved = bwd_reads / bwd_avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": measured_traffic(bwd_name, srcs),
                 "kernel": bwd_name, "avg_launch_us": round(bwd_avg_s * 1e6, 2),
-                "algorithmic_bytes_per_launch": alg["bwd_bytes"],
+                "algorithmic_bytes_per_launch": bwd_reads,
+                "bytes_with_stored_gains_per_launch": alg["bwd_bytes"],
+                "frac_with_stored_gains": round(alg["bwd_bytes"] / bwd_avg_s / 1e9 / HBM_PEAK_GBS, 5),
                 "fp64_tflops": round(alg["bwd_flops"] / bwd_avg_s / 1e12, 4),
                 "fp64_frac": round(alg["bwd_flops"] / bwd_avg_s / 1e12 / FP64_PEAK_TFLOPS, 5)}
     kernels = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]} for k, v in prof_all.items()}
@@ -221,6 +277,8 @@ def run_lqr(args, torch, L):
         "ms_per_step_without_event_pairs": round(clean_ms / args.steps, 5),
         "kernels": kernels,
         "forward_GBps": round(alg["fwd_bytes"] / fwd_avg_s / 1e9, 2),
+        "solve_algorithmic_bytes": solve_bytes,
+        "solve_GBps": round(solve_bytes / (ms_step * 1e-3) / 1e9, 2),
         "roofline": roofline,
     }
     L.bmpc_lqr_plan_destroy(plan)
@@ -281,8 +339,10 @@ def cpu_baseline_bmpc(insts, budget_s=10.0):
     instance per process), for about budget_s seconds."""
     global _BATCH_CACHE
     import multiprocessing as mp
+    import oracle
+    oracle.use_native_build()
     _BATCH_CACHE = insts
-    cores = min(16, os.cpu_count() or 1)
+    cores = baseline_cores()
     ctx = mp.get_context("fork")
     done = 0
     conv = 0
@@ -297,6 +357,7 @@ def cpu_baseline_bmpc(insts, budget_s=10.0):
                 conv += stt == 0
     el = time.perf_counter() - t0
     return {"value": conv / el, "unit": "BMPC solves/s (KKT <= 1e-6)", "cores": cores, "kind": "oracle",
+            "build": "gcc -O3 -march=native", "host": host_info(),
             "sample": f"{done} cold oracle solves of the first {done} batched instances "
                       f"({conv} converged) in {el:.1f} s, one instance per process on {cores} cores"}
 

@@ -205,10 +205,26 @@ typedef struct {
 /* Result of one solve.  r_kkt: last KKT residual of the relaxed problem
    (infinity norm of the Lagrangian gradient and of the defects); viol:
    constraint violation max |max(g, -y/rho)|; start: 1 if the solve began
-   from the caller's start point, 0 if from the cold start. */
+   from the caller's start point, 0 if from the cold start.  time_ms: device
+   time of the solve's phases, summed over its inner iterations, read from
+   the constant-rate device clock by the solving team's first thread:
+   [BMPC_PHASE_LINEARISE] linearisation, quadratisation and KKT residual,
+   [BMPC_PHASE_BACKWARD] backward Riccati, [BMPC_PHASE_FORWARD] forward
+   rollout, [BMPC_PHASE_LINESEARCH] merit slope and line search,
+   [BMPC_PHASE_UPDATE] step update and the outer (BCL) update.  The start
+   point (rollout, adjoint sweep) is not included. */
+enum {
+    BMPC_PHASE_LINEARISE = 0,
+    BMPC_PHASE_BACKWARD = 1,
+    BMPC_PHASE_FORWARD = 2,
+    BMPC_PHASE_LINESEARCH = 3,
+    BMPC_PHASE_UPDATE = 4,
+    BMPC_NUM_PHASES = 5
+};
 typedef struct {
     int32_t status, outer_it, inner_it, ls_failures, bad_node, start;
     double r_kkt, viol, rho, mu, merit;
+    double time_ms[BMPC_NUM_PHASES];
 } bmpc_stats;
 
 typedef struct bmpc_problem bmpc_problem;
@@ -338,6 +354,16 @@ BMPC_API int64_t bmpc_batch_total_nodes(const bmpc_batch* batch);
    The result is the shifted warm start for bmpc_batch_launch(warm = 7).
    The problems' x0 and references are updated.  Asynchronous. */
 BMPC_API bmpc_status bmpc_batch_shift(bmpc_batch* batch, void* stream);
+/* Shifted warm start of one problem (receding horizon, as bmpc_batch_shift)
+   from its previous solution: x (N x 4), u (N x 2), lam (N x 4), ye (N x 5)
+   DEVICE arrays, node-major, hold the previous solution on entry and the
+   shifted start point on return, for bmpc_solve(warm = 7).  x0_new (host,
+   4 entries, nullable): the newly measured state, which becomes the root
+   state and the problem's x0; NULL = the predicted F(x0, u_0).  The
+   problem's references are shifted with the tree.  Asynchronous.
+   Non-finite x0_new -> BMPC_ERR_NONFINITE. */
+BMPC_API bmpc_status bmpc_warm_shift(bmpc_problem* problem, double* x, double* u, double* lam, double* ye,
+                                     const double* x0_new, void* stream);
 /* Start points of problems 0 .. rows-1 from warm-start network outputs.
    Y: DEVICE, rows x width FP32, row-major; row i belongs to problem i:
    first u of every control node in node order (2 each), then the PHR
@@ -413,18 +439,38 @@ BMPC_API bmpc_status bmpc_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint1
  * ---------------------------------------------------------------------- */
 /* Autotuner: time every compiled (backward variant, threads per problem)
    pair on this batch (reps solves each, with settings s and warm bits warm,
-   each from the batch's current state) and keep the fastest for launches
-   with riccati_variant = BMPC_RICCATI_AUTO and block_size = 0.  The batch
-   state is restored afterwards; its stats and history are those of the last
-   run.  variant_out, block_out (host, nullable) receive the choice and
-   ms_out (host, nullable, bmpc_batch_tune_candidates() entries) the mean
-   time of each candidate.  Synchronous.  Different choices sum the merit and
-   KKT reductions in different orders, so iterates can differ by rounding. */
+   each from the batch's current state) and keep the one with the shortest
+   time per inner iteration (launch time divided by the inner iterations
+   summed over the batch) for launches with riccati_variant =
+   BMPC_RICCATI_AUTO and block_size = 0.  The batch state is restored
+   afterwards; its stats and history are those of the last run.
+   variant_out, block_out (host, nullable) receive the choice and ms_out
+   (host, nullable, bmpc_batch_tune_candidates() entries) each candidate's
+   time per inner iteration in ms.  Synchronous.  Different choices sum the
+   merit and KKT reductions in different orders, so iterates can differ by
+   rounding; the per-iteration time keeps such differences in iteration
+   counts out of the choice. */
 BMPC_API bmpc_status bmpc_batch_tune(bmpc_batch* batch, const bmpc_settings* s, int32_t warm, int32_t reps,
                                      int32_t* variant_out, int32_t* block_out, double* ms_out, void* stream);
 /* Number of tuning candidates; fills up to cap of their (variant, block)
    pairs in tuning order (host arrays, nullable). */
 BMPC_API int32_t bmpc_batch_tune_candidates(int32_t* variants, int32_t* blocks, int32_t cap);
+/* Autotuner with a time budget and a cache keyed by the batch's shape
+   (problem count, warm bits, and each problem's node, depth, leaf and
+   segment counts).  cache_path (host string, nullable): a text file of
+   lines "bmpc-autotune <key> <variant> <block> <ms per inner iteration>";
+   if it holds the batch's key, that choice is kept without any timing run
+   (*from_cache = 1).  Otherwise every candidate is timed once, then in
+   further rounds while budget_ms of host time have not passed (at most 100
+   runs each), the one with the shortest time per inner iteration is kept
+   (as bmpc_batch_tune) and a line is appended to the cache.  variant_out,
+   block_out, ms_per_iter_out, from_cache: host, nullable.  Synchronous;
+   the batch state is restored.  A cache that cannot be appended to ->
+   BMPC_ERR_INVALID_ARG (the choice is still kept). */
+BMPC_API bmpc_status bmpc_batch_autotune(bmpc_batch* batch, const bmpc_settings* s, int32_t warm,
+                                         int32_t budget_ms, const char* cache_path, int32_t* variant_out,
+                                         int32_t* block_out, double* ms_per_iter_out, int32_t* from_cache,
+                                         void* stream);
 
 /* Graph capture of asynchronous library calls on a created (non-default)
    stream: bmpc_graph_begin(stream), then any of bmpc_batch_launch,

@@ -39,6 +39,24 @@ def build(force: bool = True) -> str:
     return LIB_PATH
 
 
+def use_native_build(out_dir=None) -> str:
+    """Compile a copy of the oracle with -O3 -march=native for this host and
+    load it instead of the portable build (the CPU-baseline timings use it;
+    the arithmetic is the same C code)."""
+    global _lib
+    out_dir = out_dir or os.path.join(os.path.dirname(_HERE), "_build")
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, "liboracle_native.so")
+    srcs = [os.path.join(_HERE, s) for s in SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    tmp = path + ".tmp"
+    subprocess.run(["gcc", "-O3", "-march=native", "-std=c11", "-fPIC", "-shared", "-o", tmp] + srcs
+                   + ["-lm", "-lpthread"], check=True)
+    os.replace(tmp, path)
+    _lib = C.CDLL(path)
+    _declare(_lib)
+    return path
+
+
 _lib = None
 
 
@@ -90,6 +108,8 @@ class Stats(C.Structure):
 def _declare(L):
     L.orc_tree_lqr.restype = C.c_int
     L.orc_tree_lqr.argtypes = [C.c_int, C.c_int, C.c_int, _ip] + [_dp] * 9 + [_dp] * 7 + [_ip]
+    L.orc_tree_lqr_ld.restype = C.c_int
+    L.orc_tree_lqr_ld.argtypes = [C.c_int, C.c_int, C.c_int, _ip] + [_dp] * 9 + [_dp] * 7 + [_ip]
     L.orc_settings_default.argtypes = [C.POINTER(Settings)]
     L.orc_bmpc_solve.restype = C.c_int
     L.orc_bmpc_solve.argtypes = [C.POINTER(Problem), C.POINTER(Settings), C.c_int, _dp, _dp,
@@ -112,7 +132,7 @@ def _declare(L):
     L.orc_kkt.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, C.c_double]
     L.orc_adjoint.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_double, _dp]
     L.orc_rollout.argtypes = [C.POINTER(Problem), _dp, _dp]
-    L.orc_shift.argtypes = [C.POINTER(Problem)] + [_dp] * 10
+    L.orc_shift.argtypes = [C.POINTER(Problem)] + [_dp] * 11
     if hasattr(L, "orc_mlp_forward"):
         _declare_mlp(L)
 
@@ -146,9 +166,10 @@ def _f64(a, shape=None):
 # tree LQR
 # ----------------------------------------------------------------------------
 
-def tree_lqr(parent, A, B, c, Q, R, M, q, r, x0):
+def tree_lqr(parent, A, B, c, Q, R, M, q, r, x0, extended=False):
     """Serial tree Riccati (node-major arrays).  Returns a dict with x, u, lam,
-    K, k, P, p; raises on a non-OK status."""
+    K, k, P, p; raises on a non-OK status.  extended=True carries the
+    recursion out in long double (results rounded to double)."""
     parent = np.ascontiguousarray(parent, dtype=np.int32)
     N = len(parent)
     nx = np.shape(A)[1]
@@ -158,7 +179,8 @@ def tree_lqr(parent, A, B, c, Q, R, M, q, r, x0):
            "K": np.zeros((N, nu, nx)), "k": np.zeros((N, nu)), "P": np.zeros((N, nx, nx)),
            "p": np.zeros((N, nx))}
     bad = np.array([-1], dtype=np.int32)
-    st = lib().orc_tree_lqr(N, nx, nu, _i(parent), _d(A), _d(B), _d(c), _d(Q), _d(R), _d(M),
+    fn = lib().orc_tree_lqr_ld if extended else lib().orc_tree_lqr
+    st = fn(N, nx, nu, _i(parent), _d(A), _d(B), _d(c), _d(Q), _d(R), _d(M),
                             _d(q), _d(r), _d(x0), _d(out["x"]), _d(out["u"]), _d(out["lam"]),
                             _d(out["K"]), _d(out["k"]), _d(out["P"]), _d(out["p"]), _i(bad))
     if st != 0:
@@ -166,9 +188,9 @@ def tree_lqr(parent, A, B, c, Q, R, M, q, r, x0):
     return out
 
 
-def tree_lqr_inst(inst):
+def tree_lqr_inst(inst, extended=False):
     return tree_lqr(inst.parent, inst.A, inst.B, inst.c, inst.Q, inst.R, inst.M, inst.q,
-                    inst.r, inst.x0)
+                    inst.r, inst.x0, extended=extended)
 
 
 class OracleError(RuntimeError):
@@ -371,8 +393,9 @@ def rollout(pb, u):
     return x
 
 
-def shift(pb: BmpcProblem, state):
-    """Shifted warm start after one simulated step.  Returns (new problem,
+def shift(pb: BmpcProblem, state, x0_meas=None):
+    """Shifted warm start after one simulated step (x0_meas: the measured
+    next state, default the model's prediction).  Returns (new problem,
     shifted state dict)."""
     N = pb.N
     ref = np.zeros((N, 4))
@@ -380,7 +403,9 @@ def shift(pb: BmpcProblem, state):
     out = {"x": np.zeros((N, 4)), "u": np.zeros((N, 2)), "lam": np.zeros((N, 4)),
            "ye": np.zeros((N, 5))}
     st = {k: _f64(state[k]) for k in ("x", "u", "lam", "ye")}
-    lib().orc_shift(pb.ptr, _d(st["x"]), _d(st["u"]), _d(st["lam"]), _d(st["ye"]), _d(ref), _d(x0),
+    xa = None if x0_meas is None else _f64(x0_meas)
+    xm = None if xa is None else _d(xa)
+    lib().orc_shift(pb.ptr, _d(st["x"]), _d(st["u"]), _d(st["lam"]), _d(st["ye"]), xm, _d(ref), _d(x0),
                     _d(out["x"]), _d(out["u"]), _d(out["lam"]), _d(out["ye"]))
     new = BmpcProblem(pb.parent, pb.weight, ref, pb.obs, pb.has_obs, x0, pb.model)
     return new, out

@@ -37,6 +37,14 @@ int orc_tree_lqr(int N, int nx, int nu, const int* parent,
                  const double* q, const double* r, const double* x0,
                  double* x, double* u, double* lam,
                  double* K, double* k, double* P, double* p, int* bad_node);
+/* The same recursion carried out in long double (x87 extended precision);
+ * inputs and outputs are double.  Reference for badly conditioned problems. */
+int orc_tree_lqr_ld(int N, int nx, int nu, const int* parent,
+                    const double* A, const double* B, const double* c,
+                    const double* Q, const double* R, const double* M,
+                    const double* q, const double* r, const double* x0,
+                    double* x, double* u, double* lam,
+                    double* K, double* k, double* P, double* p, int* bad_node);
 
 /* ---- branch-MPC problem and AL multiple-shooting iLQR, oracle_bmpc.c ---- */
 #define ORC_NX 4
@@ -119,8 +127,8 @@ void orc_adjoint(const orc_problem* pb, const double* x, const double* u,
                  const double* ye, double rho, double* lam);
 void orc_rollout(const orc_problem* pb, const double* u, double* x);
 void orc_shift(const orc_problem* pb, const double* x, const double* u, const double* lam,
-               const double* ye, double* ref_new, double* x0_new, double* xs, double* us,
-               double* lams, double* yes);
+               const double* ye, const double* x0_meas, double* ref_new, double* x0_new, double* xs,
+               double* us, double* lams, double* yes);
 
 /* ---- warm-start network, oracle_mlp.c ---------------------------------- */
 double orc_bf16(double x);

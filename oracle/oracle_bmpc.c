@@ -780,12 +780,16 @@ done:
  * the new parent state and input.
  * ---------------------------------------------------------------------- */
 void orc_shift(const orc_problem* pb, const double* x, const double* u, const double* lam,
-               const double* ye, double* ref_new, double* x0_new, double* xs, double* us,
-               double* lams, double* yes)
+               const double* ye, const double* x0_meas, double* ref_new, double* x0_new, double* xs,
+               double* us, double* lams, double* yes)
 {
     const int N = pb->N;
     int* nch = child_counts(pb);
-    orc_rk4(&pb->model, pb->x0, u, x0_new, NULL, NULL);
+    /* the next initial state: measured, else predicted by the model */
+    if (x0_meas)
+        memcpy(x0_new, x0_meas, sizeof(double) * NX);
+    else
+        orc_rk4(&pb->model, pb->x0, u, x0_new, NULL, NULL);
     for (int n = 0; n < N; ++n) {
         if (nch[n] == 0) continue;
         double w = 0.0, wu = 0.0;

@@ -31,38 +31,34 @@
 
 #include "oracle.h"
 
-/* Cholesky H = L L^T in place (lower triangle).  Returns 0 on failure. */
-static int chol(int n, double* H)
-{
-    for (int j = 0; j < n; ++j) {
-        double d = H[j * n + j];
-        for (int k = 0; k < j; ++k) d -= H[j * n + k] * H[j * n + k];
-        if (!(d > 0.0) || !isfinite(d)) return 0;
-        d = sqrt(d);
-        H[j * n + j] = d;
-        for (int i = j + 1; i < n; ++i) {
-            double s = H[i * n + j];
-            for (int k = 0; k < j; ++k) s -= H[i * n + k] * H[j * n + k];
-            H[i * n + j] = s / d;
-        }
-    }
-    return 1;
-}
+/* the recursion in double ... */
+#define REAL double
+#define SQRT sqrt
+#define CHOL chol_d
+#define CHOL_SOLVE chol_solve_d
+#define LQR tree_lqr_d
+#include "oracle_lqr_impl.h"
+#undef REAL
+#undef SQRT
+#undef CHOL
+#undef CHOL_SOLVE
+#undef LQR
 
-/* Solve (L L^T) z = y in place for one right-hand side. */
-static void chol_solve(int n, const double* L, double* y)
-{
-    for (int i = 0; i < n; ++i) {
-        double s = y[i];
-        for (int k = 0; k < i; ++k) s -= L[i * n + k] * y[k];
-        y[i] = s / L[i * n + i];
-    }
-    for (int i = n - 1; i >= 0; --i) {
-        double s = y[i];
-        for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * y[k];
-        y[i] = s / L[i * n + i];
-    }
-}
+/* ... and in long double (x87 extended precision, 64-bit significand), for
+ * reference solutions of badly conditioned problems: the distance between
+ * the double recursion and this one measures the rounding floor of double
+ * arithmetic on a given problem */
+#define REAL long double
+#define SQRT sqrtl
+#define CHOL chol_ld
+#define CHOL_SOLVE chol_solve_ld
+#define LQR tree_lqr_ld
+#include "oracle_lqr_impl.h"
+#undef REAL
+#undef SQRT
+#undef CHOL
+#undef CHOL_SOLVE
+#undef LQR
 
 int orc_tree_lqr(int N, int nx, int nu, const int* parent,
                  const double* A, const double* B, const double* c,
@@ -71,171 +67,49 @@ int orc_tree_lqr(int N, int nx, int nu, const int* parent,
                  double* x, double* u, double* lam,
                  double* K, double* k, double* P, double* p, int* bad_node)
 {
-    if (N <= 0 || nx <= 0 || nu <= 0 || !parent) return ORC_ERR_INVALID_ARG;
-    if (parent[0] != -1) return ORC_ERR_TOPOLOGY;
-    for (int i = 1; i < N; ++i)
-        if (parent[i] < 0 || parent[i] >= i) return ORC_ERR_TOPOLOGY;
+    return tree_lqr_d(N, nx, nu, parent, A, B, c, Q, R, M, q, r, x0, x, u, lam, K, k, P, p, bad_node);
+}
 
-    const int nn = nx * nx, nm = nx * nu, mm = nu * nu;
-    /* children lists (CSR) in increasing node order */
-    int* cnt = calloc((size_t)N + 1, sizeof(int));
-    int* kids = malloc(sizeof(int) * (size_t)(N > 1 ? N - 1 : 1));
-    int* fill = calloc((size_t)N, sizeof(int));
-    double* H = malloc(sizeof(double) * mm);
-    double* G = malloc(sizeof(double) * nm);
-    double* g = malloc(sizeof(double) * nu);
-    double* W = malloc(sizeof(double) * nn);
-    double* w = malloc(sizeof(double) * nx);
-    double* s = malloc(sizeof(double) * nx);
-    double* PA = malloc(sizeof(double) * nn);
-    double* PB = malloc(sizeof(double) * nm);
-    double* col = malloc(sizeof(double) * nu);
-    int status = ORC_OK;
+static long double* widen(const double* a, size_t n)
+{
+    long double* w = malloc(sizeof(long double) * (n ? n : 1));
+    for (size_t i = 0; i < n; ++i) w[i] = a[i];
+    return w;
+}
 
-    for (int i = 1; i < N; ++i) cnt[parent[i] + 1]++;
-    for (int i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
-    for (int i = 1; i < N; ++i) kids[cnt[parent[i]] + fill[parent[i]]++] = i;
+static void narrow(const long double* a, double* out, size_t n)
+{
+    for (size_t i = 0; i < n; ++i) out[i] = (double)a[i];
+}
 
-    /* backward: every child has a larger index than its parent */
-    for (int n = N - 1; n >= 0 && status == ORC_OK; --n) {
-        double* Pn = P + (size_t)n * nn;
-        double* pn = p + (size_t)n * nx;
-        double* Kn = K + (size_t)n * nm;
-        double* kn = k + (size_t)n * nu;
-        if (cnt[n + 1] == cnt[n]) {             /* leaf */
-            memcpy(Pn, Q + (size_t)n * nn, sizeof(double) * nn);
-            memcpy(pn, q + (size_t)n * nx, sizeof(double) * nx);
-            memset(Kn, 0, sizeof(double) * nm);
-            memset(kn, 0, sizeof(double) * nu);
-            continue;
-        }
-        memcpy(H, R + (size_t)n * mm, sizeof(double) * mm);
-        memcpy(G, M + (size_t)n * nm, sizeof(double) * nm);
-        memcpy(g, r + (size_t)n * nu, sizeof(double) * nu);
-        memcpy(W, Q + (size_t)n * nn, sizeof(double) * nn);
-        memcpy(w, q + (size_t)n * nx, sizeof(double) * nx);
-        for (int e = cnt[n]; e < cnt[n + 1]; ++e) {
-            const int j = kids[e];
-            const double* Pj = P + (size_t)j * nn;
-            const double* pj = p + (size_t)j * nx;
-            const double* Aj = A + (size_t)j * nn;
-            const double* Bj = B + (size_t)j * nm;
-            const double* cj = c + (size_t)j * nx;
-            for (int a = 0; a < nx; ++a) {
-                double acc = pj[a];
-                for (int b = 0; b < nx; ++b) acc += Pj[a * nx + b] * cj[b];
-                s[a] = acc;
-                for (int b = 0; b < nx; ++b) {
-                    double t = 0.0;
-                    for (int l = 0; l < nx; ++l) t += Pj[a * nx + l] * Aj[l * nx + b];
-                    PA[a * nx + b] = t;
-                }
-                for (int b = 0; b < nu; ++b) {
-                    double t = 0.0;
-                    for (int l = 0; l < nx; ++l) t += Pj[a * nx + l] * Bj[l * nu + b];
-                    PB[a * nu + b] = t;
-                }
-            }
-            for (int a = 0; a < nu; ++a) {
-                for (int b = 0; b < nu; ++b) {
-                    double t = 0.0;
-                    for (int l = 0; l < nx; ++l) t += Bj[l * nu + a] * PB[l * nu + b];
-                    H[a * nu + b] += t;
-                }
-                for (int b = 0; b < nx; ++b) {
-                    double t = 0.0;
-                    for (int l = 0; l < nx; ++l) t += Bj[l * nu + a] * PA[l * nx + b];
-                    G[a * nx + b] += t;
-                }
-                double t = 0.0;
-                for (int l = 0; l < nx; ++l) t += Bj[l * nu + a] * s[l];
-                g[a] += t;
-            }
-            for (int a = 0; a < nx; ++a) {
-                for (int b = 0; b < nx; ++b) {
-                    double t = 0.0;
-                    for (int l = 0; l < nx; ++l) t += Aj[l * nx + a] * PA[l * nx + b];
-                    W[a * nx + b] += t;
-                }
-                double t = 0.0;
-                for (int l = 0; l < nx; ++l) t += Aj[l * nx + a] * s[l];
-                w[a] += t;
-            }
-        }
-        if (!chol(nu, H)) {
-            status = ORC_ERR_NOT_PD;
-            if (bad_node) *bad_node = n;
-            break;
-        }
-        /* K = -H^{-1} G column by column, k = -H^{-1} g */
-        for (int b = 0; b < nx; ++b) {
-            for (int a = 0; a < nu; ++a) col[a] = G[a * nx + b];
-            chol_solve(nu, H, col);
-            for (int a = 0; a < nu; ++a) Kn[a * nx + b] = -col[a];
-        }
-        for (int a = 0; a < nu; ++a) col[a] = g[a];
-        chol_solve(nu, H, col);
-        for (int a = 0; a < nu; ++a) kn[a] = -col[a];
-        for (int a = 0; a < nx; ++a) {
-            for (int b = 0; b < nx; ++b) {
-                double t = W[a * nx + b];
-                for (int l = 0; l < nu; ++l) t += G[l * nx + a] * Kn[l * nx + b];
-                Pn[a * nx + b] = t;
-            }
-            double t = w[a];
-            for (int l = 0; l < nu; ++l) t += G[l * nx + a] * kn[l];
-            pn[a] = t;
-        }
-        for (int a = 0; a < nx; ++a)
-            for (int b = a + 1; b < nx; ++b) {
-                double m = 0.5 * (Pn[a * nx + b] + Pn[b * nx + a]);
-                Pn[a * nx + b] = m;
-                Pn[b * nx + a] = m;
-            }
+int orc_tree_lqr_ld(int N, int nx, int nu, const int* parent,
+                    const double* A, const double* B, const double* c,
+                    const double* Q, const double* R, const double* M,
+                    const double* q, const double* r, const double* x0,
+                    double* x, double* u, double* lam,
+                    double* K, double* k, double* P, double* p, int* bad_node)
+{
+    if (N <= 0 || nx <= 0 || nu <= 0) return ORC_ERR_INVALID_ARG;
+    const size_t n = (size_t)N, nn = n * nx * nx, nm = n * nx * nu, mm = n * nu * nu;
+    long double *wA = widen(A, nn), *wB = widen(B, nm), *wc = widen(c, n * nx), *wQ = widen(Q, nn),
+                *wR = widen(R, mm), *wM = widen(M, nm), *wq = widen(q, n * nx), *wr = widen(r, n * nu),
+                *wx0 = widen(x0, (size_t)nx);
+    long double *ox = malloc(sizeof(long double) * n * nx), *ou = malloc(sizeof(long double) * n * nu),
+                *ol = malloc(sizeof(long double) * n * nx), *oK = malloc(sizeof(long double) * nm),
+                *ok = malloc(sizeof(long double) * n * nu), *oP = malloc(sizeof(long double) * nn),
+                *op = malloc(sizeof(long double) * n * nx);
+    const int st = tree_lqr_ld(N, nx, nu, parent, wA, wB, wc, wQ, wR, wM, wq, wr, wx0, ox, ou, ol, oK, ok,
+                               oP, op, bad_node);
+    if (st == ORC_OK) {
+        narrow(ox, x, n * nx);
+        narrow(ou, u, n * nu);
+        narrow(ol, lam, n * nx);
+        narrow(oK, K, nm);
+        narrow(ok, k, n * nu);
+        narrow(oP, P, nn);
+        narrow(op, p, n * nx);
     }
-
-    if (status == ORC_OK) {
-        /* forward rollout in increasing node order */
-        memcpy(x, x0, sizeof(double) * nx);
-        for (int n = 0; n < N; ++n) {
-            const double* xn = x + (size_t)n * nx;
-            double* un = u + (size_t)n * nu;
-            const double* Pn = P + (size_t)n * nn;
-            const double* pn = p + (size_t)n * nx;
-            double* ln = lam + (size_t)n * nx;
-            for (int a = 0; a < nx; ++a) {
-                double t = pn[a];
-                for (int b = 0; b < nx; ++b) t += Pn[a * nx + b] * xn[b];
-                ln[a] = t;
-            }
-            if (cnt[n + 1] == cnt[n]) {
-                memset(un, 0, sizeof(double) * nu);
-                continue;
-            }
-            const double* Kn = K + (size_t)n * nm;
-            const double* kn = k + (size_t)n * nu;
-            for (int a = 0; a < nu; ++a) {
-                double t = kn[a];
-                for (int b = 0; b < nx; ++b) t += Kn[a * nx + b] * xn[b];
-                un[a] = t;
-            }
-            for (int e = cnt[n]; e < cnt[n + 1]; ++e) {
-                const int j = kids[e];
-                const double* Aj = A + (size_t)j * nn;
-                const double* Bj = B + (size_t)j * nm;
-                const double* cj = c + (size_t)j * nx;
-                double* xj = x + (size_t)j * nx;
-                for (int a = 0; a < nx; ++a) {
-                    double t = cj[a];
-                    for (int b = 0; b < nx; ++b) t += Aj[a * nx + b] * xn[b];
-                    for (int b = 0; b < nu; ++b) t += Bj[a * nu + b] * un[b];
-                    xj[a] = t;
-                }
-            }
-        }
-    }
-
-    free(cnt); free(kids); free(fill); free(H); free(G); free(g); free(W); free(w);
-    free(s); free(PA); free(PB); free(col);
-    return status;
+    free(wA); free(wB); free(wc); free(wQ); free(wR); free(wM); free(wq); free(wr); free(wx0);
+    free(ox); free(ou); free(ol); free(oK); free(ok); free(oP); free(op);
+    return st;
 }

@@ -264,10 +264,15 @@ class bmpc_stats(C.Structure):
     _fields_ = [("status", C.c_int32), ("outer_it", C.c_int32), ("inner_it", C.c_int32),
                 ("ls_failures", C.c_int32), ("bad_node", C.c_int32), ("start", C.c_int32), ("r_kkt", C.c_double),
                 ("viol", C.c_double), ("rho", C.c_double), ("mu", C.c_double),
-                ("merit", C.c_double)]
+                ("merit", C.c_double), ("time_ms", C.c_double * 5)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["time_ms"] = dict(zip(PHASES, list(self.time_ms)))
+        return d
+
+
+PHASES = ("linearise", "backward", "forward", "line_search", "update")
 
 
 _sig("bmpc_settings_default", None, [C.POINTER(bmpc_settings)])
@@ -459,6 +464,23 @@ def bmpc_batch_start_from_network(batch, Y, rows, width, stream=None):
                                             stream_ptr(stream)))
 
 
+_sig("bmpc_warm_shift", _i32, [_vp, _vp, _vp, _vp, _vp, _pd, _vp])
+
+
+def bmpc_warm_shift(problem, x, u, lam, ye, x0_new=None, stream=None):
+    """x, u, lam, ye: device tensors, the previous solution in, the shifted
+    start point out; x0_new: host array of 4 (measured state) or None."""
+    N = _dims[_key(problem)]
+    ptrs = _state_ptrs(N, x, u, lam, ye)
+    if x0_new is not None:
+        xa, xp = _hf64(x0_new)
+        if xa.size != 4:
+            raise ValueError("x0_new: 4 entries expected")
+    else:
+        xp = None
+    check(lib.bmpc_warm_shift(problem, *ptrs, xp, stream_ptr(stream)))
+
+
 def bmpc_batch_shift(batch, stream=None):
     check(lib.bmpc_batch_shift(batch, stream_ptr(stream)))
 
@@ -577,8 +599,21 @@ def bmpc_batch_tune_candidates():
     return list(zip(v.tolist(), b.tolist()))
 
 
+_sig("bmpc_batch_autotune", _i32, [_vp, _vp, _i32, _i32, C.c_char_p, _pi32, _pi32, _pd, _pi32, _vp])
+
+
+def bmpc_batch_autotune(batch, settings, warm=0, budget_ms=0, cache_path=None, stream=None):
+    """Returns (variant, block_size, ms per inner iteration, from_cache)."""
+    v, b, fc = C.c_int32(), C.c_int32(), C.c_int32()
+    t = C.c_double()
+    check(lib.bmpc_batch_autotune(batch, C.byref(settings), warm, int(budget_ms),
+                                  cache_path.encode() if cache_path else None, C.byref(v), C.byref(b),
+                                  C.byref(t), C.byref(fc), stream_ptr(stream)))
+    return v.value, b.value, t.value, bool(fc.value)
+
+
 def bmpc_batch_tune(batch, settings, warm=0, reps=1, stream=None):
-    """Returns (variant, block_size, {(variant, block): mean ms})."""
+    """Returns (variant, block_size, {(variant, block): ms per inner iteration})."""
     cands = bmpc_batch_tune_candidates()
     v, b = C.c_int32(), C.c_int32()
     ms = np.zeros(len(cands))

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <climits>
@@ -94,9 +96,28 @@ struct SolverCfg {
     int warm;  // bits: 1 x,u given, 2 lam given, 4 ye given, 8 u given (x rolled out), 16 guarded
 };
 
+// Phases of an inner iteration whose time the solver accumulates
+enum Phase : int { PH_LINEARISE = 0, PH_BACKWARD, PH_FORWARD, PH_LINESEARCH, PH_UPDATE, PH_COUNT };
+
 struct SolveOut {
     int status, outer_it, inner_it, ls_failures, bad_node, start;
     double r_kkt, viol, rho, mu, merit;
+    unsigned long long ticks[PH_COUNT];  // constant-rate clock ticks per phase, summed over the solve
+};
+
+// Phase clock: the constant-rate device counter, read by the team's first
+// thread only (the others get 0, so their sums are unused and cheap).
+struct PhaseClock {
+    unsigned long long t = 0, acc[PH_COUNT] = {};
+    __device__ void start(bool on) { if (on) t = wall_clock64(); }
+    __device__ void lap(bool on, int ph)
+    {
+        if (on) {
+            const unsigned long long now = wall_clock64();
+            acc[ph] += now - t;
+            t = now;
+        }
+    }
 };
 
 __device__ __forceinline__ void load4(const double* p, double (&v)[4])
@@ -1329,9 +1350,12 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
         build_start<T>(I, cfg.warm, rho);
     }
 
+    PhaseClock clk;
+    const bool timer = tid == 0;
     for (outer = 0; outer < cfg.max_outer; ++outer) {
         for (int inner = 0;; ++inner) {
             double La_p, vi_p, rk_p, ld_p, dd_p;
+            clk.start(timer);
             pass_linearise<T>(I, rho, La_p, vi_p);
             T::sync();
             pass_defects_kkt<T>(I, rk_p, ld_p, dd_p);
@@ -1339,6 +1363,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             T::template reduce<2, true>(mx, sred, gpart);
             r_kkt = mx[0];
             viol = mx[1];
+            clk.lap(timer, PH_LINEARISE);
             if (!(r_kkt == r_kkt)) {
                 status = BMPC_ERR_NONFINITE;
                 goto done;
@@ -1364,6 +1389,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                 status = BMPC_ERR_NOT_PD;
                 goto done;
             }
+            clk.lap(timer, PH_BACKWARD);
             if constexpr (!T::kGrid) {
                 if (fits) {
                     if (SEGSCAN) lds_from_ws<T::BS>(I, sn);
@@ -1374,6 +1400,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             } else {
                 pass_forward_seg<T>(I);
             }
+            clk.lap(timer, PH_FORWARD);
 
             // merit slope pieces and the current merit
             double sm[6] = {0.0, 0.0, 0.0, La_p, ld_p, dd_p};
@@ -1500,6 +1527,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             } else {
                 ls_run = 0;
             }
+            clk.lap(timer, PH_LINESEARCH);
             for (int n = tid; n < N; n += T::size()) {
                 const double* w = I.ws + (long)n * W_NODE;
 #pragma unroll
@@ -1523,7 +1551,9 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                 ++nhist;
             }
             T::sync();
+            clk.lap(timer, PH_UPDATE);
         }
+        clk.start(timer);
 
         // outer update (BCL)
         if (viol <= eta) {
@@ -1554,6 +1584,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
             omega = cfg.omega0 / pow(rho, cfg.a_omega);
             eta = cfg.eta0 / pow(rho, cfg.a_eta);
         }
+        clk.lap(timer, PH_UPDATE);
         // Alg. 1 floors omega at eps_tol; eta gets the same floor, since the
         // stopping test asks only viol < eps_tol
         omega = fmax(omega, cfg.eps_tol);
@@ -1576,6 +1607,8 @@ done:
         o.rho = rho;
         o.mu = mu;
         o.merit = merit;
+#pragma unroll
+        for (int k = 0; k < PH_COUNT; ++k) o.ticks[k] = clk.acc[k];
         outs[idx] = o;
     }
     T::sync();
@@ -1635,14 +1668,21 @@ __global__ void __launch_bounds__(BS) k_bmpc_linearise(InstDesc I, double rho, d
     }
 }
 
-// Shifted warm start after one simulated step: x0' = F(x0, u_0); every
+// A measured initial state passed by value (use = 0: none).
+struct MeasuredX0 {
+    double v[4];
+    int use;
+};
+
+// Shifted warm start after one simulated step: x0' = F(x0, u_0) (or the
+// measured state when one is given); every
 // non-leaf node takes the weight-averaged values of its children (the old
 // nodes one stage later on the same scenarios), a node whose children are
 // leaves repeats its own input, leaves keep costates and multipliers,
 // extrapolate their reference and are rolled out from the new parent.
 // The workspace rows serve as scratch for the new values.
 template <int BS>
-__global__ void __launch_bounds__(BS) k_bmpc_shift(const InstDesc* __restrict__ insts)
+__global__ void __launch_bounds__(BS) k_bmpc_shift(const InstDesc* __restrict__ insts, MeasuredX0 meas)
 {
     const InstDesc I = insts[blockIdx.x];
     const int N = I.N, tid = threadIdx.x;
@@ -1702,7 +1742,7 @@ __global__ void __launch_bounds__(BS) k_bmpc_shift(const InstDesc* __restrict__ 
         double xr[BX], ur[BU] = {I.u[0], I.u[1]}, xn[BX];
         load4(I.x0, xr);
         bike_step(I.prm, xr, ur, xn);
-        for (int a = 0; a < 4; ++a) I.ws[T_X + a] = xn[a];
+        for (int a = 0; a < 4; ++a) I.ws[T_X + a] = meas.use ? meas.v[a] : xn[a];
     }
     __syncthreads();
     // leaves are rolled out from their (already shifted) parents
@@ -2280,68 +2320,214 @@ BMPC_API bmpc_status bmpc_batch_launch(bmpc_batch* b, const bmpc_settings* s, in
     return launch_solver(b, *k, cfg, st);
 }
 
-BMPC_API bmpc_status bmpc_batch_tune(bmpc_batch* b, const bmpc_settings* s, int32_t warm, int32_t reps,
-                                     int32_t* variant_out, int32_t* block_out, double* ms_out, void* stream)
+}  // extern "C"
+
+// The tuning criterion: launch time divided by the inner iterations summed
+// over the batch.  Candidates sum reductions in different orders, so their
+// iterates can part by rounding and take different iteration counts (a
+// problem that does not converge can run far longer on one candidate than on
+// another); the time per iteration compares the kernels' speed, not those
+// paths.
+struct TuneRig {
+    bmpc_batch* b;
+    SolverCfg cfg;
+    hipStream_t st;
+    double* saved = nullptr;
+    size_t bytes = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<SolveOut> outs;
+
+    bmpc_status open()
+    {
+        bytes = sizeof(double) * (size_t)b->total_nodes * 15;
+        if (hipMalloc(&saved, bytes) != hipSuccess) return fail(BMPC_ERR_OOM, "no memory to save the batch state");
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+            hipMemcpyAsync(saved, b->d_state, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return fail(BMPC_ERR_HIP, "setting up the tuning runs failed");
+        outs.resize(b->count);
+        return BMPC_OK;
+    }
+    // one solve of the batch with kernel k from the saved state
+    bmpc_status run(const WgKernel& k, double* ms, double* iters)
+    {
+        float t = 0.f;
+        if (hipMemcpyAsync(b->d_state, saved, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipEventRecord(e0, st) != hipSuccess)
+            return fail(BMPC_ERR_HIP, "tuning run failed");
+        if (launch_solver(b, k, cfg, st) != BMPC_OK || hipEventRecord(e1, st) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess ||
+            hipMemcpy(outs.data(), b->d_out, sizeof(SolveOut) * b->count, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(BMPC_ERR_HIP, "tuning run of %s failed", k.name);
+        double it = 0.0;
+        for (const auto& o : outs) it += o.inner_it;
+        *ms = t;
+        *iters = std::max(it, 1.0);
+        return BMPC_OK;
+    }
+    bmpc_status close(bmpc_status rc)
+    {
+        if (saved && (hipMemcpyAsync(b->d_state, saved, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                      hipStreamSynchronize(st) != hipSuccess) && rc == BMPC_OK)
+            rc = fail(BMPC_ERR_HIP, "restoring the batch state failed");
+        (void)hipFree(saved);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return rc;
+    }
+};
+
+constexpr int NUM_WG_KERNELS = sizeof(kWgKernels) / sizeof(kWgKernels[0]);
+
+static void keep_choice(bmpc_batch* b, const WgKernel& k)
+{
+    b->tuned_variant = k.segscan ? BMPC_RICCATI_SEGSCAN : BMPC_RICCATI_LEVEL;
+    b->tuned_block = k.block;
+}
+
+static bmpc_status check_tune_args(const bmpc_batch* b, const bmpc_settings* s, int32_t warm)
 {
     if (!b || !s) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
-    if (reps < 1 || reps > 100) return fail(BMPC_ERR_INVALID_ARG, "reps must be in [1, 100]");
     if (warm < 0 || warm > 31) return fail(BMPC_ERR_INVALID_ARG, "warm bits %d outside [0, 31]", warm);
     if (s->n_alpha < 1 || s->n_alpha > NALPHA_MAX)
         return fail(BMPC_ERR_INVALID_ARG, "n_alpha must be in [1, %d]", NALPHA_MAX);
     if (s->ls_rounds < 1 || s->ls_rounds > LS_ROUNDS_MAX)
         return fail(BMPC_ERR_INVALID_ARG, "ls_rounds must be in [1, %d]", LS_ROUNDS_MAX);
-    hipStream_t st = (hipStream_t)stream;
-    const size_t bytes = sizeof(double) * (size_t)b->total_nodes * 15;
-    double* saved = nullptr;
-    if (hipMalloc(&saved, bytes) != hipSuccess) return fail(BMPC_ERR_OOM, "no memory to save the batch state");
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    bmpc_status rc = BMPC_OK;
-    const SolverCfg cfg = to_cfg(*s, warm);
+    return BMPC_OK;
+}
+
+// Key of a batch's shape for the tuning cache: FNV-1a over the problem
+// count, the warm bits and each problem's node count, depth, leaf count and
+// segment count, in batch order.
+static unsigned long long shape_key(const bmpc_batch* b, int warm)
+{
+    unsigned long long h = 1469598103934665603ull;
+    auto mix = [&](long long v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (unsigned long long)((v >> (8 * i)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    mix(b->count);
+    mix(warm);
+    for (const bmpc_problem* p : b->problems) {
+        mix(p->N);
+        mix(p->tree->h.depth);
+        mix((long long)p->tree->h.leaves.size());
+        mix((long long)p->tree->h.seg_start.size());
+    }
+    return h;
+}
+
+extern "C" {
+
+BMPC_API bmpc_status bmpc_batch_tune(bmpc_batch* b, const bmpc_settings* s, int32_t warm, int32_t reps,
+                                     int32_t* variant_out, int32_t* block_out, double* ms_out, void* stream)
+{
+    bmpc_status rc = check_tune_args(b, s, warm);
+    if (rc != BMPC_OK) return rc;
+    if (reps < 1 || reps > 100) return fail(BMPC_ERR_INVALID_ARG, "reps must be in [1, 100]");
+    TuneRig rig{b, to_cfg(*s, warm), (hipStream_t)stream};
     const WgKernel* best = nullptr;
-    double best_ms = INFINITY;
-    int idx = 0;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
-        hipMemcpyAsync(saved, b->d_state, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) {
-        rc = fail(BMPC_ERR_HIP, "setting up the tuning runs failed");
-        goto out;
-    }
-    for (const auto& k : kWgKernels) {
-        double tot = 0.0;
-        for (int r = 0; r < reps; ++r) {
-            float ms = 0.f;
-            if (hipMemcpyAsync(b->d_state, saved, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-                hipEventRecord(e0, st) != hipSuccess) {
-                rc = fail(BMPC_ERR_HIP, "tuning run failed");
-                goto out;
+    double best_t = INFINITY;
+    if ((rc = rig.open()) == BMPC_OK) {
+        for (int idx = 0; idx < NUM_WG_KERNELS && rc == BMPC_OK; ++idx) {
+            double ms_sum = 0.0, it_sum = 0.0;
+            for (int r = 0; r < reps && rc == BMPC_OK; ++r) {
+                double ms = 0.0, it = 0.0;
+                rc = rig.run(kWgKernels[idx], &ms, &it);
+                ms_sum += ms;
+                it_sum += it;
             }
-            if (launch_solver(b, k, cfg, st) != BMPC_OK || hipEventRecord(e1, st) != hipSuccess ||
-                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                rc = fail(BMPC_ERR_HIP, "tuning run of %s failed", k.name);
-                goto out;
+            const double per_it = ms_sum / it_sum;
+            if (ms_out) ms_out[idx] = per_it;
+            if (per_it < best_t) {
+                best_t = per_it;
+                best = &kWgKernels[idx];
             }
-            tot += ms;
         }
-        const double avg = tot / reps;
-        if (ms_out) ms_out[idx] = avg;
-        if (avg < best_ms) {
-            best_ms = avg;
-            best = &k;
-        }
-        ++idx;
     }
-    b->tuned_variant = best->segscan ? BMPC_RICCATI_SEGSCAN : BMPC_RICCATI_LEVEL;
-    b->tuned_block = best->block;
+    if (rc == BMPC_OK && best) {
+        keep_choice(b, *best);
+        if (variant_out) *variant_out = b->tuned_variant;
+        if (block_out) *block_out = b->tuned_block;
+    }
+    return rig.close(rc);
+}
+
+BMPC_API bmpc_status bmpc_batch_autotune(bmpc_batch* b, const bmpc_settings* s, int32_t warm, int32_t budget_ms,
+                                         const char* cache_path, int32_t* variant_out, int32_t* block_out,
+                                         double* ms_per_iter_out, int32_t* from_cache, void* stream)
+{
+    bmpc_status rc = check_tune_args(b, s, warm);
+    if (rc != BMPC_OK) return rc;
+    if (budget_ms < 0) return fail(BMPC_ERR_INVALID_ARG, "budget_ms must be >= 0");
+    const unsigned long long key = shape_key(b, warm);
+    char keytxt[32];
+    snprintf(keytxt, sizeof keytxt, "%016llx", key);
+    if (from_cache) *from_cache = 0;
+    // a cached choice for this shape: the last matching line wins
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "r")) {
+            char line[256], k[64];
+            int v = 0, blk = 0, found = 0;
+            double t = 0.0, best_t = 0.0;
+            while (fgets(line, sizeof line, f)) {
+                int vv = 0, bb = 0;
+                if (sscanf(line, "bmpc-autotune %63s %d %d %lf", k, &vv, &bb, &t) == 4 && strcmp(k, keytxt) == 0 &&
+                    find_wg(bb, vv == BMPC_RICCATI_SEGSCAN) &&
+                    (vv == BMPC_RICCATI_LEVEL || vv == BMPC_RICCATI_SEGSCAN)) {
+                    v = vv;
+                    blk = bb;
+                    best_t = t;
+                    found = 1;
+                }
+            }
+            fclose(f);
+            if (found) {
+                keep_choice(b, *find_wg(blk, v == BMPC_RICCATI_SEGSCAN));
+                if (variant_out) *variant_out = b->tuned_variant;
+                if (block_out) *block_out = b->tuned_block;
+                if (ms_per_iter_out) *ms_per_iter_out = best_t;
+                if (from_cache) *from_cache = 1;
+                return BMPC_OK;
+            }
+        }
+    }
+    // every candidate once, then further rounds over all of them while the
+    // budget lasts (at most 100 runs each)
+    TuneRig rig{b, to_cfg(*s, warm), (hipStream_t)stream};
+    double ms_sum[NUM_WG_KERNELS] = {}, it_sum[NUM_WG_KERNELS] = {};
+    if ((rc = rig.open()) == BMPC_OK) {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int round = 0; round < 100 && rc == BMPC_OK; ++round) {
+            if (round > 0 && std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                                     .count() >= budget_ms)
+                break;
+            for (int idx = 0; idx < NUM_WG_KERNELS && rc == BMPC_OK; ++idx) {
+                double ms = 0.0, it = 0.0;
+                rc = rig.run(kWgKernels[idx], &ms, &it);
+                ms_sum[idx] += ms;
+                it_sum[idx] += it;
+            }
+        }
+    }
+    rc = rig.close(rc);
+    if (rc != BMPC_OK) return rc;
+    int best = 0;
+    for (int idx = 1; idx < NUM_WG_KERNELS; ++idx)
+        if (ms_sum[idx] / it_sum[idx] < ms_sum[best] / it_sum[best]) best = idx;
+    keep_choice(b, kWgKernels[best]);
+    const double per_it = ms_sum[best] / it_sum[best];
     if (variant_out) *variant_out = b->tuned_variant;
     if (block_out) *block_out = b->tuned_block;
-out:
-    if (hipMemcpyAsync(b->d_state, saved, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
-        if (rc == BMPC_OK) rc = fail(BMPC_ERR_HIP, "restoring the batch state failed");
+    if (ms_per_iter_out) *ms_per_iter_out = per_it;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (!f) return fail(BMPC_ERR_INVALID_ARG, "cannot append to the tuning cache %s", cache_path);
+        fprintf(f, "bmpc-autotune %s %d %d %.9g\n", keytxt, b->tuned_variant, b->tuned_block, per_it);
+        fclose(f);
     }
-    (void)hipFree(saved);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    return rc;
+    return BMPC_OK;
 }
 
 BMPC_API int32_t bmpc_batch_tune_candidates(int32_t* variants, int32_t* blocks, int32_t cap)
@@ -2363,8 +2549,12 @@ BMPC_API bmpc_status bmpc_batch_stats(bmpc_batch* b, bmpc_stats* stats, void* st
     BMPC_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     std::vector<SolveOut> o(b->count);
     BMPC_HIP_TRY(hipMemcpy(o.data(), b->d_out, sizeof(SolveOut) * b->count, hipMemcpyDeviceToHost));
+    int dev = 0, khz = 0;
+    BMPC_HIP_TRY(hipGetDevice(&dev));
+    BMPC_HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     int worst = BMPC_OK;
     for (int i = 0; i < b->count; ++i) {
+        for (int k = 0; k < PH_COUNT; ++k) stats[i].time_ms[k] = khz > 0 ? (double)o[i].ticks[k] / khz : 0.0;
         stats[i].status = o[i].status;
         stats[i].outer_it = o[i].outer_it;
         stats[i].inner_it = o[i].inner_it;
@@ -2452,10 +2642,37 @@ BMPC_API bmpc_status bmpc_batch_shift(bmpc_batch* b, void* stream)
     hipStream_t st = (hipStream_t)stream;
     {
         ProfScope ps("bmpc_shift", st);
-        hipLaunchKernelGGL(k_bmpc_shift<256>, dim3(b->count), dim3(256), 0, st, b->d_desc);
+        hipLaunchKernelGGL(k_bmpc_shift<256>, dim3(b->count), dim3(256), 0, st, b->d_desc, MeasuredX0{{0, 0, 0, 0}, 0});
     }
     BMPC_HIP_TRY(hipGetLastError());
     return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_warm_shift(bmpc_problem* p, double* x, double* u, double* lam, double* ye,
+                                     const double* x0_new, void* stream)
+{
+    if (!p || !x || !u || !lam || !ye) return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
+    MeasuredX0 m{{0, 0, 0, 0}, 0};
+    if (x0_new) {
+        for (int a = 0; a < 4; ++a) {
+            if (!std::isfinite(x0_new[a])) return fail(BMPC_ERR_NONFINITE, "x0_new has a non-finite entry");
+            m.v[a] = x0_new[a];
+        }
+        m.use = 1;
+    }
+    bmpc_status st;
+    if (!p->self) {
+        bmpc_problem* one[1] = {p};
+        if ((st = bmpc_batch_create(one, 1, 0, &p->self)) != BMPC_OK) return st;
+    }
+    if ((st = bmpc_batch_state(p->self, 0, x, u, lam, ye, 1, stream)) != BMPC_OK) return st;
+    hipStream_t sm = (hipStream_t)stream;
+    {
+        ProfScope ps("bmpc_shift", sm);
+        hipLaunchKernelGGL(k_bmpc_shift<256>, dim3(1), dim3(256), 0, sm, p->self->d_desc, m);
+    }
+    BMPC_HIP_TRY(hipGetLastError());
+    return bmpc_batch_state(p->self, 0, x, u, lam, ye, 0, stream);
 }
 
 BMPC_API bmpc_status bmpc_batch_history(bmpc_batch* b, int32_t i, double* hist, void* stream)

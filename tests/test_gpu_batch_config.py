@@ -138,3 +138,85 @@ def test_graph_replay_of_receding_horizon_loop_matches_eager():
         L.bmpc_batch_destroy(b)
     for p in pa + pb:
         p.close()
+
+
+def test_autotune_budget_and_shape_keyed_cache(tmp_path):
+    """The budgeted autotuner times the candidates, keeps the one with the
+    shortest time per inner iteration and appends it to the cache; a second
+    batch of the same shape takes the cached choice without timing runs,
+    and a batch of another shape is tuned afresh."""
+    cache = str(tmp_path / "tune.txt")
+    insts = S.batched_instances(512)[:32]
+    st = L.bmpc_settings_default()
+    pbs, b = _batch(insts)
+    v1, b1, t1, cached = L.bmpc_batch_autotune(b, st, budget_ms=200, cache_path=cache)
+    print(f"autotuned: variant {v1} block {b1}, {t1:.4f} ms per inner iteration", flush=True)
+    assert not cached and t1 > 0 and (v1, b1) in L.bmpc_batch_tune_candidates()
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("bmpc-autotune ")
+    L.bmpc_batch_destroy(b)
+    pbs2, b2 = _batch(insts)
+    v2, bb2, t2, cached2 = L.bmpc_batch_autotune(b2, st, budget_ms=200, cache_path=cache)
+    assert cached2 and (v2, bb2) == (v1, b1) and t2 == pytest.approx(t1, rel=1e-8)
+    L.bmpc_batch_destroy(b2)
+    pbs3, b3 = _batch(insts[:16])
+    _, _, _, cached3 = L.bmpc_batch_autotune(b3, st, budget_ms=0, cache_path=cache)
+    assert not cached3 and len(open(cache).read().splitlines()) == 2
+    L.bmpc_batch_destroy(b3)
+    for p in pbs + pbs2 + pbs3:
+        p.close()
+
+
+def test_phase_times_cover_the_solve():
+    """Per-phase device times of a solve are positive and their sum is at
+    most the launch time measured around it (the start point is not
+    counted), and at least half of it."""
+    insts = S.batched_instances(512)[:1]
+    pbs, b = _batch(insts)
+    st = L.bmpc_settings_default()
+    L.bmpc_batch_launch(b, st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    L.bmpc_batch_launch(b, st)
+    e1.record()
+    torch.cuda.synchronize()
+    launch = e0.elapsed_time(e1)
+    s = L.bmpc_batch_stats(b, 1)[0]
+    L.bmpc_batch_destroy(b)
+    pbs[0].close()
+    ph = s["time_ms"]
+    print(f"launch {launch:.3f} ms, {s['inner_it']} inner iterations, phases {ph}", flush=True)
+    assert all(v > 0 for v in ph.values())
+    assert 0.5 * launch <= sum(ph.values()) <= launch * 1.02
+
+
+def test_warm_shift_with_measured_state_matches_oracle():
+    """bmpc_warm_shift of one problem's solution with a measured next state
+    equals the oracle's shift with that state; a warm solve from it reaches
+    the oracle's solution of the shifted problem."""
+    inst = S.single_bmpc(4)
+    opb = oracle.problem_from_instance(inst)
+    o, os_, _ = oracle.solve(opb)
+    assert os_["status"] == 0
+    N = inst.num_nodes
+    pb = Problem(inst)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(o[k]).ravel().copy()).cuda() for k in ("x", "u", "lam", "ye")}
+    onew0, _ = oracle.shift(opb, o)
+    meas = onew0.x0 + np.array([0.2, -0.1, 0.03, -0.3])
+    L.bmpc_warm_shift(pb.handle, dev["x"], dev["u"], dev["lam"], dev["ye"], x0_new=meas)
+    torch.cuda.synchronize()
+    onew, osh = oracle.shift(opb, o, x0_meas=meas)
+    np.testing.assert_array_equal(L.bmpc_problem_get_x0(pb.handle), meas)
+    shapes = {"x": (N, 4), "u": (N, 2), "lam": (N, 4), "ye": (N, 5)}
+    for k, shp in shapes.items():
+        g = dev[k].cpu().numpy().reshape(shp)
+        assert np.abs(g - osh[k]).max() <= 1e-12 * max(1.0, np.abs(osh[k]).max()), k
+    gs = L.bmpc_solve(pb.handle, L.bmpc_settings_default(), 7, dev["x"], dev["u"], dev["lam"], dev["ye"])
+    pb.close()
+    o2, os2, _ = oracle.solve(onew, warm=osh)
+    print(f"warm after measured shift: gpu {gs['status']} inner {gs['inner_it']}; oracle {os2['status']} "
+          f"inner {os2['inner_it']}", flush=True)
+    assert gs["status"] == os2["status"] == 0
+    g = dev["x"].cpu().numpy().reshape(N, 4)
+    assert np.abs(g - o2["x"]).max() <= 1e-5 * max(1.0, np.abs(o2["x"]).max())

@@ -281,14 +281,17 @@ def test_rollout_start_and_guard_match_oracle():
 
 
 def test_large_tree_iteration_path_follows_oracle():
-    """4096-scenario bicycle tree (122,871 nodes): the first AL inner
-    iterations (KKT residual, accepted step, merit parameter, penalty) and
-    the iterate after them agree with the oracle."""
+    """4096-scenario bicycle tree (122,871 nodes), solved by the whole grid:
+    the first 12 AL inner iterations (KKT residual, accepted step, merit
+    parameter, penalty) and the iterate after them agree with the oracle.
+    (The cold start of this tree does not converge in the oracle either, so
+    the full solve cannot be compared.)"""
     inst = S.large_tree(0)
     N = inst.num_nodes
-    st = L.bmpc_settings_default(max_outer=1, max_inner=4)
+    K = 12
+    st = L.bmpc_settings_default(max_outer=1, max_inner=K)
     pb = Problem(inst)
-    cap = 8
+    cap = 16
     b = L.bmpc_batch_create([pb.handle], hist_cap=cap)
     L.bmpc_batch_launch(b, st)
     gs = L.bmpc_batch_stats(b, 1)[0]
@@ -299,11 +302,11 @@ def test_large_tree_iteration_path_follows_oracle():
     L.bmpc_batch_destroy(b)
     pb.close()
     o, os_, oh = oracle.solve(oracle.problem_from_instance(inst),
-                              oracle.default_settings(max_outer=1, max_inner=4))
+                              oracle.default_settings(max_outer=1, max_inner=K))
     print(f"large tree: gpu inner {gs['inner_it']} r_kkt {gs['r_kkt']:.6e}; oracle inner {os_['inner_it']} "
           f"r_kkt {os_['r_kkt']:.6e}", flush=True)
-    assert gs["inner_it"] == os_["inner_it"] == 4
-    np.testing.assert_allclose(h[:4, :5], oh[:4, :5], rtol=1e-6)
+    assert gs["inner_it"] == os_["inner_it"] == K
+    np.testing.assert_allclose(h[:K, :5], oh[:K, :5], rtol=1e-6)
     assert gs["r_kkt"] == pytest.approx(os_["r_kkt"], rel=1e-6)
     assert np.abs(host(x, (N, 4)) - o["x"]).max() <= 1e-6 * max(1.0, np.abs(o["x"]).max())
 

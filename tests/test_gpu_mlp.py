@@ -97,13 +97,16 @@ def test_forward_matches_oracle(B):
     assert err <= 2e-3 * max(1.0, np.abs(want).max()), err
 
 
-def test_gradients_match_oracle():
-    B = 37
+@pytest.mark.parametrize("B", [37, 1024])
+def test_gradients_match_oracle(B):
+    """Loss and every parameter-block gradient at the network's real widths,
+    including the training batch of 1,024."""
+    print(f"mlp gradients B={B}", flush=True)
     rng = np.random.default_rng(7)
     p = _params(WIDTHS, rng)
     X = rng.normal(0, 1, (B, WIDTHS[0])).astype(np.float32)
     T = rng.normal(0, 1, (B, WIDTHS[-1])).astype(np.float32)
-    h = _net(WIDTHS, 64, p)
+    h = _net(WIDTHS, max(64, B), p)
     loss, g = L.bmpc_mlp_gradients(h, torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
     L.bmpc_mlp_destroy(h)
     oloss, og = oracle.mlp_loss_grad(WIDTHS, p.astype(np.float64), X.astype(np.float64), T.astype(np.float64),

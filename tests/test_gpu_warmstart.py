@@ -135,20 +135,32 @@ def test_network_start_matches_oracle_from_same_prediction(trained):
             assert np.abs(s["x"][i] - o["x"]).max() <= 1e-5 * max(1.0, np.abs(o["x"]).max())
 
 
-def test_network_start_not_worse_than_cold(trained):
+def test_trained_network_start_saves_iterations_over_cold(trained):
+    """On 256 held-out problems (seeds never used in training) the trained
+    network's start (predicted inputs, states by rollout, multipliers from
+    the adjoint sweep) needs fewer inner iterations in total than the cold
+    start, and converges at least as often.  The full prediction and the
+    guarded start are reported beside it."""
     starter, _ = trained
     insts = [S.learned_topology_instance(200_000 + i) for i in range(256)]
     pool = ProblemPool(insts[0].parent, len(insts), first_inst=insts[0])
     pool.load(insts)
     L.bmpc_batch_launch(pool.batch, L.bmpc_settings_default())
     cold = L.bmpc_batch_stats(pool.batch, len(insts))
-    net, t = W.solve_with_network(pool, insts, starter)
+    runs = {}
+    for name, kw in (("inputs", dict(guarded=False, with_multipliers=False)),
+                     ("full", dict(guarded=False)), ("guarded", dict(guarded=True))):
+        runs[name], _ = W.solve_with_network(pool, insts, starter, **kw)
     pool.close()
-    c_ok = sum(s["status"] == 0 for s in cold)
-    n_ok = sum(s["status"] == 0 for s in net)
-    c_it = np.mean([s["inner_it"] for s in cold])
-    n_it = np.mean([s["inner_it"] for s in net])
-    used = sum(s["start"] for s in net)
-    print(f"cold: {c_ok} converged, mean inner {c_it:.1f}; network: {n_ok} converged, mean inner {n_it:.1f}, "
-          f"network start kept on {used}; {t}", flush=True)
-    assert n_ok >= c_ok - 3
+
+    def summary(st):
+        return sum(s["status"] == 0 for s in st), sum(s["inner_it"] for s in st)
+    c_ok, c_it = summary(cold)
+    print(f"cold: {c_ok} converged, {c_it} inner iterations in total", flush=True)
+    for name, st in runs.items():
+        ok, it = summary(st)
+        print(f"network start ({name}): {ok} converged, {it} inner iterations "
+              f"({it / c_it:.3f} of cold); network start kept on {sum(s['start'] for s in st)}", flush=True)
+    n_ok, n_it = summary(runs["inputs"])
+    assert n_ok >= c_ok
+    assert n_it <= 0.9 * c_it

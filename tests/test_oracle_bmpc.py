@@ -436,3 +436,47 @@ def test_total_iteration_cap():
     # a cap above the iterations needed changes nothing
     _, st2, _ = oracle.solve(pb, oracle.default_settings(max_iter_total=full["inner_it"] + 1))
     assert st2["status"] == full["status"] and st2["inner_it"] == full["inner_it"]
+
+
+def _solve_all(insts):
+    """Oracle solves on host threads (the C oracle runs outside the
+    interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        return list(ex.map(lambda i: oracle.solve(oracle.problem_from_instance(i))[1], insts))
+
+
+def test_single_tree_workload_all_1000_seeds_converge():
+    """The single-tree workload's 1,000 seeds all end with status OK and
+    max(r_kkt, violation) < 1e-6."""
+    stats = _solve_all([S.single_bmpc(s) for s in range(1000)])
+    bad = [(i, s["status"]) for i, s in enumerate(stats) if s["status"] != 0 or s["r_kkt"] >= 1e-6
+           or s["viol"] >= 1e-6]
+    assert not bad, bad
+
+
+def test_batched_workload_all_512_instances_converge():
+    """All 512 instances of the batched workload (uneven horizons, branch
+    counts and branch stages) end with status OK at KKT 1e-6."""
+    stats = _solve_all(S.batched_instances(512))
+    bad = [(i, s["status"], s["inner_it"]) for i, s in enumerate(stats) if s["status"] != 0]
+    assert not bad, bad
+    assert max(s["r_kkt"] for s in stats) < 1e-6 and max(s["viol"] for s in stats) < 1e-6
+
+
+def test_shift_with_a_measured_state_moves_only_the_root_and_its_leaves():
+    """A measured next state replaces the predicted one: the shifted tree
+    is the same except at the root (the measured state) and at leaves rolled
+    out from the root; the new problem's x0 is the measured state."""
+    inst = S.single_bmpc(1)
+    pb = oracle.problem_from_instance(inst)
+    st, stats, _ = oracle.solve(pb)
+    new_p, pred = oracle.shift(pb, st)
+    meas = new_p.x0 + np.array([0.3, -0.2, 0.05, 0.4])
+    new_m, got = oracle.shift(pb, st, x0_meas=meas)
+    np.testing.assert_array_equal(new_m.x0, meas)
+    np.testing.assert_array_equal(got["x"][0], meas)
+    np.testing.assert_array_equal(got["x"][1:], pred["x"][1:])
+    for k in ("u", "lam", "ye"):
+        np.testing.assert_array_equal(got[k], pred[k])
+    np.testing.assert_array_equal(new_m.ref, new_p.ref)

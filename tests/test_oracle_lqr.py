@@ -248,3 +248,50 @@ def test_printed_combination_signs_are_not_the_minimisation():
     assert np.allclose(good[4], o["p"][0], rtol=1e-11, atol=1e-11)
     # P is even in the sign of A, so the slip shows in the linear term p
     assert not np.allclose(bad[4], o["p"][0], rtol=1e-3, atol=1e-3)
+
+
+def _tree_qp_kkt_residual(inst, sol):
+    """Infinity norm of the KKT conditions of the tree QP at (x, u, lam),
+    evaluated in long double: stationarity in u_n and x_n (n != 0) with the
+    convention L = cost + sum_j lam_j^T (A_j x_p + B_j u_p + c_j - x_j), and
+    the dynamics."""
+    ld = np.longdouble
+    par = inst.parent
+    N = len(par)
+    A, B, c, Q, R, M, q, r = (np.asarray(getattr(inst, k), dtype=ld) for k in "ABcQRMqr")
+    x, u, lam = (np.asarray(sol[k], dtype=ld) for k in ("x", "u", "lam"))
+    nch = S.num_children(par)
+    res = ld(0)
+    for n in range(N):
+        kids = np.nonzero(par == n)[0]
+        if nch[n] > 0:
+            gu = R[n] @ u[n] + M[n] @ x[n] + r[n] + sum(B[j].T @ lam[j] for j in kids)
+            res = max(res, np.abs(gu).max())
+        if n > 0:
+            gx = Q[n] @ x[n] + q[n] - lam[n] + sum((A[j].T @ lam[j] for j in kids), np.zeros(len(q[n]), ld))
+            if nch[n] > 0:
+                gx = gx + M[n].T @ u[n]
+            res = max(res, np.abs(gx).max())
+            d = A[n] @ x[par[n]] + B[n] @ u[par[n]] + c[n] - x[n]
+            res = max(res, np.abs(d).max())
+    return float(res)
+
+
+def test_extended_precision_recursion_solves_the_same_problem_more_accurately():
+    """The long-double recursion agrees with the double one to rounding on a
+    well-conditioned tree; on a badly conditioned one (input weights 1e-7,
+    A = I + 0.3 N(0,1)) its KKT residual, evaluated in long double, is at
+    least 10 times smaller than the double recursion's (its outputs are
+    rounded to double, which bounds how small it can get)."""
+    par = S.tree_parent(12, [2, 6], 2)
+    inst = S.lqr_on(par, 4, 2, seed=8, random_cost=True)
+    d = oracle.tree_lqr_inst(inst)
+    e = oracle.tree_lqr_inst(inst, extended=True)
+    for k in ("x", "u", "lam", "P", "p"):
+        assert np.abs(d[k] - e[k]).max() <= 1e-12 * max(1.0, np.abs(e[k]).max()), k
+    bad = S.lqr_on(S.tree_parent(30, [2, 6, 14], 2), 4, 2, seed=9, a_scale=0.3, r_scale=1e-7)
+    d = oracle.tree_lqr_inst(bad)
+    e = oracle.tree_lqr_inst(bad, extended=True)
+    rd, re = _tree_qp_kkt_residual(bad, d), _tree_qp_kkt_residual(bad, e)
+    print(f"KKT residual: double {rd:.3e}, long double {re:.3e}")
+    assert re * 10 <= rd
