@@ -362,10 +362,17 @@ def cpu_baseline_bmpc(insts, budget_s=10.0):
                       f"({conv} converged) in {el:.1f} s, one instance per process on {cores} cores"}
 
 
+def phase_us_per_iteration(stats):
+    """Device time per inner iteration of each solver phase (from the
+    solver's own phase clock), summed over the given solves."""
+    its = max(1, sum(x["inner_it"] for x in stats))
+    return {k: round(sum(x["time_ms"][k] for x in stats) * 1e3 / its, 2) for k in stats[0]["time_ms"]}
+
+
 def slowest(stats, insts):
     i = int(np.argmax([x["inner_it"] for x in stats]))
     return {"instance": i, "nodes": int(insts[i].num_nodes), "inner_it": int(stats[i]["inner_it"]),
-            "status": int(stats[i]["status"])}
+            "status": int(stats[i]["status"]), "phase_us_per_iteration": phase_us_per_iteration([stats[i]])}
 
 
 def not_converged(stats):
@@ -404,7 +411,8 @@ def run_bmpc(args, torch, L):
                     "53 nodes, seeds 0-7, cold start",
         "ms_per_solve": round(ms_single, 4), "solves_per_s": round(1e3 / ms_single, 1),
         "converged": sum(s["status"] == 0 for s in st1), "of": len(st1),
-        "mean_inner_it": float(np.mean([s["inner_it"] for s in st1]))}
+        "mean_inner_it": float(np.mean([s["inner_it"] for s in st1])),
+        "phase_us_per_iteration": phase_us_per_iteration(st1)}
     for b in b1:
         L.bmpc_batch_destroy(b)
     for p in single:
@@ -509,8 +517,10 @@ def run_bmpc(args, torch, L):
                                        "solves_per_s": round(conv(s_cold2) / (ms_cold2 / 1e3), 1)},
         "autotuner": {"chosen": {"variant": "segment_scan" if tv == L.RICCATI_SEGSCAN else "level",
                                  "threads_per_problem": tb},
-                      "candidates_ms": {f"{'segment_scan' if v == L.RICCATI_SEGSCAN else 'level'}/{blk}": round(t, 3)
-                                        for (v, blk), t in cand.items()}},
+                      "criterion": "launch time per inner iteration summed over the batch",
+                      "candidates_us_per_iteration": {
+                          f"{'segment_scan' if v == L.RICCATI_SEGSCAN else 'level'}/{blk}": round(t * 1e3, 3)
+                          for (v, blk), t in cand.items()}},
         "cold_tuned": {"ms": round(ms_tuned, 3), "converged": conv(s_tuned), "mean_inner_it": mean_it(s_tuned),
                        "solves_per_s": round(conv(s_tuned) / (ms_tuned / 1e3), 1),
                        # the launch ends with its longest-running problem
@@ -650,6 +660,46 @@ def run_warmstart(args, torch, L):
     return out
 
 
+def run_solver_profile(args, torch, L):
+    """Only the branch-MPC solver on one workload, for per-kernel profiles:
+    'single' = the 53-node tree, seeds 0-7, each solved args.steps times;
+    'batched' = the 512-instance batch with a cap of 200 inner iterations
+    per problem, args.steps launches."""
+    import bmpc_synth as S
+    from paper_2506_13624_amd.bicycle import Problem
+    if args.only_solver == "single":
+        insts = [S.single_bmpc(i) for i in range(8)]
+        st = L.bmpc_settings_default()
+        pbs = [Problem(i) for i in insts]
+        bs = [L.bmpc_batch_create([p.handle]) for p in pbs]
+    else:
+        insts = S.batched_instances(512)
+        st = L.bmpc_settings_default(max_iter_total=200)
+        pbs = [Problem(i) for i in insts]
+        bs = [L.bmpc_batch_create([p.handle for p in pbs])]
+    for b in bs:
+        L.bmpc_batch_launch(b, st)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        for b in bs:
+            L.bmpc_batch_launch(b, st)
+    ev1.record()
+    torch.cuda.synchronize()
+    stats = [x for b in bs for x in L.bmpc_batch_stats(b, 1 if len(bs) > 1 else len(insts))]
+    out = {"workload": args.only_solver, "launches": args.steps * len(bs),
+           "ms_per_launch": round(ev0.elapsed_time(ev1) / (args.steps * len(bs)), 4),
+           "converged": int(sum(x["status"] == 0 for x in stats)), "of": len(stats),
+           "inner_it": int(sum(x["inner_it"] for x in stats)),
+           "phase_us_per_iteration": phase_us_per_iteration(stats)}
+    for b in bs:
+        L.bmpc_batch_destroy(b)
+    for p in pbs:
+        p.close()
+    return {"solver_profile": out}
+
+
 def run_large_tree(args, torch, L):
     """Tree LQR on the 4096-scenario bicycle tree (122,871 nodes): the Gauss-
     Newton LQR subproblem at the cold start, level-parallel vs segment-scan
@@ -732,7 +782,7 @@ def run_large_tree(args, torch, L):
     # launch that only builds the cold start
     ms_it = (ms_all - start_ms) / n_it
     al = {"inner_iterations": s["inner_it"], "ms_launch": round(ms_all, 3), "ms_start_only_launch": round(start_ms, 3),
-          "ms_per_inner_iteration": round(ms_it, 3)}
+          "ms_per_inner_iteration": round(ms_it, 3), "phase_us_per_iteration": phase_us_per_iteration([s])}
     # measured HBM traffic of the same two launches (rocprofv3 FETCH_SIZE +
     # WRITE_SIZE, profiles/), while the solver sources are unchanged
     tb = measured_traffic("bmpc_solve_grid_5_inner", SOLVER_SRCS)
@@ -765,6 +815,8 @@ def main():
     ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--no-concurrent", action="store_true",
                     help="skip the independent solves on several streams (for per-kernel profiles)")
+    ap.add_argument("--only-solver", choices=("single", "batched"), default=None,
+                    help="only the branch-MPC solver on one workload, printed on its own (for profiles)")
     ap.add_argument("--only-large", action="store_true",
                     help="only the 4096-scenario tree section, printed on its own (for counter runs)")
     ap.add_argument("--ws-train", type=int, default=200000, help="training instances of the learned warm start")
@@ -782,6 +834,17 @@ def main():
         print(json.dumps({"error": "no HIP device visible"}))
         sys.exit(1)
     from paper_2506_13624_amd import _lib as L
+
+    if args.only_solver:
+        if args.calib_copy:
+            nbytes = 512 * 2 ** 20
+            src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            del src
+        progress(f"solver profile: {args.only_solver}")
+        print(json.dumps(run_solver_profile(args, torch, L)), flush=True)
+        return
 
     if args.only_large:
         if args.calib_copy:

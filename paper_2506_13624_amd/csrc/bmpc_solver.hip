@@ -1789,6 +1789,7 @@ struct bmpc_problem {
     int n_control = 0;  // nodes with children
     int n_obs = 0;      // nodes carrying the obstacle constraint
     bmpc_batch* self = nullptr;  // one-instance batch used by bmpc_solve
+    double* d_kkt = nullptr;     // KKT residual and violation of bmpc_linearize (2 doubles)
 };
 
 struct bmpc_batch {
@@ -2184,6 +2185,7 @@ BMPC_API void bmpc_problem_destroy(bmpc_problem* p)
     (void)hipFree(p->d_obs);
     (void)hipFree(p->d_has);
     (void)hipFree(p->d_x0);
+    (void)hipFree(p->d_kkt);
     delete p;
 }
 
@@ -2763,8 +2765,9 @@ BMPC_API bmpc_status bmpc_linearize(bmpc_problem* p, const double* x, const doub
                                const_cast<double*>(lam), const_cast<double*>(ye), 1, stream)) != BMPC_OK)
         return st;
     const InstDesc& d = p->self->h_desc[0];
-    double* kk = nullptr;
-    if (kkt_viol) BMPC_HIP_TRY(hipMalloc(&kk, 2 * sizeof(double)));
+    if (kkt_viol && !p->d_kkt && !dalloc(&p->d_kkt, 2))
+        return fail(BMPC_ERR_OOM, "device allocation for the KKT residual failed");
+    double* kk = kkt_viol ? p->d_kkt : nullptr;
     {
         ProfScope ps("bmpc_linearise", sm);
         hipLaunchKernelGGL(k_bmpc_linearise<256>, dim3(1), dim3(256), 0, sm, d, rho, kk);
@@ -2783,7 +2786,6 @@ BMPC_API bmpc_status bmpc_linearize(bmpc_problem* p, const double* x, const doub
     if (kkt_viol) {
         BMPC_HIP_TRY(hipMemcpyAsync(kkt_viol, kk, 2 * sizeof(double), hipMemcpyDeviceToHost, sm));
         BMPC_HIP_TRY(hipStreamSynchronize(sm));
-        (void)hipFree(kk);
     }
     return BMPC_OK;
 }
