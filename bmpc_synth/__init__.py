@@ -276,3 +276,94 @@ def lqr_microbench(instance: int = 0) -> LqrInstance:
 def lqr_on(parent, nx, nu, seed, **kw) -> LqrInstance:
     rng = np.random.Generator(np.random.PCG64(9_000_011 + seed))
     return random_lqr(np.asarray(parent, np.int32), nx, nu, rng, **kw)
+
+
+# ----------------------------------------------------------------------------
+# chain of masses and springs (tree LQR with per-scenario dynamics)
+# ----------------------------------------------------------------------------
+
+MS_DT = 0.5          # sampling time of the discretised chain
+MS_K_RANGE = (0.5, 1.5)   # sampled spring constants (nominal 1)
+
+
+def mass_spring_matrices(M: int, k: float, dt: float = MS_DT, mass: float = 1.0):
+    """Discrete-time matrices of a chain of M equal masses joined by springs
+    of constant k, with walls at both ends (M + 1 springs) and M - 1
+    actuators, actuator i pushing mass i and mass i + 1 apart.  State
+    [positions (M), velocities (M)], input the M - 1 actuator forces.  The
+    continuous model  p' = v,  v' = (k/m) L p + (1/m) E u  (L tridiagonal
+    1, -2, 1) is held over dt (zero-order hold, matrix exponential of the
+    augmented system).  These matrices are data of the tree LQR, the model
+    a user would pass."""
+    from scipy.linalg import expm
+    nx, nu = 2 * M, M - 1
+    Lm = -2.0 * np.eye(M) + np.eye(M, k=1) + np.eye(M, k=-1)
+    E = np.zeros((M, nu))
+    for i in range(nu):
+        E[i, i] = -1.0
+        E[i + 1, i] = 1.0
+    Ac = np.zeros((nx, nx))
+    Ac[:M, M:] = np.eye(M)
+    Ac[M:, :M] = (k / mass) * Lm
+    Bc = np.zeros((nx, nu))
+    Bc[M:, :] = E / mass
+    aug = np.zeros((nx + nu, nx + nu))
+    aug[:nx, :nx] = Ac
+    aug[:nx, nx:] = Bc
+    ex = expm(aug * dt)
+    return ex[:nx, :nx], ex[:nx, nx:]
+
+
+def mass_spring_tree(M: int = 15, robust_horizon: int = 10, n_d: int = 2, horizon: int = 40,
+                     instance: int = 0, random_terms: bool = False) -> LqrInstance:
+    """Tree LQR of the mass-spring chain under spring-constant uncertainty:
+    n_d spring constants are drawn from U[0.5, 1.5]; every node of the first
+    ``robust_horizon`` stages branches into n_d children, child d taking
+    constant k_d for its incoming edge and every edge below it (so there are
+    Z = n_d ** robust_horizon scenarios); ``horizon`` control stages and
+    leaves at stage ``horizon``.  Costs Q = I, R = I, M = 0 at every control
+    node and Q_f = I at the leaves; the initial state draws positions and
+    velocities from U[-1, 1].  Linear terms and defects are zero, or with
+    ``random_terms`` N(0, 1) (q, r per control node, q_f per leaf, c per
+    edge).  Draw order: the n_d constants, then x0, then the linear terms."""
+    rng = rng_for(5, instance)
+    ks = rng.uniform(MS_K_RANGE[0], MS_K_RANGE[1], size=n_d)
+    parent = tree_parent(horizon, list(range(robust_horizon)), n_d)
+    N = len(parent)
+    nx, nu = 2 * M, M - 1
+    mats = [mass_spring_matrices(M, k) for k in ks]
+    # branch index of each node: its rank among its siblings where its
+    # parent branches, else its parent's
+    nch = num_children(parent)
+    branch = np.zeros(N, dtype=np.int64)
+    first = {}
+    for j in range(1, N):
+        p = parent[j]
+        if nch[p] > 1:
+            first.setdefault(p, j)
+            branch[j] = j - first[p]
+        else:
+            branch[j] = branch[p]
+    A = np.empty((N, nx, nx))
+    B = np.empty((N, nx, nu))
+    for d in range(n_d):
+        sel = branch == d
+        A[sel] = mats[d][0]
+        B[sel] = mats[d][1]
+    A[0] = 0.0
+    B[0] = 0.0
+    Q = np.broadcast_to(np.eye(nx), (N, nx, nx)).copy()
+    R = np.broadcast_to(np.eye(nu), (N, nu, nu)).copy()
+    Mx = np.zeros((N, nu, nx))
+    x0 = rng.uniform(-1.0, 1.0, size=nx)
+    if random_terms:
+        q = rng.standard_normal((N, nx))
+        r = rng.standard_normal((N, nu))
+        c = rng.standard_normal((N, nx))
+        c[0] = 0.0
+    else:
+        q, r, c = np.zeros((N, nx)), np.zeros((N, nu)), np.zeros((N, nx))
+    leaves = nch == 0
+    R[leaves] = 0.0
+    r[leaves] = 0.0
+    return LqrInstance(parent=parent, A=A, B=B, c=c, Q=Q, R=R, M=Mx, q=q, r=r, x0=x0)

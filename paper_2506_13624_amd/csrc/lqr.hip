@@ -805,6 +805,283 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
 }
 
 // ------------------------------------------------------------------------
+// Backward pass for larger state dimensions (the mass-spring chain,
+// nx = 30, nu = 14): one workgroup of four wavefronts walks a leaf
+// segment upwards, with the same last-arriver merges as k_bwd_wave.  Per
+// child, the two dense products run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4, 16 x 16 output tiles spread over the wavefronts):
+//   S = P [A B c] + [0 0 p]         (NX x NC, NC = NX + NU + 1)
+//   Z += [A B]^T S                  (Z = [[W G^T w],[G H g]], NZ x NC)
+// then one wavefront factors H = L L^T, lanes take the columns of
+// L^-1 [G g] and of the gains, and all threads form
+//   P = (W + W^T)/2 - Gh^T Gh,  p = w - Gh^T gh  (Gh = L^-1 G, gh = L^-1 g).
+// Operand layout of v_mfma_f64_16x16x4 (lane l, li = l % 16, lk = l / 16):
+// A entry (li, lk), B entry (lk, li), result entries (lk + 4 v, li), v < 4.
+// ------------------------------------------------------------------------
+__host__ __device__ constexpr int pad16(int v) { return (v + 15) / 16 * 16; }
+
+template <int NX, int NU, int LAY>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_bwd_mfma(TreeDev t, LqrArgs a, int* arrive)
+{
+    constexpr int NZ = NX + NU, NC = NZ + 1;
+    constexpr int NXP = pad16(NX), NCP = pad16(NC), NZP = pad16(NZ);
+    constexpr int TS = (NXP / 16) * (NCP / 16);   // tiles of S
+    constexpr int TZ = (NZP / 16) * (NCP / 16);   // tiles of Z
+    constexpr int KS = NXP / 4;                   // k steps of both products
+    __shared__ __align__(16) double sD[NX][NCP];  // [A B c 0 ..] of the child edge
+    __shared__ __align__(16) double sP[NX][NXP];  // the child's P (columns >= NX unused)
+    __shared__ __align__(16) double sp[NXP];
+    __shared__ __align__(16) double sS[NX][NCP];
+    __shared__ __align__(16) double sZ[NZ][NCP];
+    __shared__ __align__(16) double sG[NU][NX + 1];  // L^-1 [G g]
+    __shared__ __align__(16) double sL[NU][NU + 1];
+    __shared__ double sInv[NU];
+    __shared__ int sgo, sok;
+
+    // thread indices are re-derived through an opaque copy at every step of
+    // the walk, so that the compiler recomputes the many per-lane LDS
+    // addresses where they are used instead of keeping them all live
+    // across the walk (they would not fit in the registers)
+    int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int li = lane & 15, lk = lane >> 4;
+    auto refresh_ids = [&]() {
+        int v = threadIdx.x;
+        asm volatile("" : "+v"(v));
+        tid = v;
+        lane = v & 63;
+        wave = v >> 6;
+        li = lane & 15;
+        lk = lane >> 4;
+    };
+    const int N = t.N;
+    int n = t.leaves[blockIdx.x];
+
+    #pragma unroll 1
+
+    for (int e = tid; e < NX * NCP; e += 256)
+        if (e % NCP >= NC) sD[e / NCP][e % NCP] = 0.0;
+
+    // stage data of node m into Z: [[Q M^T q],[M R r]]
+    auto load_stage = [&](int m) {
+        #pragma unroll 1
+        for (int e = tid; e < NZ * NC; e += 256) {
+            const int i = e / NC, j = e % NC;
+            double v;
+            if (i < NX) {
+                if (j < NX) v = a.Q[lidx<LAY>(m, i * NX + j, NX * NX, N)];
+                else if (j < NZ) v = a.M[lidx<LAY>(m, (j - NX) * NX + i, NU * NX, N)];
+                else v = a.q[lidx<LAY>(m, i, NX, N)];
+            } else {
+                const int ii = i - NX;
+                if (j < NX) v = a.M[lidx<LAY>(m, ii * NX + j, NU * NX, N)];
+                else if (j < NZ) v = a.R[lidx<LAY>(m, ii * NU + j - NX, NU * NU, N)];
+                else v = a.r[lidx<LAY>(m, ii, NU, N)];
+            }
+            sZ[i][j] = v;
+        }
+    };
+    // edge into node j: [A B c] into D
+    auto load_edge = [&](int j) {
+        #pragma unroll 1
+        for (int e = tid; e < NX * NC; e += 256) {
+            const int i = e / NC, col = e % NC;
+            double v;
+            if (col < NX) v = a.A[lidx<LAY>(j, i * NX + col, NX * NX, N)];
+            else if (col < NZ) v = a.B[lidx<LAY>(j, i * NU + col - NX, NX * NU, N)];
+            else v = a.c[lidx<LAY>(j, i, NX, N)];
+            sD[i][col] = v;
+        }
+    };
+    // value function of child j, written by another workgroup
+    auto load_value = [&](int j) {
+        #pragma unroll 1
+        for (int e = tid; e < NX * NX; e += 256)
+            sP[e / NX][e % NX] = ld_shared_dev(&a.P[lidx<LAY>(j, e, NX * NX, N)]);
+        #pragma unroll 1
+        for (int e = tid; e < NX; e += 256) sp[e] = ld_shared_dev(&a.p[lidx<LAY>(j, e, NX, N)]);
+    };
+    auto add_child = [&]() {
+        __syncthreads();
+        #pragma unroll 1
+        for (int tt = wave; tt < TS; tt += 4) {
+            const int ti = tt / (NCP / 16), tj = tt % (NCP / 16);
+            const int row = 16 * ti + li, col = 16 * tj + li;
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + lk;
+                const double av = (row < NX && k < NX) ? sP[row][k] : 0.0;
+                const double bv = k < NX ? sD[k][col] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * ti + lk + 4 * v;
+                if (r < NX) sS[r][col] = col == NZ ? acc[v] + sp[r] : acc[v];
+            }
+        }
+        __syncthreads();
+        #pragma unroll 1
+        for (int tt = wave; tt < TZ; tt += 4) {
+            const int ti = tt / (NCP / 16), tj = tt % (NCP / 16);
+            const int rowa = 16 * ti + li, col = 16 * tj + li;
+            f64x4 acc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * ti + lk + 4 * v;
+                acc[v] = r < NZ ? sZ[r][col] : 0.0;
+            }
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + lk;
+                const double av = (k < NX && rowa < NCP) ? sD[k][rowa] : 0.0;
+                const double bv = k < NX ? sS[k][col] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * ti + lk + 4 * v;
+                if (r < NZ) sZ[r][col] = acc[v];
+            }
+        }
+        __syncthreads();
+    };
+    // gains and value function of node m from the accumulated Z
+    auto finish = [&](int m, bool shared_out) {
+        if (wave == 0) {
+            // H = L L^T, right-looking, by one wavefront
+            #pragma unroll 1
+            for (int e = lane; e < NU * NU; e += 64) sL[e / NU][e % NU] = sZ[NX + e / NU][NX + e % NU];
+            bool ok = true;
+#pragma unroll 1
+            for (int j = 0; j < NU; ++j) {
+                wave_sync();
+                const double d = sL[j][j];
+                ok = ok && d > 0.0;
+                const double y = rsqrt_refined(d > 0.0 ? d : 1.0);
+                if (lane == 0) {
+                    sL[j][j] = (d > 0.0 ? d : 1.0) * y;
+                    sInv[j] = y;
+                }
+                if (lane > j && lane < NU) sL[lane][j] *= y;
+                wave_sync();
+                #pragma unroll 1
+                for (int e = lane; e < NU * NU; e += 64) {
+                    const int r = e / NU, c = e % NU;
+                    if (c > j && r >= c) sL[r][c] -= sL[r][j] * sL[c][j];
+                }
+            }
+            wave_sync();
+            if (lane == 0) sok = ok ? 1 : 0;
+            // lane c takes column c of [G g]: Gh = L^-1 [G g] into sG, then
+            // [K k] = -L^-T Gh (the column's unknowns in sS, free after the
+            // products); each lane reads back only its own column
+            if (lane <= NX) {
+                const int col = lane < NX ? lane : NZ;
+#pragma unroll 1
+                for (int i = 0; i < NU; ++i) {
+                    double s = sZ[NX + i][col];
+                    for (int k = 0; k < i; ++k) s -= sL[i][k] * sG[k][lane];
+                    sG[i][lane] = s * sInv[i];
+                }
+#pragma unroll 1
+                for (int i = NU - 1; i >= 0; --i) {
+                    double s = sG[i][lane];
+                    for (int k = i + 1; k < NU; ++k) s -= sL[k][i] * sS[k][lane];
+                    s *= sInv[i];
+                    sS[i][lane] = s;
+                    if (lane < NX) a.K[lidx<LAY>(m, i * NX + lane, NU * NX, N)] = -s;
+                    else a.k[lidx<LAY>(m, i, NU, N)] = -s;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0 && !sok) atomicMin(a.bad, m);
+        // (the child's P in sP was last read by the products)
+        #pragma unroll 1
+        for (int e = tid; e < NX * NX; e += 256) {
+            const int i = e / NX, j = e % NX;
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < NU; ++r) s = fma(sG[r][i], sG[r][j], s);
+            const double v = 0.5 * (sZ[i][j] + sZ[j][i]) - s;
+            sP[i][j] = v;
+            if (shared_out) st_shared_dev(&a.P[lidx<LAY>(m, e, NX * NX, N)], v);
+            else a.P[lidx<LAY>(m, e, NX * NX, N)] = v;
+        }
+        #pragma unroll 1
+        for (int i = tid; i < NX; i += 256) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < NU; ++r) s = fma(sG[r][i], sG[r][NX], s);
+            const double v = sZ[i][NZ] - s;
+            sp[i] = v;
+            if (shared_out) st_shared_dev(&a.p[lidx<LAY>(m, i, NX, N)], v);
+            else a.p[lidx<LAY>(m, i, NX, N)] = v;
+        }
+        __syncthreads();
+    };
+
+    // the leaf: P = Q_f, p = q_f, no gains
+    {
+        const int4 inf = t.info[n];
+        const bool shared_out = inf.w > 1;
+        #pragma unroll 1
+        for (int e = tid; e < NX * NX; e += 256) {
+            const double v = a.Q[lidx<LAY>(n, e, NX * NX, N)];
+            sP[e / NX][e % NX] = v;
+            if (shared_out) st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], v);
+            else a.P[lidx<LAY>(n, e, NX * NX, N)] = v;
+        }
+        #pragma unroll 1
+        for (int e = tid; e < NX; e += 256) {
+            const double v = a.q[lidx<LAY>(n, e, NX, N)];
+            sp[e] = v;
+            if (shared_out) st_shared_dev(&a.p[lidx<LAY>(n, e, NX, N)], v);
+            else a.p[lidx<LAY>(n, e, NX, N)] = v;
+        }
+        #pragma unroll 1
+        for (int e = tid; e < NU * NX; e += 256) a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0;
+        #pragma unroll 1
+        for (int e = tid; e < NU; e += 256) a.k[lidx<LAY>(n, e, NU, N)] = 0.0;
+    }
+    for (;;) {
+        refresh_ids();
+        const int4 inf = t.info[n];
+        const int par = inf.z, nsib = inf.w;
+        if (par < 0) break;
+        if (nsib > 1) {
+            // hand the value function over: every thread's stores complete
+            // before the count
+            wait_own_stores();
+            __syncthreads();
+            if (tid == 0) sgo = (atomicAdd(&arrive[par], 1) == nsib - 1);
+            __syncthreads();
+            if (!sgo) break;
+        }
+        const int child = n;
+        n = par;
+        const int4 pinf = t.info[n];
+        const bool shared_out = pinf.w > 1;
+        __syncthreads();
+        load_stage(n);
+        if (nsib == 1) {
+            // the only child's value function is still in sP, sp
+            load_edge(child);
+            add_child();
+        } else {
+            for (int j = pinf.x; j < pinf.y; ++j) {
+                __syncthreads();
+                load_edge(j);
+                load_value(j);
+                add_child();
+            }
+        }
+        finish(n, shared_out);
+    }
+}
+
+// ------------------------------------------------------------------------
 // forward rollout: G lanes per root-to-leaf path, inputs D steps ahead
 // ------------------------------------------------------------------------
 // Value of lane j of each row of 16 lanes, for every lane of the row
@@ -820,11 +1097,22 @@ __device__ __forceinline__ int row_bcast_int(int v)
     return __builtin_amdgcn_update_dpp(0, v, 0x150 + J, 0xf, 0xf, false);
 }
 // lane J of the group of G lanes that starts at lane base
+// lane J of the wavefront (a group of 64 lanes): one scalar read per dword
+template <int J>
+__device__ __forceinline__ double wave_lane(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), J);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), J);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 template <int G, int J>
 __device__ __forceinline__ double group_value(double v, int base)
 {
     if constexpr (G == 16)
         return row_bcast<J>(v);
+    else if constexpr (G == 64)
+        return wave_lane<J>(v);
     else
         return __shfl(v, base + J, 64);
 }
@@ -833,6 +1121,8 @@ __device__ __forceinline__ int group_value_int(int v, int base)
 {
     if constexpr (G == 16)
         return row_bcast_int<J>(v);
+    else if constexpr (G == 64)
+        return __builtin_amdgcn_readlane(v, J);
     else
         return __shfl(v, base + J, 64);
 }
@@ -994,6 +1284,7 @@ struct LqrKernels {
     int nx, nu, layout, group;
     void (*bwd_lane)(TreeDev, LqrArgs, int*);
     void (*bwd_wave)(TreeDev, LqrArgs, int*);
+    void (*bwd_mfma)(TreeDev, LqrArgs, int*);
     void (*bwd_seg)(TreeDev, LqrArgs, int*);
     void (*fwd)(TreeDev, LqrArgs);
     void (*costate)(TreeDev, LqrArgs, int*);
@@ -1004,11 +1295,21 @@ static LqrKernels make_k()
 {
     // rows of 16 lanes: the broadcasts inside a group are DPP row moves
     constexpr int G = 16;
-    LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, nullptr, k_fwd_rows<NX, NU, LAY, G, 4>,
+    LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, nullptr, nullptr, k_fwd_rows<NX, NU, LAY, G, 4>,
                  k_costate<NX, LAY>};
     if constexpr (LANE) k.bwd_lane = k_bwd_lane<NX, NU, LAY>;
     if constexpr (NX <= 4) k.bwd_seg = k_bwd_seg<NX, NU, LAY>;
     return k;
+}
+
+// larger state dimensions: the matrix-core backward pass (four wavefronts
+// per leaf segment) and a whole wavefront per path in the forward pass
+template <int NX, int NU, int LAY>
+static LqrKernels make_k_mfma()
+{
+    constexpr int G = 64;
+    return LqrKernels{NX, NU, LAY, G, nullptr, nullptr, k_bwd_mfma<NX, NU, LAY>, nullptr,
+                      k_fwd_rows<NX, NU, LAY, G, 2>, k_costate<NX, LAY>};
 }
 
 static const LqrKernels* find_kernels(int nx, int nu, int layout)
@@ -1018,6 +1319,7 @@ static const LqrKernels* find_kernels(int nx, int nu, int layout)
         make_k<4, 2, 0, true>(),   make_k<4, 2, 1, true>(),
         make_k<6, 3, 0, true>(),   make_k<6, 3, 1, true>(),
         make_k<12, 4, 0, false>(), make_k<12, 4, 1, false>(),
+        make_k_mfma<30, 14, 0>(),  make_k_mfma<30, 14, 1>(),
     };
     for (const auto& k : table)
         if (k.nx == nx && k.nu == nu && k.layout == layout) return &k;
@@ -1120,6 +1422,9 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
     if (variant == BMPC_RICCATI_SEGSCAN) {
         ProfScope ps("lqr_backward_segscan", s);
         hipLaunchKernelGGL(pl->kern->bwd_seg, dim3(Z), dim3(64), 0, s, t, a, pl->arrive);
+    } else if (pl->kern->bwd_mfma) {
+        ProfScope ps("lqr_backward_level_mfma", s);
+        hipLaunchKernelGGL(pl->kern->bwd_mfma, dim3(Z), dim3(256), 0, s, t, a, pl->arrive);
     } else if (pl->kern->bwd_lane) {
         ProfScope ps("lqr_backward_level_lane", s);
         hipLaunchKernelGGL(pl->kern->bwd_lane, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);

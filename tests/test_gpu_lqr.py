@@ -330,3 +330,59 @@ def test_lqr_on_large_tree_cold_start_subproblem(variant):
     g, stt, bad = gpu_lqr(sub, L.LAYOUT_ELEM_MAJOR, variant=variant)
     assert stt == 0, bad
     assert_parity(g, o)
+
+
+# ----------------------------------------------------------------------------
+# chain of masses and springs: nx = 30, nu = 14, matrix-core backward pass
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("layout", [L.LAYOUT_NODE_MAJOR, L.LAYOUT_ELEM_MAJOR])
+@pytest.mark.parametrize("nr", [1, 3, 6])
+def test_mass_spring_tree_lqr_matches_oracle(nr, layout):
+    """15 masses (nx = 30, nu = 14), two sampled spring constants, robust
+    horizon nr (2 ** nr scenarios), horizon 12, random linear terms and
+    defects: every output array within 1e-9 of the oracle."""
+    inst = S.mass_spring_tree(M=15, robust_horizon=nr, n_d=2, horizon=12, instance=nr, random_terms=True)
+    print(f"mass-spring nr={nr} N={len(inst.parent)} layout={layout}", flush=True)
+    o = oracle.tree_lqr_inst(inst)
+    g, st, bad = gpu_lqr(inst, layout)
+    assert st == 0, bad
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("name", ["fig1b", "ternary", "random_b"])
+def test_nx30_random_data_matches_oracle(name):
+    """nx = 30, nu = 14 on irregular trees with random dense costs (cross
+    terms M included) and dynamics A = I + 0.1 N(0, 1)."""
+    par = TREES[name]
+    inst = S.lqr_on(par, 30, 14, seed=23, random_cost=True)
+    print(f"nx30 tree={name} N={len(par)}", flush=True)
+    o = oracle.tree_lqr_inst(inst)
+    g, st, bad = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR)
+    assert st == 0, bad
+    assert_parity(g, o)
+
+
+def test_mass_spring_tree_full_size():
+    """The benchmarked mass-spring workload: 1,024 scenarios (robust
+    horizon 10), horizon 40, 32,767 nodes, nx = 30: every output element
+    against the oracle, and bitwise equal over repeated solves."""
+    inst = S.mass_spring_tree()
+    print(f"mass-spring full size N={len(inst.parent)}", flush=True)
+    o = oracle.tree_lqr_inst(inst)
+    runs = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR, repeat=2)
+    for g, st, bad in runs:
+        assert st == 0, bad
+        assert_parity(g, o)
+    for k in runs[0][0]:
+        assert np.array_equal(runs[0][0][k], runs[1][0][k]), k
+
+
+def test_nx30_not_positive_definite_reports_node():
+    par = TREES["fig1b"]
+    inst = S.lqr_on(par, 30, 14, seed=2, random_cost=True)
+    inst.R[5] = -10.0 * np.eye(14)
+    inst.B[7] = 0.0
+    inst.B[8] = 0.0
+    g, st, bad = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR)
+    assert st == 3 and bad == 5

@@ -295,3 +295,85 @@ def test_extended_precision_recursion_solves_the_same_problem_more_accurately():
     rd, re = _tree_qp_kkt_residual(bad, d), _tree_qp_kkt_residual(bad, e)
     print(f"KKT residual: double {rd:.3e}, long double {re:.3e}")
     assert re * 10 <= rd
+
+
+# ----------------------------------------------------------------------------
+# chain of masses and springs (per-scenario dynamics)
+# ----------------------------------------------------------------------------
+
+def test_mass_spring_model_conserves_energy_and_branches_take_their_constant():
+    """The discretised chain (no damping, zero-order hold) keeps the
+    energy 1/2 v^T v - k/2 p^T L p of a free motion (u = 0) to rounding, and
+    each edge of the tree carries the matrices of its branch's spring
+    constant: siblings differ, a chain below a branch repeats its edge."""
+    M, k = 4, 0.8
+    A, B = S.mass_spring_matrices(M, k)
+    Lm = -2.0 * np.eye(M) + np.eye(M, k=1) + np.eye(M, k=-1)
+    W = np.zeros((2 * M, 2 * M))
+    W[:M, :M] = -k * Lm
+    W[M:, M:] = np.eye(M)
+    x = np.random.default_rng(0).standard_normal(2 * M)
+    for _ in range(20):
+        xn = A @ x
+        assert abs(xn @ W @ xn - x @ W @ x) <= 1e-10 * (x @ W @ x)
+        x = xn
+    # an actuator pushes its two masses apart: opposite velocities, equal up
+    # to what the springs transmit within the step; no net momentum at first
+    # order in dt
+    v = (B @ np.eye(M - 1)[0])[M:]
+    assert v[0] < 0 < v[1] and abs(v[0] + v[1]) < 1e-3 * v[1] and np.all(np.abs(v[2:]) < 0.05 * v[1])
+    inst = S.mass_spring_tree(M=3, robust_horizon=2, n_d=2, horizon=5)
+    par = inst.parent
+    nch = S.num_children(par)
+    kids0 = np.nonzero(par == 0)[0]
+    assert len(kids0) == 2 and not np.allclose(inst.A[kids0[0]], inst.A[kids0[1]])
+    for j in range(1, len(par)):
+        p = par[j]
+        if p > 0 and nch[p] == 1:
+            np.testing.assert_array_equal(inst.A[j], inst.A[p])
+
+
+@pytest.mark.parametrize("nr", [1, 2])
+def test_mass_spring_tree_lqr_matches_dense_kkt(nr):
+    """The oracle's tree Riccati on small mass-spring trees (per-edge
+    dynamics, random linear terms and defects) against a dense solve of the
+    equality-constrained QP."""
+    inst = S.mass_spring_tree(M=3, robust_horizon=nr, n_d=2, horizon=6, random_terms=True)
+    o = oracle.tree_lqr_inst(inst)
+    x, u = _dense(inst)
+    assert np.abs(o["x"] - x).max() <= 1e-10 * max(1.0, np.abs(x).max())
+    assert np.abs(o["u"] - u).max() <= 1e-10 * max(1.0, np.abs(u).max())
+
+
+def _dense(inst):
+    out = dense_tree_qp(inst.parent, inst.A, inst.B, inst.c, inst.Q, inst.R, inst.M, inst.q, inst.r, inst.x0)
+    return out[0], out[1]
+
+
+def test_mass_spring_identical_constants_make_every_scenario_the_chain():
+    """With all n_d spring constants equal, the branches of the tree are
+    copies: the tree LQR's inputs along every path equal those of the
+    single chain whose costs after the branching carry the number of
+    copies as weight (duplicate branches = chain with summed weights)."""
+    inst = S.mass_spring_tree(M=3, robust_horizon=2, n_d=2, horizon=6)
+    A, B = S.mass_spring_matrices(3, 1.0)
+    N = len(inst.parent)
+    nch = S.num_children(inst.parent)
+    for j in range(1, N):
+        inst.A[j], inst.B[j] = A, B
+    o = oracle.tree_lqr_inst(inst)
+    # the chain: stage t carries the number of tree nodes at stage t
+    stages = S.stages_of(inst.parent)
+    H = stages.max()
+    chain = S.tree_parent(H, [], 1)
+    cnt = np.array([np.sum(stages == t) for t in range(H + 1)], dtype=float)
+    ci = S.LqrInstance(parent=chain, A=np.array([A] * (H + 1)), B=np.array([B] * (H + 1)),
+                       c=np.zeros((H + 1, 6)), Q=np.array([np.eye(6) * cnt[t] for t in range(H + 1)]),
+                       R=np.array([np.eye(2) * cnt[t] for t in range(H + 1)]), M=np.zeros((H + 1, 2, 6)),
+                       q=np.zeros((H + 1, 6)), r=np.zeros((H + 1, 2)), x0=inst.x0)
+    ci.R[H] = 0.0
+    oc = oracle.tree_lqr_inst(ci)
+    for n in range(N):
+        np.testing.assert_allclose(o["x"][n], oc["x"][stages[n]], rtol=1e-10, atol=1e-12)
+        if nch[n] > 0:
+            np.testing.assert_allclose(o["u"][n], oc["u"][stages[n]], rtol=1e-10, atol=1e-12)
