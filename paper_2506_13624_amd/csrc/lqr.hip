@@ -820,23 +820,40 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
 // ------------------------------------------------------------------------
 __host__ __device__ constexpr int pad16(int v) { return (v + 15) / 16 * 16; }
 
+// Value of v in lane src of the wavefront (scalar reads of both halves;
+// they read the register whether or not lane src is active)
+__device__ __forceinline__ double lane_value(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Workgroup barrier that waits for this wavefront's LDS operations only, so
+// that global loads in flight (the next node's inputs) stay in flight
+// across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 template <int NX, int NU, int LAY>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_bwd_mfma(TreeDev t, LqrArgs a, int* arrive)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_bwd_mfma(TreeDev t, LqrArgs a, int* arrive)
 {
     constexpr int NZ = NX + NU, NC = NZ + 1;
     constexpr int NXP = pad16(NX), NCP = pad16(NC), NZP = pad16(NZ);
-    constexpr int TS = (NXP / 16) * (NCP / 16);   // tiles of S
-    constexpr int TZ = (NZP / 16) * (NCP / 16);   // tiles of Z
     constexpr int KS = NXP / 4;                   // k steps of both products
-    __shared__ __align__(16) double sD[NX][NCP];  // [A B c 0 ..] of the child edge
-    __shared__ __align__(16) double sP[NX][NXP];  // the child's P (columns >= NX unused)
+    constexpr int NG = NX + 1;                    // columns of [G g]
+    constexpr int NT = NU + NG;                   // columns of [H G g]
+    constexpr int CW = NC + 1;                    // row pitch of D and Z
+    static_assert(NXP == 32 && NCP / 16 <= 4, "two row tiles of S per column block, one wavefront per block");
+    __shared__ __align__(16) double sD[NX][CW];   // [A B c] of the child edge
+    __shared__ __align__(16) double sP[NX][NX + 1];  // the child's P (odd pitch: its columns are read across lanes)
     __shared__ __align__(16) double sp[NXP];
-    __shared__ __align__(16) double sS[NX][NCP];
-    __shared__ __align__(16) double sZ[NZ][NCP];
-    __shared__ __align__(16) double sG[NU][NX + 1];  // L^-1 [G g]
-    __shared__ __align__(16) double sL[NU][NU + 1];
-    __shared__ double sInv[NU];
-    __shared__ int sgo, sok;
+    __shared__ __align__(16) double sZ[NZ][CW];
+    __shared__ __align__(16) double sG[NU][NG];   // L^-1 [G g]
+    __shared__ int sgo;
 
     // thread indices are re-derived through an opaque copy at every step of
     // the walk, so that the compiler recomputes the many per-lane LDS
@@ -856,170 +873,243 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     const int N = t.N;
     int n = t.leaves[blockIdx.x];
 
-    #pragma unroll 1
 
-    for (int e = tid; e < NX * NCP; e += 256)
-        if (e % NCP >= NC) sD[e / NCP][e % NCP] = 0.0;
-
-    // stage data of node m into Z: [[Q M^T q],[M R r]]
+    // Every thread's share of a block of elements is requested at once and
+    // stored to LDS afterwards, so that a thread has all its loads in flight
+    // together instead of one after the other.
+    // stage data of node m into Z: [[Q M^T q],[M R r]], element e of the
+    // node's Q (NX x NX), M (NU x NX), q, R (NU x NU), r in that order, so
+    // that the lanes of a wavefront read consecutive entries of one array
+    constexpr int SE = NX * NX + NU * NX + NX + NU * NU + NU;
+    auto stage_get = [&](int m, int e) -> double {
+        if (e < NX * NX) return a.Q[lidx<LAY>(m, e, NX * NX, N)];
+        e -= NX * NX;
+        if (e < NU * NX) return a.M[lidx<LAY>(m, e, NU * NX, N)];
+        e -= NU * NX;
+        if (e < NX) return a.q[lidx<LAY>(m, e, NX, N)];
+        e -= NX;
+        if (e < NU * NU) return a.R[lidx<LAY>(m, e, NU * NU, N)];
+        return a.r[lidx<LAY>(m, e - NU * NU, NU, N)];
+    };
+    auto stage_put = [&](int e, double v) {
+        if (e < NX * NX) {
+            sZ[e / NX][e % NX] = v;
+            return;
+        }
+        e -= NX * NX;
+        if (e < NU * NX) {
+            const int i = e / NX, j = e % NX;
+            sZ[NX + i][j] = v;
+            sZ[j][NX + i] = v;
+            return;
+        }
+        e -= NU * NX;
+        if (e < NX) {
+            sZ[e][NZ] = v;
+            return;
+        }
+        e -= NX;
+        if (e < NU * NU) {
+            sZ[NX + e / NU][NX + e % NU] = v;
+            return;
+        }
+        sZ[NX + e - NU * NU][NZ] = v;
+    };
+    // edge into node j: A (NX x NX), B (NX x NU), c into D = [A B c]
+    constexpr int EE = NX * NX + NX * NU + NX;
+    auto edge_get = [&](int j, int e) -> double {
+        if (e < NX * NX) return a.A[lidx<LAY>(j, e, NX * NX, N)];
+        e -= NX * NX;
+        if (e < NX * NU) return a.B[lidx<LAY>(j, e, NX * NU, N)];
+        return a.c[lidx<LAY>(j, e - NX * NU, NX, N)];
+    };
+    auto edge_put = [&](int e, double v) {
+        if (e < NX * NX) {
+            sD[e / NX][e % NX] = v;
+            return;
+        }
+        e -= NX * NX;
+        if (e < NX * NU) {
+            sD[e / NU][NX + e % NU] = v;
+            return;
+        }
+        sD[e - NX * NU][NZ] = v;
+    };
+    // every thread's share is requested at once, then stored
+    constexpr int CNT_S = (SE + 255) / 256, CNT_E = (EE + 255) / 256;
     auto load_stage = [&](int m) {
-        #pragma unroll 1
-        for (int e = tid; e < NZ * NC; e += 256) {
-            const int i = e / NC, j = e % NC;
-            double v;
-            if (i < NX) {
-                if (j < NX) v = a.Q[lidx<LAY>(m, i * NX + j, NX * NX, N)];
-                else if (j < NZ) v = a.M[lidx<LAY>(m, (j - NX) * NX + i, NU * NX, N)];
-                else v = a.q[lidx<LAY>(m, i, NX, N)];
-            } else {
-                const int ii = i - NX;
-                if (j < NX) v = a.M[lidx<LAY>(m, ii * NX + j, NU * NX, N)];
-                else if (j < NZ) v = a.R[lidx<LAY>(m, ii * NU + j - NX, NU * NU, N)];
-                else v = a.r[lidx<LAY>(m, ii, NU, N)];
-            }
-            sZ[i][j] = v;
+        double v[CNT_S];
+#pragma unroll
+        for (int it = 0; it < CNT_S; ++it) {
+            const int e = tid + 256 * it;
+            v[it] = e < SE ? stage_get(m, e) : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < CNT_S; ++it) {
+            const int e = tid + 256 * it;
+            if (e < SE) stage_put(e, v[it]);
         }
     };
-    // edge into node j: [A B c] into D
     auto load_edge = [&](int j) {
-        #pragma unroll 1
-        for (int e = tid; e < NX * NC; e += 256) {
-            const int i = e / NC, col = e % NC;
-            double v;
-            if (col < NX) v = a.A[lidx<LAY>(j, i * NX + col, NX * NX, N)];
-            else if (col < NZ) v = a.B[lidx<LAY>(j, i * NU + col - NX, NX * NU, N)];
-            else v = a.c[lidx<LAY>(j, i, NX, N)];
-            sD[i][col] = v;
+        double v[CNT_E];
+#pragma unroll
+        for (int it = 0; it < CNT_E; ++it) {
+            const int e = tid + 256 * it;
+            v[it] = e < EE ? edge_get(j, e) : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < CNT_E; ++it) {
+            const int e = tid + 256 * it;
+            if (e < EE) edge_put(e, v[it]);
         }
     };
     // value function of child j, written by another workgroup
     auto load_value = [&](int j) {
-        #pragma unroll 1
-        for (int e = tid; e < NX * NX; e += 256)
-            sP[e / NX][e % NX] = ld_shared_dev(&a.P[lidx<LAY>(j, e, NX * NX, N)]);
-        #pragma unroll 1
-        for (int e = tid; e < NX; e += 256) sp[e] = ld_shared_dev(&a.p[lidx<LAY>(j, e, NX, N)]);
+        constexpr int CNT = (NX * NX + NX + 255) / 256;
+        double v[CNT];
+#pragma unroll
+        for (int it = 0; it < CNT; ++it) {
+            const int e = tid + 256 * it;
+            v[it] = e < NX * NX ? ld_shared_dev(&a.P[lidx<LAY>(j, e, NX * NX, N)])
+                  : (e < NX * NX + NX ? ld_shared_dev(&a.p[lidx<LAY>(j, e - NX * NX, NX, N)]) : 0.0);
+        }
+#pragma unroll
+        for (int it = 0; it < CNT; ++it) {
+            const int e = tid + 256 * it;
+            if (e < NX * NX) sP[e / NX][e % NX] = v[it];
+            else if (e < NX * NX + NX) sp[e - NX * NX] = v[it];
+        }
     };
+    // Per child: wavefront w < NCP / 16 takes column block w (16 columns) of
+    // S and of Z.  It computes both row tiles of S = P [A B c] + [0 0 p] for
+    // its block and keeps them in the accumulator registers, whose layout
+    // (lane l, element v: row l / 16 + 4 v) is the B-operand layout of the
+    // k-blocks of Z += [A B]^T S, so S never goes through LDS.
     auto add_child = [&]() {
-        __syncthreads();
-        #pragma unroll 1
-        for (int tt = wave; tt < TS; tt += 4) {
-            const int ti = tt / (NCP / 16), tj = tt % (NCP / 16);
-            const int row = 16 * ti + li, col = 16 * tj + li;
-            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        lds_barrier();
+        if (wave < NCP / 16) {
+            const int col = 16 * wave + li;
+            const bool cin = col < NC;
+            f64x4 s0 = {0.0, 0.0, 0.0, 0.0}, s1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 const int k = 4 * ks + lk;
-                const double av = (row < NX && k < NX) ? sP[row][k] : 0.0;
-                const double bv = k < NX ? sD[k][col] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                const double bv = (k < NX && cin) ? sD[k][col] : 0.0;
+                const double a0 = (li < NX && k < NX) ? sP[li][k] : 0.0;
+                const double a1 = (16 + li < NX && k < NX) ? sP[16 + li][k] : 0.0;
+                s0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, s0, 0, 0, 0);
+                s1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, s1, 0, 0, 0);
+            }
+            if (col == NZ) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    s0[v] += sp[lk + 4 * v];
+                    if (16 + lk + 4 * v < NX) s1[v] += sp[16 + lk + 4 * v];
+                }
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 16 * ti + lk + 4 * v;
-                if (r < NX) sS[r][col] = col == NZ ? acc[v] + sp[r] : acc[v];
+            for (int ti = 0; ti < NZP / 16; ++ti) {
+                const int rowa = 16 * ti + li;
+                f64x4 acc;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * ti + lk + 4 * v;
+                    acc[v] = (r < NZ && cin) ? sZ[r][col] : 0.0;
+                }
+#pragma unroll
+                for (int kb = 0; kb < KS; ++kb) {
+                    const int k = 4 * kb + lk;
+                    const double av = (k < NX && rowa < NC) ? sD[k][rowa] : 0.0;
+                    const double bv = kb < 4 ? s0[kb & 3] : s1[kb & 3];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * ti + lk + 4 * v;
+                    if (r < NZ && cin) sZ[r][col] = acc[v];
+                }
             }
         }
-        __syncthreads();
-        #pragma unroll 1
-        for (int tt = wave; tt < TZ; tt += 4) {
-            const int ti = tt / (NCP / 16), tj = tt % (NCP / 16);
-            const int rowa = 16 * ti + li, col = 16 * tj + li;
-            f64x4 acc;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 16 * ti + lk + 4 * v;
-                acc[v] = r < NZ ? sZ[r][col] : 0.0;
-            }
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int k = 4 * ks + lk;
-                const double av = (k < NX && rowa < NCP) ? sD[k][rowa] : 0.0;
-                const double bv = k < NX ? sS[k][col] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 16 * ti + lk + 4 * v;
-                if (r < NZ) sZ[r][col] = acc[v];
-            }
-        }
-        __syncthreads();
+        lds_barrier();
     };
-    // gains and value function of node m from the accumulated Z
+    // Gains and value function of node m from the accumulated Z, by one
+    // wavefront without barriers: lane c holds column c of T = [H G g]
+    // (NU x NT) in registers and the lanes run the right-looking Cholesky
+    // factorisation of H with the columns of [G g] carried along; the pivot
+    // and the column of step j come from lane j by scalar reads.  Afterwards
+    // lane c < NU holds row c of L and lane NU + c column c of
+    // Gh = L^-1 [G g]; the latter solve L^T X = Gh for their column (X =
+    // -[K k]) with the entries of L read from the lanes that hold them.
+    // Then all threads form P = (W + W^T)/2 - Gh^T Gh and p = w - Gh^T gh.
     auto finish = [&](int m, bool shared_out) {
         if (wave == 0) {
-            // H = L L^T, right-looking, by one wavefront
-            #pragma unroll 1
-            for (int e = lane; e < NU * NU; e += 64) sL[e / NU][e % NU] = sZ[NX + e / NU][NX + e % NU];
+            const int c = lane;
+            double col[NU];
+#pragma unroll
+            for (int r = 0; r < NU; ++r)
+                col[r] = c < NU ? sZ[NX + r][NX + c]
+                       : (c < NT ? sZ[NX + r][c - NU < NX ? c - NU : NZ] : 0.0);
+            double inv[NU];
             bool ok = true;
-#pragma unroll 1
+#pragma unroll
             for (int j = 0; j < NU; ++j) {
-                wave_sync();
-                const double d = sL[j][j];
+                const double d = lane_value(col[j], j);
                 ok = ok && d > 0.0;
-                const double y = rsqrt_refined(d > 0.0 ? d : 1.0);
-                if (lane == 0) {
-                    sL[j][j] = (d > 0.0 ? d : 1.0) * y;
-                    sInv[j] = y;
+                const double dd = d > 0.0 ? d : 1.0;
+                const double y = rsqrt_refined(dd);
+                inv[j] = y;
+                const double tjc = col[j] * y;  // row j of L^T / of Gh in lane c > j
+#pragma unroll
+                for (int r = j + 1; r < NU; ++r) {
+                    const double lrj = lane_value(col[r], j) * y;  // L[r][j], from lane j
+                    if (c > j) col[r] -= lrj * tjc;
                 }
-                if (lane > j && lane < NU) sL[lane][j] *= y;
-                wave_sync();
-                #pragma unroll 1
-                for (int e = lane; e < NU * NU; e += 64) {
-                    const int r = e / NU, c = e % NU;
-                    if (c > j && r >= c) sL[r][c] -= sL[r][j] * sL[c][j];
-                }
+                col[j] = c == j ? dd * y : (c > j ? tjc : col[j]);
             }
-            wave_sync();
-            if (lane == 0) sok = ok ? 1 : 0;
-            // lane c takes column c of [G g]: Gh = L^-1 [G g] into sG, then
-            // [K k] = -L^-T Gh (the column's unknowns in sS, free after the
-            // products); each lane reads back only its own column
-            if (lane <= NX) {
-                const int col = lane < NX ? lane : NZ;
-#pragma unroll 1
-                for (int i = 0; i < NU; ++i) {
-                    double s = sZ[NX + i][col];
-                    for (int k = 0; k < i; ++k) s -= sL[i][k] * sG[k][lane];
-                    sG[i][lane] = s * sInv[i];
+            if (lane == 0 && !ok) atomicMin(a.bad, m);
+            if (c >= NU && c < NT) {
+                const int g = c - NU;  // column of [G g]
+#pragma unroll
+                for (int r = 0; r < NU; ++r) sG[r][g] = col[r];
+                // L^T x = gh column: L[k][j] is entry j of lane k's registers
+                double x[NU];
+#pragma unroll
+                for (int j = NU - 1; j >= 0; --j) {
+                    double s = col[j];
+#pragma unroll
+                    for (int k = j + 1; k < NU; ++k) s -= lane_value(col[j], k) * x[k];
+                    x[j] = s * inv[j];
                 }
-#pragma unroll 1
-                for (int i = NU - 1; i >= 0; --i) {
-                    double s = sG[i][lane];
-                    for (int k = i + 1; k < NU; ++k) s -= sL[k][i] * sS[k][lane];
-                    s *= sInv[i];
-                    sS[i][lane] = s;
-                    if (lane < NX) a.K[lidx<LAY>(m, i * NX + lane, NU * NX, N)] = -s;
-                    else a.k[lidx<LAY>(m, i, NU, N)] = -s;
+#pragma unroll
+                for (int r = 0; r < NU; ++r) {
+                    if (g < NX) a.K[lidx<LAY>(m, r * NX + g, NU * NX, N)] = -x[r];
+                    else a.k[lidx<LAY>(m, r, NU, N)] = -x[r];
                 }
             }
         }
-        __syncthreads();
-        if (tid == 0 && !sok) atomicMin(a.bad, m);
-        // (the child's P in sP was last read by the products)
-        #pragma unroll 1
+        lds_barrier();
+        // P and p from Gh (the child's P in sP was last read by the products)
+#pragma unroll 1
         for (int e = tid; e < NX * NX; e += 256) {
             const int i = e / NX, j = e % NX;
             double s = 0.0;
 #pragma unroll
             for (int r = 0; r < NU; ++r) s = fma(sG[r][i], sG[r][j], s);
-            const double v = 0.5 * (sZ[i][j] + sZ[j][i]) - s;
-            sP[i][j] = v;
-            if (shared_out) st_shared_dev(&a.P[lidx<LAY>(m, e, NX * NX, N)], v);
-            else a.P[lidx<LAY>(m, e, NX * NX, N)] = v;
+            const double pv = 0.5 * (sZ[i][j] + sZ[j][i]) - s;
+            sP[i][j] = pv;
+            if (shared_out) st_shared_dev(&a.P[lidx<LAY>(m, e, NX * NX, N)], pv);
+            else a.P[lidx<LAY>(m, e, NX * NX, N)] = pv;
         }
-        #pragma unroll 1
-        for (int i = tid; i < NX; i += 256) {
+        if (tid < NX) {
             double s = 0.0;
 #pragma unroll
-            for (int r = 0; r < NU; ++r) s = fma(sG[r][i], sG[r][NX], s);
-            const double v = sZ[i][NZ] - s;
-            sp[i] = v;
-            if (shared_out) st_shared_dev(&a.p[lidx<LAY>(m, i, NX, N)], v);
-            else a.p[lidx<LAY>(m, i, NX, N)] = v;
+            for (int r = 0; r < NU; ++r) s = fma(sG[r][tid], sG[r][NX], s);
+            const double pv = sZ[tid][NZ] - s;
+            sp[tid] = pv;
+            if (shared_out) st_shared_dev(&a.p[lidx<LAY>(m, tid, NX, N)], pv);
+            else a.p[lidx<LAY>(m, tid, NX, N)] = pv;
         }
-        __syncthreads();
+        lds_barrier();
     };
 
     // the leaf: P = Q_f, p = q_f, no gains
@@ -1063,15 +1153,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         n = par;
         const int4 pinf = t.info[n];
         const bool shared_out = pinf.w > 1;
-        __syncthreads();
-        load_stage(n);
+        lds_barrier();
         if (nsib == 1) {
             // the only child's value function is still in sP, sp
+            load_stage(n);
             load_edge(child);
             add_child();
         } else {
+            load_stage(n);
             for (int j = pinf.x; j < pinf.y; ++j) {
-                __syncthreads();
+                lds_barrier();
                 load_edge(j);
                 load_value(j);
                 add_child();
