@@ -700,6 +700,62 @@ def run_solver_profile(args, torch, L):
     return {"solver_profile": out}
 
 
+def run_mass_spring(args, torch, L):
+    """Tree LQR of the mass-spring chain (15 masses: nx = 30, nu = 14), two
+    sampled spring constants, robust horizon 10 (1,024 scenarios), horizon
+    40: 32,767 nodes, FP64, node-major, inputs resident in HBM."""
+    import bmpc_synth as S
+    from paper_2506_13624_amd.layout import empty, to_device
+    inst = S.mass_spring_tree()
+    par = inst.parent
+    N = len(par)
+    nx, nu = inst.nx, inst.nu
+    tree = L.bmpc_tree_create(par)
+    plan = L.bmpc_lqr_plan_create(tree, nx, nu, L.LAYOUT_NODE_MAJOR)
+    d = {k: to_device(getattr(inst, k), L.LAYOUT_NODE_MAJOR) for k in "ABcQRMqr"}
+    x0 = to_device(inst.x0, L.LAYOUT_NODE_MAJOR)
+    outs = [empty((N, nx)), empty((N, nu)), empty((N, nx)), empty((N, nu, nx)), empty((N, nu)), empty((N, nx, nx)),
+            empty((N, nx))]
+
+    def step():
+        L.bmpc_lqr_solve(plan, d["A"], d["B"], d["c"], d["Q"], d["R"], d["M"], d["q"], d["r"], x0, *outs)
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    st, bad = L.bmpc_lqr_check(plan)
+    if st != 0:
+        raise RuntimeError(f"mass-spring LQR failed (status {st}, node {bad})")
+    steps = max(20, args.steps // 10)
+    L.bmpc_profile_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    prof = L.bmpc_profile_read()
+    L.bmpc_profile_enable(False)
+    ms = ev0.elapsed_time(ev1) / steps
+    L.bmpc_lqr_plan_destroy(plan)
+    L.bmpc_tree_destroy(tree)
+    kern = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]} for k, v in prof.items()}
+    bwd_us = kern["lqr_backward_level_mfma"]["avg_us"]
+    reads, solve_bytes = lqr_solve_algorithmic_bytes(par, nx, nu)
+    alg = lqr_algorithmic(par, nx, nu)
+    tflops = alg["bwd_flops"] / (bwd_us * 1e-6) / 1e12
+    return {"mass_spring_tree": {
+        "workload": "mass-spring chain tree LQR: 15 masses (nx=30, nu=14), 2 sampled spring constants, robust "
+                    f"horizon 10 (1024 scenarios), horizon 40, {N} nodes, FP64",
+        "ms_per_solve": round(ms, 4), "nodes_per_s": round(N / (ms * 1e-3), 1), "kernels": kern,
+        "backward_algorithmic_bytes": reads, "backward_flops": alg["bwd_flops"],
+        "backward_GBps": round(reads / (bwd_us * 1e-6) / 1e9, 2),
+        "backward_fp64_tflops": round(tflops, 3),
+        "roofline_backward": {"bound": "mfma", "achieved": round(tflops, 3), "peak": FP64_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 5),
+                              "hbm_frac": round(reads / (bwd_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)},
+    }}
+
+
 def run_large_tree(args, torch, L):
     """Tree LQR on the 4096-scenario bicycle tree (122,871 nodes): the Gauss-
     Newton LQR subproblem at the cold start, level-parallel vs segment-scan
@@ -817,6 +873,8 @@ def main():
                     help="skip the independent solves on several streams (for per-kernel profiles)")
     ap.add_argument("--only-solver", choices=("single", "batched"), default=None,
                     help="only the branch-MPC solver on one workload, printed on its own (for profiles)")
+    ap.add_argument("--only-mass-spring", action="store_true",
+                    help="only the mass-spring tree LQR, printed on its own (for profiles)")
     ap.add_argument("--only-large", action="store_true",
                     help="only the 4096-scenario tree section, printed on its own (for counter runs)")
     ap.add_argument("--ws-train", type=int, default=200000, help="training instances of the learned warm start")
@@ -846,6 +904,17 @@ def main():
         print(json.dumps(run_solver_profile(args, torch, L)), flush=True)
         return
 
+    if args.only_mass_spring:
+        if args.calib_copy:
+            nbytes = 512 * 2 ** 20
+            src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            del src
+        progress("mass-spring tree LQR")
+        print(json.dumps(run_mass_spring(args, torch, L)), flush=True)
+        return
+
     if args.only_large:
         if args.calib_copy:
             nbytes = 512 * 2 ** 20
@@ -868,6 +937,8 @@ def main():
     if not args.skip_bmpc and not args.skip_large:
         progress("large tree")
         out.update(run_large_tree(args, torch, L))
+    progress("mass-spring tree LQR")
+    out.update(run_mass_spring(args, torch, L))
     if not args.no_cpu_baseline:
         progress("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline_lqr(inst, args.cpu_budget)

@@ -935,6 +935,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         }
         sD[e - NX * NU][NZ] = v;
     };
+    // Loaders of the elements [e0, e1) of the stage or edge data by NT_
+    // threads (rank t): every thread's share is requested at once, then
+    // stored.  Stage elements: Q [0, QE), M [QE, ME), q [ME, RE0), R and r
+    // [RE0, SE); the "upper" part (Q, q) is what the value function's
+    // formation still reads from Z.
+    constexpr int QE = NX * NX, ME = QE + NU * NX, RE0 = ME + NX;
+    auto load_part = [&](auto get, auto put, int node, int e0, int e1, auto ntc, int t) {
+        constexpr int NT_ = decltype(ntc)::value;
+        constexpr int CNT = (SE + NT_ - 1) / NT_;
+        double v[CNT];
+#pragma unroll
+        for (int it = 0; it < CNT; ++it) {
+            const int e = e0 + t + NT_ * it;
+            v[it] = e < e1 ? get(node, e) : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < CNT; ++it) {
+            const int e = e0 + t + NT_ * it;
+            if (e < e1) put(e, v[it]);
+        }
+    };
     // every thread's share is requested at once, then stored
     constexpr int CNT_S = (SE + 255) / 256, CNT_E = (EE + 255) / 256;
     auto load_stage = [&](int m) {
@@ -1041,14 +1062,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     // Gh = L^-1 [G g]; the latter solve L^T X = Gh for their column (X =
     // -[K k]) with the entries of L read from the lanes that hold them.
     // Then all threads form P = (W + W^T)/2 - Gh^T Gh and p = w - Gh^T gh.
-    auto finish = [&](int m, bool shared_out) {
+    // next_stage >= 0: the next step is a chain step (node next_stage, edge
+    // into m); while wavefront 0 computes the gains, the other three load
+    // its edge into D and the parts of its stage data that the formation
+    // of P no longer reads (M, R, r) into Z.
+    auto finish = [&](int m, bool shared_out, int next_stage) {
+        double col[NU];
         if (wave == 0) {
             const int c = lane;
-            double col[NU];
 #pragma unroll
             for (int r = 0; r < NU; ++r)
                 col[r] = c < NU ? sZ[NX + r][NX + c]
                        : (c < NT ? sZ[NX + r][c - NU < NX ? c - NU : NZ] : 0.0);
+        }
+        // rows NX.. of Z and all of D are free from here on
+        lds_barrier();
+        if (wave == 0) {
+            const int c = lane;
             double inv[NU];
             bool ok = true;
 #pragma unroll
@@ -1086,6 +1116,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                     else a.k[lidx<LAY>(m, r, NU, N)] = -x[r];
                 }
             }
+        } else if (next_stage >= 0) {
+            const int t3 = tid - 64;
+            load_part(edge_get, edge_put, m, 0, EE, std::integral_constant<int, 192>{}, t3);
+            load_part(stage_get, stage_put, next_stage, QE, ME, std::integral_constant<int, 192>{}, t3);
+            load_part(stage_get, stage_put, next_stage, RE0, SE, std::integral_constant<int, 192>{}, t3);
         }
         lds_barrier();
         // P and p from Gh (the child's P in sP was last read by the products)
@@ -1135,6 +1170,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         #pragma unroll 1
         for (int e = tid; e < NU; e += 256) a.k[lidx<LAY>(n, e, NU, N)] = 0.0;
     }
+    bool have_next = false;
     for (;;) {
         refresh_ids();
         const int4 inf = t.info[n];
@@ -1156,8 +1192,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         lds_barrier();
         if (nsib == 1) {
             // the only child's value function is still in sP, sp
-            load_stage(n);
-            load_edge(child);
+            if (have_next) {
+                // edge and lower stage data were loaded during the last step
+                load_part(stage_get, stage_put, n, 0, QE, std::integral_constant<int, 256>{}, tid);
+                load_part(stage_get, stage_put, n, ME, RE0, std::integral_constant<int, 256>{}, tid);
+            } else {
+                load_stage(n);
+                load_edge(child);
+            }
             add_child();
         } else {
             load_stage(n);
@@ -1168,7 +1210,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                 add_child();
             }
         }
-        finish(n, shared_out);
+        // the next step is a chain step: n is its parent's only child
+        have_next = pinf.z >= 0 && pinf.w == 1;
+        finish(n, shared_out, have_next ? pinf.z : -1);
     }
 }
 
