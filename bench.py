@@ -812,6 +812,47 @@ def run_large_tree(args, torch, L):
                      "backward_fp64_frac": round(alg["bwd_flops"] / (bwd_us * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 6),
                      "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]}
                                  for k, v in prof.items()}}
+    # the same subproblem in FP32, and in mixed precision (FP32 sweeps, FP64
+    # residuals, refinement steps added until the FP64 residual floor)
+    L.bmpc_lqr_solve(plan, Ae, Be, c, Q, R, M, q, r, x0, *outs, variant=L.RICCATI_LEVEL)
+    ref = [o.clone() for o in outs[:3]]
+    f32_in = [t.float() for t in (Ae, Be, c, Q, R, M, q, r, x0)]
+    f32_out = [o.float() for o in outs]
+
+    def timed(fn, kernels):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        L.bmpc_profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        prof = L.bmpc_profile_read()
+        L.bmpc_profile_enable(False)
+        return e0.elapsed_time(e1) / steps * 1e3, {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]}
+                                                  for k, v in prof.items() if k in kernels}
+
+    fp32_k = ("lqr_backward_level_lane_f32", "lqr_forward_paths_f32", "lqr_costate_f32")
+    us32, k32 = timed(lambda: L.bmpc_lqr_solve_f32(plan, *f32_in, *f32_out), fp32_k)
+    rel = lambda a, b: float((a.double() - b).abs().max() / b.abs().max())
+    mixed = {"fp32_solve_us": round(us32, 2), "fp32_kernels": k32,
+             "fp32_rel_error_x": rel(f32_out[0], ref[0]), "refinement": {}}
+    for rs in (1, 2, 3):
+        # timed without the residual norms (a diagnostic), which are then
+        # read from one more call
+        norms = torch.zeros(rs + 2, dtype=torch.float64, device="cuda")
+        mo = [torch.zeros_like(o) for o in outs[:3]]
+        usm, km = timed(lambda: L.bmpc_lqr_solve_mixed(plan, Ae, Be, c, Q, R, M, q, r, x0, *mo, rs),
+                        fp32_k + ("lqr_residual_f64", "lqr_refine_update", "lqr_matrices_to_f32"))
+        L.bmpc_lqr_solve_mixed(plan, Ae, Be, c, Q, R, M, q, r, x0, *mo, rs, norms)
+        mixed["refinement"][f"{rs}_steps"] = {
+            "solve_us": round(usm, 2), "residual_norms": [float(v) for v in norms.cpu()],
+            "rel_diff_to_fp64_solve": {k: rel(a, b) for k, a, b in zip(("x", "u", "lam"), mo, ref)},
+            "kernels": km}
+    res["mixed_precision"] = mixed
     L.bmpc_lqr_plan_destroy(plan)
     L.bmpc_tree_destroy(tree)
     # AL iterations on this tree (a single large problem: the whole grid);

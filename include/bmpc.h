@@ -151,6 +151,39 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* plan, const double* A, const 
                                     const double* x0, double* x, double* u, double* lam,
                                     double* K, double* k, double* P, double* p, int32_t variant,
                                     void* stream);
+/* The same solve in FP32 (the single-precision variant of the recursion,
+   Sec. V-A): float arrays of the sizes and layout above.  Compiled for the
+   dimensions whose FP64 solve uses one lane per node (nx <= 6); others
+   return BMPC_ERR_UNSUPPORTED.  The first FP32 or mixed-precision call on a
+   plan allocates the plan's FP32 workspace (so it cannot be captured in a
+   graph); later calls allocate nothing.  Positive definiteness is reported
+   by bmpc_lqr_check as for the FP64 solve. */
+BMPC_API bmpc_status bmpc_lqr_solve_f32(bmpc_lqr_plan* plan, const float* A, const float* B, const float* c,
+                                        const float* Q, const float* R, const float* M, const float* q,
+                                        const float* r, const float* x0, float* x, float* u, float* lam, float* K,
+                                        float* k, float* P, float* p, void* stream);
+
+#define BMPC_LQR_REFINE_MAX 64
+/* Mixed precision: the FP64 problem of bmpc_lqr_solve (same arrays, sizes
+   and layout) solved by FP32 Riccati sweeps with FP64 iterative refinement.
+   The matrices are rounded to FP32 once; then 1 + refine_steps FP32 solves
+   each take as linear terms the FP64 KKT residual of the current FP64
+   iterate (x, u, lam) -- stationarity in u and x and the dynamics defects,
+   with the convention of the costates above -- and add their solution to
+   it.  Each step shrinks the error by about cond * 2^-24, so a few steps
+   reach FP64 accuracy on well-conditioned trees; ill-conditioned ones
+   converge slowly or not at all, which res_norms shows.
+   refine_steps: 0 .. BMPC_LQR_REFINE_MAX.
+   res_norms: DEVICE array of refine_steps + 2 doubles, or NULL; entry i is
+   the largest |KKT residual row| after i FP32 solves (entry 0: of the data,
+   i.e. at x = u = lam = 0).  Asynchronous on `stream`; bmpc_lqr_check
+   reports the positive-definiteness status of the last FP32 solve.
+   Returns BMPC_ERR_UNSUPPORTED where bmpc_lqr_solve_f32 does. */
+BMPC_API bmpc_status bmpc_lqr_solve_mixed(bmpc_lqr_plan* plan, const double* A, const double* B, const double* c,
+                                          const double* Q, const double* R, const double* M, const double* q,
+                                          const double* r, const double* x0, double* x, double* u, double* lam,
+                                          int32_t refine_steps, double* res_norms, void* stream);
+
 /* Synchronises `stream` and reports the numerical status of the last solve
    on this plan: BMPC_OK, or BMPC_ERR_NOT_PD with *bad_node set (smallest
    failing node id).  bad_node may be NULL. */

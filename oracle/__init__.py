@@ -110,6 +110,8 @@ def _declare(L):
     L.orc_tree_lqr.argtypes = [C.c_int, C.c_int, C.c_int, _ip] + [_dp] * 9 + [_dp] * 7 + [_ip]
     L.orc_tree_lqr_ld.restype = C.c_int
     L.orc_tree_lqr_ld.argtypes = [C.c_int, C.c_int, C.c_int, _ip] + [_dp] * 9 + [_dp] * 7 + [_ip]
+    L.orc_tree_lqr_f.restype = C.c_int
+    L.orc_tree_lqr_f.argtypes = [C.c_int, C.c_int, C.c_int, _ip] + [_dp] * 9 + [_dp] * 7 + [_ip]
     L.orc_settings_default.argtypes = [C.POINTER(Settings)]
     L.orc_bmpc_solve.restype = C.c_int
     L.orc_bmpc_solve.argtypes = [C.POINTER(Problem), C.POINTER(Settings), C.c_int, _dp, _dp,
@@ -166,10 +168,11 @@ def _f64(a, shape=None):
 # tree LQR
 # ----------------------------------------------------------------------------
 
-def tree_lqr(parent, A, B, c, Q, R, M, q, r, x0, extended=False):
+def tree_lqr(parent, A, B, c, Q, R, M, q, r, x0, extended=False, single=False):
     """Serial tree Riccati (node-major arrays).  Returns a dict with x, u, lam,
     K, k, P, p; raises on a non-OK status.  extended=True carries the
-    recursion out in long double (results rounded to double)."""
+    recursion out in long double (results rounded to double); single=True in
+    float (inputs rounded to float, results widened)."""
     parent = np.ascontiguousarray(parent, dtype=np.int32)
     N = len(parent)
     nx = np.shape(A)[1]
@@ -179,7 +182,7 @@ def tree_lqr(parent, A, B, c, Q, R, M, q, r, x0, extended=False):
            "K": np.zeros((N, nu, nx)), "k": np.zeros((N, nu)), "P": np.zeros((N, nx, nx)),
            "p": np.zeros((N, nx))}
     bad = np.array([-1], dtype=np.int32)
-    fn = lib().orc_tree_lqr_ld if extended else lib().orc_tree_lqr
+    fn = lib().orc_tree_lqr_ld if extended else lib().orc_tree_lqr_f if single else lib().orc_tree_lqr
     st = fn(N, nx, nu, _i(parent), _d(A), _d(B), _d(c), _d(Q), _d(R), _d(M),
                             _d(q), _d(r), _d(x0), _d(out["x"]), _d(out["u"]), _d(out["lam"]),
                             _d(out["K"]), _d(out["k"]), _d(out["P"]), _d(out["p"]), _i(bad))
@@ -188,9 +191,9 @@ def tree_lqr(parent, A, B, c, Q, R, M, q, r, x0, extended=False):
     return out
 
 
-def tree_lqr_inst(inst, extended=False):
+def tree_lqr_inst(inst, extended=False, single=False):
     return tree_lqr(inst.parent, inst.A, inst.B, inst.c, inst.Q, inst.R, inst.M, inst.q,
-                    inst.r, inst.x0, extended=extended)
+                    inst.r, inst.x0, extended=extended, single=single)
 
 
 class OracleError(RuntimeError):

@@ -45,6 +45,14 @@ int orc_tree_lqr_ld(int N, int nx, int nu, const int* parent,
                     const double* q, const double* r, const double* x0,
                     double* x, double* u, double* lam,
                     double* K, double* k, double* P, double* p, int* bad_node);
+/* The same recursion in single precision (inputs rounded to float, outputs
+ * widened to double): the FP32 variant of the solver, serially. */
+int orc_tree_lqr_f(int N, int nx, int nu, const int* parent,
+                   const double* A, const double* B, const double* c,
+                   const double* Q, const double* R, const double* M,
+                   const double* q, const double* r, const double* x0,
+                   double* x, double* u, double* lam,
+                   double* K, double* k, double* P, double* p, int* bad_node);
 
 /* ---- branch-MPC problem and AL multiple-shooting iLQR, oracle_bmpc.c ---- */
 #define ORC_NX 4

@@ -60,6 +60,20 @@
 #undef CHOL_SOLVE
 #undef LQR
 
+/* and in single precision: the FP32 variant of the recursion, every
+ * operation rounded to float in the serial order above */
+#define REAL float
+#define SQRT sqrtf
+#define CHOL chol_f
+#define CHOL_SOLVE chol_solve_f
+#define LQR tree_lqr_f
+#include "oracle_lqr_impl.h"
+#undef REAL
+#undef SQRT
+#undef CHOL
+#undef CHOL_SOLVE
+#undef LQR
+
 int orc_tree_lqr(int N, int nx, int nu, const int* parent,
                  const double* A, const double* B, const double* c,
                  const double* Q, const double* R, const double* M,
@@ -70,46 +84,49 @@ int orc_tree_lqr(int N, int nx, int nu, const int* parent,
     return tree_lqr_d(N, nx, nu, parent, A, B, c, Q, R, M, q, r, x0, x, u, lam, K, k, P, p, bad_node);
 }
 
-static long double* widen(const double* a, size_t n)
-{
-    long double* w = malloc(sizeof(long double) * (n ? n : 1));
-    for (size_t i = 0; i < n; ++i) w[i] = a[i];
-    return w;
-}
-
-static void narrow(const long double* a, double* out, size_t n)
-{
-    for (size_t i = 0; i < n; ++i) out[i] = (double)a[i];
-}
-
-int orc_tree_lqr_ld(int N, int nx, int nu, const int* parent,
-                    const double* A, const double* B, const double* c,
-                    const double* Q, const double* R, const double* M,
-                    const double* q, const double* r, const double* x0,
-                    double* x, double* u, double* lam,
-                    double* K, double* k, double* P, double* p, int* bad_node)
-{
-    if (N <= 0 || nx <= 0 || nu <= 0) return ORC_ERR_INVALID_ARG;
-    const size_t n = (size_t)N, nn = n * nx * nx, nm = n * nx * nu, mm = n * nu * nu;
-    long double *wA = widen(A, nn), *wB = widen(B, nm), *wc = widen(c, n * nx), *wQ = widen(Q, nn),
-                *wR = widen(R, mm), *wM = widen(M, nm), *wq = widen(q, n * nx), *wr = widen(r, n * nu),
-                *wx0 = widen(x0, (size_t)nx);
-    long double *ox = malloc(sizeof(long double) * n * nx), *ou = malloc(sizeof(long double) * n * nu),
-                *ol = malloc(sizeof(long double) * n * nx), *oK = malloc(sizeof(long double) * nm),
-                *ok = malloc(sizeof(long double) * n * nu), *oP = malloc(sizeof(long double) * nn),
-                *op = malloc(sizeof(long double) * n * nx);
-    const int st = tree_lqr_ld(N, nx, nu, parent, wA, wB, wc, wQ, wR, wM, wq, wr, wx0, ox, ou, ol, oK, ok,
-                               oP, op, bad_node);
-    if (st == ORC_OK) {
-        narrow(ox, x, n * nx);
-        narrow(ou, u, n * nu);
-        narrow(ol, lam, n * nx);
-        narrow(oK, K, nm);
-        narrow(ok, k, n * nu);
-        narrow(oP, P, nn);
-        narrow(op, p, n * nx);
+/* The recursion in another precision: inputs rounded from double, outputs
+ * converted back to double. */
+#define ORC_LQR_IN_TYPE(NAME, TYPE, IMPL)                                                            \
+    static TYPE* NAME##_widen(const double* a, size_t n)                                             \
+    {                                                                                                \
+        TYPE* w = malloc(sizeof(TYPE) * (n ? n : 1));                                                \
+        for (size_t i = 0; i < n; ++i) w[i] = (TYPE)a[i];                                            \
+        return w;                                                                                    \
+    }                                                                                                \
+    static void NAME##_narrow(const TYPE* a, double* out, size_t n)                                  \
+    {                                                                                                \
+        for (size_t i = 0; i < n; ++i) out[i] = (double)a[i];                                        \
+    }                                                                                                \
+    int NAME(int N, int nx, int nu, const int* parent, const double* A, const double* B,            \
+             const double* c, const double* Q, const double* R, const double* M, const double* q,   \
+             const double* r, const double* x0, double* x, double* u, double* lam, double* K,       \
+             double* k, double* P, double* p, int* bad_node)                                         \
+    {                                                                                                \
+        if (N <= 0 || nx <= 0 || nu <= 0) return ORC_ERR_INVALID_ARG;                               \
+        const size_t n = (size_t)N, nn = n * nx * nx, nm = n * nx * nu, mm = n * nu * nu;            \
+        TYPE *wA = NAME##_widen(A, nn), *wB = NAME##_widen(B, nm), *wc = NAME##_widen(c, n * nx),   \
+             *wQ = NAME##_widen(Q, nn), *wR = NAME##_widen(R, mm), *wM = NAME##_widen(M, nm),        \
+             *wq = NAME##_widen(q, n * nx), *wr = NAME##_widen(r, n * nu),                           \
+             *wx0 = NAME##_widen(x0, (size_t)nx);                                                    \
+        TYPE *ox = malloc(sizeof(TYPE) * n * nx), *ou = malloc(sizeof(TYPE) * n * nu),              \
+             *ol = malloc(sizeof(TYPE) * n * nx), *oK = malloc(sizeof(TYPE) * nm),                   \
+             *ok = malloc(sizeof(TYPE) * n * nu), *oP = malloc(sizeof(TYPE) * nn),                   \
+             *op = malloc(sizeof(TYPE) * n * nx);                                                    \
+        const int st = IMPL(N, nx, nu, parent, wA, wB, wc, wQ, wR, wM, wq, wr, wx0, ox, ou, ol, oK, \
+                            ok, oP, op, bad_node);                                                   \
+        if (st == ORC_OK) {                                                                          \
+            NAME##_narrow(ox, x, n * nx);                                                            \
+            NAME##_narrow(ou, u, n * nu);                                                            \
+            NAME##_narrow(ol, lam, n * nx);                                                          \
+            NAME##_narrow(oK, K, nm);                                                                \
+            NAME##_narrow(ok, k, n * nu);                                                            \
+            NAME##_narrow(oP, P, nn);                                                                \
+            NAME##_narrow(op, p, n * nx);                                                            \
+        }                                                                                            \
+        free(wA); free(wB); free(wc); free(wQ); free(wR); free(wM); free(wq); free(wr); free(wx0);  \
+        free(ox); free(ou); free(ol); free(oK); free(ok); free(oP); free(op);                        \
+        return st;                                                                                   \
     }
-    free(wA); free(wB); free(wc); free(wQ); free(wR); free(wM); free(wq); free(wr); free(wx0);
-    free(ox); free(ou); free(ol); free(oK); free(ok); free(oP); free(op);
-    return st;
-}
+
+ORC_LQR_IN_TYPE(orc_tree_lqr_ld, long double, tree_lqr_ld)
+ORC_LQR_IN_TYPE(orc_tree_lqr_f, float, tree_lqr_f)

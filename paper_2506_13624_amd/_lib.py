@@ -62,6 +62,8 @@ _sig("bmpc_lqr_plan_create", _i32, [_vp, _i32, _i32, _i32, C.POINTER(_vp)])
 _sig("bmpc_lqr_plan_destroy", None, [_vp])
 _sig("bmpc_lqr_supported", _i32, [_i32, _i32, _i32])
 _sig("bmpc_lqr_solve", _i32, [_vp] + [_vp] * 16 + [_i32, _vp])
+_sig("bmpc_lqr_solve_f32", _i32, [_vp] + [_vp] * 16 + [_vp])
+_sig("bmpc_lqr_solve_mixed", _i32, [_vp] + [_vp] * 12 + [_i32, _vp, _vp])
 _sig("bmpc_lqr_check", _i32, [_vp, _pi32, _vp])
 _sig("bmpc_profile_enable", _i32, [_i32])
 _sig("bmpc_profile_read", _i32, [C.c_char_p, _pd, _pi32, _i32])
@@ -210,6 +212,34 @@ def bmpc_lqr_solve(plan, A, B, c, Q, R, M, q, r, x0, x, u, lam, K=None, k=None, 
     args = _dptrs([(v, "float64", cnt, nm) for v, (nm, cnt) in zip((A, B, c, Q, R, M, q, r, x0, x, u, lam, K, k,
                                                                      P, p), sizes)])
     check(lib.bmpc_lqr_solve(plan, *args, variant, stream_ptr(stream)))
+
+
+def _lqr_sizes(plan):
+    N, n, m = _dims[_key(plan)]
+    return (("A", N * n * n), ("B", N * n * m), ("c", N * n), ("Q", N * n * n), ("R", N * m * m),
+            ("M", N * m * n), ("q", N * n), ("r", N * m), ("x0", n), ("x", N * n), ("u", N * m),
+            ("lam", N * n), ("K", N * m * n), ("k", N * m), ("P", N * n * n), ("p", N * n))
+
+
+def bmpc_lqr_solve_f32(plan, A, B, c, Q, R, M, q, r, x0, x, u, lam, K=None, k=None, P=None, p=None, stream=None):
+    """FP32 tree LQR: every array float32, sizes and layout as bmpc_lqr_solve."""
+    args = _dptrs([(v, "float32", cnt, nm) for v, (nm, cnt) in zip((A, B, c, Q, R, M, q, r, x0, x, u, lam, K, k,
+                                                                     P, p), _lqr_sizes(plan))])
+    check(lib.bmpc_lqr_solve_f32(plan, *args, stream_ptr(stream)))
+
+
+LQR_REFINE_MAX = 64
+
+
+def bmpc_lqr_solve_mixed(plan, A, B, c, Q, R, M, q, r, x0, x, u, lam, refine_steps, res_norms=None, stream=None):
+    """FP64 tree LQR by FP32 solves with FP64 iterative refinement;
+    res_norms (float64, refine_steps + 2 entries) receives the largest KKT
+    residual after each FP32 solve."""
+    specs = [(v, "float64", cnt, nm) for v, (nm, cnt) in zip((A, B, c, Q, R, M, q, r, x0, x, u, lam),
+                                                              _lqr_sizes(plan))]
+    specs.append((res_norms, "float64", refine_steps + 2, "res_norms"))
+    args = _dptrs(specs)
+    check(lib.bmpc_lqr_solve_mixed(plan, *args[:12], int(refine_steps), args[12], stream_ptr(stream)))
 
 
 def bmpc_lqr_check(plan, stream=None):

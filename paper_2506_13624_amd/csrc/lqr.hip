@@ -25,7 +25,9 @@
 // nodes in parallel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
+#include <initializer_list>
 #include <utility>
 
 #include "bmpc_internal.hpp"
@@ -52,6 +54,14 @@ __device__ __forceinline__ double ld_shared_dev(const double* p)
 {
     return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void st_shared_dev(float* p, float v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_shared_dev(const float* p)
+{
+    return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 // all earlier memory operations of this lane have completed
 __device__ __forceinline__ void wait_own_stores()
 {
@@ -60,9 +70,9 @@ __device__ __forceinline__ void wait_own_stores()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <int NX, int LAY>
-__device__ __forceinline__ void store_value_dev(const LqrArgs& a, int N, int n, const double (&P)[NX][NX],
-                                                const double (&p)[NX])
+template <int NX, int LAY, class T>
+__device__ __forceinline__ void store_value_dev(const LqrArgsT<T>& a, int N, int n, const T (&P)[NX][NX],
+                                                const T (&p)[NX])
 {
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
@@ -72,9 +82,9 @@ __device__ __forceinline__ void store_value_dev(const LqrArgs& a, int N, int n, 
     }
 }
 
-template <int NX, int LAY>
-__device__ __forceinline__ void load_value_dev(const LqrArgs& a, int N, int j, double (&P)[NX][NX],
-                                               double (&p)[NX])
+template <int NX, int LAY, class T>
+__device__ __forceinline__ void load_value_dev(const LqrArgsT<T>& a, int N, int j, T (&P)[NX][NX],
+                                               T (&p)[NX])
 {
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
@@ -87,8 +97,8 @@ __device__ __forceinline__ void load_value_dev(const LqrArgs& a, int N, int j, d
 // ------------------------------------------------------------------------
 // lane-per-segment backward
 // ------------------------------------------------------------------------
-template <int NX, int NU, int LAY>
-__global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgs a, int* arrive)
+template <int NX, int NU, int LAY, class T = double>
+__global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgsT<T> a, int* arrive)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= t.num_leaves) return;
@@ -97,9 +107,9 @@ __global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgs a, int* arri
     int4 inf = t.info[n];
     int from = -1;
     bool pref = false;  // stage/edge hold the inputs of n (single child == from)
-    double P[NX][NX], p[NX];
-    StageRegs<NX, NU> stage;
-    EdgeRegs<NX, NU> edge;
+    T P[NX][NX], p[NX];
+    StageRegs<NX, NU, T> stage;
+    EdgeRegs<NX, NU, T> edge;
     for (;;) {
         const int c0 = inf.x, c1 = inf.y, par = inf.z, nsib = inf.w;
         // the next node's topology record, in flight while this node is computed
@@ -107,18 +117,18 @@ __global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgs a, int* arri
         if (c0 == c1) {
             load_value<NX, LAY>(a.Q, a.q, N, n, P, p);
 #pragma unroll
-            for (int e = 0; e < NU * NX; ++e) a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0;
+            for (int e = 0; e < NU * NX; ++e) a.K[lidx<LAY>(n, e, NU * NX, N)] = T(0);
 #pragma unroll
-            for (int e = 0; e < NU; ++e) a.k[lidx<LAY>(n, e, NU, N)] = 0.0;
+            for (int e = 0; e < NU; ++e) a.k[lidx<LAY>(n, e, NU, N)] = T(0);
             if (nsib == 1) {
                 load_stage<NX, NU, LAY>(a, N, par, stage);
                 load_edge<NX, NU, LAY, false>(a, N, par, n, edge);
             }
         } else {
-            RicAcc<NX, NU> acc;
+            RicAcc<NX, NU, T> acc;
             if (pref) {
                 acc.init(stage);
-                const EdgeRegs<NX, NU> e0 = edge;
+                const EdgeRegs<NX, NU, T> e0 = edge;
                 // inputs of the parent are independent of this step: start them now
                 if (nsib == 1) {
                     load_stage<NX, NU, LAY>(a, N, par, stage);
@@ -138,7 +148,7 @@ __global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgs a, int* arri
                     load_edge<NX, NU, LAY, false>(a, N, par, n, edge);
                 }
             }
-            double Kn[NU][NX], kn[NU];
+            T Kn[NU][NX], kn[NU];
             if (!acc.finish(Kn, kn, P, p)) atomicMin(a.bad, n);
 #pragma unroll
             for (int i = 0; i < NU; ++i) {
@@ -1227,12 +1237,22 @@ __device__ __forceinline__ double row_bcast(double v)
     return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xf, 0xf, false);
 }
 template <int J>
+__device__ __forceinline__ float row_bcast(float v)
+{
+    return __builtin_amdgcn_update_dpp(0.0f, v, 0x150 + J, 0xf, 0xf, false);
+}
+template <int J>
 __device__ __forceinline__ int row_bcast_int(int v)
 {
     return __builtin_amdgcn_update_dpp(0, v, 0x150 + J, 0xf, 0xf, false);
 }
 // lane J of the group of G lanes that starts at lane base
 // lane J of the wavefront (a group of 64 lanes): one scalar read per dword
+template <int J>
+__device__ __forceinline__ float wave_lane(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), J));
+}
 template <int J>
 __device__ __forceinline__ double wave_lane(double v)
 {
@@ -1241,8 +1261,8 @@ __device__ __forceinline__ double wave_lane(double v)
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), J);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-template <int G, int J>
-__device__ __forceinline__ double group_value(double v, int base)
+template <int G, int J, class T>
+__device__ __forceinline__ T group_value(T v, int base)
 {
     if constexpr (G == 16)
         return row_bcast<J>(v);
@@ -1261,8 +1281,8 @@ __device__ __forceinline__ int group_value_int(int v, int base)
     else
         return __shfl(v, base + J, 64);
 }
-template <int G, int... J>
-__device__ __forceinline__ void group_gather(double v, int base, double* out, std::integer_sequence<int, J...>)
+template <int G, class T, int... J>
+__device__ __forceinline__ void group_gather(T v, int base, T* out, std::integer_sequence<int, J...>)
 {
     ((out[J] = group_value<G, J>(v, base)), ...);
 }
@@ -1281,13 +1301,13 @@ __device__ __forceinline__ void unroll(F&& f)
 // the next node; lane NX + i holds row i of [K k] of the node (lanes past
 // NX + NU repeat the last row).  Both roles evaluate r = w . x + c0, which is
 // A x + c on the first lanes and u = K x + k on the others.
-template <int NX, int NU>
+template <int NX, int NU, class T = double>
 struct FwdRow {
-    double w[NX], b[NU], c0;
+    T w[NX], b[NU], c0;
 };
 
-template <int NX, int NU, int LAY>
-__device__ __forceinline__ void fwd_row_fill(const LqrArgs& a, int N, int n, int m, int g, FwdRow<NX, NU>& f)
+template <int NX, int NU, int LAY, class T>
+__device__ __forceinline__ void fwd_row_fill(const LqrArgsT<T>& a, int N, int n, int m, int g, FwdRow<NX, NU, T>& f)
 {
     // the last step of a path needs no inputs, and stages past its end
     // none at all: those read the entries of node n, or of the root, which
@@ -1296,7 +1316,7 @@ __device__ __forceinline__ void fwd_row_fill(const LqrArgs& a, int N, int n, int
     const int me = m >= 0 ? m : nn;
     const bool krow = g >= NX;
     const int i = krow ? (g - NX < NU ? g - NX : NU - 1) : g;
-    const double* wp = krow ? a.K : a.A;
+    const T* wp = krow ? a.K : a.A;
     const int wn = krow ? nn : me, wsz = krow ? NU * NX : NX * NX;
 #pragma unroll
     for (int j = 0; j < NX; ++j) f.w[j] = wp[lidx<LAY>(wn, i * NX + j, wsz, N)];
@@ -1306,8 +1326,8 @@ __device__ __forceinline__ void fwd_row_fill(const LqrArgs& a, int N, int n, int
     f.c0 = krow ? a.k[lidx<LAY>(nn, i, NU, N)] : a.c[lidx<LAY>(me, i, NX, N)];
 }
 
-template <int NX, int NU, int LAY, int G, int D>
-__global__ void __launch_bounds__(64) k_fwd_rows(TreeDev t, LqrArgs a)
+template <int NX, int NU, int LAY, int G, int D, class T = double>
+__global__ void __launch_bounds__(64) k_fwd_rows(TreeDev t, LqrArgsT<T> a)
 {
     static_assert(NX + NU <= G && 64 % G == 0 && G % D == 0, "group must hold the rows of [A B c] and [K k]");
     const int tid = blockIdx.x * 64 + threadIdx.x;
@@ -1326,7 +1346,7 @@ __global__ void __launch_bounds__(64) k_fwd_rows(TreeDev t, LqrArgs a)
         return s <= last ? t.path[(long)s * Z + path] : -1;
     };
     int blk0 = ids(0), blk1 = ids(G);
-    FwdRow<NX, NU> ring[D];
+    FwdRow<NX, NU, T> ring[D];
     // node at stage s0 + K (K a constant, K < 2G) of the blocks held
     auto node_at = [&](auto kc) -> int {
         constexpr int K = decltype(kc)::value;
@@ -1340,7 +1360,7 @@ __global__ void __launch_bounds__(64) k_fwd_rows(TreeDev t, LqrArgs a)
         fwd_row_fill<NX, NU, LAY>(a, N, node_at(std::integral_constant<int, d>{}),
                                   node_at(std::integral_constant<int, d + 1>{}), g, ring[d]);
     });
-    double xg = g < NX ? a.x0[g] : 0.0;
+    T xg = g < NX ? a.x0[g] : T(0);
     for (int s0 = 0; s0 <= last; s0 += G) {
         const int blk2 = ids(s0 + 2 * G);
         unroll<G>([&](auto kc) {
@@ -1350,17 +1370,17 @@ __global__ void __launch_bounds__(64) k_fwd_rows(TreeDev t, LqrArgs a)
             // kept on one side of a branch and loaded on the other would be
             // merged by a copy, and the copy waits for every load in flight
             const bool live = s <= last, fin = s == last;
-            FwdRow<NX, NU>& f = ring[k % D];
+            FwdRow<NX, NU, T>& f = ring[k % D];
             const int n = node_at(std::integral_constant<int, k>{});
             const bool writer = live && s >= wfrom;
-            double xs[NX];
+            T xs[NX];
             group_gather<G>(xg, base, xs, std::make_integer_sequence<int, NX>{});
             if (writer && g < NX) a.x[lidx<LAY>(n, g, NX, N)] = xg;
-            double r = f.c0;
+            T r = f.c0;
 #pragma unroll
             for (int j = 0; j < NX; ++j) r += f.w[j] * xs[j];
-            if (writer && g >= NX && g < NX + NU) a.u[lidx<LAY>(n, g - NX, NU, N)] = fin ? 0.0 : r;
-            double us[NU];
+            if (writer && g >= NX && g < NX + NU) a.u[lidx<LAY>(n, g - NX, NU, N)] = fin ? T(0) : r;
+            T us[NU];
             unroll<NU>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 us[i] = group_value<G, NX + i>(r, base);
@@ -1386,8 +1406,8 @@ __global__ void __launch_bounds__(64) k_fwd_rows(TreeDev t, LqrArgs a)
 
 // Costates lam_n = P_n x_n + p_n for every node; also re-arms the branch
 // counters and the positive-definiteness flag for the next solve.
-template <int NX, int LAY>
-__global__ void __launch_bounds__(256) k_costate(TreeDev t, LqrArgs a, int* arrive)
+template <int NX, int LAY, class T = double>
+__global__ void __launch_bounds__(256) k_costate(TreeDev t, LqrArgsT<T> a, int* arrive)
 {
     const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int N = t.N;
@@ -1405,11 +1425,156 @@ __global__ void __launch_bounds__(256) k_costate(TreeDev t, LqrArgs a, int* arri
         n = (int)(tid % N);
     }
     if (i == 0) arrive[n] = 0;
-    double acc = a.p[lidx<LAY>(n, i, NX, N)];
+    T acc = a.p[lidx<LAY>(n, i, NX, N)];
 #pragma unroll
     for (int j = 0; j < NX; ++j)
         acc += a.P[lidx<LAY>(n, i * NX + j, NX * NX, N)] * a.x[lidx<LAY>(n, j, NX, N)];
     a.lam[lidx<LAY>(n, i, NX, N)] = acc;
+}
+
+// ------------------------------------------------------------------------
+// mixed precision: FP32 Riccati solves, FP64 residuals, iterative refinement
+// ------------------------------------------------------------------------
+
+// Elementwise FP64 -> FP32 copy of one matrix array.
+__global__ void __launch_bounds__(256) k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+// Largest |value| over the workgroup (256 threads), merged into *slot by
+// one atomic: IEEE order of non-negative doubles is the order of their bit
+// patterns, and a NaN's pattern lies above that of every finite value and
+// infinity, so it survives the maximum.
+__device__ __forceinline__ void block_abs_max_into(double v, unsigned long long* slot)
+{
+    __shared__ unsigned long long wmax[4];
+    unsigned long long b = (unsigned long long)__double_as_longlong(fabs(v));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(b, off, 64);
+        b = o > b ? o : b;
+    }
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long m01 = wmax[0] > wmax[1] ? wmax[0] : wmax[1];
+        const unsigned long long m23 = wmax[2] > wmax[3] ? wmax[2] : wmax[3];
+        atomicMax(slot, m01 > m23 ? m01 : m23);
+    }
+}
+
+// KKT residual of the tree LQR at the FP64 iterate (x, u, lam), one thread
+// per (node n, state row i).  With z = 0 (FIRST) the residual is the data
+// itself.  Rows, for the Lagrangian cost + sum_j lam_j^T (A_j x_p + B_j u_p
+// + c_j - x_j) + lam_0^T (x0 - x_0):
+//   g_u[n] = R u + M x + r + sum_{j child} B_j^T lam_j         (control nodes)
+//   g_x[n] = Q x + M^T u + q + sum_{j child} A_j^T lam_j - lam_n
+//   d[n]   = A_n x_p + B_n u_p + c_n - x_n   (root: x0 - x_0)
+// They are the linear terms of the correction problem, written in FP32 as
+// its (r, q, c, x0); the largest |row| is merged into *norm if it is set.
+template <int NX, int NU, int LAY, bool FIRST>
+__global__ void __launch_bounds__(256) k_lqr_residual(TreeDev t, LqrArgs a, float* __restrict__ q32,
+                                                      float* __restrict__ r32, float* __restrict__ c32,
+                                                      float* __restrict__ x032, unsigned long long* norm)
+{
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = t.N;
+    double worst = 0.0;
+    if (tid < (long)N * NX) {
+        int n, i;
+        if constexpr (LAY == BMPC_LAYOUT_NODE_MAJOR) {
+            n = (int)(tid / NX);
+            i = (int)(tid % NX);
+        } else {
+            i = (int)(tid / N);
+            n = (int)(tid % N);
+        }
+        const int4 inf = t.info[n];
+        const bool leaf = inf.x == inf.y;
+        auto X = [&](int m, int k) { return FIRST ? 0.0 : a.x[lidx<LAY>(m, k, NX, N)]; };
+        auto U = [&](int m, int k) { return FIRST ? 0.0 : a.u[lidx<LAY>(m, k, NU, N)]; };
+        auto Lm = [&](int m, int k) { return FIRST ? 0.0 : a.lam[lidx<LAY>(m, k, NX, N)]; };
+        // stationarity in x
+        double gx = a.q[lidx<LAY>(n, i, NX, N)];
+        if constexpr (!FIRST) {
+#pragma unroll
+            for (int k = 0; k < NX; ++k) gx += a.Q[lidx<LAY>(n, i * NX + k, NX * NX, N)] * X(n, k);
+            if (!leaf) {
+#pragma unroll
+                for (int k = 0; k < NU; ++k) gx += a.M[lidx<LAY>(n, k * NX + i, NU * NX, N)] * U(n, k);
+            }
+            for (int j = inf.x; j < inf.y; ++j) {
+#pragma unroll
+                for (int k = 0; k < NX; ++k) gx += a.A[lidx<LAY>(j, k * NX + i, NX * NX, N)] * Lm(j, k);
+            }
+            gx -= Lm(n, i);
+        }
+        q32[lidx<LAY>(n, i, NX, N)] = (float)gx;
+        // dynamics defect of the edge into n
+        double d;
+        if (inf.z < 0) {
+            d = a.x0[i] - X(n, i);
+            x032[i] = (float)d;
+        } else {
+            const int pn = inf.z;
+            d = a.c[lidx<LAY>(n, i, NX, N)];
+            if constexpr (!FIRST) {
+#pragma unroll
+                for (int k = 0; k < NX; ++k) d += a.A[lidx<LAY>(n, i * NX + k, NX * NX, N)] * X(pn, k);
+#pragma unroll
+                for (int k = 0; k < NU; ++k) d += a.B[lidx<LAY>(n, i * NU + k, NX * NU, N)] * U(pn, k);
+                d -= X(n, i);
+            }
+        }
+        c32[lidx<LAY>(n, i, NX, N)] = (float)d;
+        worst = fmax(fabs(gx), fabs(d));
+        if (gx != gx || d != d) worst = gx + d;
+        // stationarity in u
+        if (i < NU) {
+            double gu = 0.0;
+            if (!leaf) {
+                gu = a.r[lidx<LAY>(n, i, NU, N)];
+                if constexpr (!FIRST) {
+#pragma unroll
+                    for (int k = 0; k < NU; ++k) gu += a.R[lidx<LAY>(n, i * NU + k, NU * NU, N)] * U(n, k);
+#pragma unroll
+                    for (int k = 0; k < NX; ++k) gu += a.M[lidx<LAY>(n, i * NX + k, NU * NX, N)] * X(n, k);
+                    for (int j = inf.x; j < inf.y; ++j) {
+#pragma unroll
+                        for (int k = 0; k < NX; ++k) gu += a.B[lidx<LAY>(j, k * NU + i, NX * NU, N)] * Lm(j, k);
+                    }
+                }
+            }
+            r32[lidx<LAY>(n, i, NU, N)] = (float)gu;
+            if (fabs(gu) > worst || gu != gu) worst = gu != gu ? gu : fabs(gu);
+        }
+    }
+    if (norm) block_abs_max_into(worst, norm);
+}
+
+// z <- z + dz (or z <- dz on the first solve), elementwise over the
+// flat arrays: x and lam have N*NX entries, u N*NU, in the same layout as
+// their FP32 corrections.
+template <bool FIRST>
+__global__ void __launch_bounds__(256) k_lqr_update(long nxe, long nue, double* __restrict__ x,
+                                                    double* __restrict__ u, double* __restrict__ lam,
+                                                    const float* __restrict__ dx, const float* __restrict__ du,
+                                                    const float* __restrict__ dl)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nxe) {
+        x[i] = FIRST ? (double)dx[i] : x[i] + (double)dx[i];
+        lam[i] = FIRST ? (double)dl[i] : lam[i] + (double)dl[i];
+    }
+    if (i < nue) u[i] = FIRST ? (double)du[i] : u[i] + (double)du[i];
+}
+
+__global__ void k_zero_norms(unsigned long long* norm, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) norm[i] = 0ull;
 }
 
 // ------------------------------------------------------------------------
@@ -1423,6 +1588,12 @@ struct LqrKernels {
     void (*bwd_seg)(TreeDev, LqrArgs, int*);
     void (*fwd)(TreeDev, LqrArgs);
     void (*costate)(TreeDev, LqrArgs, int*);
+    // FP32 solve and the FP64 residual of the mixed-precision refinement
+    void (*bwd_lane32)(TreeDev, LqrArgsT<float>, int*);
+    void (*fwd32)(TreeDev, LqrArgsT<float>);
+    void (*costate32)(TreeDev, LqrArgsT<float>, int*);
+    void (*residual_first)(TreeDev, LqrArgs, float*, float*, float*, float*, unsigned long long*);
+    void (*residual)(TreeDev, LqrArgs, float*, float*, float*, float*, unsigned long long*);
 };
 
 template <int NX, int NU, int LAY, bool LANE>
@@ -1432,7 +1603,14 @@ static LqrKernels make_k()
     constexpr int G = 16;
     LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, nullptr, nullptr, k_fwd_rows<NX, NU, LAY, G, 4>,
                  k_costate<NX, LAY>};
-    if constexpr (LANE) k.bwd_lane = k_bwd_lane<NX, NU, LAY>;
+    if constexpr (LANE) {
+        k.bwd_lane = k_bwd_lane<NX, NU, LAY>;
+        k.bwd_lane32 = k_bwd_lane<NX, NU, LAY, float>;
+        k.fwd32 = k_fwd_rows<NX, NU, LAY, G, 4, float>;
+        k.costate32 = k_costate<NX, LAY, float>;
+        k.residual_first = k_lqr_residual<NX, NU, LAY, true>;
+        k.residual = k_lqr_residual<NX, NU, LAY, false>;
+    }
     if constexpr (NX <= 4) k.bwd_seg = k_bwd_seg<NX, NU, LAY>;
     return k;
 }
@@ -1444,7 +1622,7 @@ static LqrKernels make_k_mfma()
 {
     constexpr int G = 64;
     return LqrKernels{NX, NU, LAY, G, nullptr, nullptr, k_bwd_mfma<NX, NU, LAY>, nullptr,
-                      k_fwd_rows<NX, NU, LAY, G, 2>, k_costate<NX, LAY>};
+                      k_fwd_rows<NX, NU, LAY, G, 2>, k_costate<NX, LAY>, nullptr, nullptr, nullptr, nullptr, nullptr};
 }
 
 static const LqrKernels* find_kernels(int nx, int nu, int layout)
@@ -1472,7 +1650,56 @@ struct bmpc_lqr_plan {
     double *K = nullptr, *k = nullptr, *P = nullptr, *p = nullptr;
     int* arrive = nullptr;
     int* bad = nullptr;  // [0] live flag, [1] copy taken after the last backward pass
+    // FP32 workspace, allocated by the first FP32 or mixed-precision solve:
+    // gains and value functions, then (mixed only) the FP32 copies of the
+    // matrices, the correction problem's linear terms and its solution
+    float *K32 = nullptr, *k32 = nullptr, *P32 = nullptr, *p32 = nullptr;
+    float *A32 = nullptr, *B32 = nullptr, *Q32 = nullptr, *R32 = nullptr, *M32 = nullptr;
+    float *q32 = nullptr, *r32 = nullptr, *c32 = nullptr, *x032 = nullptr;
+    float *x32 = nullptr, *u32 = nullptr, *l32 = nullptr;
 };
+
+namespace {
+
+bool alloc_f32(float** p, size_t n) { return *p || hipMalloc(p, sizeof(float) * (n ? n : 1)) == hipSuccess; }
+
+bmpc_status ensure_f32(bmpc_lqr_plan* pl, bool mixed)
+{
+    const size_t N = pl->tree->h.N, n = pl->nx, m = pl->nu;
+    bool ok = alloc_f32(&pl->K32, N * m * n) && alloc_f32(&pl->k32, N * m) && alloc_f32(&pl->P32, N * n * n) &&
+              alloc_f32(&pl->p32, N * n);
+    if (ok && mixed)
+        ok = alloc_f32(&pl->A32, N * n * n) && alloc_f32(&pl->B32, N * n * m) && alloc_f32(&pl->Q32, N * n * n) &&
+             alloc_f32(&pl->R32, N * m * m) && alloc_f32(&pl->M32, N * m * n) && alloc_f32(&pl->q32, N * n) &&
+             alloc_f32(&pl->r32, N * m) && alloc_f32(&pl->c32, N * n) && alloc_f32(&pl->x032, n) &&
+             alloc_f32(&pl->x32, N * n) && alloc_f32(&pl->u32, N * m) && alloc_f32(&pl->l32, N * n);
+    return ok ? BMPC_OK : fail(BMPC_ERR_OOM, "device allocation of the FP32 LQR workspace failed");
+}
+
+void launch_f32(bmpc_lqr_plan* pl, const LqrArgsT<float>& a, hipStream_t s)
+{
+    const TreeDev& t = pl->tree->d;
+    const int Z = t.num_leaves;
+    {
+        ProfScope ps("lqr_backward_level_lane_f32", s);
+        hipLaunchKernelGGL(pl->kern->bwd_lane32, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
+    }
+    {
+        ProfScope ps("lqr_forward_paths_f32", s);
+        const long threads = (long)Z * pl->kern->group;
+        hipLaunchKernelGGL(pl->kern->fwd32, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, t, a);
+    }
+    {
+        ProfScope ps("lqr_costate_f32", s);
+        const long threads = (long)t.N * pl->nx;
+        hipLaunchKernelGGL(pl->kern->costate32, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, t, a,
+                           pl->arrive);
+    }
+}
+
+unsigned grid_for(long n, int block) { return (unsigned)std::max(1L, std::min((n + block - 1) / block, 65536L)); }
+
+}  // namespace
 
 extern "C" {
 
@@ -1532,6 +1759,9 @@ BMPC_API void bmpc_lqr_plan_destroy(bmpc_lqr_plan* pl)
     (void)hipFree(pl->p);
     (void)hipFree(pl->arrive);
     (void)hipFree(pl->bad);
+    for (float* f : {pl->K32, pl->k32, pl->P32, pl->p32, pl->A32, pl->B32, pl->Q32, pl->R32, pl->M32, pl->q32,
+                     pl->r32, pl->c32, pl->x032, pl->x32, pl->u32, pl->l32})
+        (void)hipFree(f);
     delete pl;
 }
 
@@ -1577,6 +1807,82 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
         const long threads = (long)t.N * pl->nx;
         hipLaunchKernelGGL(pl->kern->costate, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
                            t, a, pl->arrive);
+    }
+    BMPC_HIP_TRY(hipGetLastError());
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_lqr_solve_f32(bmpc_lqr_plan* pl, const float* A, const float* B, const float* c,
+                                        const float* Q, const float* R, const float* M, const float* q,
+                                        const float* r, const float* x0, float* x, float* u, float* lam, float* K,
+                                        float* k, float* P, float* p, void* stream)
+{
+    if (!pl) return fail(BMPC_ERR_INVALID_ARG, "plan is NULL");
+    if (!A || !B || !c || !Q || !R || !M || !q || !r || !x0 || !x || !u || !lam)
+        return fail(BMPC_ERR_INVALID_ARG, "NULL input or output array");
+    if (!pl->kern->bwd_lane32)
+        return fail(BMPC_ERR_UNSUPPORTED, "no FP32 tree-LQR kernel compiled for nx=%d nu=%d", pl->nx, pl->nu);
+    bmpc_status st = ensure_f32(pl, false);
+    if (st != BMPC_OK) return st;
+    LqrArgsT<float> a{A, B, c, Q, R, M, q, r, x0, x, u, lam, K ? K : pl->K32, k ? k : pl->k32,
+                      P ? P : pl->P32, p ? p : pl->p32, pl->bad, pl->bad + 1};
+    launch_f32(pl, a, (hipStream_t)stream);
+    BMPC_HIP_TRY(hipGetLastError());
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_lqr_solve_mixed(bmpc_lqr_plan* pl, const double* A, const double* B, const double* c,
+                                          const double* Q, const double* R, const double* M, const double* q,
+                                          const double* r, const double* x0, double* x, double* u, double* lam,
+                                          int32_t refine_steps, double* res_norms, void* stream)
+{
+    if (!pl) return fail(BMPC_ERR_INVALID_ARG, "plan is NULL");
+    if (!A || !B || !c || !Q || !R || !M || !q || !r || !x0 || !x || !u || !lam)
+        return fail(BMPC_ERR_INVALID_ARG, "NULL input or output array");
+    if (refine_steps < 0 || refine_steps > BMPC_LQR_REFINE_MAX)
+        return fail(BMPC_ERR_INVALID_ARG, "refine_steps %d outside [0, %d]", refine_steps, BMPC_LQR_REFINE_MAX);
+    if (!pl->kern->bwd_lane32)
+        return fail(BMPC_ERR_UNSUPPORTED, "no FP32 tree-LQR kernel compiled for nx=%d nu=%d", pl->nx, pl->nu);
+    bmpc_status st = ensure_f32(pl, true);
+    if (st != BMPC_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const TreeDev& t = pl->tree->d;
+    const long N = t.N, n = pl->nx, m = pl->nu;
+    {
+        ProfScope ps("lqr_matrices_to_f32", s);
+        const std::pair<const double*, float*> mats[] = {
+            {A, pl->A32}, {B, pl->B32}, {Q, pl->Q32}, {R, pl->R32}, {M, pl->M32}};
+        const long sizes[] = {N * n * n, N * n * m, N * n * n, N * m * m, N * m * n};
+        for (int i = 0; i < 5; ++i)
+            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(sizes[i], 256)), dim3(256), 0, s, mats[i].first,
+                               mats[i].second, sizes[i]);
+    }
+    auto* norms = reinterpret_cast<unsigned long long*>(res_norms);
+    if (norms) hipLaunchKernelGGL(k_zero_norms, dim3(1), dim3(128), 0, s, norms, refine_steps + 2);
+    const LqrArgs a64{A, B, c, Q, R, M, q, r, x0, x, u, lam, nullptr, nullptr, nullptr, nullptr, pl->bad, pl->bad + 1};
+    const LqrArgsT<float> a32{pl->A32, pl->B32, pl->c32, pl->Q32, pl->R32, pl->M32, pl->q32, pl->r32,
+                              pl->x032, pl->x32, pl->u32, pl->l32, pl->K32, pl->k32, pl->P32, pl->p32,
+                              pl->bad, pl->bad + 1};
+    const unsigned rgrid = (unsigned)((N * n + 255) / 256), ugrid = (unsigned)((std::max(n, m) * N + 255) / 256);
+    for (int it = 0; it <= refine_steps + 1; ++it) {
+        unsigned long long* slot = norms ? norms + it : nullptr;
+        if (it == refine_steps + 1 && !slot) break;
+        {
+            ProfScope ps("lqr_residual_f64", s);
+            hipLaunchKernelGGL(it == 0 ? pl->kern->residual_first : pl->kern->residual, dim3(rgrid), dim3(256), 0,
+                               s, t, a64, pl->q32, pl->r32, pl->c32, pl->x032, slot);
+        }
+        if (it == refine_steps + 1) break;
+        launch_f32(pl, a32, s);
+        {
+            ProfScope ps("lqr_refine_update", s);
+            if (it == 0)
+                hipLaunchKernelGGL(k_lqr_update<true>, dim3(ugrid), dim3(256), 0, s, N * n, N * m, x, u, lam,
+                                   pl->x32, pl->u32, pl->l32);
+            else
+                hipLaunchKernelGGL(k_lqr_update<false>, dim3(ugrid), dim3(256), 0, s, N * n, N * m, x, u, lam,
+                                   pl->x32, pl->u32, pl->l32);
+        }
     }
     BMPC_HIP_TRY(hipGetLastError());
     return BMPC_OK;

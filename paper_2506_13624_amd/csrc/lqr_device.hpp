@@ -9,46 +9,48 @@
 
 namespace bmpc {
 
-struct LqrArgs {
-    const double* __restrict__ A;
-    const double* __restrict__ B;
-    const double* __restrict__ c;
-    const double* __restrict__ Q;
-    const double* __restrict__ R;
-    const double* __restrict__ M;
-    const double* __restrict__ q;
-    const double* __restrict__ r;
-    const double* __restrict__ x0;
-    double* __restrict__ x;
-    double* __restrict__ u;
-    double* __restrict__ lam;
-    double* __restrict__ K;
-    double* __restrict__ k;
-    double* __restrict__ P;
-    double* __restrict__ p;
+template <class T = double>
+struct LqrArgsT {
+    const T* __restrict__ A;
+    const T* __restrict__ B;
+    const T* __restrict__ c;
+    const T* __restrict__ Q;
+    const T* __restrict__ R;
+    const T* __restrict__ M;
+    const T* __restrict__ q;
+    const T* __restrict__ r;
+    const T* __restrict__ x0;
+    T* __restrict__ x;
+    T* __restrict__ u;
+    T* __restrict__ lam;
+    T* __restrict__ K;
+    T* __restrict__ k;
+    T* __restrict__ P;
+    T* __restrict__ p;
     int* bad;      // smallest node whose H was not positive definite (INT_MAX: none)
     int* bad_out;  // copy of *bad taken after the backward pass
 };
+using LqrArgs = LqrArgsT<double>;
 
 // Cholesky H = L L^T in place (lower triangle used); inv receives the
 // reciprocals of the diagonal of L.  False if H is not numerically positive
 // definite.
-template <int n>
-__device__ __forceinline__ bool chol_inplace(double (&H)[n][n], double (&inv)[n])
+template <int n, class T = double>
+__device__ __forceinline__ bool chol_inplace(T (&H)[n][n], T (&inv)[n])
 {
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < n; ++j) {
-        double d = H[j][j];
+        T d = H[j][j];
 #pragma unroll
         for (int k = 0; k < j; ++k) d -= H[j][k] * H[j][k];
-        ok = ok && (d > 0.0);
-        d = sqrt(d > 0.0 ? d : 1.0);
+        ok = ok && (d > T(0));
+        d = sqrt(d > T(0) ? d : T(1));
         H[j][j] = d;
-        inv[j] = 1.0 / d;
+        inv[j] = T(1) / d;
 #pragma unroll
         for (int i = j + 1; i < n; ++i) {
-            double s = H[i][j];
+            T s = H[i][j];
 #pragma unroll
             for (int k = 0; k < j; ++k) s -= H[i][k] * H[j][k];
             H[i][j] = s * inv[j];
@@ -122,19 +124,19 @@ __device__ __forceinline__ void chol_bwd(const double (&L)[n][n], const double (
 }
 
 // Solve (L L^T) v = v in place, given the reciprocal diagonal.
-template <int n>
-__device__ __forceinline__ void chol_solve(const double (&L)[n][n], const double (&inv)[n], double (&v)[n])
+template <int n, class T = double>
+__device__ __forceinline__ void chol_solve(const T (&L)[n][n], const T (&inv)[n], T (&v)[n])
 {
 #pragma unroll
     for (int i = 0; i < n; ++i) {
-        double s = v[i];
+        T s = v[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= L[i][k] * v[k];
         v[i] = s * inv[i];
     }
 #pragma unroll
     for (int i = n - 1; i >= 0; --i) {
-        double s = v[i];
+        T s = v[i];
 #pragma unroll
         for (int k = i + 1; k < n; ++k) s -= L[k][i] * v[k];
         v[i] = s * inv[i];
@@ -142,19 +144,19 @@ __device__ __forceinline__ void chol_solve(const double (&L)[n][n], const double
 }
 
 // Stage cost of one node in registers.
-template <int NX, int NU>
+template <int NX, int NU, class T = double>
 struct StageRegs {
-    double Q[NX][NX], q[NX], R[NU][NU], M[NU][NX], r[NU];
+    T Q[NX][NX], q[NX], R[NU][NU], M[NU][NX], r[NU];
 };
 
 // Data of one edge (A, B of the transition, c of the child) in registers.
-template <int NX, int NU>
+template <int NX, int NU, class T = double>
 struct EdgeRegs {
-    double A[NX][NX], B[NX][NU], c[NX];
+    T A[NX][NX], B[NX][NU], c[NX];
 };
 
-template <int NX, int NU, int LAY>
-__device__ __forceinline__ void load_stage(const LqrArgs& a, int N, int n, StageRegs<NX, NU>& s)
+template <int NX, int NU, int LAY, class T>
+__device__ __forceinline__ void load_stage(const LqrArgsT<T>& a, int N, int n, StageRegs<NX, NU, T>& s)
 {
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
@@ -175,8 +177,8 @@ __device__ __forceinline__ void load_stage(const LqrArgs& a, int N, int n, Stage
 // Edge into child j; with SHARED_AB the Jacobians are stored once at the
 // parent n (all out-edges of n share the linearisation point) while the
 // defect c stays per child.
-template <int NX, int NU, int LAY, bool SHARED_AB>
-__device__ __forceinline__ void load_edge(const LqrArgs& a, int N, int n, int j, EdgeRegs<NX, NU>& e)
+template <int NX, int NU, int LAY, bool SHARED_AB, class T>
+__device__ __forceinline__ void load_edge(const LqrArgsT<T>& a, int N, int n, int j, EdgeRegs<NX, NU, T>& e)
 {
     const int ab = SHARED_AB ? n : j;
 #pragma unroll
@@ -189,9 +191,9 @@ __device__ __forceinline__ void load_edge(const LqrArgs& a, int N, int n, int j,
     }
 }
 
-template <int NX, int LAY>
-__device__ __forceinline__ void load_value(const double* __restrict__ Pg, const double* __restrict__ pg,
-                                           int N, int j, double (&P)[NX][NX], double (&p)[NX])
+template <int NX, int LAY, class T>
+__device__ __forceinline__ void load_value(const T* __restrict__ Pg, const T* __restrict__ pg,
+                                           int N, int j, T (&P)[NX][NX], T (&p)[NX])
 {
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
@@ -201,9 +203,9 @@ __device__ __forceinline__ void load_value(const double* __restrict__ Pg, const 
     }
 }
 
-template <int NX, int LAY>
-__device__ __forceinline__ void store_value(const LqrArgs& a, int N, int n, const double (&P)[NX][NX],
-                                            const double (&p)[NX])
+template <int NX, int LAY, class T>
+__device__ __forceinline__ void store_value(const LqrArgsT<T>& a, int N, int n, const T (&P)[NX][NX],
+                                            const T (&p)[NX])
 {
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
@@ -214,11 +216,11 @@ __device__ __forceinline__ void store_value(const LqrArgs& a, int N, int n, cons
 }
 
 // Accumulator of one Riccati step: W = Q + sum A^T P A, w, H, G, g.
-template <int NX, int NU>
+template <int NX, int NU, class T = double>
 struct RicAcc {
-    double H[NU][NU], G[NU][NX], g[NU], W[NX][NX], w[NX];
+    T H[NU][NU], G[NU][NX], g[NU], W[NX][NX], w[NX];
 
-    __device__ __forceinline__ void init(const StageRegs<NX, NU>& s)
+    __device__ __forceinline__ void init(const StageRegs<NX, NU, T>& s)
     {
 #pragma unroll
         for (int i = 0; i < NU; ++i) {
@@ -237,26 +239,26 @@ struct RicAcc {
     }
 
     // add the child's value function (P, p) seen through edge e
-    __device__ __forceinline__ void add_child(const EdgeRegs<NX, NU>& e, const double (&P)[NX][NX],
-                                              const double (&p)[NX])
+    __device__ __forceinline__ void add_child(const EdgeRegs<NX, NU, T>& e, const T (&P)[NX][NX],
+                                              const T (&p)[NX])
     {
-        double s[NX], PA[NX][NX], PB[NX][NU];
+        T s[NX], PA[NX][NX], PB[NX][NU];
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-            double acc = 0.0;
+            T acc = 0.0;
 #pragma unroll
             for (int k = 0; k < NX; ++k) acc += P[i][k] * e.c[k];
             s[i] = p[i] + acc;
 #pragma unroll
             for (int b = 0; b < NX; ++b) {
-                double t = 0.0;
+                T t = 0.0;
 #pragma unroll
                 for (int k = 0; k < NX; ++k) t += P[i][k] * e.A[k][b];
                 PA[i][b] = t;
             }
 #pragma unroll
             for (int b = 0; b < NU; ++b) {
-                double t = 0.0;
+                T t = 0.0;
 #pragma unroll
                 for (int k = 0; k < NX; ++k) t += P[i][k] * e.B[k][b];
                 PB[i][b] = t;
@@ -266,19 +268,19 @@ struct RicAcc {
         for (int i = 0; i < NU; ++i) {
 #pragma unroll
             for (int b = 0; b < NU; ++b) {
-                double t = 0.0;
+                T t = 0.0;
 #pragma unroll
                 for (int k = 0; k < NX; ++k) t += e.B[k][i] * PB[k][b];
                 H[i][b] += t;
             }
 #pragma unroll
             for (int b = 0; b < NX; ++b) {
-                double t = 0.0;
+                T t = 0.0;
 #pragma unroll
                 for (int k = 0; k < NX; ++k) t += e.B[k][i] * PA[k][b];
                 G[i][b] += t;
             }
-            double t = 0.0;
+            T t = 0.0;
 #pragma unroll
             for (int k = 0; k < NX; ++k) t += e.B[k][i] * s[k];
             g[i] += t;
@@ -287,12 +289,12 @@ struct RicAcc {
         for (int i = 0; i < NX; ++i) {
 #pragma unroll
             for (int b = 0; b < NX; ++b) {
-                double t = 0.0;
+                T t = 0.0;
 #pragma unroll
                 for (int k = 0; k < NX; ++k) t += e.A[k][i] * PA[k][b];
                 W[i][b] += t;
             }
-            double t = 0.0;
+            T t = 0.0;
 #pragma unroll
             for (int k = 0; k < NX; ++k) t += e.A[k][i] * s[k];
             w[i] += t;
@@ -301,10 +303,10 @@ struct RicAcc {
 
     // gains K = -H^-1 G, k = -H^-1 g and the new value function; returns
     // false if H is not positive definite
-    __device__ __forceinline__ bool finish(double (&Kn)[NU][NX], double (&kn)[NU], double (&P)[NX][NX],
-                                          double (&p)[NX]) const
+    __device__ __forceinline__ bool finish(T (&Kn)[NU][NX], T (&kn)[NU], T (&P)[NX][NX],
+                                          T (&p)[NX]) const
     {
-        double L[NU][NU], inv[NU];
+        T L[NU][NU], inv[NU];
 #pragma unroll
         for (int i = 0; i < NU; ++i)
 #pragma unroll
@@ -312,7 +314,7 @@ struct RicAcc {
         const bool ok = chol_inplace<NU>(L, inv);
 #pragma unroll
         for (int b = 0; b < NX; ++b) {
-            double v[NU];
+            T v[NU];
 #pragma unroll
             for (int i = 0; i < NU; ++i) v[i] = G[i][b];
             chol_solve<NU>(L, inv, v);
@@ -320,7 +322,7 @@ struct RicAcc {
             for (int i = 0; i < NU; ++i) Kn[i][b] = -v[i];
         }
         {
-            double v[NU];
+            T v[NU];
 #pragma unroll
             for (int i = 0; i < NU; ++i) v[i] = g[i];
             chol_solve<NU>(L, inv, v);
@@ -332,12 +334,12 @@ struct RicAcc {
         for (int i = 0; i < NX; ++i) {
 #pragma unroll
             for (int b = 0; b < NX; ++b) {
-                double t = W[i][b];
+                T t = W[i][b];
 #pragma unroll
                 for (int rr = 0; rr < NU; ++rr) t += G[rr][i] * Kn[rr][b];
                 P[i][b] = t;
             }
-            double t = w[i];
+            T t = w[i];
 #pragma unroll
             for (int rr = 0; rr < NU; ++rr) t += G[rr][i] * kn[rr];
             p[i] = t;
@@ -346,7 +348,7 @@ struct RicAcc {
         for (int i = 0; i < NX; ++i)
 #pragma unroll
             for (int b = i + 1; b < NX; ++b) {
-                const double m = 0.5 * (P[i][b] + P[b][i]);
+                const T m = 0.5 * (P[i][b] + P[b][i]);
                 P[i][b] = m;
                 P[b][i] = m;
             }

@@ -297,6 +297,76 @@ def test_extended_precision_recursion_solves_the_same_problem_more_accurately():
     assert re * 10 <= rd
 
 
+def _kkt_rows(inst, sol):
+    """KKT rows of the tree QP at (x, u, lam), every node including the root:
+    g_u (control nodes; zero at leaves), g_x (with -lam_n; at the root lam_0 is
+    the multiplier of x_0 = x0) and the defects d (root: x0 - x_0)."""
+    par = inst.parent
+    N = len(par)
+    x, u, lam = sol["x"], sol["u"], sol["lam"]
+    nch = S.num_children(par)
+    gx, gu, d = np.zeros_like(x), np.zeros_like(u), np.zeros_like(x)
+    for n in range(N):
+        kids = np.nonzero(par == n)[0]
+        gx[n] = inst.Q[n] @ x[n] + inst.q[n] - lam[n] + sum((inst.A[j].T @ lam[j] for j in kids), 0.0)
+        if nch[n] > 0:
+            gx[n] += inst.M[n].T @ u[n]
+            gu[n] = inst.R[n] @ u[n] + inst.M[n] @ x[n] + inst.r[n] + sum(inst.B[j].T @ lam[j] for j in kids)
+        d[n] = inst.x0 - x[n] if par[n] < 0 else inst.A[n] @ x[par[n]] + inst.B[n] @ u[par[n]] + inst.c[n] - x[n]
+    return gx, gu, d
+
+
+def test_single_precision_recursion_is_float_accurate():
+    """The float recursion (inputs rounded to float) agrees with the
+    long-double one to float accuracy on well-conditioned trees, not better:
+    relative errors between 1e-9 and 1e-5, and the KKT rows of its solution
+    are of the same order."""
+    for dims, seed in (((3, 1), 1), ((4, 2), 2), ((6, 3), 3)):
+        inst = S.lqr_on(S.tree_parent(9, [1, 3, 6], 3), *dims, seed=seed, random_cost=True)
+        e = oracle.tree_lqr_inst(inst, extended=True)
+        f = oracle.tree_lqr_inst(inst, single=True)
+        for k in ("x", "u", "lam", "K", "P"):
+            err = np.abs(f[k] - e[k]).max() / np.abs(e[k]).max()
+            assert 1e-9 < err < 1e-5, (dims, k, err)
+        rows = _kkt_rows(inst, f)
+        scale = max(np.abs(inst.q).max(), np.abs(inst.c).max(), 1.0)
+        assert max(np.abs(r).max() for r in rows) < 1e-4 * scale
+        assert max(np.abs(r).max() for r in _kkt_rows(inst, e)) < 1e-12 * scale
+
+
+def test_iterative_refinement_with_float_solves_reaches_the_double_solution():
+    """Refinement as the mixed-precision solver does it, carried out with the
+    oracle's float recursion: each step solves the tree QP whose linear terms
+    (q, r, c, x0) are the KKT rows of the current iterate and adds the
+    solution.  The error contracts by about cond * 2^-24 per step and three
+    steps reach the double-precision solution to 1e-12; with the signs of
+    any one linear term flipped the iteration does not converge."""
+    inst = S.lqr_on(S.tree_parent(12, [2, 6], 2), 4, 2, seed=4, random_cost=True)
+    ref = oracle.tree_lqr_inst(inst, extended=True)
+
+    def refine(flip=None, steps=3):
+        z = {k: np.zeros_like(ref[k]) for k in ("x", "u", "lam")}
+        errs = []
+        for _ in range(steps + 1):
+            gx, gu, d = _kkt_rows(inst, z)
+            lin = {"q": gx, "r": gu, "c": d.copy(), "x0": d[0].copy()}
+            if flip:
+                lin[flip] = -lin[flip]
+            dz = oracle.tree_lqr(inst.parent, inst.A, inst.B, lin["c"], inst.Q, inst.R, inst.M, lin["q"],
+                                 lin["r"], lin["x0"], single=True)
+            for k in z:
+                z[k] = z[k] + dz[k]
+            errs.append(max(np.abs(z[k] - ref[k]).max() / np.abs(ref[k]).max() for k in z))
+        return errs
+
+    errs = refine()
+    print("refinement errors", errs)
+    assert errs[0] > 1e-9 and errs[-1] < 1e-12
+    assert all(b < 1e-3 * a or b < 1e-13 for a, b in zip(errs, errs[1:]))
+    for flip in ("q", "r", "c"):
+        assert refine(flip)[-1] > 1e-3, flip
+
+
 # ----------------------------------------------------------------------------
 # chain of masses and springs (per-scenario dynamics)
 # ----------------------------------------------------------------------------
