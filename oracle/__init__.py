@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = ["oracle_lqr.c", "oracle_bmpc.c", "oracle_mlp.c"]
+SOURCES = ["oracle_lqr.c", "oracle_bmpc.c", "oracle_hess.c", "oracle_mlp.c"]
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "TOPOLOGY", 3: "NOT_PD", 4: "NONFINITE",
           5: "MAXITER", 6: "LINESEARCH"}
@@ -92,7 +92,8 @@ class Settings(C.Structure):
                 ("a_eta", C.c_double), ("b_eta", C.c_double), ("rho0", C.c_double),
                 ("mu0", C.c_double), ("armijo_beta", C.c_double), ("n_alpha", C.c_int),
                 ("max_outer", C.c_int), ("max_inner", C.c_int), ("max_ls_fail", C.c_int),
-                ("max_iter_total", C.c_int), ("ls_rounds", C.c_int)]
+                ("max_iter_total", C.c_int), ("ls_rounds", C.c_int), ("hessian", C.c_int),
+                ("eig_floor", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -130,6 +131,18 @@ def _declare(L):
     L.orc_direction.restype = C.c_int
     L.orc_direction.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, C.c_double, C.c_double,
                                 _dp, _dp, _dp, _dp]
+    L.orc_direction_h.restype = C.c_int
+    L.orc_direction_h.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_int,
+                                  C.c_double, _dp, _dp, _dp, _dp]
+    L.orc_rk4_hessian.restype = None
+    L.orc_rk4_hessian.argtypes = [C.POINTER(Model), _dp, _dp, _dp, _dp]
+    L.orc_sym_eig.restype = C.c_int
+    L.orc_sym_eig.argtypes = [C.c_int, _dp, _dp, _dp]
+    L.orc_eig_modify.restype = C.c_int
+    L.orc_eig_modify.argtypes = [C.c_int, _dp, C.c_double, _dp]
+    L.orc_node_quadratic.restype = None
+    L.orc_node_quadratic.argtypes = [C.POINTER(Problem), C.c_int, _dp, _dp, _dp, _dp, C.c_double, C.c_int,
+                                     C.c_double, C.c_int, _dp, _dp, _dp, _dp, _dp]
     L.orc_kkt.restype = C.c_double
     L.orc_kkt.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, _dp, C.c_double]
     L.orc_adjoint.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_double, _dp]
@@ -365,19 +378,56 @@ def kkt(pb, x, u, lam, ye, rho):
     return lib().orc_kkt(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(lam)), _d(_f64(ye)), rho)
 
 
-def direction(pb, x, u, lam, ye, rho, mu):
+def direction(pb, x, u, lam, ye, rho, mu, hessian=0, eig_floor=1e-6):
     """One search direction at (x, u, lam): the tree-LQR step and the merit
     slope pieces.  Returns (dx, du, lam_hat, dict) with the dict holding
-    gtd, dhd, lhd, dd, mu_hat, mu, dphi0, phi0."""
+    gtd, dhd, lhd, dd, mu_hat, mu, dphi0, phi0.  hessian=1 takes the exact
+    Hessian with eigenvalue modification."""
     N = pb.N
     dx, du, lh = np.zeros((N, 4)), np.zeros((N, 2)), np.zeros((N, 4))
     out = np.zeros(8)
-    st = lib().orc_direction(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(lam)), _d(_f64(ye)), rho, mu,
-                             _d(dx), _d(du), _d(lh), _d(out))
+    st = lib().orc_direction_h(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(lam)), _d(_f64(ye)), rho, mu,
+                               int(hessian), float(eig_floor), _d(dx), _d(du), _d(lh), _d(out))
     if st != 0:
         raise OracleError(st)
     keys = ("gtd", "dhd", "lhd", "dd", "mu_hat", "mu", "dphi0", "phi0")
     return dx, du, lh, dict(zip(keys, out.tolist()))
+
+
+def rk4_hessian(model: Model, x, u, mu):
+    """Second derivatives (6 x 6, z = (x, u)) of mu^T F(x, u)."""
+    H = np.zeros((6, 6))
+    lib().orc_rk4_hessian(C.byref(model), _d(_f64(x)), _d(_f64(u)), _d(_f64(mu)), _d(H))
+    return H
+
+
+def sym_eig(A):
+    A = _f64(A)
+    n = A.shape[0]
+    w, V = np.zeros(n), np.zeros((n, n))
+    st = lib().orc_sym_eig(n, _d(A), _d(w), _d(V))
+    if st != 0:
+        raise OracleError(st)
+    return w, V
+
+
+def eig_modify(A, delta):
+    A = _f64(A)
+    n = A.shape[0]
+    out = np.zeros((n, n))
+    st = lib().orc_eig_modify(n, _d(A), float(delta), _d(out))
+    if st != 0:
+        raise OracleError(st)
+    return out
+
+
+def node_quadratic(pb, n, x, u, lam, ye, rho, hessian=1, eig_floor=1e-6, modify=True):
+    """Quadratic model of node n: q, r, Q, R, M (whole-tree state arrays)."""
+    q, r = np.zeros(4), np.zeros(2)
+    Q, R, M = np.zeros((4, 4)), np.zeros((2, 2)), np.zeros((2, 4))
+    lib().orc_node_quadratic(pb.ptr, int(n), _d(_f64(x)), _d(_f64(u)), _d(_f64(lam)), _d(_f64(ye)), float(rho),
+                             int(hessian), float(eig_floor), int(bool(modify)), _d(q), _d(r), _d(Q), _d(R), _d(M))
+    return q, r, Q, R, M
 
 
 def violation(pb, x, u, ye, rho):

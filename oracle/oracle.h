@@ -89,6 +89,8 @@ typedef struct {
     int n_alpha, max_outer, max_inner, max_ls_fail;
     int max_iter_total; /* cap on inner iterations over all outer ones, 0 = none */
     int ls_rounds;      /* backtracking rounds of n_alpha step sizes each */
+    int hessian;        /* 0 = Gauss-Newton, 1 = exact with eigenvalue modification */
+    double eig_floor;   /* eigenvalues of the exact node Hessian raised to at least this */
 } orc_settings;
 
 typedef struct {
@@ -108,6 +110,22 @@ int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm,
 /* pieces exported for pinning */
 void orc_rk4(const orc_model* m, const double* x, const double* u, double* xn,
              double* A, double* B);
+/* ---- exact Hessian pieces, oracle_hess.c ---- */
+/* H (6 x 6, z = (x, u)) = second derivatives of mu^T F(x, u), F the model's
+ * step (zero for the linear model). */
+void orc_rk4_hessian(const orc_model* m, const double* x, const double* u, const double* mu,
+                     double* H);
+/* Symmetric eigendecomposition A = V diag(w) V^T (n <= 6, cyclic Jacobi);
+ * V row-major, eigenvector k in column k. */
+int orc_sym_eig(int n, const double* A, double* w, double* V);
+/* out = V diag(max(w, delta)) V^T */
+int orc_eig_modify(int n, const double* A, double delta, double* out);
+/* Quadratic model of node n (all state arrays of the whole tree): q, r and
+ * the Hessian blocks Q (4x4), R (2x2), M (2x4) for the given Hessian choice;
+ * modify = 0 leaves the exact Hessian unmodified (for the pins). */
+void orc_node_quadratic(const orc_problem* pb, int n, const double* x, const double* u,
+                        const double* lam, const double* ye, double rho, int hessian, double delta,
+                        int modify, double* q, double* r, double* Q, double* R, double* M);
 void orc_node_weights(int N, const int* parent, const double* leaf_prob, double* weight);
 void orc_node_refs(int N, const int* parent, const double* leaf_prob, const double* leaf_offset,
                    double dt, double speed, double* ref);
@@ -126,6 +144,9 @@ double orc_kkt(const orc_problem* pb, const double* x, const double* u, const do
  *   out[3] = d^T d, out[4] = mu_hat (0 if d = 0), out[5] = mu after the
  *   update, out[6] = phi'(0) at that mu, out[7] = phi(0) at that mu.
  * Returns the LQR status. */
+int orc_direction_h(const orc_problem* pb, const double* x, const double* u, const double* lam,
+                    const double* ye, double rho, double mu, int hessian, double delta, double* dx,
+                    double* du, double* lh, double* out);
 int orc_direction(const orc_problem* pb, const double* x, const double* u, const double* lam,
                   const double* ye, double rho, double mu, double* dx, double* du, double* lh,
                   double* out);

@@ -13,7 +13,9 @@
  * Readings of the paper taken here (each stated where it is used):
  *   - node weights pi_n multiply the stage and terminal costs, not the
  *     constraints; pi_n is the total probability of the scenarios through n;
- *   - Gauss-Newton Hessian: dynamics and constraint curvature are dropped;
+ *   - Hessian: Gauss-Newton (dynamics and constraint curvature dropped) by
+ *     default; or the exact Hessian of the Lagrangian per node with its
+ *     eigenvalues below delta raised to delta (settings.hessian = 1);
  *   - the merit's J is the augmented objective L_a; lambda is line-searched
  *     jointly with (x, u) towards the LQR costates;
  *   - alpha set {2^0 .. 2^-(K-1)}, Armijo constant 1e-4;
@@ -50,6 +52,8 @@ void orc_settings_default(orc_settings* s)
     s->max_ls_fail = 3;
     s->max_iter_total = 0;
     s->ls_rounds = 3;
+    s->hessian = 0;
+    s->eig_floor = 1e-6;
 }
 
 /* ------------------------------------------------------------------------
@@ -280,6 +284,87 @@ static int* child_counts(const orc_problem* pb)
     return nch;
 }
 
+/* The quadratic model of node n (Sec. IV-A, search direction): gradient
+ * (q, r) of the augmented objective and the Hessian blocks Q, R, M of the
+ * node's part of the Lagrangian
+ *   L_a,n(x_n, u_n) + sum_{j child of n} lam_j^T f(x_n, u_n).
+ * hessian = 0: Gauss-Newton (M = 0).  hessian = 1: exact, i.e. in addition
+ *   - the curvature of the active obstacle penalty, rho t grad^2 g with
+ *     t = g + y/rho and grad^2 g = -(I - e e^T) / dist (e the unit vector
+ *     from the obstacle to the position), and
+ *   - the dynamics curvature sum_a mu_a grad^2 F_a, mu = sum of the
+ *     children's multipliers;
+ * then, with modify, the whole (x, u) block (x only at a leaf) has its
+ * eigenvalues below delta raised to delta. */
+static void node_quadratic(const orc_problem* pb, const int* nch, int n, const double* x,
+                           const double* u, const double* lam, const double* ye, double rho,
+                           int hessian, double delta, int modify, double* q, double* r, double* Q,
+                           double* R, double* M)
+{
+    const int leaf = nch[n] == 0;
+    const double* xn = x + (size_t)n * NX;
+    const double* un = u + (size_t)n * NU;
+    const double* yn = ye + (size_t)n * NG;
+    double Hxx[NX * NX], Huu[NU * NU];
+    node_terms_impl(pb, n, leaf, xn, un, yn, rho, NULL, q, r, Hxx, Huu);
+    memcpy(Q, Hxx, sizeof Hxx);
+    memcpy(R, Huu, sizeof Huu);
+    memset(M, 0, sizeof(double) * NU * NX);
+    if (hessian == 0) return;
+    enum { NZ = NX + NU };
+    double H[NZ * NZ];
+    memset(H, 0, sizeof H);
+    for (int a = 0; a < NX; ++a)
+        for (int b = 0; b < NX; ++b) H[a * NZ + b] = Hxx[a * NX + b];
+    for (int a = 0; a < NU; ++a)
+        for (int b = 0; b < NU; ++b) H[(NX + a) * NZ + NX + b] = Huu[a * NU + b];
+    if (pb->has_obs[n]) {
+        const double ddx = xn[0] - pb->obs[n * 2 + 0];
+        const double ddy = xn[1] - pb->obs[n * 2 + 1];
+        const double dist = sqrt(ddx * ddx + ddy * ddy);
+        const double t = (pb->model.obs_r - dist) + yn[4] / rho;
+        if (t > 0.0 && dist > 0.0) {
+            const double e[2] = {ddx / dist, ddy / dist};
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    H[a * NZ + b] += rho * t * (-((a == b ? 1.0 : 0.0) - e[a] * e[b]) / dist);
+        }
+    }
+    if (!leaf) {
+        double mu[NX] = {0, 0, 0, 0}, Hd[NZ * NZ];
+        for (int j = 1; j < pb->N; ++j)
+            if (pb->parent[j] == n)
+                for (int a = 0; a < NX; ++a) mu[a] += lam[(size_t)j * NX + a];
+        orc_rk4_hessian(&pb->model, xn, un, mu, Hd);
+        for (int e = 0; e < NZ * NZ; ++e) H[e] += Hd[e];
+    }
+    const int nz = leaf ? NX : NZ;
+    double Hm[NZ * NZ], Hs[NZ * NZ];
+    for (int a = 0; a < nz; ++a)
+        for (int b = 0; b < nz; ++b) Hs[a * nz + b] = H[a * NZ + b];
+    if (modify)
+        orc_eig_modify(nz, Hs, delta, Hm);
+    else
+        memcpy(Hm, Hs, sizeof(double) * nz * nz);
+    for (int a = 0; a < NX; ++a)
+        for (int b = 0; b < NX; ++b) Q[a * NX + b] = Hm[a * nz + b];
+    if (!leaf) {
+        for (int a = 0; a < NU; ++a) {
+            for (int b = 0; b < NX; ++b) M[a * NX + b] = Hm[(NX + a) * nz + b];
+            for (int b = 0; b < NU; ++b) R[a * NU + b] = Hm[(NX + a) * nz + NX + b];
+        }
+    }
+}
+
+void orc_node_quadratic(const orc_problem* pb, int n, const double* x, const double* u,
+                        const double* lam, const double* ye, double rho, int hessian, double delta,
+                        int modify, double* q, double* r, double* Q, double* R, double* M)
+{
+    int* nch = child_counts(pb);
+    node_quadratic(pb, nch, n, x, u, lam, ye, rho, hessian, delta, modify, q, r, Q, R, M);
+    free(nch);
+}
+
 double orc_node_terms(const orc_problem* pb, int n, const double* x, const double* u,
                       const double* ye, double rho, double* g, double* gx, double* gu,
                       double* Hxx, double* Huu)
@@ -497,16 +582,16 @@ static double start_measure(const orc_problem* pb, const double* x, const double
  * (lh - 2 lambda)^T d, ||d||^2, mu_hat, the new mu, phi'(0) and phi(0). */
 static int direction_step(const orc_problem* pb, const int* nch, const double* x,
                           const double* u, const double* lam, const double* ye, double rho,
-                          double mu, double* A, double* B, double* c, double* Q, double* R,
+                          double mu, int hessian, double delta, double* A, double* B, double* c,
+                          double* Q, double* R,
                           double* M, double* q, double* r, double* dx, double* du, double* lh,
                           double* K, double* kk, double* P, double* p, int* bad, double* sl)
 {
     const int N = pb->N;
     const double zero_x[NX] = {0, 0, 0, 0};
     for (int n = 0; n < N; ++n) {
-        node_terms_impl(pb, n, nch[n] == 0, x + n * NX, u + n * NU, ye + n * NG, rho, NULL,
-                        q + n * NX, r + n * NU, Q + n * NX * NX, R + n * NU * NU);
-        memset(M + n * NU * NX, 0, sizeof(double) * NU * NX);
+        node_quadratic(pb, nch, n, x, u, lam, ye, rho, hessian, delta, 1, q + n * NX, r + n * NU,
+                       Q + n * NX * NX, R + n * NU * NU, M + n * NU * NX);
         if (n > 0) defect(pb, n, x, u, c + n * NX, A + n * NX * NX, B + n * NX * NU);
     }
     const int lst = orc_tree_lqr(N, NX, NU, pb->parent, A, B, c, Q, R, M, q, r, zero_x, dx,
@@ -516,6 +601,7 @@ static int direction_step(const orc_problem* pb, const int* nch, const double* x
     for (int n = 0; n < N; ++n) {
         const double* Qn = Q + n * NX * NX;
         const double* Rn = R + n * NU * NU;
+        const double* Mn = M + n * NU * NX;
         for (int a = 0; a < NX; ++a) {
             gtd += q[n * NX + a] * dx[n * NX + a];
             for (int b = 0; b < NX; ++b) dhd += dx[n * NX + a] * Qn[a * NX + b] * dx[n * NX + b];
@@ -524,6 +610,7 @@ static int direction_step(const orc_problem* pb, const int* nch, const double* x
             for (int a = 0; a < NU; ++a) {
                 gtd += r[n * NU + a] * du[n * NU + a];
                 for (int b = 0; b < NU; ++b) dhd += du[n * NU + a] * Rn[a * NU + b] * du[n * NU + b];
+                for (int b = 0; b < NX; ++b) dhd += 2.0 * du[n * NU + a] * Mn[a * NX + b] * dx[n * NX + b];
             }
         if (n > 0)
             for (int a = 0; a < NX; ++a) {
@@ -551,6 +638,13 @@ int orc_direction(const orc_problem* pb, const double* x, const double* u, const
                   const double* ye, double rho, double mu, double* dx, double* du, double* lh,
                   double* out)
 {
+    return orc_direction_h(pb, x, u, lam, ye, rho, mu, 0, 0.0, dx, du, lh, out);
+}
+
+int orc_direction_h(const orc_problem* pb, const double* x, const double* u, const double* lam,
+                    const double* ye, double rho, double mu, int hessian, double delta, double* dx,
+                    double* du, double* lh, double* out)
+{
     const int N = pb->N;
     int* nch = child_counts(pb);
     double* A = calloc((size_t)N * NX * NX, sizeof(double));
@@ -566,7 +660,7 @@ int orc_direction(const orc_problem* pb, const double* x, const double* u, const
     double* P = calloc((size_t)N * NX * NX, sizeof(double));
     double* p = calloc((size_t)N * NX, sizeof(double));
     int bad = -1;
-    const int st = direction_step(pb, nch, x, u, lam, ye, rho, mu, A, B, c, Q, R, M, q, r, dx,
+    const int st = direction_step(pb, nch, x, u, lam, ye, rho, mu, hessian, delta, A, B, c, Q, R, M, q, r, dx,
                                   du, lh, K, kk, P, p, &bad, out);
     free(nch); free(A); free(B); free(c); free(Q); free(R); free(M); free(q); free(r);
     free(K); free(kk); free(P); free(p);
@@ -660,7 +754,8 @@ int orc_bmpc_solve(const orc_problem* pb, const orc_settings* st, int warm, doub
 
             /* search direction, merit slope and the adaptive mu */
             double sl[8];
-            int lst = direction_step(pb, nch, x, u, lam, ye, rho, mu, A, B, c, Q, R, M, q, r,
+            int lst = direction_step(pb, nch, x, u, lam, ye, rho, mu, st->hessian, st->eig_floor, A, B, c,
+                                     Q, R, M, q, r,
                                      dx, du, lh, K, kk, P, p, &bad, sl);
             if (lst != ORC_OK) {
                 status = lst;
