@@ -406,13 +406,30 @@ def run_bmpc(args, torch, L):
     torch.cuda.synchronize()
     ms_single = ev0.elapsed_time(ev1) / (reps * len(b1))
     st1 = [L.bmpc_batch_stats(b, 1)[0] for b in b1]
+    # the same solves with the exact Hessian and eigenvalue modification
+    st_ex = L.bmpc_settings_default(hessian=L.HESSIAN_EXACT)
+    for b in b1:
+        L.bmpc_batch_launch(b, st_ex)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        for b in b1:
+            L.bmpc_batch_launch(b, st_ex)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_single_ex = ev0.elapsed_time(ev1) / (reps * len(b1))
+    st1_ex = [L.bmpc_batch_stats(b, 1)[0] for b in b1]
     out["bmpc_single"] = {
         "workload": "single branch-MPC tree: bicycle, horizon 20, trunk 5 stages then 3 branches, "
                     "53 nodes, seeds 0-7, cold start",
         "ms_per_solve": round(ms_single, 4), "solves_per_s": round(1e3 / ms_single, 1),
         "converged": sum(s["status"] == 0 for s in st1), "of": len(st1),
         "mean_inner_it": float(np.mean([s["inner_it"] for s in st1])),
-        "phase_us_per_iteration": phase_us_per_iteration(st1)}
+        "phase_us_per_iteration": phase_us_per_iteration(st1),
+        "exact_hessian": {"ms_per_solve": round(ms_single_ex, 4), "solves_per_s": round(1e3 / ms_single_ex, 1),
+                          "converged": sum(s["status"] == 0 for s in st1_ex), "of": len(st1_ex),
+                          "mean_inner_it": float(np.mean([s["inner_it"] for s in st1_ex])),
+                          "phase_us_per_iteration": phase_us_per_iteration(st1_ex)}}
     for b in b1:
         L.bmpc_batch_destroy(b)
     for p in single:
@@ -456,6 +473,13 @@ def run_bmpc(args, torch, L):
     torch.cuda.synchronize()
     ms_cap = ev0.elapsed_time(ev1)
     s_cap = L.bmpc_batch_stats(b, len(insts))
+    # cold, exact Hessian with eigenvalue modification (tuned pair)
+    ev0.record()
+    L.bmpc_batch_launch(b, st_ex)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_ex = ev0.elapsed_time(ev1)
+    s_ex = L.bmpc_batch_stats(b, len(insts))
     # receding-horizon step, then warm and cold solves of the same shifted problems
     L.bmpc_batch_launch(b, st)  # back to the solution at t
     torch.cuda.synchronize()
@@ -529,6 +553,11 @@ def run_bmpc(args, torch, L):
         "cold_tuned_cap_200_iterations": {"ms": round(ms_cap, 3), "converged": conv(s_cap),
                                           "mean_inner_it": mean_it(s_cap),
                                           "solves_per_s": round(conv(s_cap) / (ms_cap / 1e3), 1)},
+        "cold_tuned_exact_hessian": {"ms": round(ms_ex, 3), "converged": conv(s_ex), "mean_inner_it": mean_it(s_ex),
+                                     "solves_per_s": round(conv(s_ex) / (ms_ex / 1e3), 1),
+                                     "most_iterations": slowest(s_ex, insts),
+                                     "not_converged_by_status": not_converged(s_ex),
+                                     "phase_us_per_iteration": phase_us_per_iteration(s_ex)},
         "closed_loop_graph_replay": {"captured": "shift + shifted-warm solve", "steps": len(loop_ms),
                                      "ms_per_step": [round(v, 3) for v in loop_ms], "converged": loop_conv},
         "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]} for k, v in prof.items()},

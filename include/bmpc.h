@@ -211,7 +211,8 @@ typedef struct {
    a_omega = b_omega = 1, a_eta 0.1, b_eta 0.9, rho0 100, mu0 100, Armijo
    constant 1e-4, n_alpha 10 step sizes 2^0 .. 2^-9 per backtracking round,
    ls_rounds 3, max_outer 50, max_inner 100 (per outer iteration),
-   max_ls_fail 3 consecutive line-search failures.  The merit of a trial
+   max_ls_fail 3 consecutive line-search failures, Gauss-Newton Hessian
+   (eig_floor 1e-6 for the exact one).  The merit of a trial
    point whose steering angle leaves (-pi/2, pi/2), where the bicycle model is
    undefined, is +inf.  Tolerances omega and eta are floored at eps_tol. */
 typedef struct {
@@ -233,7 +234,16 @@ typedef struct {
        a step, the step 2^-(ls_rounds n_alpha - 1) is taken and counted as a
        line-search failure */
     int32_t ls_rounds;
+    /* Hessian of the quadratic model (Sec. IV-A): BMPC_HESSIAN_GAUSS_NEWTON
+       (dynamics and constraint curvature dropped), or BMPC_HESSIAN_EXACT:
+       the Hessian of the Lagrangian per node -- with the curvature of the
+       active obstacle penalty and the dynamics curvature contracted with the
+       children's multipliers, which gives a cross block M -- whose
+       eigenvalues below eig_floor (> 0) are raised to eig_floor. */
+    int32_t hessian;
+    double eig_floor;
 } bmpc_settings;
+enum { BMPC_HESSIAN_GAUSS_NEWTON = 0, BMPC_HESSIAN_EXACT = 1 };
 
 /* Result of one solve.  r_kkt: last KKT residual of the relaxed problem
    (infinity norm of the Lagrangian gradient and of the defects); viol:
@@ -326,10 +336,19 @@ BMPC_API bmpc_status bmpc_linearize(bmpc_problem* problem, const double* x, cons
                                     double* c, double* Q, double* R, double* q, double* r, double* kkt_viol,
                                     void* stream);
 
+/* The same with the exact Hessian with eigenvalue modification
+   (BMPC_HESSIAN_EXACT, floor eig_floor > 0): additionally M (N*2*4, the
+   cross block d2/du dx per node, zero at leaves); Q and R are the modified
+   blocks. */
+BMPC_API bmpc_status bmpc_linearize_exact(bmpc_problem* problem, double eig_floor, const double* x,
+                                          const double* u, const double* lam, const double* ye, double rho,
+                                          double* A, double* B, double* c, double* Q, double* R, double* M,
+                                          double* q, double* r, double* kkt_viol, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
    capture, tight serving loops, harnesses that forbid hipMalloc): the same
    linearisation as bmpc_linearize, with its workspace rows in a fixed
-   library-owned array of BMPC_NOALLOC_MAX_NODES rows per GPU (3.4 MB, held
+   library-owned array of BMPC_NOALLOC_MAX_NODES rows per GPU (3.6 MB, held
    until the process ends) instead of memory allocated for the problem.
    The call allocates nothing.  Arguments as in bmpc_linearize, except
    kkt_viol: a DEVICE pointer (2 doubles, nullable) written by the kernel,

@@ -287,7 +287,12 @@ class bmpc_settings(C.Structure):
                 ("mu0", C.c_double), ("armijo_beta", C.c_double), ("n_alpha", C.c_int32),
                 ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("max_ls_fail", C.c_int32),
                 ("riccati_variant", C.c_int32), ("block_size", C.c_int32),
-                ("max_iter_total", C.c_int32), ("ls_rounds", C.c_int32)]
+                ("max_iter_total", C.c_int32), ("ls_rounds", C.c_int32), ("hessian", C.c_int32),
+                ("eig_floor", C.c_double)]
+
+
+HESSIAN_GAUSS_NEWTON = 0
+HESSIAN_EXACT = 1
 
 
 class bmpc_stats(C.Structure):
@@ -322,6 +327,7 @@ _sig("bmpc_solve", _i32, [_vp, C.POINTER(bmpc_settings), _i32, _vp, _vp, _vp, _v
                           C.POINTER(bmpc_stats), _vp])
 _sig("bmpc_linearize", _i32, [_vp, _vp, _vp, _vp, _vp, C.c_double] + [_vp] * 7 + [_pd, _vp])
 _sig("bmpc_linearize_noalloc", _i32, [_vp, _vp, _vp, _vp, _vp, C.c_double] + [_vp] * 8 + [_vp])
+_sig("bmpc_linearize_exact", _i32, [_vp, C.c_double, _vp, _vp, _vp, _vp, C.c_double] + [_vp] * 8 + [_pd, _vp])
 NOALLOC_MAX_NODES = 2048
 _sig("bmpc_batch_create", _i32, [C.POINTER(_vp), _i32, _i32, C.POINTER(_vp)])
 _sig("bmpc_batch_destroy", None, [_vp])
@@ -421,6 +427,19 @@ def bmpc_linearize(problem, x, u, lam, ye, rho, A, B, c, Q, R, q, r, stream=None
           (Q, 16, "Q"), (R, 4, "R"), (q, 4, "q"), (r, 2, "r"))])
     check(lib.bmpc_linearize(problem, f[0], f[1], f[2], f[3], rho, *f[4:], kv.ctypes.data_as(_pd),
                              stream_ptr(stream)))
+    return float(kv[0]), float(kv[1])
+
+
+def bmpc_linearize_exact(problem, eig_floor, x, u, lam, ye, rho, A, B, c, Q, R, M, q, r, stream=None):
+    """bmpc_linearize with the exact Hessian and eigenvalue modification;
+    M (N*2*4) receives the cross blocks."""
+    kv = np.zeros(2)
+    N = _dims[_key(problem)]
+    f = _dptrs([(v, "float64", N * w, nm) for v, w, nm in
+         ((x, 4, "x"), (u, 2, "u"), (lam, 4, "lam"), (ye, 5, "ye"), (A, 16, "A"), (B, 8, "B"), (c, 4, "c"),
+          (Q, 16, "Q"), (R, 4, "R"), (M, 8, "M"), (q, 4, "q"), (r, 2, "r"))])
+    check(lib.bmpc_linearize_exact(problem, float(eig_floor), f[0], f[1], f[2], f[3], rho, *f[4:],
+                                   kv.ctypes.data_as(_pd), stream_ptr(stream)))
     return float(kv[0]), float(kv[1])
 
 

@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "bmpc_device.hpp"
+#include "bmpc_hess_device.hpp"
 #include "bmpc_internal.hpp"
 #include "lqr_device.hpp"
 #include "cvf_device.hpp"
@@ -60,7 +61,8 @@ enum WsOff : int {
     W_LH = 94,         // 4: LQR costates
     W_S0 = 98,         // 56: conditional value function (A, c, C, P, p), scan buffer 0
     W_S1 = 154,        // 56: scan buffer 1
-    W_NODE = 210
+    W_M = 210,         // 8: cross block d2/du dx of the model (zero for Gauss-Newton)
+    W_NODE = 218
 };
 
 struct InstDesc {
@@ -94,6 +96,8 @@ struct SolverCfg {
     double eps_tol, tau, omega0, eta0, a_omega, b_omega, a_eta, b_eta, rho0, mu0, beta;
     int n_alpha, max_outer, max_inner, max_ls_fail, max_total, ls_rounds;
     int warm;  // bits: 1 x,u given, 2 lam given, 4 ye given, 8 u given (x rolled out), 16 guarded
+    int hess;  // 0 Gauss-Newton, 1 exact Hessian with eigenvalue modification
+    double eig_floor;
 };
 
 // Phases of an inner iteration whose time the solver accumulates
@@ -245,9 +249,12 @@ struct TeamGrid {
 
 // ---------------------------------------------------------------- passes
 // Linearise dynamics, quadratise L_a; returns this thread's partial L_a and
-// constraint violation.
+// constraint violation.  hess = 1 replaces the Gauss-Newton Hessian blocks by
+// the exact ones with eigenvalue modification (floor eig_floor), which
+// take the children's multipliers.
 template <class T>
-__device__ void pass_linearise(const InstDesc& I, double rho, double& La, double& viol)
+__device__ void pass_linearise(const InstDesc& I, double rho, double& La, double& viol, int hess = 0,
+                               double eig_floor = 0.0)
 {
     La = 0.0;
     viol = 0.0;
@@ -259,10 +266,21 @@ __device__ void pass_linearise(const InstDesc& I, double rho, double& La, double
         u[1] = I.u[n * 2 + 1];
 #pragma unroll
         for (int s = 0; s < BG; ++s) ye[s] = I.ye[n * BG + s];
-        double q[BX], r[BU], Qh[BX][BX], Rh[BU][BU];
+        double q[BX], r[BU], Qh[BX][BX], Rh[BU][BU], Mh[BU][BX] = {};
         La += node_quad(I.prm, nd, x, u, ye, rho, q, r, Qh, Rh);
         if (!nd.leaf && !steer_in_domain(u)) La = INFINITY;
+        if (hess) {
+            double mu[BX] = {0.0, 0.0, 0.0, 0.0};
+            for (int j = I.child_off[n]; j < I.child_off[n + 1]; ++j)
+#pragma unroll
+                for (int i = 0; i < BX; ++i) mu[i] += I.lam[j * 4 + i];
+            exact_node_model(I.prm, nd, x, u, ye, rho, mu, eig_floor, Qh, Rh, Mh);
+        }
         double* w = I.ws + (long)n * W_NODE;
+#pragma unroll
+        for (int i = 0; i < BU; ++i)
+#pragma unroll
+            for (int j = 0; j < BX; ++j) w[W_M + i * 4 + j] = Mh[i][j];
 #pragma unroll
         for (int i = 0; i < BX; ++i) {
             w[W_QV + i] = q[i];
@@ -377,7 +395,7 @@ __device__ __forceinline__ void ric_node_ws(const InstDesc& I, int n, int* bad)
 #pragma unroll
         for (int j = 0; j < BU; ++j) st.R[i][j] = w[W_R + i * 2 + j];
 #pragma unroll
-        for (int j = 0; j < BX; ++j) st.M[i][j] = 0.0;
+        for (int j = 0; j < BX; ++j) st.M[i][j] = w[W_M + i * 4 + j];
         st.r[i] = w[W_RV + i];
     }
     RicAcc<BX, BU> acc;
@@ -494,7 +512,7 @@ __device__ __forceinline__ void stage_from_ws(const double* w, StageRegs<BX, BU>
 #pragma unroll
         for (int j = 0; j < BU; ++j) st.R[i][j] = w[W_R + i * 2 + j];
 #pragma unroll
-        for (int j = 0; j < BX; ++j) st.M[i][j] = 0.0;
+        for (int j = 0; j < BX; ++j) st.M[i][j] = w[W_M + i * 4 + j];
         st.r[i] = w[W_RV + i];
     }
 }
@@ -1356,7 +1374,7 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
         for (int inner = 0;; ++inner) {
             double La_p, vi_p, rk_p, ld_p, dd_p;
             clk.start(timer);
-            pass_linearise<T>(I, rho, La_p, vi_p);
+            pass_linearise<T>(I, rho, La_p, vi_p, cfg.hess, cfg.eig_floor);
             T::sync();
             pass_defects_kkt<T>(I, rk_p, ld_p, dd_p);
             double mx[2] = {rk_p, vi_p};
@@ -1421,6 +1439,8 @@ __device__ __forceinline__ void solve_one(const InstDesc* __restrict__ insts, in
                         sm[0] += w[W_RV + i] * w[W_DU + i];
 #pragma unroll
                         for (int j = 0; j < BU; ++j) sm[1] += w[W_DU + i] * w[W_R + i * 2 + j] * w[W_DU + j];
+#pragma unroll
+                        for (int j = 0; j < BX; ++j) sm[1] += 2.0 * w[W_DU + i] * w[W_M + i * 4 + j] * dx[j];
                     }
                 }
                 if (n > 0)
@@ -1653,11 +1673,12 @@ __global__ void __launch_bounds__(256) k_bmpc_grid(const InstDesc* __restrict__ 
 // Linearisation and quadratisation only (row a2), for testing and for
 // callers that bring their own LQR solver.
 template <int BS>
-__global__ void __launch_bounds__(BS) k_bmpc_linearise(InstDesc I, double rho, double* kkt_out)
+__global__ void __launch_bounds__(BS) k_bmpc_linearise(InstDesc I, double rho, double* kkt_out, int hess,
+                                                       double eig_floor)
 {
     __shared__ double sred[2 * (BS / 64)];
     double La, vi, rk, ld, dd;
-    pass_linearise<TeamWG<BS>>(I, rho, La, vi);
+    pass_linearise<TeamWG<BS>>(I, rho, La, vi, hess, eig_floor);
     __syncthreads();
     pass_defects_kkt<TeamWG<BS>>(I, rk, ld, dd);
     double mx[2] = {rk, vi};
@@ -1974,6 +1995,8 @@ static SolverCfg to_cfg(const bmpc_settings& s, int warm)
     c.max_ls_fail = s.max_ls_fail;
     c.ls_rounds = s.ls_rounds;
     c.warm = warm;
+    c.hess = s.hessian;
+    c.eig_floor = s.eig_floor;
     return c;
 }
 
@@ -2049,6 +2072,8 @@ BMPC_API void bmpc_settings_default(bmpc_settings* s)
     s->block_size = 0;
     s->max_iter_total = 0;
     s->ls_rounds = 3;
+    s->hessian = BMPC_HESSIAN_GAUSS_NEWTON;
+    s->eig_floor = 1e-6;
 }
 
 BMPC_API void bmpc_bicycle_default(bmpc_bicycle_params* p)
@@ -2297,6 +2322,10 @@ BMPC_API bmpc_status bmpc_batch_launch(bmpc_batch* b, const bmpc_settings* s, in
         return fail(BMPC_ERR_INVALID_ARG, "n_alpha must be in [1, %d]", NALPHA_MAX);
     if (s->ls_rounds < 1 || s->ls_rounds > LS_ROUNDS_MAX)
         return fail(BMPC_ERR_INVALID_ARG, "ls_rounds must be in [1, %d]", LS_ROUNDS_MAX);
+    if (s->hessian != BMPC_HESSIAN_GAUSS_NEWTON && s->hessian != BMPC_HESSIAN_EXACT)
+        return fail(BMPC_ERR_INVALID_ARG, "unknown Hessian choice %d", s->hessian);
+    if (s->hessian == BMPC_HESSIAN_EXACT && !(s->eig_floor > 0.0 && s->eig_floor < INFINITY))
+        return fail(BMPC_ERR_INVALID_ARG, "eig_floor must be positive and finite");
     if (s->riccati_variant != BMPC_RICCATI_AUTO && s->riccati_variant != BMPC_RICCATI_LEVEL &&
         s->riccati_variant != BMPC_RICCATI_SEGSCAN)
         return fail(BMPC_ERR_INVALID_ARG, "unknown Riccati variant %d", s->riccati_variant);
@@ -2394,6 +2423,10 @@ static bmpc_status check_tune_args(const bmpc_batch* b, const bmpc_settings* s, 
         return fail(BMPC_ERR_INVALID_ARG, "n_alpha must be in [1, %d]", NALPHA_MAX);
     if (s->ls_rounds < 1 || s->ls_rounds > LS_ROUNDS_MAX)
         return fail(BMPC_ERR_INVALID_ARG, "ls_rounds must be in [1, %d]", LS_ROUNDS_MAX);
+    if (s->hessian != BMPC_HESSIAN_GAUSS_NEWTON && s->hessian != BMPC_HESSIAN_EXACT)
+        return fail(BMPC_ERR_INVALID_ARG, "unknown Hessian choice %d", s->hessian);
+    if (s->hessian == BMPC_HESSIAN_EXACT && !(s->eig_floor > 0.0 && s->eig_floor < INFINITY))
+        return fail(BMPC_ERR_INVALID_ARG, "eig_floor must be positive and finite");
     return BMPC_OK;
 }
 
@@ -2748,13 +2781,16 @@ static bmpc_status scratch_for_current_device(double** out)
 
 extern "C" {
 
-BMPC_API bmpc_status bmpc_linearize(bmpc_problem* p, const double* x, const double* u, const double* lam,
-                                    const double* ye, double rho, double* A, double* B, double* c, double* Q,
-                                    double* R, double* q, double* r, double* kkt_viol, void* stream)
+static bmpc_status linearize_impl(bmpc_problem* p, int hess, double eig_floor, const double* x, const double* u,
+                                  const double* lam, const double* ye, double rho, double* A, double* B, double* c,
+                                  double* Q, double* R, double* M, double* q, double* r, double* kkt_viol,
+                                  void* stream)
 {
-    if (!p || !x || !u || !lam || !ye || !A || !B || !c || !Q || !R || !q || !r)
+    if (!p || !x || !u || !lam || !ye || !A || !B || !c || !Q || !R || !q || !r || (hess && !M))
         return fail(BMPC_ERR_INVALID_ARG, "NULL argument");
     if (!(rho > 0.0)) return fail(BMPC_ERR_INVALID_ARG, "rho must be positive");
+    if (hess && !(eig_floor > 0.0 && eig_floor < INFINITY))
+        return fail(BMPC_ERR_INVALID_ARG, "eig_floor must be positive and finite");
     bmpc_status st;
     if (!p->self) {
         bmpc_problem* one[1] = {p};
@@ -2770,7 +2806,7 @@ BMPC_API bmpc_status bmpc_linearize(bmpc_problem* p, const double* x, const doub
     double* kk = kkt_viol ? p->d_kkt : nullptr;
     {
         ProfScope ps("bmpc_linearise", sm);
-        hipLaunchKernelGGL(k_bmpc_linearise<256>, dim3(1), dim3(256), 0, sm, d, rho, kk);
+        hipLaunchKernelGGL(k_bmpc_linearise<256>, dim3(1), dim3(256), 0, sm, d, rho, kk, hess, eig_floor);
     }
     BMPC_HIP_TRY(hipGetLastError());
     // unpack the workspace rows into the caller's node-major arrays
@@ -2779,15 +2815,32 @@ BMPC_API bmpc_status bmpc_linearize(bmpc_problem* p, const double* x, const doub
     struct {
         double* dst;
         int off, w;
-    } parts[7] = {{A, W_A, 16}, {B, W_B, 8}, {c, W_C, 4}, {Q, W_Q, 16}, {R, W_R, 4}, {q, W_QV, 4}, {r, W_RV, 2}};
+    } parts[8] = {{A, W_A, 16}, {B, W_B, 8}, {c, W_C, 4}, {Q, W_Q, 16}, {R, W_R, 4}, {q, W_QV, 4}, {r, W_RV, 2},
+                  {M, W_M, 8}};
     for (auto& pt : parts)
-        BMPC_HIP_TRY(hipMemcpy2DAsync(pt.dst, sizeof(double) * pt.w, d.ws + pt.off, pitch, sizeof(double) * pt.w,
-                                      N, hipMemcpyDeviceToDevice, sm));
+        if (pt.dst)
+            BMPC_HIP_TRY(hipMemcpy2DAsync(pt.dst, sizeof(double) * pt.w, d.ws + pt.off, pitch,
+                                          sizeof(double) * pt.w, N, hipMemcpyDeviceToDevice, sm));
     if (kkt_viol) {
         BMPC_HIP_TRY(hipMemcpyAsync(kkt_viol, kk, 2 * sizeof(double), hipMemcpyDeviceToHost, sm));
         BMPC_HIP_TRY(hipStreamSynchronize(sm));
     }
     return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_linearize(bmpc_problem* p, const double* x, const double* u, const double* lam,
+                                    const double* ye, double rho, double* A, double* B, double* c, double* Q,
+                                    double* R, double* q, double* r, double* kkt_viol, void* stream)
+{
+    return linearize_impl(p, 0, 0.0, x, u, lam, ye, rho, A, B, c, Q, R, nullptr, q, r, kkt_viol, stream);
+}
+
+BMPC_API bmpc_status bmpc_linearize_exact(bmpc_problem* p, double eig_floor, const double* x, const double* u,
+                                          const double* lam, const double* ye, double rho, double* A, double* B,
+                                          double* c, double* Q, double* R, double* M, double* q, double* r,
+                                          double* kkt_viol, void* stream)
+{
+    return linearize_impl(p, 1, eig_floor, x, u, lam, ye, rho, A, B, c, Q, R, M, q, r, kkt_viol, stream);
 }
 
 BMPC_API bmpc_status bmpc_linearize_noalloc(const bmpc_problem* p, const double* x, const double* u,
@@ -2827,7 +2880,7 @@ BMPC_API bmpc_status bmpc_linearize_noalloc(const bmpc_problem* p, const double*
     hipStream_t sm = (hipStream_t)stream;
     {
         ProfScope ps("bmpc_linearise", sm);
-        hipLaunchKernelGGL(k_bmpc_linearise<256>, dim3(1), dim3(256), 0, sm, d, rho, kkt_viol);
+        hipLaunchKernelGGL(k_bmpc_linearise<256>, dim3(1), dim3(256), 0, sm, d, rho, kkt_viol, 0, 0.0);
     }
     BMPC_HIP_TRY(hipGetLastError());
     const size_t N = d.N;
