@@ -1107,6 +1107,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                 col[j] = c == j ? dd * y : (c > j ? tjc : col[j]);
             }
             if (lane == 0 && !ok) atomicMin(a.bad, m);
+            // The solve below reads entries of L from lanes that do not take
+            // its branch: an opaque copy makes every lane finish its column
+            // here, so the compiler cannot sink the last step of the
+            // factorisation into the branch (where the lanes of L would
+            // never run it).
+#pragma unroll
+            for (int j = 0; j < NU; ++j) asm volatile("" : "+v"(col[j]));
             if (c >= NU && c < NT) {
                 const int g = c - NU;  // column of [G g]
 #pragma unroll
