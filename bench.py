@@ -787,7 +787,11 @@ def run_mass_spring(args, torch, L):
         "backward_fp64_tflops": round(tflops, 3),
         "roofline_backward": {"bound": "mfma", "achieved": round(tflops, 3), "peak": FP64_PEAK_TFLOPS,
                               "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 5),
-                              "hbm_frac": round(reads / (bwd_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)},
+                              "hbm_frac": round(reads / (bwd_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
+                              "traffic": measured_traffic("lqr_backward_level_mfma_mass_spring",
+                                                          ["paper_2506_13624_amd/csrc/lqr.hip",
+                                                           "paper_2506_13624_amd/csrc/lqr_device.hpp",
+                                                           "paper_2506_13624_amd/csrc/cvf_device.hpp"])},
     }}
 
 
