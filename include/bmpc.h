@@ -212,7 +212,7 @@ typedef struct {
    constant 1e-4, n_alpha 10 step sizes 2^0 .. 2^-9 per backtracking round,
    ls_rounds 3, max_outer 50, max_inner 100 (per outer iteration),
    max_ls_fail 3 consecutive line-search failures, Gauss-Newton Hessian
-   (eig_floor 1e-6 for the exact one).  The merit of a trial
+   (eig_floor 1e-9 for the exact one).  The merit of a trial
    point whose steering angle leaves (-pi/2, pi/2), where the bicycle model is
    undefined, is +inf.  Tolerances omega and eta are floored at eps_tol. */
 typedef struct {
@@ -239,7 +239,8 @@ typedef struct {
        the Hessian of the Lagrangian per node -- with the curvature of the
        active obstacle penalty and the dynamics curvature contracted with the
        children's multipliers, which gives a cross block M -- whose
-       eigenvalues below eig_floor (> 0) are raised to eig_floor. */
+       eigenvalues are raised to at least eig_floor (> 0) times
+       max(1, the block's largest |eigenvalue|). */
     int32_t hessian;
     double eig_floor;
 } bmpc_settings;
@@ -337,7 +338,7 @@ BMPC_API bmpc_status bmpc_linearize(bmpc_problem* problem, const double* x, cons
                                     void* stream);
 
 /* The same with the exact Hessian with eigenvalue modification
-   (BMPC_HESSIAN_EXACT, floor eig_floor > 0): additionally M (N*2*4, the
+   (BMPC_HESSIAN_EXACT, relative floor eig_floor > 0): additionally M (N*2*4, the
    cross block d2/du dx per node, zero at leaves); Q and R are the modified
    blocks. */
 BMPC_API bmpc_status bmpc_linearize_exact(bmpc_problem* problem, double eig_floor, const double* x,

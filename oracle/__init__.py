@@ -378,7 +378,7 @@ def kkt(pb, x, u, lam, ye, rho):
     return lib().orc_kkt(pb.ptr, _d(_f64(x)), _d(_f64(u)), _d(_f64(lam)), _d(_f64(ye)), rho)
 
 
-def direction(pb, x, u, lam, ye, rho, mu, hessian=0, eig_floor=1e-6):
+def direction(pb, x, u, lam, ye, rho, mu, hessian=0, eig_floor=1e-9):
     """One search direction at (x, u, lam): the tree-LQR step and the merit
     slope pieces.  Returns (dx, du, lam_hat, dict) with the dict holding
     gtd, dhd, lhd, dd, mu_hat, mu, dphi0, phi0.  hessian=1 takes the exact
@@ -421,7 +421,7 @@ def eig_modify(A, delta):
     return out
 
 
-def node_quadratic(pb, n, x, u, lam, ye, rho, hessian=1, eig_floor=1e-6, modify=True):
+def node_quadratic(pb, n, x, u, lam, ye, rho, hessian=1, eig_floor=1e-9, modify=True):
     """Quadratic model of node n: q, r, Q, R, M (whole-tree state arrays)."""
     q, r = np.zeros(4), np.zeros(2)
     Q, R, M = np.zeros((4, 4)), np.zeros((2, 2)), np.zeros((2, 4))

@@ -90,7 +90,8 @@ typedef struct {
     int max_iter_total; /* cap on inner iterations over all outer ones, 0 = none */
     int ls_rounds;      /* backtracking rounds of n_alpha step sizes each */
     int hessian;        /* 0 = Gauss-Newton, 1 = exact with eigenvalue modification */
-    double eig_floor;   /* eigenvalues of the exact node Hessian raised to at least this */
+    double eig_floor;   /* exact node Hessian: eigenvalues raised to at least
+                           eig_floor * max(1, largest |eigenvalue| of the block) */
 } orc_settings;
 
 typedef struct {

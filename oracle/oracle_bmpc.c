@@ -15,7 +15,8 @@
  *     constraints; pi_n is the total probability of the scenarios through n;
  *   - Hessian: Gauss-Newton (dynamics and constraint curvature dropped) by
  *     default; or the exact Hessian of the Lagrangian per node with its
- *     eigenvalues below delta raised to delta (settings.hessian = 1);
+ *     eigenvalues raised to at least delta times the block's largest
+ *     |eigenvalue| (at least 1) (settings.hessian = 1);
  *   - the merit's J is the augmented objective L_a; lambda is line-searched
  *     jointly with (x, u) towards the LQR costates;
  *   - alpha set {2^0 .. 2^-(K-1)}, Armijo constant 1e-4;
@@ -53,7 +54,7 @@ void orc_settings_default(orc_settings* s)
     s->max_iter_total = 0;
     s->ls_rounds = 3;
     s->hessian = 0;
-    s->eig_floor = 1e-6;
+    s->eig_floor = 1e-9;
 }
 
 /* ------------------------------------------------------------------------
@@ -295,7 +296,8 @@ static int* child_counts(const orc_problem* pb)
  *   - the dynamics curvature sum_a mu_a grad^2 F_a, mu = sum of the
  *     children's multipliers;
  * then, with modify, the whole (x, u) block (x only at a leaf) has its
- * eigenvalues below delta raised to delta. */
+ * eigenvalues below delta * max(1, largest |eigenvalue|) raised to that
+ * floor. */
 static void node_quadratic(const orc_problem* pb, const int* nch, int n, const double* x,
                            const double* u, const double* lam, const double* ye, double rho,
                            int hessian, double delta, int modify, double* q, double* r, double* Q,
@@ -342,9 +344,13 @@ static void node_quadratic(const orc_problem* pb, const int* nch, int n, const d
     double Hm[NZ * NZ], Hs[NZ * NZ];
     for (int a = 0; a < nz; ++a)
         for (int b = 0; b < nz; ++b) Hs[a * nz + b] = H[a * NZ + b];
-    if (modify)
-        orc_eig_modify(nz, Hs, delta, Hm);
-    else
+    if (modify) {
+        /* floor relative to the block's largest |eigenvalue| (at least 1) */
+        double w[NZ], V[NZ * NZ], big = 1.0;
+        orc_sym_eig(nz, Hs, w, V);
+        for (int i = 0; i < nz; ++i) big = fmax(big, fabs(w[i]));
+        orc_eig_modify(nz, Hs, delta * big, Hm);
+    } else
         memcpy(Hm, Hs, sizeof(double) * nz * nz);
     for (int a = 0; a < NX; ++a)
         for (int b = 0; b < NX; ++b) Q[a * NX + b] = Hm[a * nz + b];

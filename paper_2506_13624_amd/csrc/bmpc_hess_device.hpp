@@ -9,7 +9,9 @@
 //     g = r - |p - o|, t = g + y/rho and grad^2 g = -(I - e e^T) / |p - o|;
 //   - the dynamics curvature mu^T grad^2 F with mu = sum of the children's
 //     multipliers.
-// Its eigenvalues below delta are then raised to delta.
+// Its eigenvalues are then raised to at least delta * max(1, largest
+// |eigenvalue|): a floor relative to the block's scale keeps the modified
+// block numerically positive definite whatever the penalty's size.
 //
 // Structure used here: the position (px, py) enters neither the bicycle's
 // right-hand side nor the input bounds, and the state weight is diagonal,
@@ -113,13 +115,12 @@ __device__ __forceinline__ void bike_step_hessian(const BikeParams& P, const dou
     }
 }
 
-// A <- V diag(max(w, delta)) V^T for a symmetric n x n A = V diag(w) V^T,
-// by cyclic Jacobi rotations (each zeroes one off-diagonal pair) until the
-// off-diagonal part is negligible.
+// Symmetric A = V diag(w) V^T by cyclic Jacobi rotations (each zeroes one
+// off-diagonal pair) until the off-diagonal part is negligible: on return
+// the diagonal of A holds w (the rest is rounding) and V the eigenvectors.
 template <int n>
-__device__ __forceinline__ void eig_floor_sym(double (&A)[n][n], double delta)
+__device__ __forceinline__ void jacobi_eig(double (&A)[n][n], double (&V)[n][n])
 {
-    double V[n][n];
 #pragma unroll
     for (int i = 0; i < n; ++i)
 #pragma unroll
@@ -164,6 +165,12 @@ __device__ __forceinline__ void eig_floor_sym(double (&A)[n][n], double delta)
                 }
             }
     }
+}
+
+// A <- V diag(max(w, delta)) V^T from the output of jacobi_eig.
+template <int n>
+__device__ __forceinline__ void eig_rebuild(double (&A)[n][n], const double (&V)[n][n], double delta)
+{
     double w[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) w[i] = fmax(A[i][i], delta);
@@ -200,24 +207,30 @@ __device__ __forceinline__ void exact_node_model(const BikeParams& P, const Node
             Pp[1][1] += f * (1.0 - e1 * e1);
         }
     }
-    eig_floor_sym<2>(Pp, delta);
+    double Vp[2][2];
+    jacobi_eig<2>(Pp, Vp);
 #pragma unroll
     for (int i = 0; i < BU; ++i)
 #pragma unroll
         for (int j = 0; j < BX; ++j) Mh[i][j] = 0.0;
-    Qh[0][0] = Pp[0][0];
-    Qh[0][1] = Pp[0][1];
-    Qh[1][0] = Pp[1][0];
-    Qh[1][1] = Pp[1][1];
+    double big = fmax(1.0, fmax(fabs(Pp[0][0]), fabs(Pp[1][1])));
     if (nd.leaf) {
-        Qh[2][2] = fmax(Qh[2][2], delta);
-        Qh[3][3] = fmax(Qh[3][3], delta);
+        // (psi, v) block: the diagonal weights
+        big = fmax(big, fmax(fabs(Qh[2][2]), fabs(Qh[3][3])));
+        const double fl = delta * big;
+        eig_rebuild<2>(Pp, Vp, fl);
+        Qh[0][0] = Pp[0][0];
+        Qh[0][1] = Pp[0][1];
+        Qh[1][0] = Pp[1][0];
+        Qh[1][1] = Pp[1][1];
+        Qh[2][2] = fmax(Qh[2][2], fl);
+        Qh[3][3] = fmax(Qh[3][3], fl);
         return;
     }
     // (psi, v, a, delta) block
     double Hd[10];
     bike_step_hessian(P, x, u, mu, Hd);
-    double B4[4][4];
+    double B4[4][4], V4[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -228,7 +241,16 @@ __device__ __forceinline__ void exact_node_model(const BikeParams& P, const Node
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) B4[2 + i][2 + j] += Rh[i][j];
-    eig_floor_sym<4>(B4, delta);
+    jacobi_eig<4>(B4, V4);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) big = fmax(big, fabs(B4[i][i]));
+    const double fl = delta * big;
+    eig_rebuild<2>(Pp, Vp, fl);
+    Qh[0][0] = Pp[0][0];
+    Qh[0][1] = Pp[0][1];
+    Qh[1][0] = Pp[1][0];
+    Qh[1][1] = Pp[1][1];
+    eig_rebuild<4>(B4, V4, fl);
     Qh[2][2] = B4[0][0];
     Qh[2][3] = B4[0][1];
     Qh[3][2] = B4[1][0];

@@ -2073,7 +2073,7 @@ BMPC_API void bmpc_settings_default(bmpc_settings* s)
     s->max_iter_total = 0;
     s->ls_rounds = 3;
     s->hessian = BMPC_HESSIAN_GAUSS_NEWTON;
-    s->eig_floor = 1e-6;
+    s->eig_floor = 1e-9;
 }
 
 BMPC_API void bmpc_bicycle_default(bmpc_bicycle_params* p)

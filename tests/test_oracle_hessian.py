@@ -157,21 +157,28 @@ def test_exact_node_hessian_matches_central_differences_of_the_gradient(seed):
 
 
 def test_modified_node_hessian_is_positive_definite_and_unchanged_when_convex():
+    """The modified block's spectrum is floored at eig_floor times
+    max(1, the block's largest |eigenvalue|); a block already above the
+    floor is unchanged.  A large floor exercises both branches."""
     pb, x, u, lam, ye, rho, n_obs = _bicycle_point(1)
-    delta = 1e-6
-    for n in range(pb.N):
-        q, r, Q, R, M = oracle.node_quadratic(pb, n, x, u, lam, ye, rho, hessian=1, eig_floor=delta)
-        _, _, Qe, Re, Me = oracle.node_quadratic(pb, n, x, u, lam, ye, rho, hessian=1, modify=False)
-        leaf = not np.any(pb.parent == n)
-        H = Q if leaf else np.block([[Q, M.T], [M, R]])
-        He = Qe if leaf else np.block([[Qe, Me.T], [Me, Re]])
-        w = np.linalg.eigvalsh(H)
-        assert w.min() >= delta * (1 - 1e-6)
-        we = np.linalg.eigvalsh(He)
-        if we.min() > delta:
-            assert np.abs(H - He).max() <= 1e-12 * np.abs(He).max()
-        else:
-            assert np.abs(H - oracle.eig_modify(He, delta)).max() <= 1e-14 * max(1.0, np.abs(He).max())
+    for delta in (1e-9, 1e-2):
+        clamped = kept = 0
+        for n in range(pb.N):
+            q, r, Q, R, M = oracle.node_quadratic(pb, n, x, u, lam, ye, rho, hessian=1, eig_floor=delta)
+            _, _, Qe, Re, Me = oracle.node_quadratic(pb, n, x, u, lam, ye, rho, hessian=1, modify=False)
+            leaf = not np.any(pb.parent == n)
+            H = Q if leaf else np.block([[Q, M.T], [M, R]])
+            He = Qe if leaf else np.block([[Qe, Me.T], [Me, Re]])
+            we = np.linalg.eigvalsh(He)
+            floor = delta * max(1.0, np.abs(we).max())
+            assert np.linalg.eigvalsh(H).min() >= floor * (1 - 1e-6)
+            if we.min() > floor:
+                assert np.abs(H - He).max() <= 1e-12 * np.abs(He).max()
+                kept += 1
+            else:
+                assert np.abs(H - oracle.eig_modify(He, floor)).max() <= 1e-13 * max(1.0, np.abs(He).max())
+                clamped += 1
+        assert clamped > 0 and kept > 0, (delta, clamped, kept)
 
 
 @pytest.mark.parametrize("seed", range(3))
