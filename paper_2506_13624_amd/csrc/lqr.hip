@@ -815,6 +815,269 @@ __global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arri
 }
 
 // ------------------------------------------------------------------------
+// Register-resident matrix-core backward pass (nx = 12, nu = 4): one
+// wavefront per leaf chain, the value function P kept in the accumulator
+// registers of v_mfma_f64_16x16x4 from one step to the next.
+//
+// Lane l (li = l % 16, lk = l / 16) holds element v of a 16 x 16 matrix
+// tile as entry (lk + 4 v, li).  For a symmetric P that is also entry
+// (li, lk + 4 v), which is exactly the A operand of k-block v of the product
+// P [A B c]: so P needs no trip through LDS between steps.  The edge data
+// [A B c] are read from memory straight into the operand layout (entry
+// (4 m + lk, li) for k-block m), the stage data straight into the
+// accumulator layout of Z = [[Q M^T q],[M R r]], two steps ahead along the
+// leaf's root path.  Per child:
+//   S = P [A B] (+ P c + p in column 0 of a second accumulator)
+//   Z += [A B]^T S
+// Only rows NX.. of Z ([G H g]) go through LDS, for the gains.
+// ------------------------------------------------------------------------
+struct WregIn {
+    double d[3];   // [A B] of the edge, entry (4 m + lk, li), m < 3
+    double cb[3];  // c of the edge, entry 4 m + lk (used in lanes li == 0)
+    double z[4];   // stage data [[Q M^T],[M R]], entry (lk + 4 v, li)
+    double zc[4];  // [q; r], entry lk + 4 v (used in lanes li == 0)
+};
+
+template <int NX, int NU, int LAY>
+__global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arrive)
+{
+    static_assert(NX == 12 && NU == 4, "three k-blocks of P and one 16 x 16 tile of [A B]");
+    constexpr int NZ = NX + NU;
+    __shared__ double sH[NU][NZ + 1];   // rows NX.. of Z: [G H g]
+    __shared__ double sG[NU][NX + 1];   // L^-1 [G g], L L^T = H
+    __shared__ int sgo;
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int l = blockIdx.x, NL = t.num_leaves, N = t.N;
+    int s = t.leaf_stage[l];
+    int n = t.leaves[l];
+    // The walk's topology, 64 stages at a time, one stage per lane: lane i
+    // holds the node at stage base - i of this leaf's root path, its first
+    // child and its number of children.  A step reads them with readlane
+    // (no memory latency on the path of the walk).
+    int base = s, pathv = -1, c0v = 0, cntv = 0;
+    auto reload = [&](int st) {
+        base = st;
+        const int sl = st - lane;
+        pathv = sl >= 0 ? t.path[(long)sl * NL + l] : -1;
+        c0v = pathv >= 0 ? t.child_off[pathv] : 0;
+        cntv = pathv >= 0 ? t.child_off[pathv + 1] - c0v : 0;
+    };
+    reload(s);
+    // stages base .. base - 63 are held; a step reads stages s .. s - 3
+    auto lane_of = [&](int st) -> int { return base - st; };
+    auto node_at = [&](int st) -> int { return st >= 0 ? __builtin_amdgcn_readlane(pathv, lane_of(st)) : -1; };
+
+    // edge into child j, operand layout; one load per entry and lane (the
+    // per-lane address picks A or B), so that no branch waits on the loads
+    auto load_edge = [&](int j, WregIn& in) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int k = 4 * m + lk;
+            const double* pd = li < NX ? &a.A[lidx<LAY>(j, k * NX + li, NX * NX, N)]
+                                       : &a.B[lidx<LAY>(j, k * NU + (li - NX), NX * NU, N)];
+            in.d[m] = *pd;
+            in.cb[m] = a.c[lidx<LAY>(j, k, NX, N)];
+        }
+    };
+    // stage data of node m, accumulator layout: rows lk + 4 v < NX for v < 3
+    auto load_stage = [&](int m, WregIn& in) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = lk + 4 * v;
+            const double* pz;
+            const double* pc;
+            if (v < 3) {
+                pz = li < NX ? &a.Q[lidx<LAY>(m, r * NX + li, NX * NX, N)]
+                             : &a.M[lidx<LAY>(m, (li - NX) * NX + r, NU * NX, N)];
+                pc = &a.q[lidx<LAY>(m, r, NX, N)];
+            } else {
+                pz = li < NX ? &a.M[lidx<LAY>(m, (r - NX) * NX + li, NU * NX, N)]
+                             : &a.R[lidx<LAY>(m, (r - NX) * NU + (li - NX), NU * NU, N)];
+                pc = &a.r[lidx<LAY>(m, r - NX, NU, N)];
+            }
+            in.z[v] = *pz;
+            in.zc[v] = *pc;
+        }
+    };
+    // the child's contribution D^T (P D + [0 0 p]) added to (zm, zc)
+    auto add_child = [&](const f64x4& Pr, const double (&pv)[4], const WregIn& e, f64x4& zm, f64x4& zc) {
+        f64x4 sm = {0.0, 0.0, 0.0, 0.0}, sc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sc[v] = (li == 0 && v < 3) ? pv[v] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const double cbm = li == 0 ? e.cb[m] : 0.0;
+            sm = __builtin_amdgcn_mfma_f64_16x16x4f64(Pr[m], e.d[m], sm, 0, 0, 0);
+            sc = __builtin_amdgcn_mfma_f64_16x16x4f64(Pr[m], cbm, sc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            zm = __builtin_amdgcn_mfma_f64_16x16x4f64(e.d[m], sm[m], zm, 0, 0, 0);
+            zc = __builtin_amdgcn_mfma_f64_16x16x4f64(e.d[m], sc[m], zc, 0, 0, 0);
+        }
+    };
+    // value function of child j (another walker's), accumulator layout
+    auto load_value_dev = [&](int j, f64x4& Pr, double (&pv)[4]) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = lk + 4 * v;
+            Pr[v] = (v < 3 && li < NX) ? ld_shared_dev(&a.P[lidx<LAY>(j, r * NX + li, NX * NX, N)]) : 0.0;
+            pv[v] = v < 3 ? ld_shared_dev(&a.p[lidx<LAY>(j, r, NX, N)]) : 0.0;
+        }
+    };
+    auto store_value = [&](int m, const f64x4& Pr, const double (&pv)[4], bool shared) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const int r = lk + 4 * v;
+            if (li < NX) {
+                double* dst = &a.P[lidx<LAY>(m, r * NX + li, NX * NX, N)];
+                if (shared) st_shared_dev(dst, Pr[v]);
+                else *dst = Pr[v];
+            }
+            if (li == 0) {
+                double* dst = &a.p[lidx<LAY>(m, r, NX, N)];
+                if (shared) st_shared_dev(dst, pv[v]);
+                else *dst = pv[v];
+            }
+        }
+    };
+
+    // the leaf: P = Q_f, p = q_f, no gains
+    f64x4 Preg;
+    double pvec[4];
+    // number of children of the parent (1 for the root, which has none)
+    auto nsib_of = [&](int st) -> int { return st > 0 ? __builtin_amdgcn_readlane(cntv, lane_of(st - 1)) : 1; };
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = lk + 4 * v;
+        Preg[v] = (v < 3 && li < NX) ? a.Q[lidx<LAY>(n, r * NX + li, NX * NX, N)] : 0.0;
+        pvec[v] = v < 3 ? a.q[lidx<LAY>(n, r, NX, N)] : 0.0;
+    }
+    each_elem<NU * NX>(lane, [&](int e) { a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0; });
+    each_elem<NU>(lane, [&](int e) { a.k[lidx<LAY>(n, e, NU, N)] = 0.0; });
+    store_value(n, Preg, pvec, nsib_of(s) > 1);
+    // inputs of the next two steps along the root path: step to stage s - 1
+    // reads buffer A, to stage s - 2 buffer B, then they alternate
+    WregIn bufA, bufB;
+    if (s >= 1) {
+        load_stage(node_at(s - 1), bufA);
+        load_edge(n, bufA);
+    }
+    if (s >= 2) {
+        load_stage(node_at(s - 2), bufB);
+        load_edge(node_at(s - 1), bufB);
+    }
+
+    // One step up from n (stage s) to its parent; false when the walk ends.
+    auto up = [&](WregIn& in) -> bool {
+        if (s == 0) return false;
+        if (base - (s - 3) >= 64) reload(s);
+        const int nsib = nsib_of(s);
+        const int par = node_at(s - 1);
+        if (nsib > 1) {
+            // hand the value function over: the stores complete before the count
+            wait_own_stores();
+            __syncthreads();
+            if (lane == 0) sgo = (atomicAdd(&arrive[par], 1) == nsib - 1);
+            __syncthreads();
+            if (!sgo) return false;
+        }
+        const int child = n;
+        n = par;
+        --s;
+        const int k = lane_of(s);
+        const int cfirst = __builtin_amdgcn_readlane(c0v, k), ccount = __builtin_amdgcn_readlane(cntv, k);
+        f64x4 zm, zc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            zm[v] = in.z[v];
+            zc[v] = li == 0 ? in.zc[v] : 0.0;
+        }
+        if (ccount == 1) {
+            add_child(Preg, pvec, in, zm, zc);
+        } else {
+            // every child in child order (deterministic sums): this walker's
+            // own child from registers, the others from memory
+            for (int j = cfirst; j < cfirst + ccount; ++j) {
+                f64x4 Pj;
+                double pj[4];
+                WregIn ej;
+                if (j == child) {
+                    Pj = Preg;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) pj[v] = pvec[v];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        ej.d[m] = in.d[m];
+                        ej.cb[m] = in.cb[m];
+                    }
+                } else {
+                    load_value_dev(j, Pj, pj);
+                    load_edge(j, ej);
+                }
+                add_child(Pj, pj, ej, zm, zc);
+            }
+        }
+        // the step after next: its inputs into the buffer just consumed
+        if (s >= 2) {
+            load_stage(node_at(s - 2), in);
+            load_edge(node_at(s - 1), in);
+        }
+        // gains from rows NX.. of Z (element 3 of every lane)
+        sH[lk][li] = zm[3];
+        if (li == 0) sH[lk][NZ] = zc[3];
+        wave_sync();
+        {
+            double L[NU][NU], inv[NU];
+#pragma unroll
+            for (int i = 0; i < NU; ++i)
+#pragma unroll
+                for (int j = 0; j < NU; ++j) L[i][j] = sH[i][NX + j];
+            const bool ok = chol_inplace_rsq<NU>(L, inv);
+            if (!ok && lane == 0) atomicMin(a.bad, n);
+            const int col = lane < NX ? lane : NZ;
+            const int gcol = lane < NX ? lane : NX;
+            double v[NU];
+#pragma unroll
+            for (int i = 0; i < NU; ++i) v[i] = sH[i][col];
+            chol_fwd<NU>(L, inv, v);
+#pragma unroll
+            for (int i = 0; i < NU; ++i) sG[i][gcol] = v[i];
+            chol_bwd<NU>(L, inv, v);
+#pragma unroll
+            for (int i = 0; i < NU; ++i) {
+                double* dst = lane < NX ? &a.K[lidx<LAY>(n, i * NX + lane, NU * NX, N)]
+                                        : &a.k[lidx<LAY>(n, i, NU, N)];
+                *dst = -v[i];
+            }
+        }
+        wave_sync();
+        // P = W - Gh^T Gh and p = w - Gh^T gh, in the accumulator layout
+        const int lic = li < NX ? li : 0;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const int i = lk + 4 * v;
+            double tP = 0.0, tp = 0.0;
+#pragma unroll
+            for (int r = 0; r < NU; ++r) {
+                tP = fma(sG[r][i], sG[r][lic], tP);
+                tp = fma(sG[r][i], sG[r][NX], tp);
+            }
+            Preg[v] = li < NX ? zm[v] - tP : 0.0;
+            pvec[v] = zc[v] - tp;
+        }
+        Preg[3] = 0.0;
+        pvec[3] = 0.0;
+        store_value(n, Preg, pvec, nsib_of(s) > 1);
+        return true;
+    };
+    for (;;) {
+        if (!up(bufA)) break;
+        if (!up(bufB)) break;
+    }
+}
+
+// ------------------------------------------------------------------------
 // Backward pass for larger state dimensions (the mass-spring chain,
 // nx = 30, nu = 14): one workgroup of four wavefronts walks a leaf
 // segment upwards, with the same last-arriver merges as k_bwd_wave.  Per
@@ -1601,6 +1864,8 @@ struct LqrKernels {
     void (*costate32)(TreeDev, LqrArgsT<float>, int*);
     void (*residual_first)(TreeDev, LqrArgs, float*, float*, float*, float*, unsigned long long*);
     void (*residual)(TreeDev, LqrArgs, float*, float*, float*, float*, unsigned long long*);
+    // nx = 12, nu = 4: register-resident matrix-core backward pass
+    void (*bwd_wreg)(TreeDev, LqrArgs, int*);
 };
 
 template <int NX, int NU, int LAY, bool LANE>
@@ -1610,6 +1875,7 @@ static LqrKernels make_k()
     constexpr int G = 16;
     LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, nullptr, nullptr, k_fwd_rows<NX, NU, LAY, G, 4>,
                  k_costate<NX, LAY>};
+    if constexpr (NX == 12 && NU == 4) k.bwd_wreg = k_bwd_wreg<NX, NU, LAY>;
     if constexpr (LANE) {
         k.bwd_lane = k_bwd_lane<NX, NU, LAY>;
         k.bwd_lane32 = k_bwd_lane<NX, NU, LAY, float>;
@@ -1629,7 +1895,8 @@ static LqrKernels make_k_mfma()
 {
     constexpr int G = 64;
     return LqrKernels{NX, NU, LAY, G, nullptr, nullptr, k_bwd_mfma<NX, NU, LAY>, nullptr,
-                      k_fwd_rows<NX, NU, LAY, G, 2>, k_costate<NX, LAY>, nullptr, nullptr, nullptr, nullptr, nullptr};
+                      k_fwd_rows<NX, NU, LAY, G, 2>, k_costate<NX, LAY>, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      nullptr};
 }
 
 static const LqrKernels* find_kernels(int nx, int nu, int layout)
@@ -1797,6 +2064,9 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
     } else if (pl->kern->bwd_mfma) {
         ProfScope ps("lqr_backward_level_mfma", s);
         hipLaunchKernelGGL(pl->kern->bwd_mfma, dim3(Z), dim3(256), 0, s, t, a, pl->arrive);
+    } else if (pl->kern->bwd_wreg) {
+        ProfScope ps("lqr_backward_level_wreg", s);
+        hipLaunchKernelGGL(pl->kern->bwd_wreg, dim3(Z), dim3(64), 0, s, t, a, pl->arrive);
     } else if (pl->kern->bwd_lane) {
         ProfScope ps("lqr_backward_level_lane", s);
         hipLaunchKernelGGL(pl->kern->bwd_lane, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
