@@ -340,43 +340,6 @@ __global__ void __launch_bounds__(64) k_bwd_seg(TreeDev t, LqrArgs a, int* arriv
 // wavefront-per-segment backward (LDS staging; used for larger nx)
 // ------------------------------------------------------------------------
 
-// A lane's share of CNT consecutive elements of one node (element e = lane + 64 s).
-template <int CNT>
-struct Slots {
-    static constexpr int S = (CNT + 63) / 64;
-    double v[S];
-
-    template <int LAY>
-    __device__ __forceinline__ void load(const double* __restrict__ base, int node, int N, int lane)
-    {
-#pragma unroll
-        for (int s = 0; s < S; ++s) v[s] = base[lidx<LAY>(node, elem(lane, s), CNT, N)];
-    }
-    template <int LAY>
-    __device__ __forceinline__ void load_dev(const double* base, int node, int N, int lane)
-    {
-#pragma unroll
-        for (int s = 0; s < S; ++s) v[s] = ld_shared_dev(&base[lidx<LAY>(node, elem(lane, s), CNT, N)]);
-    }
-    // Every lane loads in every slot (lanes past the end re-read the last
-    // element, whose copy is never used): the loads then need no branch
-    // around them and no zeroing of their destination, either of which
-    // would make the compiler wait for every load still in flight.
-    static __device__ __forceinline__ int elem(int lane, int s)
-    {
-        const int e = lane + 64 * s;
-        return e < CNT ? e : CNT - 1;
-    }
-    // Lanes past the end repeat the last element with the value they
-    // loaded for it: a repeated LDS or memory write of the same value.
-    template <class F>
-    __device__ __forceinline__ void each(int lane, F f) const
-    {
-#pragma unroll
-        for (int s = 0; s < S; ++s) f(elem(lane, s), v[s]);
-    }
-};
-
 // f(e) for the CNT elements of a node over the 64 lanes, without branches:
 // lanes past the end repeat the last element (f must write the same value
 // for the same element).
@@ -390,61 +353,6 @@ __device__ __forceinline__ void each_elem(int lane, F f)
     }
 }
 
-// Column counts padded to a multiple of 4 so that tiles of 4 columns can be
-// read with 16-byte LDS loads.
-template <int NX, int NU>
-struct WaveDims {
-    static constexpr int NZ = NX + NU;         // rows of [A B]^T
-    static constexpr int ND = NX + NU + 1;     // columns of [A B c]
-    static constexpr int NDP = (ND + 3) / 4 * 4;
-    static constexpr int NQ = NDP / 4;         // column quads
-    static constexpr int NZP = (NZ + 1) / 2 * 2;
-};
-
-template <int NX, int NU, int LAY>
-struct WaveIn {
-    using Dm = WaveDims<NX, NU>;
-    static constexpr int NZ = Dm::NZ, NDP = Dm::NDP;
-    Slots<NX * NX> Q;
-    Slots<NX> q;
-    Slots<NU * NX> M;
-    Slots<NU * NU> R;
-    Slots<NU> r;
-    Slots<NX * NX> A;
-    Slots<NX * NU> B;
-    Slots<NX> c;
-
-    __device__ __forceinline__ void load_stage(const LqrArgs& a, int N, int n, int lane)
-    {
-        Q.template load<LAY>(a.Q, n, N, lane);
-        q.template load<LAY>(a.q, n, N, lane);
-        M.template load<LAY>(a.M, n, N, lane);
-        R.template load<LAY>(a.R, n, N, lane);
-        r.template load<LAY>(a.r, n, N, lane);
-    }
-    __device__ __forceinline__ void load_edge(const LqrArgs& a, int N, int j, int lane)
-    {
-        A.template load<LAY>(a.A, j, N, lane);
-        B.template load<LAY>(a.B, j, N, lane);
-        c.template load<LAY>(a.c, j, N, lane);
-    }
-    // Z rows 0..NX-1 = [W . w], rows NX.. = [G H g]
-    __device__ __forceinline__ void stage_to(double (*sZ)[NDP], int lane) const
-    {
-        Q.each(lane, [&](int e, double v) { sZ[e / NX][e % NX] = v; });
-        q.each(lane, [&](int e, double v) { sZ[e][NZ] = v; });
-        M.each(lane, [&](int e, double v) { sZ[NX + e / NX][e % NX] = v; });
-        R.each(lane, [&](int e, double v) { sZ[NX + e / NU][NX + e % NU] = v; });
-        r.each(lane, [&](int e, double v) { sZ[NX + e][NZ] = v; });
-    }
-    __device__ __forceinline__ void edge_to(double (*sD)[NDP], int lane) const
-    {
-        A.each(lane, [&](int e, double v) { sD[e / NX][e % NX] = v; });
-        B.each(lane, [&](int e, double v) { sD[e / NU][NX + e % NU] = v; });
-        c.each(lane, [&](int e, double v) { sD[e][NZ] = v; });
-    }
-};
-
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Single-wavefront workgroups: LDS accesses of one wavefront complete in
@@ -454,364 +362,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int NX, int NU, int LAY>
-__global__ void __launch_bounds__(64) k_bwd_wave(TreeDev t, LqrArgs a, int* arrive)
-{
-    using Dm = WaveDims<NX, NU>;
-    constexpr int NZ = Dm::NZ, NDP = Dm::NDP, NQ = Dm::NQ, NZP = Dm::NZP;
-    // [A B c 0..] of the current child edge; row NX is the constant
-    // [0 .. 0 1 0 ..] (1 in column NZ) that adds p to the last column of S
-    __shared__ __align__(16) double sD[NX + 1][NDP];
-    __shared__ __align__(16) double sP[NX][NX];
-    __shared__ __align__(16) double sp[NX];
-    __shared__ __align__(16) double sS[NX][NDP];   // P [A B c] + [0 0 p]
-    __shared__ __align__(16) double sZ[NZ][NDP];   // [[W . w],[G H g]]
-    __shared__ __align__(16) double sGh[NU][NX + 1];  // L^-1 [G g], L L^T = H
-    __shared__ int sgo;
-
-    const int l = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int N = t.N;
-    int n = t.leaves[l];
-    int4 inf = t.info[n];
-    // The parent's record is requested one step ahead: lane i holds field
-    // i % 4 (a per-lane value, so that the compiler does not move it into
-    // scalar registers, and wait for it, right after the load).
-    auto request_info = [&](int node) -> int {
-        const int f = lane & 3;
-        return node >= 0 ? reinterpret_cast<const int*>(t.info)[4 * node + f] : (f == 2 ? -1 : 0);
-    };
-    auto unpack_info = [&](int v) -> int4 {
-        return make_int4(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 1),
-                         __builtin_amdgcn_readlane(v, 2), __builtin_amdgcn_readlane(v, 3));
-    };
-    int infp = request_info(inf.z);
-    int from = -1;
-    bool pref = false;
-    // inputs of the next two nodes of a chain are in flight: node k of a walk
-    // uses buffer k % 2, which is refilled with node k + 2 once consumed
-    WaveIn<NX, NU, LAY> bufA, bufB;
-    // a worker reaching a branching node requests the merge's stage data and
-    // first two child edges before it counts itself in (whether or not it
-    // turns out to be the last child), so that they arrive during the count
-    bool merge_pre = false;
-
-    // padding columns of D stay zero
-    for (int e = lane; e < NX * NDP; e += 64)
-        if (e % NDP >= NZ + 1) sD[e / NDP][e % NDP] = 0.0;
-    for (int e = lane; e < NDP; e += 64) sD[NX][e] = (e == NZ) ? 1.0 : 0.0;
-
-    // S = P [A B c] (+p in the last column), tiles of 1 row x 4 columns;
-    // then Z += [A B]^T S, tiles of 2 rows x 4 columns
-    // With NZ = 16 (nx + nu = 16) the products run on the FP64 matrix
-    // cores (v_mfma_f64_16x16x4, k = 4 per call):
-    //   S  = P [A B]           (rows >= NX of the A operand are zero)
-    //   S' = P [c 0 ..] + [p 0 ..]
-    //   Z  += [A B]^T S,  Z[:, NZ] += [A B]^T S'[:, 0]
-    // Lane l holds A operand entry (l % 16, l / 16), B operand entry
-    // (l / 16, l % 16) and result entries (l / 16 + 4 v, l % 16), v < 4: the
-    // result of S in element v is exactly the B operand of the Z product
-    // for its k-block v, so S never leaves the registers, and [A B] serves
-    // as the B operand of S and the A operand of Z.
-    auto add_child_mfma = [&]() {
-        wave_sync();
-        const int li = lane & 15, lk = lane >> 4;
-        double d[3], pa[3], cb[3];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            d[m] = sD[4 * m + lk][li];
-            pa[m] = li < NX ? sP[li][4 * m + lk] : 0.0;
-            cb[m] = li == 0 ? sD[4 * m + lk][NZ] : 0.0;
-        }
-        f64x4 sm = {0.0, 0.0, 0.0, 0.0}, sc;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) sc[v] = (li == 0 && lk + 4 * v < NX) ? sp[lk + 4 * v] : 0.0;
-        f64x4 zm, zc;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            zm[v] = sZ[lk + 4 * v][li];
-            zc[v] = li == 0 ? sZ[lk + 4 * v][NZ] : 0.0;
-        }
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            sm = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[m], d[m], sm, 0, 0, 0);
-            sc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[m], cb[m], sc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            zm = __builtin_amdgcn_mfma_f64_16x16x4f64(d[m], sm[m], zm, 0, 0, 0);
-            zc = __builtin_amdgcn_mfma_f64_16x16x4f64(d[m], sc[m], zc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            sZ[lk + 4 * v][li] = zm[v];
-            if (li == 0) sZ[lk + 4 * v][NZ] = zc[v];
-        }
-        wave_sync();
-    };
-    auto add_child = [&]() {
-        if constexpr (NZ == 16) {
-            add_child_mfma();
-            return;
-        }
-        wave_sync();
-        for (int tt = lane; tt < NX * NQ; tt += 64) {
-            const int r = tt / NQ, c4 = 4 * (tt % NQ);
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            // k = NX multiplies p by the constant row of D: p is added to
-            // column NZ, exactly, after the sum over k < NX
-#pragma unroll
-            for (int k = 0; k <= NX; ++k) {
-                const double pk = k < NX ? sP[r][k] : sp[r];
-                const double2 d01 = *reinterpret_cast<const double2*>(&sD[k][c4]);
-                const double2 d23 = *reinterpret_cast<const double2*>(&sD[k][c4 + 2]);
-                s0 += pk * d01.x;
-                s1 += pk * d01.y;
-                s2 += pk * d23.x;
-                s3 += pk * d23.y;
-            }
-            *reinterpret_cast<double2*>(&sS[r][c4]) = make_double2(s0, s1);
-            *reinterpret_cast<double2*>(&sS[r][c4 + 2]) = make_double2(s2, s3);
-        }
-        wave_sync();
-        for (int tt = lane; tt < (NZP / 2) * NQ; tt += 64) {
-            const int r0 = 2 * (tt / NQ), c4 = 4 * (tt % NQ);
-            // the tile's current Z, requested before the sums
-            double2 old[2][2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int r = (NZP == NZ || r0 + i < NZ) ? r0 + i : NZ - 1;
-                const double2* zr = reinterpret_cast<const double2*>(&sZ[r][c4]);
-                old[i][0] = zr[0];
-                old[i][1] = zr[1];
-            }
-            double z[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-#pragma unroll
-            for (int k = 0; k < NX; ++k) {
-                const double2 dr = *reinterpret_cast<const double2*>(&sD[k][r0]);
-                const double2 s01 = *reinterpret_cast<const double2*>(&sS[k][c4]);
-                const double2 s23 = *reinterpret_cast<const double2*>(&sS[k][c4 + 2]);
-                z[0][0] += dr.x * s01.x;
-                z[0][1] += dr.x * s01.y;
-                z[0][2] += dr.x * s23.x;
-                z[0][3] += dr.x * s23.y;
-                z[1][0] += dr.y * s01.x;
-                z[1][1] += dr.y * s01.y;
-                z[1][2] += dr.y * s23.x;
-                z[1][3] += dr.y * s23.y;
-            }
-            // whole 16-byte pairs, padding columns included (never read):
-            // a store under a per-element condition lets the compiler sink
-            // each element's sum into its own branch and run the eight sums
-            // one after another
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int r = r0 + i;
-                if (NZP == NZ || r < NZ) {
-                    double2* zr = reinterpret_cast<double2*>(&sZ[r][c4]);
-                    double2 z01 = old[i][0], z23 = old[i][1];
-                    z01.x += z[i][0];
-                    z01.y += z[i][1];
-                    z23.x += z[i][2];
-                    z23.y += z[i][3];
-                    zr[0] = z01;
-                    zr[1] = z23;
-                }
-            }
-        }
-        wave_sync();
-    };
-
-    // after a leaf or a merge: the parent's inputs into oth and, if the
-    // chain goes on, the grandparent's into cur (free again)
-    auto prefetch_two = [&](WaveIn<NX, NU, LAY>& cur, WaveIn<NX, NU, LAY>& oth, int par, int nsib,
-                            int4 inf_next) {
-        if (nsib != 1) return;
-        oth.load_stage(a, N, par, lane);
-        oth.load_edge(a, N, n, lane);
-        if (inf_next.w == 1 && inf_next.z >= 0) {
-            cur.load_stage(a, N, inf_next.z, lane);
-            cur.load_edge(a, N, par, lane);
-        }
-    };
-    auto step = [&](WaveIn<NX, NU, LAY>& in, WaveIn<NX, NU, LAY>& oth) -> bool {
-            const int c0 = inf.x, c1 = inf.y, par = inf.z, nsib = inf.w;
-            const int4 inf_next = unpack_info(infp);
-            const int inf_next2 = request_info(inf_next.z);
-            if (c0 == c1) {
-                Slots<NX * NX> Pv;
-                Slots<NX> pv;
-                Pv.template load<LAY>(a.Q, n, N, lane);
-                pv.template load<LAY>(a.q, n, N, lane);
-                Pv.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
-                pv.each(lane, [&](int e, double v) { sp[e] = v; });
-                each_elem<NU * NX>(lane, [&](int e) { a.K[lidx<LAY>(n, e, NU * NX, N)] = 0.0; });
-                each_elem<NU>(lane, [&](int e) { a.k[lidx<LAY>(n, e, NU, N)] = 0.0; });
-                prefetch_two(in, oth, par, nsib, inf_next);
-                wave_sync();
-            } else {
-                if (!pref && !merge_pre) in.load_stage(a, N, n, lane);
-                if (pref) {
-                    in.stage_to(sZ, lane);
-                    in.edge_to(sD, lane);  // the only child's P is still in sP
-                    // the parent's inputs are already in oth; start the grandparent's
-                    if (nsib == 1 && inf_next.w == 1 && inf_next.z >= 0) {
-                        in.load_stage(a, N, inf_next.z, lane);
-                        in.load_edge(a, N, par, lane);
-                    }
-                    add_child();
-                } else {
-                    // children two at a time: both edges and both value functions
-                    // are requested before either is used
-                    for (int j = c0; j < c1; j += 2) {
-                        const bool two = j + 1 < c1;
-                        Slots<NX * NX> Pv0, Pv1;
-                        Slots<NX> pv0, pv1;
-                        const bool keep = (c1 - c0 == 1) && from == j;
-                        const bool pre = merge_pre && j == c0;  // edges already requested
-                        if (!pre) in.load_edge(a, N, j, lane);
-                        if (!keep) {
-                            Pv0.template load_dev<LAY>(a.P, j, N, lane);
-                            pv0.template load_dev<LAY>(a.p, j, N, lane);
-                        }
-                        if (two) {
-                            if (!pre) oth.load_edge(a, N, j + 1, lane);
-                            Pv1.template load_dev<LAY>(a.P, j + 1, N, lane);
-                            pv1.template load_dev<LAY>(a.p, j + 1, N, lane);
-                        }
-                        if (j == c0) in.stage_to(sZ, lane);  // stage data requested with the first children
-                        wave_sync();
-                        in.edge_to(sD, lane);
-                        if (!keep) {
-                            Pv0.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
-                            pv0.each(lane, [&](int e, double v) { sp[e] = v; });
-                        }
-                        add_child();
-                        if (two) {
-                            oth.edge_to(sD, lane);
-                            Pv1.each(lane, [&](int e, double v) { sP[e / NX][e % NX] = v; });
-                            pv1.each(lane, [&](int e, double v) { sp[e] = v; });
-                            add_child();
-                        }
-                    }
-                    merge_pre = false;
-                    prefetch_two(in, oth, par, nsib, inf_next);
-                }
-                // Gains with H = L L^T: every lane factors H; lane i < NX
-                // takes column i of G, the others the column g.  With
-                // Gh = L^-1 [G g]:  [K k] = -L^-T Gh,  G^T K = -Gh^T Gh and
-                // G^T k = -Gh^T gh, so P and p need only Gh, and K, k go to
-                // memory straight from the lanes' registers.
-                {
-                    double L[NU][NU], inv[NU];
-#pragma unroll
-                    for (int i = 0; i < NU; ++i)
-#pragma unroll
-                        for (int j = 0; j < NU; ++j) L[i][j] = sZ[NX + i][NX + j];
-                    const bool ok = chol_inplace_rsq<NU>(L, inv);
-                    if (!ok && lane == 0) atomicMin(a.bad, n);
-                    const int col = lane < NX ? lane : NZ;
-                    const int gcol = lane < NX ? lane : NX;
-                    double v[NU];
-#pragma unroll
-                    for (int i = 0; i < NU; ++i) v[i] = sZ[NX + i][col];
-                    chol_fwd<NU>(L, inv, v);
-#pragma unroll
-                    for (int i = 0; i < NU; ++i) sGh[i][gcol] = v[i];
-                    chol_bwd<NU>(L, inv, v);
-#pragma unroll
-                    for (int i = 0; i < NU; ++i) {
-                        double* dst = lane < NX ? &a.K[lidx<LAY>(n, i * NX + lane, NU * NX, N)]
-                                                : &a.k[lidx<LAY>(n, i, NU, N)];
-                        *dst = -v[i];
-                    }
-                }
-                wave_sync();
-                // P = (W + W^T)/2 - Gh^T Gh (exactly symmetric), p = w - Gh^T gh;
-                // every lane computes (lanes past the end repeat the last
-                // element), so that the slots' sums interleave
-                constexpr int PS = (NX * NX + 63) / 64, VS = (NX + 63) / 64;
-                double pv[PS], qv[VS];
-#pragma unroll
-                for (int s = 0; s < PS; ++s) {
-                    const int e0 = lane + 64 * s;
-                    const int e = e0 < NX * NX ? e0 : NX * NX - 1;
-                    const int i = e / NX, j = e % NX;
-                    double t = 0.0;
-#pragma unroll
-                    for (int rr = 0; rr < NU; ++rr) t = fma(sGh[rr][i], sGh[rr][j], t);
-                    pv[s] = 0.5 * (sZ[i][j] + sZ[j][i]) - t;
-                }
-#pragma unroll
-                for (int s = 0; s < VS; ++s) {
-                    const int i0 = lane + 64 * s;
-                    const int i = i0 < NX ? i0 : NX - 1;
-                    double t = 0.0;
-#pragma unroll
-                    for (int rr = 0; rr < NU; ++rr) t = fma(sGh[rr][i], sGh[rr][NX], t);
-                    qv[s] = sZ[i][NZ] - t;
-                }
-                // (the child's P in sP was last read by the products)
-#pragma unroll
-                for (int s = 0; s < PS; ++s) {
-                    const int e0 = lane + 64 * s;
-                    const int e = e0 < NX * NX ? e0 : NX * NX - 1;
-                    sP[e / NX][e % NX] = pv[s];
-                    if (nsib > 1)
-                        st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], pv[s]);
-                    else
-                        a.P[lidx<LAY>(n, e, NX * NX, N)] = pv[s];
-                }
-#pragma unroll
-                for (int s = 0; s < VS; ++s) {
-                    const int i0 = lane + 64 * s;
-                    const int i = i0 < NX ? i0 : NX - 1;
-                    sp[i] = qv[s];
-                    if (nsib > 1)
-                        st_shared_dev(&a.p[lidx<LAY>(n, i, NX, N)], qv[s]);
-                    else
-                        a.p[lidx<LAY>(n, i, NX, N)] = qv[s];
-                }
-                wave_sync();
-            }
-            if (c0 == c1) {
-                // leaf: P = Q_f, p = q_f, already in sP, sp
-                if (nsib > 1) {
-                    each_elem<NX * NX>(lane, [&](int e) { st_shared_dev(&a.P[lidx<LAY>(n, e, NX * NX, N)], sP[e / NX][e % NX]); });
-                    each_elem<NX>(lane, [&](int e) { st_shared_dev(&a.p[lidx<LAY>(n, e, NX, N)], sp[e]); });
-                } else {
-                    each_elem<NX * NX>(lane, [&](int e) { a.P[lidx<LAY>(n, e, NX * NX, N)] = sP[e / NX][e % NX]; });
-                    each_elem<NX>(lane, [&](int e) { a.p[lidx<LAY>(n, e, NX, N)] = sp[e]; });
-                }
-            }
-            if (par < 0) return false;
-            pref = nsib == 1;
-            if (nsib > 1) {
-                wait_own_stores();
-                // requested after the stores have completed (a wait for them
-                // would also wait for these loads); they travel with the count.
-                // The next step runs with (in, oth) = (oth, in) of this one.
-                oth.load_stage(a, N, par, lane);
-                oth.load_edge(a, N, inf_next.x, lane);
-                in.load_edge(a, N, inf_next.x + 1, lane);
-                merge_pre = true;
-                __syncthreads();
-                if (lane == 0) sgo = (atomicAdd(&arrive[par], 1) == nsib - 1);
-                __syncthreads();
-                if (!sgo) return false;
-            }
-            from = n;
-            n = par;
-            inf = inf_next;
-            infp = inf_next2;
-            return true;
-    };
-    for (;;) {
-        if (!step(bufA, bufB)) break;
-        if (!step(bufB, bufA)) break;
-    }
 }
 
 // ------------------------------------------------------------------------
@@ -844,7 +394,6 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
     static_assert(NX == 12 && NU == 4, "three k-blocks of P and one 16 x 16 tile of [A B]");
     constexpr int NZ = NX + NU;
     __shared__ double sH[NU][NZ + 1];   // rows NX.. of Z: [G H g]
-    __shared__ double sG[NU][NX + 1];   // L^-1 [G g], L L^T = H
     __shared__ int sgo;
     const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
     const int l = blockIdx.x, NL = t.num_leaves, N = t.N;
@@ -861,6 +410,11 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
         pathv = sl >= 0 ? t.path[(long)sl * NL + l] : -1;
         c0v = pathv >= 0 ? t.child_off[pathv] : 0;
         cntv = pathv >= 0 ? t.child_off[pathv + 1] - c0v : 0;
+        // used here, so that the loads are waited for inside this (rare)
+        // branch: a load that might still be in flight where a step reads
+        // the values would make the compiler wait for every load in flight
+        // there, the prefetched inputs included
+        asm volatile("" : "+v"(pathv), "+v"(c0v), "+v"(cntv));
     };
     reload(s);
     // stages base .. base - 63 are held; a step reads stages s .. s - 3
@@ -958,15 +512,15 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
     store_value(n, Preg, pvec, nsib_of(s) > 1);
     // inputs of the next two steps along the root path: step to stage s - 1
     // reads buffer A, to stage s - 2 buffer B, then they alternate
+    // (Near the root the root's own data are loaded instead, unused: every
+    // path then issues the same loads, and the compiler's count of loads
+    // still in flight -- its waits -- need not assume that a buffer's loads
+    // were the last ones issued.)
     WregIn bufA, bufB;
-    if (s >= 1) {
-        load_stage(node_at(s - 1), bufA);
-        load_edge(n, bufA);
-    }
-    if (s >= 2) {
-        load_stage(node_at(s - 2), bufB);
-        load_edge(node_at(s - 1), bufB);
-    }
+    load_stage(node_at(max(s - 1, 0)), bufA);
+    load_edge(n, bufA);
+    load_stage(node_at(max(s - 2, 0)), bufB);
+    load_edge(node_at(max(s - 1, 0)), bufB);
 
     // One step up from n (stage s) to its parent; false when the walk ends.
     auto up = [&](WregIn& in) -> bool {
@@ -974,9 +528,19 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
         if (base - (s - 3) >= 64) reload(s);
         const int nsib = nsib_of(s);
         const int par = node_at(s - 1);
+        // with one sibling, its edge is requested with the count (after
+        // the wait for this walker's stores, which would wait for it too),
+        // for the case that this walker arrives last
+        WregIn sib;
+        int sib_j = -1;
         if (nsib > 1) {
             // hand the value function over: the stores complete before the count
             wait_own_stores();
+            if (nsib == 2) {
+                const int pf = __builtin_amdgcn_readlane(c0v, lane_of(s - 1));
+                sib_j = pf == n ? pf + 1 : pf;
+                load_edge(sib_j, sib);
+            }
             __syncthreads();
             if (lane == 0) sgo = (atomicAdd(&arrive[par], 1) == nsib - 1);
             __syncthreads();
@@ -1011,6 +575,9 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
                         ej.d[m] = in.d[m];
                         ej.cb[m] = in.cb[m];
                     }
+                } else if (j == sib_j) {
+                    load_value_dev(j, Pj, pj);
+                    ej = sib;
                 } else {
                     load_value_dev(j, Pj, pj);
                     load_edge(j, ej);
@@ -1019,49 +586,55 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
             }
         }
         // the step after next: its inputs into the buffer just consumed
-        if (s >= 2) {
-            load_stage(node_at(s - 2), in);
-            load_edge(node_at(s - 1), in);
-        }
-        // gains from rows NX.. of Z (element 3 of every lane)
+        load_stage(node_at(max(s - 2, 0)), in);
+        load_edge(node_at(max(s - 1, 0)), in);
+        // gains from rows NX.. of Z (element 3 of every lane): every lane
+        // factors H = L L^T and forms the columns of Gh = L^-1 [G g] it
+        // needs itself -- its own column li (for the gains and P), the
+        // columns lk + 4 v (v < 3, rows of P) and gh -- so that no column
+        // goes back through LDS
         sH[lk][li] = zm[3];
         if (li == 0) sH[lk][NZ] = zc[3];
         wave_sync();
-        {
-            double L[NU][NU], inv[NU];
+        double L[NU][NU], inv[NU];
 #pragma unroll
-            for (int i = 0; i < NU; ++i)
+        for (int i = 0; i < NU; ++i)
 #pragma unroll
-                for (int j = 0; j < NU; ++j) L[i][j] = sH[i][NX + j];
-            const bool ok = chol_inplace_rsq<NU>(L, inv);
-            if (!ok && lane == 0) atomicMin(a.bad, n);
-            const int col = lane < NX ? lane : NZ;
-            const int gcol = lane < NX ? lane : NX;
-            double v[NU];
+            for (int j = 0; j < NU; ++j) L[i][j] = sH[i][NX + j];
+        const bool ok = chol_inplace_rsq<NU>(L, inv);
+        if (!ok && lane == 0) atomicMin(a.bad, n);
+        auto column = [&](int c, double (&v)[NU]) {
 #pragma unroll
-            for (int i = 0; i < NU; ++i) v[i] = sH[i][col];
+            for (int i = 0; i < NU; ++i) v[i] = sH[i][c];
             chol_fwd<NU>(L, inv, v);
+        };
+        double gl[NU], gg[NU], gi[3][NU];
+        column(li < NX ? li : NZ, gl);
+        column(NZ, gg);
 #pragma unroll
-            for (int i = 0; i < NU; ++i) sG[i][gcol] = v[i];
-            chol_bwd<NU>(L, inv, v);
+        for (int v = 0; v < 3; ++v) column(lk + 4 * v, gi[v]);
+        wave_sync();  // sH is rewritten by the next step
+        {
+            // [K k] = -L^-T Gh: lanes li < NX take column li of K, the
+            // others k (the same values)
+            double x[NU];
+#pragma unroll
+            for (int i = 0; i < NU; ++i) x[i] = gl[i];
+            chol_bwd<NU>(L, inv, x);
 #pragma unroll
             for (int i = 0; i < NU; ++i) {
-                double* dst = lane < NX ? &a.K[lidx<LAY>(n, i * NX + lane, NU * NX, N)]
-                                        : &a.k[lidx<LAY>(n, i, NU, N)];
-                *dst = -v[i];
+                double* dst = li < NX ? &a.K[lidx<LAY>(n, i * NX + li, NU * NX, N)] : &a.k[lidx<LAY>(n, i, NU, N)];
+                *dst = -x[i];
             }
         }
-        wave_sync();
         // P = W - Gh^T Gh and p = w - Gh^T gh, in the accumulator layout
-        const int lic = li < NX ? li : 0;
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
-            const int i = lk + 4 * v;
             double tP = 0.0, tp = 0.0;
 #pragma unroll
             for (int r = 0; r < NU; ++r) {
-                tP = fma(sG[r][i], sG[r][lic], tP);
-                tp = fma(sG[r][i], sG[r][NX], tp);
+                tP = fma(gi[v][r], gl[r], tP);
+                tp = fma(gi[v][r], gg[r], tp);
             }
             Preg[v] = li < NX ? zm[v] - tP : 0.0;
             pvec[v] = zc[v] - tp;
@@ -1080,7 +653,7 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
 // ------------------------------------------------------------------------
 // Backward pass for larger state dimensions (the mass-spring chain,
 // nx = 30, nu = 14): one workgroup of four wavefronts walks a leaf
-// segment upwards, with the same last-arriver merges as k_bwd_wave.  Per
+// segment upwards, with the same last-arriver merges as k_bwd_wreg.  Per
 // child, the two dense products run on the FP64 matrix cores
 // (v_mfma_f64_16x16x4, 16 x 16 output tiles spread over the wavefronts):
 //   S = P [A B c] + [0 0 p]         (NX x NC, NC = NX + NU + 1)
@@ -1853,7 +1426,6 @@ __global__ void k_zero_norms(unsigned long long* norm, int n)
 struct LqrKernels {
     int nx, nu, layout, group;
     void (*bwd_lane)(TreeDev, LqrArgs, int*);
-    void (*bwd_wave)(TreeDev, LqrArgs, int*);
     void (*bwd_mfma)(TreeDev, LqrArgs, int*);
     void (*bwd_seg)(TreeDev, LqrArgs, int*);
     void (*fwd)(TreeDev, LqrArgs);
@@ -1873,7 +1445,7 @@ static LqrKernels make_k()
 {
     // rows of 16 lanes: the broadcasts inside a group are DPP row moves
     constexpr int G = 16;
-    LqrKernels k{NX, NU, LAY, G, nullptr, k_bwd_wave<NX, NU, LAY>, nullptr, nullptr, k_fwd_rows<NX, NU, LAY, G, 4>,
+    LqrKernels k{NX, NU, LAY, G, nullptr, nullptr, nullptr, k_fwd_rows<NX, NU, LAY, G, 4>,
                  k_costate<NX, LAY>};
     if constexpr (NX == 12 && NU == 4) k.bwd_wreg = k_bwd_wreg<NX, NU, LAY>;
     if constexpr (LANE) {
@@ -1894,7 +1466,7 @@ template <int NX, int NU, int LAY>
 static LqrKernels make_k_mfma()
 {
     constexpr int G = 64;
-    return LqrKernels{NX, NU, LAY, G, nullptr, nullptr, k_bwd_mfma<NX, NU, LAY>, nullptr,
+    return LqrKernels{NX, NU, LAY, G, nullptr, k_bwd_mfma<NX, NU, LAY>, nullptr,
                       k_fwd_rows<NX, NU, LAY, G, 2>, k_costate<NX, LAY>, nullptr, nullptr, nullptr, nullptr, nullptr,
                       nullptr};
 }
@@ -2067,12 +1639,10 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
     } else if (pl->kern->bwd_wreg) {
         ProfScope ps("lqr_backward_level_wreg", s);
         hipLaunchKernelGGL(pl->kern->bwd_wreg, dim3(Z), dim3(64), 0, s, t, a, pl->arrive);
-    } else if (pl->kern->bwd_lane) {
+    } else {
+        // every table entry without one of the two above has the lane kernel
         ProfScope ps("lqr_backward_level_lane", s);
         hipLaunchKernelGGL(pl->kern->bwd_lane, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
-    } else {
-        ProfScope ps("lqr_backward_level_wave", s);
-        hipLaunchKernelGGL(pl->kern->bwd_wave, dim3(Z), dim3(64), 0, s, t, a, pl->arrive);
     }
     {
         ProfScope ps("lqr_forward_paths", s);
