@@ -421,36 +421,47 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
     auto lane_of = [&](int st) -> int { return base - st; };
     auto node_at = [&](int st) -> int { return st >= 0 ? __builtin_amdgcn_readlane(pathv, lane_of(st)) : -1; };
 
-    // edge into child j, operand layout; one load per entry and lane (the
-    // per-lane address picks A or B), so that no branch waits on the loads
+    // Per-lane addresses of node 0's entries and the distance from one node
+    // to the next, computed once: the edge into child j, operand layout (an
+    // entry of A or of B, picked per lane), and the stage data of a node,
+    // accumulator layout (rows lk + 4 v < NX for v < 3).  A load is then one
+    // multiply-add of the node id.
+    constexpr bool NM = LAY == BMPC_LAYOUT_NODE_MAJOR;
+    auto at = [&](const double* arr, int e) -> const double* { return NM ? arr + e : arr + (long)e * N; };
+    auto stride = [](int esize) -> int { return NM ? esize : 1; };
+    const double* pd0[3];
+    const double* pc0[3];
+    const double* pz0[4];
+    const double* pq0[4];
+    const int sd = li < NX ? stride(NX * NX) : stride(NX * NU);
+    const int sz0 = li < NX ? stride(NX * NX) : stride(NU * NX);
+    const int sz3 = li < NX ? stride(NU * NX) : stride(NU * NU);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int k = 4 * m + lk;
+        pd0[m] = li < NX ? at(a.A, k * NX + li) : at(a.B, k * NU + (li - NX));
+        pc0[m] = at(a.c, k);
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const int r = lk + 4 * v;
+        pz0[v] = li < NX ? at(a.Q, r * NX + li) : at(a.M, (li - NX) * NX + r);
+        pq0[v] = at(a.q, r);
+    }
+    pz0[3] = li < NX ? at(a.M, lk * NX + li) : at(a.R, lk * NU + (li - NX));
+    pq0[3] = at(a.r, lk);
     auto load_edge = [&](int j, WregIn& in) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const int k = 4 * m + lk;
-            const double* pd = li < NX ? &a.A[lidx<LAY>(j, k * NX + li, NX * NX, N)]
-                                       : &a.B[lidx<LAY>(j, k * NU + (li - NX), NX * NU, N)];
-            in.d[m] = *pd;
-            in.cb[m] = a.c[lidx<LAY>(j, k, NX, N)];
+            in.d[m] = pd0[m][(long)j * sd];
+            in.cb[m] = pc0[m][(long)j * stride(NX)];
         }
     };
-    // stage data of node m, accumulator layout: rows lk + 4 v < NX for v < 3
     auto load_stage = [&](int m, WregIn& in) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int r = lk + 4 * v;
-            const double* pz;
-            const double* pc;
-            if (v < 3) {
-                pz = li < NX ? &a.Q[lidx<LAY>(m, r * NX + li, NX * NX, N)]
-                             : &a.M[lidx<LAY>(m, (li - NX) * NX + r, NU * NX, N)];
-                pc = &a.q[lidx<LAY>(m, r, NX, N)];
-            } else {
-                pz = li < NX ? &a.M[lidx<LAY>(m, (r - NX) * NX + li, NU * NX, N)]
-                             : &a.R[lidx<LAY>(m, (r - NX) * NU + (li - NX), NU * NU, N)];
-                pc = &a.r[lidx<LAY>(m, r - NX, NU, N)];
-            }
-            in.z[v] = *pz;
-            in.zc[v] = *pc;
+            in.z[v] = pz0[v][(long)m * (v < 3 ? sz0 : sz3)];
+            in.zc[v] = pq0[v][(long)m * (v < 3 ? stride(NX) : stride(NU))];
         }
     };
     // the child's contribution D^T (P D + [0 0 p]) added to (zm, zc)
