@@ -450,6 +450,20 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
     }
     pz0[3] = li < NX ? at(a.M, lk * NX + li) : at(a.R, lk * NU + (li - NX));
     pq0[3] = at(a.r, lk);
+    // and of the outputs: this lane's entries of P and p (accumulator
+    // layout) and its column of K (or k)
+    auto atw = [&](double* arr, int e) -> double* { return NM ? arr + e : arr + (long)e * N; };
+    double* pP0[3];
+    double* pp0[3];
+    double* pK0[NU];
+    const int sK = li < NX ? stride(NU * NX) : stride(NU);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        pP0[v] = atw(a.P, (lk + 4 * v) * NX + (li < NX ? li : 0));
+        pp0[v] = atw(a.p, lk + 4 * v);
+    }
+#pragma unroll
+    for (int i = 0; i < NU; ++i) pK0[i] = li < NX ? atw(a.K, i * NX + li) : atw(a.k, i);
     auto load_edge = [&](int j, WregIn& in) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
@@ -491,18 +505,18 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
         }
     };
     auto store_value = [&](int m, const f64x4& Pr, const double (&pv)[4], bool shared) {
+        const long oP = (long)m * stride(NX * NX), op = (long)m * stride(NX);
+        if (shared) {
 #pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            const int r = lk + 4 * v;
-            if (li < NX) {
-                double* dst = &a.P[lidx<LAY>(m, r * NX + li, NX * NX, N)];
-                if (shared) st_shared_dev(dst, Pr[v]);
-                else *dst = Pr[v];
+            for (int v = 0; v < 3; ++v) {
+                if (li < NX) st_shared_dev(pP0[v] + oP, Pr[v]);
+                if (li == 0) st_shared_dev(pp0[v] + op, pv[v]);
             }
-            if (li == 0) {
-                double* dst = &a.p[lidx<LAY>(m, r, NX, N)];
-                if (shared) st_shared_dev(dst, pv[v]);
-                else *dst = pv[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                if (li < NX) pP0[v][oP] = Pr[v];
+                if (li == 0) pp0[v][op] = pv[v];
             }
         }
     };
@@ -633,10 +647,7 @@ __global__ void __launch_bounds__(64) k_bwd_wreg(TreeDev t, LqrArgs a, int* arri
             for (int i = 0; i < NU; ++i) x[i] = gl[i];
             chol_bwd<NU>(L, inv, x);
 #pragma unroll
-            for (int i = 0; i < NU; ++i) {
-                double* dst = li < NX ? &a.K[lidx<LAY>(n, i * NX + li, NU * NX, N)] : &a.k[lidx<LAY>(n, i, NU, N)];
-                *dst = -x[i];
-            }
+            for (int i = 0; i < NU; ++i) pK0[i][(long)n * sK] = -x[i];
         }
         // P = W - Gh^T Gh and p = w - Gh^T gh, in the accumulator layout
 #pragma unroll
