@@ -926,9 +926,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     // (NU x NT) in registers and the lanes run the right-looking Cholesky
     // factorisation of H with the columns of [G g] carried along; the pivot
     // and the column of step j come from lane j by scalar reads.  Afterwards
-    // lane c < NU holds row c of L and lane NU + c column c of
-    // Gh = L^-1 [G g]; the latter solve L^T X = Gh for their column (X =
-    // -[K k]) with the entries of L read from the lanes that hold them.
+    // lane j < NU holds column j of L and lane NU + c column c of
+    // Gh = L^-1 [G g], both unscaled; the latter solve L^T X = Gh for their
+    // column (X = -[K k]) with the entries of L read from the lanes that
+    // hold them.
     // Then all threads form P = (W + W^T)/2 - Gh^T Gh and p = w - Gh^T gh.
     // next_stage >= 0: the next step is a chain step (node next_stage, edge
     // into m); while wavefront 0 computes the gains, the other three load
@@ -956,34 +957,40 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                 const double dd = d > 0.0 ? d : 1.0;
                 const double y = rsqrt_refined(dd);
                 inv[j] = y;
-                const double tjc = col[j] * y;  // row j of L^T / of Gh in lane c > j
+                const double tjc = col[j] * y;  // L[c][j] in lane c > j
 #pragma unroll
                 for (int r = j + 1; r < NU; ++r) {
                     const double lrj = lane_value(col[r], j) * y;  // L[r][j], from lane j
                     if (c > j) col[r] -= lrj * tjc;
                 }
-                col[j] = c == j ? dd * y : (c > j ? tjc : col[j]);
             }
             if (lane == 0 && !ok) atomicMin(a.bad, m);
-            // The solve below reads entries of L from lanes that do not take
-            // its branch: an opaque copy makes every lane finish its column
-            // here, so the compiler cannot sink the last step of the
-            // factorisation into the branch (where the lanes of L would
-            // never run it).
+            // No column is scaled in place: lane j keeps column j of the
+            // Schur complement of step j unscaled (L[r][j] = col[r] inv[j]
+            // for r > j) and lane NU + c its column of [G g] after step j
+            // (Gh[j][c] = col[j] inv[j]).  The solve reads the former across
+            // lanes, in a branch that lane j does not take; inside the branch
+            // the compiler may take a lane-dependent select for the side
+            // that the branch's own lanes see (and it does), so an opaque
+            // copy pins every lane's columns before the branch.
 #pragma unroll
             for (int j = 0; j < NU; ++j) asm volatile("" : "+v"(col[j]));
             if (c >= NU && c < NT) {
                 const int g = c - NU;  // column of [G g]
+                double gh[NU];
 #pragma unroll
-                for (int r = 0; r < NU; ++r) sG[r][g] = col[r];
-                // L^T x = gh column: L[k][j] is entry j of lane k's registers
+                for (int r = 0; r < NU; ++r) {
+                    gh[r] = col[r] * inv[r];
+                    sG[r][g] = gh[r];
+                }
+                // L^T x = gh
                 double x[NU];
 #pragma unroll
                 for (int j = NU - 1; j >= 0; --j) {
-                    double s = col[j];
+                    double t = 0.0;
 #pragma unroll
-                    for (int k = j + 1; k < NU; ++k) s -= lane_value(col[j], k) * x[k];
-                    x[j] = s * inv[j];
+                    for (int k = j + 1; k < NU; ++k) t = fma(lane_value(col[k], j), x[k], t);
+                    x[j] = (gh[j] - t * inv[j]) * inv[j];
                 }
 #pragma unroll
                 for (int r = 0; r < NU; ++r) {
