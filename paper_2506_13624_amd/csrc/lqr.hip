@@ -186,18 +186,29 @@ __global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgsT<T> a, int* 
 // element with all elements below it in log2(length) rounds, and applying
 // the value function of the segment's end node then gives every node's
 // (P, p) at once (eq. V_ki_min).  Gains K, k follow from one Riccati step
-// on the child's value (eq. tree_feedback_laws).  Segments longer than 64
-// nodes are done in chunks of 64 from the bottom.
+// on the child's value (eq. tree_feedback_laws).  The single-child nodes
+// of a segment are done in chunks of ch <= 64 from the bottom; ch is the
+// tree's longest such run (at most 64), and the LDS of a workgroup is two
+// scan buffers of ch elements (the chunk's value functions go to the one not
+// holding the scan's result), so short segments leave room for more
+// segments per compute unit.
 template <int NX>
 struct ValueLds {
     double P[NX][NX], p[NX];
 };
 
+// Two wavefronts per SIMD (the compiler keeps a lane within 256 registers,
+// spilling a few hundred bytes): with the LDS sized to the chunk, a compute
+// unit then holds up to eight segments.
 template <int NX, int NU, int LAY>
-__global__ void __launch_bounds__(64) k_bwd_seg(TreeDev t, LqrArgs a, int* arrive)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_bwd_seg(TreeDev t, LqrArgs a, int* arrive, int ch)
 {
-    __shared__ Cvf<NX> sbuf[2][64];
-    __shared__ ValueLds<NX> sval[64];
+    static_assert(sizeof(ValueLds<NX>) <= sizeof(Cvf<NX>), "a chunk's values fit in a scan buffer");
+    extern __shared__ __align__(16) unsigned char seg_lds[];
+    // element i of scan buffer b (indexed off the LDS symbol itself, so that
+    // every access stays an LDS access)
+    auto sbuf = [&](int b, int i) -> Cvf<NX>& { return reinterpret_cast<Cvf<NX>*>(seg_lds)[b * ch + i]; };
     __shared__ ValueLds<NX> send;
     __shared__ int sgo;
     const int lane = threadIdx.x;
@@ -252,7 +263,7 @@ __global__ void __launch_bounds__(64) k_bwd_seg(TreeDev t, LqrArgs a, int* arriv
         __syncthreads();
         // single-child nodes at positions [0, len-1), bottom chunk first
         for (int hi = len - 1; hi > 0;) {
-            const int lo = hi > 64 ? hi - 64 : 0;
+            const int lo = hi > ch ? hi - ch : 0;
             const int cnt = hi - lo;
             const int pos = lo + lane;
             const bool act = lane < cnt;
@@ -263,7 +274,7 @@ __global__ void __launch_bounds__(64) k_bwd_seg(TreeDev t, LqrArgs a, int* arriv
             if (act) {
                 load_stage<NX, NU, LAY>(a, N, n, st);
                 load_edge<NX, NU, LAY, false>(a, N, n, j, ed);
-                if (!cvf_element<NX, NU>(st.Q, st.R, st.M, st.q, st.r, ed.A, ed.B, ed.c, sbuf[0][lane]))
+                if (!cvf_element<NX, NU>(st.Q, st.R, st.M, st.q, st.r, ed.A, ed.B, ed.c, sbuf(0, lane)))
                     atomicMin(a.bad, n);
             }
             __syncthreads();
@@ -271,16 +282,17 @@ __global__ void __launch_bounds__(64) k_bwd_seg(TreeDev t, LqrArgs a, int* arriv
             for (int span = 1; span < cnt; span <<= 1) {
                 if (act) {
                     if (lane + span < cnt)
-                        cvf_combine<NX>(sbuf[cur][lane], sbuf[cur][lane + span], sbuf[cur ^ 1][lane]);
+                        cvf_combine<NX>(sbuf(cur, lane), sbuf(cur, lane + span), sbuf(cur ^ 1, lane));
                     else
-                        sbuf[cur ^ 1][lane] = sbuf[cur][lane];
+                        sbuf(cur ^ 1, lane) = sbuf(cur, lane);
                 }
                 __syncthreads();
                 cur ^= 1;
             }
+            ValueLds<NX>* const sval = reinterpret_cast<ValueLds<NX>*>(&sbuf(cur ^ 1, 0));
             double P[NX][NX], p[NX];
             if (act) {
-                cvf_apply_value<NX>(sbuf[cur][lane], send.P, send.p, P, p);
+                cvf_apply_value<NX>(sbuf(cur, lane), send.P, send.p, P, p);
 #pragma unroll
                 for (int i = 0; i < NX; ++i) {
 #pragma unroll
@@ -290,13 +302,13 @@ __global__ void __launch_bounds__(64) k_bwd_seg(TreeDev t, LqrArgs a, int* arriv
             }
             __syncthreads();
             if (act) {
-                const ValueLds<NX>& ch = lane + 1 < cnt ? sval[lane + 1] : send;
+                const ValueLds<NX>& cv = lane + 1 < cnt ? sval[lane + 1] : send;
                 double Pc[NX][NX], pc[NX];
 #pragma unroll
                 for (int i = 0; i < NX; ++i) {
 #pragma unroll
-                    for (int k = 0; k < NX; ++k) Pc[i][k] = ch.P[i][k];
-                    pc[i] = ch.p[i];
+                    for (int k = 0; k < NX; ++k) Pc[i][k] = cv.P[i][k];
+                    pc[i] = cv.p[i];
                 }
                 RicAcc<NX, NU> acc;
                 acc.init(st);
@@ -1456,7 +1468,7 @@ struct LqrKernels {
     int nx, nu, layout, group;
     void (*bwd_lane)(TreeDev, LqrArgs, int*);
     void (*bwd_mfma)(TreeDev, LqrArgs, int*);
-    void (*bwd_seg)(TreeDev, LqrArgs, int*);
+    void (*bwd_seg)(TreeDev, LqrArgs, int*, int);
     void (*fwd)(TreeDev, LqrArgs);
     void (*costate)(TreeDev, LqrArgs, int*);
     // FP32 solve and the FP64 residual of the mixed-precision refinement
@@ -1467,6 +1479,8 @@ struct LqrKernels {
     void (*residual)(TreeDev, LqrArgs, float*, float*, float*, float*, unsigned long long*);
     // nx = 12, nu = 4: register-resident matrix-core backward pass
     void (*bwd_wreg)(TreeDev, LqrArgs, int*);
+    // bytes of one segment-scan element (the kernel's LDS per chunk node)
+    size_t seg_cvf_bytes;
 };
 
 template <int NX, int NU, int LAY, bool LANE>
@@ -1485,7 +1499,10 @@ static LqrKernels make_k()
         k.residual_first = k_lqr_residual<NX, NU, LAY, true>;
         k.residual = k_lqr_residual<NX, NU, LAY, false>;
     }
-    if constexpr (NX <= 4) k.bwd_seg = k_bwd_seg<NX, NU, LAY>;
+    if constexpr (NX <= 4) {
+        k.bwd_seg = k_bwd_seg<NX, NU, LAY>;
+        k.seg_cvf_bytes = sizeof(Cvf<NX>);
+    }
     return k;
 }
 
@@ -1661,7 +1678,10 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
     const int Z = t.num_leaves;
     if (variant == BMPC_RICCATI_SEGSCAN) {
         ProfScope ps("lqr_backward_segscan", s);
-        hipLaunchKernelGGL(pl->kern->bwd_seg, dim3(Z), dim3(64), 0, s, t, a, pl->arrive);
+        // single-child nodes of the longest segment (all but its bottom node)
+        const int ch = std::min(64, std::max(1, t.max_seg_len - 1));
+        hipLaunchKernelGGL(pl->kern->bwd_seg, dim3(Z), dim3(64), 2 * ch * pl->kern->seg_cvf_bytes, s, t, a,
+                           pl->arrive, ch);
     } else if (pl->kern->bwd_mfma) {
         ProfScope ps("lqr_backward_level_mfma", s);
         hipLaunchKernelGGL(pl->kern->bwd_mfma, dim3(Z), dim3(256), 0, s, t, a, pl->arrive);
