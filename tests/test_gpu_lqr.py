@@ -158,6 +158,12 @@ SEG_TREES = dict(TREES)
 SEG_TREES["long_chain"] = S.tree_parent(150, [], 1)         # one segment in 3 chunks of <= 64
 SEG_TREES["long_branches"] = S.tree_parent(90, [2], 3)       # 3 leaf segments of 88 nodes
 SEG_TREES["cfg0_topology"] = S.tree_parent(20, [4], 3)
+# the scan's LDS is sized to the longest run of single-child nodes (at most
+# 64): runs of 0 (every node branches), exactly 64 (one full chunk) and 65
+# (a full chunk and a chunk of one)
+SEG_TREES["all_branching"] = S.tree_parent(6, range(6), 2)
+SEG_TREES["run_64"] = S.tree_parent(65, [0], 2)
+SEG_TREES["run_65"] = S.tree_parent(66, [0], 2)
 
 
 @pytest.mark.parametrize("a_scale", [0.03, 0.1])
