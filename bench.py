@@ -828,7 +828,7 @@ def run_large_tree(args, torch, L):
     alg = lqr_algorithmic(par, 4, 2)
     res = {}
     steps = max(20, args.steps // 10)
-    for name, variant, kname in (("level", L.RICCATI_LEVEL, "lqr_backward_level_lane"),
+    for name, variant, kname in (("level", L.RICCATI_LEVEL, "lqr_backward_level"),
                                  ("segment_scan", L.RICCATI_SEGSCAN, "lqr_backward_segscan")):
         def step():
             L.bmpc_lqr_solve(plan, Ae, Be, c, Q, R, M, q, r, x0, *outs, variant=variant)
@@ -842,6 +842,8 @@ def run_large_tree(args, torch, L):
         torch.cuda.synchronize()
         prof = L.bmpc_profile_read()
         L.bmpc_profile_enable(False)
+        # the backward kernel that ran (its name carries the variant)
+        kname = next(k for k in prof if k.startswith(kname))
         bwd_us = prof[kname][0] / prof[kname][1] * 1e3
         tot_us = sum(v[0] for v in prof.values()) / steps * 1e3
         res[name] = {"backward_us": round(bwd_us, 2), "lqr_solve_us": round(tot_us, 2), "status": int(status),

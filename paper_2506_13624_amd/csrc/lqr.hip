@@ -175,6 +175,300 @@ __global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgsT<T> a, int* 
 }
 
 // ------------------------------------------------------------------------
+// nx = 4, nu = 2: a group of 16 lanes per leaf chain
+// ------------------------------------------------------------------------
+// Same walk and merges as k_bwd_lane, but the work of a step is spread over
+// the 16 lanes of a DPP row: lane q = 4 i + j holds entry (i, j) of P and
+// of the step's 4 x 4 products, entry (a, j) of G for both rows a, and
+// entry (a, j % 2) of H.  Row i of P comes from the lane's quad (quad_perm
+// broadcasts); the column of S = P [A B] and the vector s = P c + p that
+// the second products need come from the lanes 4, 8 and 12 further on in
+// the row (row rotations), so every lane reads only the entries of A, B it
+// multiplies.  H, g and the gains are small and formed by every lane.
+
+// lane K of this lane's quad
+template <int K>
+__device__ __forceinline__ double quad_bcast(double v)
+{
+    return __builtin_amdgcn_update_dpp(0.0, v, K | (K << 2) | (K << 4) | (K << 6), 0xf, 0xf, false);
+}
+// the other lane of this lane's pair in the quad (lane ^ 1)
+__device__ __forceinline__ double quad_swap1(double v)
+{
+    return __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xf, 0xf, false);
+}
+// lane J of this lane's row of 16
+template <int J>
+__device__ __forceinline__ double row_lane(double v)
+{
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xf, 0xf, false);
+}
+// rotation by R lanes within the row of 16
+template <int R>
+__device__ __forceinline__ double row_rot(double v)
+{
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x120 + R, 0xf, 0xf, false);
+}
+template <int R>
+__device__ __forceinline__ int row_rot_int(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x120 + R, 0xf, 0xf, false);
+}
+
+struct QuadEdge {
+    double Acol[4], Bcol[4], c[4];  // A[k][j], B[k][j % 2], c[k]
+    double Arot[4], Brot[2][4];     // A[r_d][i], B[r_d][a]: r_d the row held by the lane 4 d further on
+};
+struct QuadStage {
+    double Q, M[2], R[2], r[2], q;  // Q[i][j], M[a][j], R[a][j % 2], r[a], q[i]
+};
+struct QuadAcc {
+    double W, w, G[2], H[2], g[2];  // W[i][j], w[i], G[a][j], H[a][j % 2], g[a]
+};
+
+template <int LAY>
+__global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arrive)
+{
+    constexpr int NX = 4, NU = 2;
+    const int tid = blockIdx.x * 64 + threadIdx.x;
+    const int chain = tid >> 4;
+    if (chain >= t.num_leaves) return;  // the whole group leaves together
+    const int q = tid & 15, i = q >> 2, j = q & 3, jb = j & 1;
+    const int N = t.N;
+    // row of the matrices held by the lane 4 d further on in the row (d = 0
+    // is this lane), found with the same rotation that moves the values
+    int rrow[4];
+    rrow[0] = i;
+    rrow[1] = row_rot_int<12>(i);
+    rrow[2] = row_rot_int<8>(i);
+    rrow[3] = row_rot_int<4>(i);
+
+    auto load_edge_q = [&](int ch, QuadEdge& e) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            e.Acol[k] = a.A[lidx<LAY>(ch, k * NX + j, NX * NX, N)];
+            e.Bcol[k] = a.B[lidx<LAY>(ch, k * NU + jb, NX * NU, N)];
+            e.c[k] = a.c[lidx<LAY>(ch, k, NX, N)];
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            e.Arot[d] = a.A[lidx<LAY>(ch, rrow[d] * NX + i, NX * NX, N)];
+#pragma unroll
+            for (int b = 0; b < NU; ++b) e.Brot[b][d] = a.B[lidx<LAY>(ch, rrow[d] * NU + b, NX * NU, N)];
+        }
+    };
+    auto load_stage_q = [&](int m, QuadStage& st) {
+        st.Q = a.Q[lidx<LAY>(m, i * NX + j, NX * NX, N)];
+        st.q = a.q[lidx<LAY>(m, i, NX, N)];
+#pragma unroll
+        for (int b = 0; b < NU; ++b) {
+            st.M[b] = a.M[lidx<LAY>(m, b * NX + j, NU * NX, N)];
+            st.R[b] = a.R[lidx<LAY>(m, b * NU + jb, NU * NU, N)];
+            st.r[b] = a.r[lidx<LAY>(m, b, NU, N)];
+        }
+    };
+    auto acc_init = [&](const QuadStage& st, QuadAcc& z) {
+        z.W = st.Q;
+        z.w = st.q;
+#pragma unroll
+        for (int b = 0; b < NU; ++b) {
+            z.G[b] = st.M[b];
+            z.H[b] = st.R[b];
+            z.g[b] = st.r[b];
+        }
+    };
+    // the child's value function (entry Pv of P, entry pv of p) through edge e
+    auto acc_add = [&](const QuadEdge& e, double Pv, double pv, QuadAcc& z) {
+        double prow[4];
+        prow[0] = quad_bcast<0>(Pv);
+        prow[1] = quad_bcast<1>(Pv);
+        prow[2] = quad_bcast<2>(Pv);
+        prow[3] = quad_bcast<3>(Pv);
+        double SA = 0.0, SB = 0.0, sv = pv;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            SA = fma(prow[k], e.Acol[k], SA);
+            SB = fma(prow[k], e.Bcol[k], SB);
+            sv = fma(prow[k], e.c[k], sv);
+        }
+        double rSA[4], rSB[4], rs[4];
+        rSA[0] = SA;
+        rSB[0] = SB;
+        rs[0] = sv;
+        rSA[1] = row_rot<12>(SA);
+        rSB[1] = row_rot<12>(SB);
+        rs[1] = row_rot<12>(sv);
+        rSA[2] = row_rot<8>(SA);
+        rSB[2] = row_rot<8>(SB);
+        rs[2] = row_rot<8>(sv);
+        rSA[3] = row_rot<4>(SA);
+        rSB[3] = row_rot<4>(SB);
+        rs[3] = row_rot<4>(sv);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            z.W = fma(e.Arot[d], rSA[d], z.W);
+            z.w = fma(e.Arot[d], rs[d], z.w);
+#pragma unroll
+            for (int b = 0; b < NU; ++b) {
+                z.G[b] = fma(e.Brot[b][d], rSA[d], z.G[b]);
+                z.H[b] = fma(e.Brot[b][d], rSB[d], z.H[b]);
+                z.g[b] = fma(e.Brot[b][d], rs[d], z.g[b]);
+            }
+        }
+    };
+    double Pv, pv;  // this lane's entries of the current value function
+    // gains and value function of node m from the accumulated z
+    auto finish = [&](const QuadAcc& z, int m) {
+        const double ho0 = quad_swap1(z.H[0]), ho1 = quad_swap1(z.H[1]);
+        double L[2][2], inv[2];
+        L[0][0] = jb == 0 ? z.H[0] : ho0;
+        L[0][1] = jb == 1 ? z.H[0] : ho0;
+        L[1][0] = jb == 0 ? z.H[1] : ho1;
+        L[1][1] = jb == 1 ? z.H[1] : ho1;
+        const bool ok = chol_inplace_rsq<2>(L, inv);
+        if (!ok && q == 0) atomicMin(a.bad, m);
+        double Kj[2] = {z.G[0], z.G[1]}, kv[2] = {z.g[0], z.g[1]};
+        chol_solve<2>(L, inv, Kj);
+        chol_solve<2>(L, inv, kv);
+#pragma unroll
+        for (int b = 0; b < NU; ++b) {
+            Kj[b] = -Kj[b];
+            kv[b] = -kv[b];
+        }
+        // G[a][i]: entry i of row a, held by lane i of the row
+        double Gi[2];
+#pragma unroll
+        for (int b = 0; b < NU; ++b) {
+            const double g0 = row_lane<0>(z.G[b]), g1 = row_lane<1>(z.G[b]);
+            const double g2 = row_lane<2>(z.G[b]), g3 = row_lane<3>(z.G[b]);
+            Gi[b] = i == 0 ? g0 : (i == 1 ? g1 : (i == 2 ? g2 : g3));
+        }
+        double X = z.W, pn = z.w;
+#pragma unroll
+        for (int b = 0; b < NU; ++b) {
+            X = fma(Gi[b], Kj[b], X);
+            pn = fma(Gi[b], kv[b], pn);
+        }
+        // (X is symmetric up to rounding; it is kept as it is rather than
+        // averaged with the transposed lane's entry, an LDS permute on the
+        // walk's path)
+        Pv = X;
+        pv = pn;
+        if (i < NU) a.K[lidx<LAY>(m, i * NX + j, NU * NX, N)] = i == 0 ? Kj[0] : Kj[1];
+        if (q < NU) a.k[lidx<LAY>(m, q, NU, N)] = q == 0 ? kv[0] : kv[1];
+    };
+    auto store_value_q = [&](int m, bool shared) {
+        double* pP = &a.P[lidx<LAY>(m, i * NX + j, NX * NX, N)];
+        double* pp = &a.p[lidx<LAY>(m, i, NX, N)];
+        if (shared) {
+            st_shared_dev(pP, Pv);
+            if (j == 0) st_shared_dev(pp, pv);
+        } else {
+            *pP = Pv;
+            if (j == 0) *pp = pv;
+        }
+    };
+
+    int n = t.leaves[chain];
+    int4 inf = t.info[n];
+    int from = -1;
+    bool pref = false;  // stage / edge hold the inputs of n (its single child is from)
+    bool pre2 = false;  // mst / me0 / me1 hold the inputs of n (two children, one is from)
+    QuadStage stage, mst;
+    QuadEdge edge, me0, me1;
+    for (;;) {
+        const int c0 = inf.x, c1 = inf.y, par = inf.z, nsib = inf.w;
+        // the next node's topology record, in flight while this node is computed
+        const int4 inf_next = par >= 0 ? t.info[par] : make_int4(0, 0, -1, 0);
+        if (c0 == c1) {
+            Pv = a.Q[lidx<LAY>(n, i * NX + j, NX * NX, N)];
+            pv = a.q[lidx<LAY>(n, i, NX, N)];
+            if (i < NU) a.K[lidx<LAY>(n, i * NX + j, NU * NX, N)] = 0.0;
+            if (q < NU) a.k[lidx<LAY>(n, q, NU, N)] = 0.0;
+            if (nsib == 1) {
+                load_stage_q(par, stage);
+                load_edge_q(n, edge);
+            }
+        } else {
+            QuadAcc z;
+            if (pref) {
+                acc_init(stage, z);
+                const QuadEdge e0 = edge;
+                // inputs of the parent are independent of this step: start them now
+                if (nsib == 1) {
+                    load_stage_q(par, stage);
+                    load_edge_q(n, edge);
+                }
+                acc_add(e0, Pv, pv, z);
+            } else if (pre2) {
+                // two children: the stage and both edges were requested with
+                // the count; the sibling's value function is read now, this
+                // group's own is in registers; sums in child order
+                acc_init(mst, z);
+                const bool own0 = from == c0;
+                double P0 = Pv, p0 = pv, P1 = Pv, p1 = pv;
+                if (own0) {
+                    P1 = ld_shared_dev(&a.P[lidx<LAY>(c0 + 1, i * NX + j, NX * NX, N)]);
+                    p1 = ld_shared_dev(&a.p[lidx<LAY>(c0 + 1, i, NX, N)]);
+                } else {
+                    P0 = ld_shared_dev(&a.P[lidx<LAY>(c0, i * NX + j, NX * NX, N)]);
+                    p0 = ld_shared_dev(&a.p[lidx<LAY>(c0, i, NX, N)]);
+                }
+                if (nsib == 1) {
+                    load_stage_q(par, stage);
+                    load_edge_q(n, edge);
+                }
+                acc_add(me0, P0, p0, z);
+                acc_add(me1, P1, p1, z);
+            } else {
+                QuadStage st;
+                load_stage_q(n, st);
+                acc_init(st, z);
+                for (int ch = c0; ch < c1; ++ch) {
+                    QuadEdge e;
+                    load_edge_q(ch, e);
+                    double Pc = Pv, pc = pv;
+                    if (!(c1 - c0 == 1 && from == ch)) {
+                        Pc = ld_shared_dev(&a.P[lidx<LAY>(ch, i * NX + j, NX * NX, N)]);
+                        pc = ld_shared_dev(&a.p[lidx<LAY>(ch, i, NX, N)]);
+                    }
+                    acc_add(e, Pc, pc, z);
+                }
+                if (nsib == 1) {
+                    load_stage_q(par, stage);
+                    load_edge_q(n, edge);
+                }
+            }
+            finish(z, n);
+        }
+        store_value_q(n, nsib > 1);
+        if (par < 0) break;
+        pref = nsib == 1;
+        pre2 = nsib == 2;
+        if (nsib > 1) {
+            // hand the value function over: all of the group's stores
+            // complete before its one count
+            wait_own_stores();
+            // with one sibling, the parent's stage and both edges are
+            // requested with the count, for the case that this group
+            // arrives last
+            if (pre2) {
+                load_stage_q(par, mst);
+                load_edge_q(inf_next.x, me0);
+                load_edge_q(inf_next.x + 1, me1);
+            }
+            int old = 0;
+            if (q == 0) old = atomicAdd(&arrive[par], 1);
+            old = __shfl(old, (int)(threadIdx.x & 48), 64);
+            if (old != nsib - 1) break;
+        }
+        from = n;
+        n = par;
+        inf = inf_next;
+    }
+}
+
+// ------------------------------------------------------------------------
 // log-depth backward: segment scan of conditional value functions
 // ------------------------------------------------------------------------
 // One wavefront per maximal unbranched segment, with the same dataflow over
@@ -1479,6 +1773,8 @@ struct LqrKernels {
     void (*residual)(TreeDev, LqrArgs, float*, float*, float*, float*, unsigned long long*);
     // nx = 12, nu = 4: register-resident matrix-core backward pass
     void (*bwd_wreg)(TreeDev, LqrArgs, int*);
+    // nx = 4, nu = 2: 16 lanes per leaf chain
+    void (*bwd_quad)(TreeDev, LqrArgs, int*);
     // bytes of one segment-scan element (the kernel's LDS per chunk node)
     size_t seg_cvf_bytes;
 };
@@ -1491,6 +1787,7 @@ static LqrKernels make_k()
     LqrKernels k{NX, NU, LAY, G, nullptr, nullptr, nullptr, k_fwd_rows<NX, NU, LAY, G, 4>,
                  k_costate<NX, LAY>};
     if constexpr (NX == 12 && NU == 4) k.bwd_wreg = k_bwd_wreg<NX, NU, LAY>;
+    if constexpr (NX == 4 && NU == 2) k.bwd_quad = k_bwd_quad<LAY>;
     if constexpr (LANE) {
         k.bwd_lane = k_bwd_lane<NX, NU, LAY>;
         k.bwd_lane32 = k_bwd_lane<NX, NU, LAY, float>;
@@ -1688,8 +1985,13 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
     } else if (pl->kern->bwd_wreg) {
         ProfScope ps("lqr_backward_level_wreg", s);
         hipLaunchKernelGGL(pl->kern->bwd_wreg, dim3(Z), dim3(64), 0, s, t, a, pl->arrive);
+    } else if (pl->kern->bwd_quad) {
+        ProfScope ps("lqr_backward_level_quad", s);
+        const long threads = (long)Z * 16;
+        hipLaunchKernelGGL(pl->kern->bwd_quad, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, t, a,
+                           pl->arrive);
     } else {
-        // every table entry without one of the two above has the lane kernel
+        // every table entry without one of the three above has the lane kernel
         ProfScope ps("lqr_backward_level_lane", s);
         hipLaunchKernelGGL(pl->kern->bwd_lane, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
     }
