@@ -876,7 +876,8 @@ def run_large_tree(args, torch, L):
         return e0.elapsed_time(e1) / steps * 1e3, {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]}
                                                   for k, v in prof.items() if k in kernels}
 
-    fp32_k = ("lqr_backward_level_lane_f32", "lqr_forward_paths_f32", "lqr_costate_f32")
+    fp32_k = ("lqr_backward_level_quad_f32", "lqr_backward_level_lane_f32", "lqr_forward_paths_f32",
+              "lqr_costate_f32")
     us32, k32 = timed(lambda: L.bmpc_lqr_solve_f32(plan, *f32_in, *f32_out), fp32_k)
     rel = lambda a, b: float((a.double() - b).abs().max() / b.abs().max())
     mixed = {"fp32_solve_us": round(us32, 2), "fp32_kernels": k32,

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <climits>
 #include <initializer_list>
+#include <type_traits>
 #include <utility>
 
 #include "bmpc_internal.hpp"
@@ -187,27 +188,28 @@ __global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgsT<T> a, int* 
 // multiplies.  H, g and the gains are small and formed by every lane.
 
 // lane K of this lane's quad
-template <int K>
-__device__ __forceinline__ double quad_bcast(double v)
+template <int K, class T>
+__device__ __forceinline__ T quad_bcast(T v)
 {
-    return __builtin_amdgcn_update_dpp(0.0, v, K | (K << 2) | (K << 4) | (K << 6), 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(T(0), v, K | (K << 2) | (K << 4) | (K << 6), 0xf, 0xf, false);
 }
 // the other lane of this lane's pair in the quad (lane ^ 1)
-__device__ __forceinline__ double quad_swap1(double v)
+template <class T>
+__device__ __forceinline__ T quad_swap1(T v)
 {
-    return __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(T(0), v, 0xB1, 0xf, 0xf, false);
 }
 // lane J of this lane's row of 16
-template <int J>
-__device__ __forceinline__ double row_lane(double v)
+template <int J, class T>
+__device__ __forceinline__ T row_lane(T v)
 {
-    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(T(0), v, 0x150 + J, 0xf, 0xf, false);
 }
 // rotation by R lanes within the row of 16
-template <int R>
-__device__ __forceinline__ double row_rot(double v)
+template <int R, class T>
+__device__ __forceinline__ T row_rot(T v)
 {
-    return __builtin_amdgcn_update_dpp(0.0, v, 0x120 + R, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(T(0), v, 0x120 + R, 0xf, 0xf, false);
 }
 template <int R>
 __device__ __forceinline__ int row_rot_int(int v)
@@ -215,19 +217,22 @@ __device__ __forceinline__ int row_rot_int(int v)
     return __builtin_amdgcn_update_dpp(0, v, 0x120 + R, 0xf, 0xf, false);
 }
 
+template <class T>
 struct QuadEdge {
-    double Acol[4], Bcol[4], c[4];  // A[k][j], B[k][j % 2], c[k]
-    double Arot[4], Brot[2][4];     // A[r_d][i], B[r_d][a]: r_d the row held by the lane 4 d further on
+    T Acol[4], Bcol[4], c[4];  // A[k][j], B[k][j % 2], c[k]
+    T Arot[4], Brot[2][4];     // A[r_d][i], B[r_d][a]: r_d the row held by the lane 4 d further on
 };
+template <class T>
 struct QuadStage {
-    double Q, M[2], R[2], r[2], q;  // Q[i][j], M[a][j], R[a][j % 2], r[a], q[i]
+    T Q, M[2], R[2], r[2], q;  // Q[i][j], M[a][j], R[a][j % 2], r[a], q[i]
 };
+template <class T>
 struct QuadAcc {
-    double W, w, G[2], H[2], g[2];  // W[i][j], w[i], G[a][j], H[a][j % 2], g[a]
+    T W, w, G[2], H[2], g[2];  // W[i][j], w[i], G[a][j], H[a][j % 2], g[a]
 };
 
-template <int LAY>
-__global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arrive)
+template <int LAY, class T = double>
+__global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgsT<T> a, int* arrive)
 {
     constexpr int NX = 4, NU = 2;
     const int tid = blockIdx.x * 64 + threadIdx.x;
@@ -243,7 +248,7 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
     rrow[2] = row_rot_int<8>(i);
     rrow[3] = row_rot_int<4>(i);
 
-    auto load_edge_q = [&](int ch, QuadEdge& e) {
+    auto load_edge_q = [&](int ch, QuadEdge<T>& e) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             e.Acol[k] = a.A[lidx<LAY>(ch, k * NX + j, NX * NX, N)];
@@ -257,7 +262,7 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
             for (int b = 0; b < NU; ++b) e.Brot[b][d] = a.B[lidx<LAY>(ch, rrow[d] * NU + b, NX * NU, N)];
         }
     };
-    auto load_stage_q = [&](int m, QuadStage& st) {
+    auto load_stage_q = [&](int m, QuadStage<T>& st) {
         st.Q = a.Q[lidx<LAY>(m, i * NX + j, NX * NX, N)];
         st.q = a.q[lidx<LAY>(m, i, NX, N)];
 #pragma unroll
@@ -267,7 +272,7 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
             st.r[b] = a.r[lidx<LAY>(m, b, NU, N)];
         }
     };
-    auto acc_init = [&](const QuadStage& st, QuadAcc& z) {
+    auto acc_init = [&](const QuadStage<T>& st, QuadAcc<T>& z) {
         z.W = st.Q;
         z.w = st.q;
 #pragma unroll
@@ -278,20 +283,20 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
         }
     };
     // the child's value function (entry Pv of P, entry pv of p) through edge e
-    auto acc_add = [&](const QuadEdge& e, double Pv, double pv, QuadAcc& z) {
-        double prow[4];
+    auto acc_add = [&](const QuadEdge<T>& e, T Pv, T pv, QuadAcc<T>& z) {
+        T prow[4];
         prow[0] = quad_bcast<0>(Pv);
         prow[1] = quad_bcast<1>(Pv);
         prow[2] = quad_bcast<2>(Pv);
         prow[3] = quad_bcast<3>(Pv);
-        double SA = 0.0, SB = 0.0, sv = pv;
+        T SA = T(0), SB = T(0), sv = pv;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             SA = fma(prow[k], e.Acol[k], SA);
             SB = fma(prow[k], e.Bcol[k], SB);
             sv = fma(prow[k], e.c[k], sv);
         }
-        double rSA[4], rSB[4], rs[4];
+        T rSA[4], rSB[4], rs[4];
         rSA[0] = SA;
         rSB[0] = SB;
         rs[0] = sv;
@@ -316,18 +321,22 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
             }
         }
     };
-    double Pv, pv;  // this lane's entries of the current value function
+    T Pv, pv;  // this lane's entries of the current value function
     // gains and value function of node m from the accumulated z
-    auto finish = [&](const QuadAcc& z, int m) {
-        const double ho0 = quad_swap1(z.H[0]), ho1 = quad_swap1(z.H[1]);
-        double L[2][2], inv[2];
+    auto finish = [&](const QuadAcc<T>& z, int m) {
+        const T ho0 = quad_swap1(z.H[0]), ho1 = quad_swap1(z.H[1]);
+        T L[2][2], inv[2];
         L[0][0] = jb == 0 ? z.H[0] : ho0;
         L[0][1] = jb == 1 ? z.H[0] : ho0;
         L[1][0] = jb == 0 ? z.H[1] : ho1;
         L[1][1] = jb == 1 ? z.H[1] : ho1;
-        const bool ok = chol_inplace_rsq<2>(L, inv);
+        bool ok;
+        if constexpr (std::is_same<T, double>::value)
+            ok = chol_inplace_rsq<2>(L, inv);
+        else
+            ok = chol_inplace<2, T>(L, inv);
         if (!ok && q == 0) atomicMin(a.bad, m);
-        double Kj[2] = {z.G[0], z.G[1]}, kv[2] = {z.g[0], z.g[1]};
+        T Kj[2] = {z.G[0], z.G[1]}, kv[2] = {z.g[0], z.g[1]};
         chol_solve<2>(L, inv, Kj);
         chol_solve<2>(L, inv, kv);
 #pragma unroll
@@ -336,14 +345,14 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
             kv[b] = -kv[b];
         }
         // G[a][i]: entry i of row a, held by lane i of the row
-        double Gi[2];
+        T Gi[2];
 #pragma unroll
         for (int b = 0; b < NU; ++b) {
-            const double g0 = row_lane<0>(z.G[b]), g1 = row_lane<1>(z.G[b]);
-            const double g2 = row_lane<2>(z.G[b]), g3 = row_lane<3>(z.G[b]);
+            const T g0 = row_lane<0>(z.G[b]), g1 = row_lane<1>(z.G[b]);
+            const T g2 = row_lane<2>(z.G[b]), g3 = row_lane<3>(z.G[b]);
             Gi[b] = i == 0 ? g0 : (i == 1 ? g1 : (i == 2 ? g2 : g3));
         }
-        double X = z.W, pn = z.w;
+        T X = z.W, pn = z.w;
 #pragma unroll
         for (int b = 0; b < NU; ++b) {
             X = fma(Gi[b], Kj[b], X);
@@ -358,8 +367,8 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
         if (q < NU) a.k[lidx<LAY>(m, q, NU, N)] = q == 0 ? kv[0] : kv[1];
     };
     auto store_value_q = [&](int m, bool shared) {
-        double* pP = &a.P[lidx<LAY>(m, i * NX + j, NX * NX, N)];
-        double* pp = &a.p[lidx<LAY>(m, i, NX, N)];
+        T* pP = &a.P[lidx<LAY>(m, i * NX + j, NX * NX, N)];
+        T* pp = &a.p[lidx<LAY>(m, i, NX, N)];
         if (shared) {
             st_shared_dev(pP, Pv);
             if (j == 0) st_shared_dev(pp, pv);
@@ -374,8 +383,8 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
     int from = -1;
     bool pref = false;  // stage / edge hold the inputs of n (its single child is from)
     bool pre2 = false;  // mst / me0 / me1 hold the inputs of n (two children, one is from)
-    QuadStage stage, mst;
-    QuadEdge edge, me0, me1;
+    QuadStage<T> stage, mst;
+    QuadEdge<T> edge, me0, me1;
     for (;;) {
         const int c0 = inf.x, c1 = inf.y, par = inf.z, nsib = inf.w;
         // the next node's topology record, in flight while this node is computed
@@ -383,17 +392,17 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
         if (c0 == c1) {
             Pv = a.Q[lidx<LAY>(n, i * NX + j, NX * NX, N)];
             pv = a.q[lidx<LAY>(n, i, NX, N)];
-            if (i < NU) a.K[lidx<LAY>(n, i * NX + j, NU * NX, N)] = 0.0;
-            if (q < NU) a.k[lidx<LAY>(n, q, NU, N)] = 0.0;
+            if (i < NU) a.K[lidx<LAY>(n, i * NX + j, NU * NX, N)] = T(0);
+            if (q < NU) a.k[lidx<LAY>(n, q, NU, N)] = T(0);
             if (nsib == 1) {
                 load_stage_q(par, stage);
                 load_edge_q(n, edge);
             }
         } else {
-            QuadAcc z;
+            QuadAcc<T> z;
             if (pref) {
                 acc_init(stage, z);
-                const QuadEdge e0 = edge;
+                const QuadEdge<T> e0 = edge;
                 // inputs of the parent are independent of this step: start them now
                 if (nsib == 1) {
                     load_stage_q(par, stage);
@@ -406,7 +415,7 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
                 // group's own is in registers; sums in child order
                 acc_init(mst, z);
                 const bool own0 = from == c0;
-                double P0 = Pv, p0 = pv, P1 = Pv, p1 = pv;
+                T P0 = Pv, p0 = pv, P1 = Pv, p1 = pv;
                 if (own0) {
                     P1 = ld_shared_dev(&a.P[lidx<LAY>(c0 + 1, i * NX + j, NX * NX, N)]);
                     p1 = ld_shared_dev(&a.p[lidx<LAY>(c0 + 1, i, NX, N)]);
@@ -421,13 +430,13 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgs a, int* arri
                 acc_add(me0, P0, p0, z);
                 acc_add(me1, P1, p1, z);
             } else {
-                QuadStage st;
+                QuadStage<T> st;
                 load_stage_q(n, st);
                 acc_init(st, z);
                 for (int ch = c0; ch < c1; ++ch) {
-                    QuadEdge e;
+                    QuadEdge<T> e;
                     load_edge_q(ch, e);
-                    double Pc = Pv, pc = pv;
+                    T Pc = Pv, pc = pv;
                     if (!(c1 - c0 == 1 && from == ch)) {
                         Pc = ld_shared_dev(&a.P[lidx<LAY>(ch, i * NX + j, NX * NX, N)]);
                         pc = ld_shared_dev(&a.p[lidx<LAY>(ch, i, NX, N)]);
@@ -1775,6 +1784,7 @@ struct LqrKernels {
     void (*bwd_wreg)(TreeDev, LqrArgs, int*);
     // nx = 4, nu = 2: 16 lanes per leaf chain
     void (*bwd_quad)(TreeDev, LqrArgs, int*);
+    void (*bwd_quad32)(TreeDev, LqrArgsT<float>, int*);
     // bytes of one segment-scan element (the kernel's LDS per chunk node)
     size_t seg_cvf_bytes;
 };
@@ -1787,7 +1797,10 @@ static LqrKernels make_k()
     LqrKernels k{NX, NU, LAY, G, nullptr, nullptr, nullptr, k_fwd_rows<NX, NU, LAY, G, 4>,
                  k_costate<NX, LAY>};
     if constexpr (NX == 12 && NU == 4) k.bwd_wreg = k_bwd_wreg<NX, NU, LAY>;
-    if constexpr (NX == 4 && NU == 2) k.bwd_quad = k_bwd_quad<LAY>;
+    if constexpr (NX == 4 && NU == 2) {
+        k.bwd_quad = k_bwd_quad<LAY>;
+        k.bwd_quad32 = k_bwd_quad<LAY, float>;
+    }
     if constexpr (LANE) {
         k.bwd_lane = k_bwd_lane<NX, NU, LAY>;
         k.bwd_lane32 = k_bwd_lane<NX, NU, LAY, float>;
@@ -1869,7 +1882,12 @@ void launch_f32(bmpc_lqr_plan* pl, const LqrArgsT<float>& a, hipStream_t s)
 {
     const TreeDev& t = pl->tree->d;
     const int Z = t.num_leaves;
-    {
+    if (pl->kern->bwd_quad32) {
+        ProfScope ps("lqr_backward_level_quad_f32", s);
+        const long threads = (long)Z * 16;
+        hipLaunchKernelGGL(pl->kern->bwd_quad32, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, t, a,
+                           pl->arrive);
+    } else {
         ProfScope ps("lqr_backward_level_lane_f32", s);
         hipLaunchKernelGGL(pl->kern->bwd_lane32, dim3((Z + 63) / 64), dim3(64), 0, s, t, a, pl->arrive);
     }
