@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(64) k_bwd_lane(TreeDev t, LqrArgsT<T> a, int* 
 // of the step's 4 x 4 products, entry (a, j) of G for both rows a, and
 // entry (a, j % 2) of H.  Row i of P comes from the lane's quad (quad_perm
 // broadcasts); the column of S = P [A B] and the vector s = P c + p that
-// the second products need come from the lanes 4, 8 and 12 further on in
+// the second products need come from the lanes at distance 4, 8 and 12 in
 // the row (row rotations), so every lane reads only the entries of A, B it
 // multiplies.  H, g and the gains are small and formed by every lane.
 
@@ -220,7 +220,7 @@ __device__ __forceinline__ int row_rot_int(int v)
 template <class T>
 struct QuadEdge {
     T Acol[4], Bcol[4], c[4];  // A[k][j], B[k][j % 2], c[k]
-    T Arot[4], Brot[2][4];     // A[r_d][i], B[r_d][a]: r_d the row held by the lane 4 d further on
+    T Arot[4], Brot[2][4];     // A[r_d][i], B[r_d][a]: r_d the row held by the lane rotated in by 4 d
 };
 template <class T>
 struct QuadStage {
@@ -240,8 +240,8 @@ __global__ void __launch_bounds__(64) k_bwd_quad(TreeDev t, LqrArgsT<T> a, int* 
     if (chain >= t.num_leaves) return;  // the whole group leaves together
     const int q = tid & 15, i = q >> 2, j = q & 3, jb = j & 1;
     const int N = t.N;
-    // row of the matrices held by the lane 4 d further on in the row (d = 0
-    // is this lane), found with the same rotation that moves the values
+    // row of the matrices held by the lane that a rotation by 4 d brings in
+    // (d = 0: this lane), found with the same rotation that moves the values
     int rrow[4];
     rrow[0] = i;
     rrow[1] = row_rot_int<12>(i);
