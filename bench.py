@@ -323,6 +323,29 @@ def run_lqr(args, torch, L):
                                     "backward_bytes_GBps": round(alg["bwd_bytes"] * args.steps / el / 1e9, 2)}
     if conc:
         out["concurrent_independent_solves"] = conc
+
+    # The same solves from host arrays (bmpc_lqr_solve_host: pinned staging,
+    # one transfer each way, blocking): the PCIe-inclusive rate, reported
+    # beside `value`, which has its inputs resident in HBM.
+    if not args.no_concurrent:
+        hplan = L.bmpc_lqr_plan_create(tree, nx, nu, layout)
+        host = [[d[k].cpu().numpy() for k in "ABcQRMqr"] + [d["x0"].cpu().numpy()] for d in dev]
+        for i in range(max(1, args.warmup)):
+            L.bmpc_lqr_solve_host(hplan, *host[i % n_inst], variant=L.RICCATI_LEVEL)
+        n_host = max(5, args.steps // 2)
+        t0 = time.perf_counter()
+        for i in range(n_host):
+            L.bmpc_lqr_solve_host(hplan, *host[i % n_inst], variant=L.RICCATI_LEVEL)
+        el = time.perf_counter() - t0
+        st, bad = L.bmpc_lqr_check(hplan)
+        if st != 0:
+            raise RuntimeError(f"host-array LQR solve failed (status {st}, node {bad})")
+        L.bmpc_lqr_plan_destroy(hplan)
+        in_bytes = 8 * sum(a.size for a in host[0])
+        out["host_arrays_pcie_inclusive"] = {
+            "solves": n_host, "ms_per_solve": round(el / n_host * 1e3, 4),
+            "nodes_per_s": round(N * n_host / el, 1),
+            "bytes_in": in_bytes, "bytes_out": 8 * N * (2 * nx + nu)}
     L.bmpc_tree_destroy(tree)
     return out, insts[0]
 

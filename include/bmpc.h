@@ -25,7 +25,8 @@
  *  parent[0] = -1, 0 <= parent[i] < i, and parent[] non-decreasing for i >= 1.
  *  This is the stage-major breadth-first order: the nodes of one stage are
  *  contiguous and the children of one node are contiguous.  Other orders are
- *  rejected with BMPC_ERR_TOPOLOGY.  The stage of a node is its depth; a
+ *  rejected with BMPC_ERR_TOPOLOGY (a tree in another order goes through
+ *  bmpc_tree_create_any and bmpc_tree_permute).  The stage of a node is its depth; a
  *  leaf is a node with no children; "control nodes" are all other nodes.
  *  Dynamics are stored on the edge, i.e. at the child: (A_j, B_j, c_j) at
  *  node j describe x_j = A_j x_{p(j)} + B_j u_{p(j)} + c_j.  Entries of the
@@ -113,6 +114,40 @@ BMPC_API bmpc_status bmpc_tree_segments(const bmpc_tree* tree, int32_t* seg_of_n
 BMPC_API bmpc_status bmpc_weights_from_probs(const bmpc_tree* tree, const double* leaf_prob,
                                              double* node_weight);
 
+/* Trees in the caller's own node order (the index sets of Sec. II-B fix
+   none).  parent: host, num_nodes entries; exactly one node has parent -1
+   (the root), every other node's parent is another node's index, and every
+   node descends from the root (else BMPC_ERR_TOPOLOGY, e.g. for a parent
+   cycle).  The library's order is the breadth-first order from the root
+   with each node's children in increasing caller index.
+   bmpc_tree_order writes order[k] = caller index of library node k (host
+   output, num_nodes entries) and, if lib_parent is not NULL, the parent
+   array in the library's order (host output, num_nodes entries; it
+   satisfies the rules above and can be given to bmpc_tree_create).  On
+   error the outputs are unspecified.  Host only. */
+BMPC_API bmpc_status bmpc_tree_order(const int32_t* parent, int32_t num_nodes, int32_t* order,
+                                     int32_t* lib_parent);
+/* bmpc_tree_create for a parent array in any order (rules of
+   bmpc_tree_order).  The tree keeps the permutation for bmpc_tree_permute;
+   order (host output, nullable) receives it as in bmpc_tree_order.  Node k
+   of every other call on this tree is library node k. */
+BMPC_API bmpc_status bmpc_tree_create_any(const int32_t* parent, int32_t num_nodes, int32_t* order,
+                                          bmpc_tree** out);
+enum { BMPC_TO_LIBRARY_ORDER = 0, BMPC_TO_CALLER_ORDER = 1 };
+/* Moves per-node data between the caller's node order and the library's:
+   BMPC_TO_LIBRARY_ORDER gathers dst[library node k] = src[caller node
+   order[k]], BMPC_TO_CALLER_ORDER scatters the other way.  src, dst: device,
+   num_nodes x width doubles each in the given layout (BMPC_LAYOUT_*; width =
+   rows * cols of one node's entry), caller-owned, distinct and not
+   overlapping.  For a tree from bmpc_tree_create the orders agree and the
+   call is a device copy.  The first call on a reordered tree allocates
+   num_nodes int32 on the current device for the permutation (owned by the
+   tree); later calls allocate nothing.  Asynchronous on stream.
+   BMPC_ERR_INVALID_ARG for NULL pointers, src == dst, width <= 0 or an
+   unknown direction or layout. */
+BMPC_API bmpc_status bmpc_tree_permute(bmpc_tree* tree, int32_t direction, int32_t layout,
+                                       int32_t width, const double* src, double* dst, void* stream);
+
 /* ------------------------------------------------------------------------
  * Tree LQR (Sec. III, eq. lqr_tree_approx; recursion of eq. tree_Riccati with
  * the gains of eq. tree_feedback_laws; forward rollout of eq.
@@ -151,6 +186,23 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* plan, const double* A, const 
                                     const double* x0, double* x, double* u, double* lam,
                                     double* K, double* k, double* P, double* p, int32_t variant,
                                     void* stream);
+/* bmpc_lqr_solve for HOST arrays (Sec. III, eq. lqr_tree_approx): A ... r,
+   x0 inputs and x, u, lam outputs are caller-owned host pointers with the
+   sizes and the plan's layout of bmpc_lqr_solve; no gains or value
+   functions are returned.  The call packs the inputs into a pinned host
+   block, copies it to the device in one transfer, runs the same kernels on
+   `stream`, copies x, u, lam back in one transfer and synchronises the
+   stream before it returns (blocking).  The first call on a plan allocates
+   the pinned and device staging blocks (N (2 nx^2 + 2 nx nu + nu^2 + 4 nx +
+   2 nu) + nx doubles each, owned by the plan); later calls allocate
+   nothing.  Errors as bmpc_lqr_solve, BMPC_ERR_OOM if a staging block
+   cannot be allocated; positive definiteness is reported by
+   bmpc_lqr_check. */
+BMPC_API bmpc_status bmpc_lqr_solve_host(bmpc_lqr_plan* plan, const double* A, const double* B,
+                                         const double* c, const double* Q, const double* R,
+                                         const double* M, const double* q, const double* r,
+                                         const double* x0, double* x, double* u, double* lam,
+                                         int32_t variant, void* stream);
 /* The same solve in FP32 (the single-precision variant of the recursion,
    Sec. V-A): float arrays of the sizes and layout above.  Compiled for the
    dimensions whose FP64 solve uses one lane per node (nx <= 6); others

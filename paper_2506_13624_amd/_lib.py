@@ -58,10 +58,14 @@ _sig("bmpc_tree_destroy", None, [_vp])
 _sig("bmpc_tree_info", _i32, [_vp, _pi32, _pi32, _pi32, _pi32])
 _sig("bmpc_tree_segments", _i32, [_vp, _pi32])
 _sig("bmpc_weights_from_probs", _i32, [_vp, _pd, _pd])
+_sig("bmpc_tree_order", _i32, [_pi32, _i32, _pi32, _pi32])
+_sig("bmpc_tree_create_any", _i32, [_pi32, _i32, _pi32, C.POINTER(_vp)])
+_sig("bmpc_tree_permute", _i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp])
 _sig("bmpc_lqr_plan_create", _i32, [_vp, _i32, _i32, _i32, C.POINTER(_vp)])
 _sig("bmpc_lqr_plan_destroy", None, [_vp])
 _sig("bmpc_lqr_supported", _i32, [_i32, _i32, _i32])
 _sig("bmpc_lqr_solve", _i32, [_vp] + [_vp] * 16 + [_i32, _vp])
+_sig("bmpc_lqr_solve_host", _i32, [_vp] + [_pd] * 12 + [_i32, _vp])
 _sig("bmpc_lqr_solve_f32", _i32, [_vp] + [_vp] * 16 + [_vp])
 _sig("bmpc_lqr_solve_mixed", _i32, [_vp] + [_vp] * 12 + [_i32, _vp, _vp])
 _sig("bmpc_lqr_check", _i32, [_vp, _pi32, _vp])
@@ -187,6 +191,35 @@ def bmpc_weights_from_probs(h, leaf_prob, num_nodes):
     return out
 
 
+TO_LIBRARY_ORDER = 0
+TO_CALLER_ORDER = 1
+
+
+def bmpc_tree_order(parent):
+    """(order, lib_parent): order[k] = caller index of library node k."""
+    parent, pp = _hi32(parent)
+    order = np.zeros(len(parent), dtype=np.int32)
+    lib_parent = np.zeros(len(parent), dtype=np.int32)
+    check(lib.bmpc_tree_order(pp, len(parent), order.ctypes.data_as(_pi32),
+                              lib_parent.ctypes.data_as(_pi32)))
+    return order, lib_parent
+
+
+def bmpc_tree_create_any(parent):
+    """(tree handle, order) for a parent array in any node order."""
+    parent, pp = _hi32(parent)
+    order = np.zeros(len(parent), dtype=np.int32)
+    h = _vp()
+    check(lib.bmpc_tree_create_any(pp, len(parent), order.ctypes.data_as(_pi32), C.byref(h)))
+    return h, order
+
+
+def bmpc_tree_permute(tree, direction, layout, width, src, dst, stream=None):
+    n = bmpc_tree_info(tree)["num_nodes"] * width
+    ps, pd = _dptrs([(src, "float64", n, "src"), (dst, "float64", n, "dst")])
+    check(lib.bmpc_tree_permute(tree, direction, layout, width, ps, pd, stream_ptr(stream)))
+
+
 def bmpc_lqr_supported(nx, nu, variant=RICCATI_AUTO):
     return bool(lib.bmpc_lqr_supported(nx, nu, variant))
 
@@ -212,6 +245,23 @@ def bmpc_lqr_solve(plan, A, B, c, Q, R, M, q, r, x0, x, u, lam, K=None, k=None, 
     args = _dptrs([(v, "float64", cnt, nm) for v, (nm, cnt) in zip((A, B, c, Q, R, M, q, r, x0, x, u, lam, K, k,
                                                                      P, p), sizes)])
     check(lib.bmpc_lqr_solve(plan, *args, variant, stream_ptr(stream)))
+
+
+def bmpc_lqr_solve_host(plan, A, B, c, Q, R, M, q, r, x0, variant=RICCATI_AUTO, stream=None):
+    """Host NumPy inputs in the plan's layout (flattened); returns host
+    (x, u, lam) as flat float64 arrays in that layout."""
+    N, n, m = _dims[_key(plan)]
+    sizes = _lqr_sizes(plan)
+    ins = []
+    for v, (nm, cnt) in zip((A, B, c, Q, R, M, q, r, x0), sizes):
+        a = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
+        if a.size != cnt:
+            raise ValueError(f"{nm}: {a.size} elements, {cnt} expected")
+        ins.append(a)
+    outs = [np.zeros(N * n), np.zeros(N * m), np.zeros(N * n)]
+    check(lib.bmpc_lqr_solve_host(plan, *[a.ctypes.data_as(_pd) for a in ins + outs], variant,
+                                  stream_ptr(stream)))
+    return tuple(outs)
 
 
 def _lqr_sizes(plan):

@@ -80,6 +80,11 @@ struct bmpc_tree {
     std::vector<void*> allocations;
     int device = 0;
     bool on_device = false;
+    // trees made from a caller's own node order: order[k] = the caller's
+    // index of library node k (empty = the caller's order is the library's);
+    // d_order is its device copy, uploaded by the first permute call
+    std::vector<int32_t> order;
+    const int32_t* d_order = nullptr;
 };
 
 namespace bmpc {

@@ -25,6 +25,8 @@
 // nodes in parallel.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include <algorithm>
 #include <climits>
 #include <initializer_list>
@@ -1859,6 +1861,10 @@ struct bmpc_lqr_plan {
     float *A32 = nullptr, *B32 = nullptr, *Q32 = nullptr, *R32 = nullptr, *M32 = nullptr;
     float *q32 = nullptr, *r32 = nullptr, *c32 = nullptr, *x032 = nullptr;
     float *x32 = nullptr, *u32 = nullptr, *l32 = nullptr;
+    // host-pointer solves: one pinned staging block and one device block of
+    // the same size (inputs, then x0, then outputs), allocated by the first
+    double* stage_host = nullptr;
+    double* stage_dev = nullptr;
 };
 
 namespace {
@@ -1969,6 +1975,8 @@ BMPC_API void bmpc_lqr_plan_destroy(bmpc_lqr_plan* pl)
     for (float* f : {pl->K32, pl->k32, pl->P32, pl->p32, pl->A32, pl->B32, pl->Q32, pl->R32, pl->M32, pl->q32,
                      pl->r32, pl->c32, pl->x032, pl->x32, pl->u32, pl->l32})
         (void)hipFree(f);
+    (void)hipHostFree(pl->stage_host);
+    (void)hipFree(pl->stage_dev);
     delete pl;
 }
 
@@ -2025,6 +2033,74 @@ BMPC_API bmpc_status bmpc_lqr_solve(bmpc_lqr_plan* pl, const double* A, const do
                            t, a, pl->arrive);
     }
     BMPC_HIP_TRY(hipGetLastError());
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_lqr_solve_host(bmpc_lqr_plan* pl, const double* A, const double* B,
+                                         const double* c, const double* Q, const double* R,
+                                         const double* M, const double* q, const double* r,
+                                         const double* x0, double* x, double* u, double* lam,
+                                         int32_t variant, void* stream)
+{
+    if (!pl) return fail(BMPC_ERR_INVALID_ARG, "plan is NULL");
+    if (!A || !B || !c || !Q || !R || !M || !q || !r || !x0 || !x || !u || !lam)
+        return fail(BMPC_ERR_INVALID_ARG, "NULL input or output array");
+    const size_t N = pl->tree->h.N, n = pl->nx, m = pl->nu;
+    // input arrays and their sizes in doubles, in staging order
+    const double* in[8] = {A, B, c, Q, R, M, q, r};
+    const size_t in_len[8] = {N * n * n, N * n * m, N * n, N * n * n, N * m * m, N * m * n, N * n, N * m};
+    size_t in_total = 0;
+    for (size_t len : in_len) in_total += len;
+    const size_t out_len[3] = {N * n, N * m, N * n};
+    const size_t total = in_total + n + out_len[0] + out_len[1] + out_len[2];
+    if (!pl->stage_host) {
+        if (hipHostMalloc((void**)&pl->stage_host, sizeof(double) * total, hipHostMallocDefault) != hipSuccess) {
+            pl->stage_host = nullptr;
+            return fail(BMPC_ERR_OOM, "pinned staging block of %zu bytes failed", sizeof(double) * total);
+        }
+        if (hipMalloc((void**)&pl->stage_dev, sizeof(double) * total) != hipSuccess) {
+            (void)hipHostFree(pl->stage_host);
+            pl->stage_host = nullptr;
+            pl->stage_dev = nullptr;
+            return fail(BMPC_ERR_OOM, "device staging block of %zu bytes failed", sizeof(double) * total);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // the previous call on this plan has finished with the pinned block:
+    // every call ends with a stream synchronisation
+    double* h = pl->stage_host;
+    const double* d_in[8];
+    size_t off = 0;
+    for (int i = 0; i < 8; ++i) {
+        std::memcpy(h + off, in[i], sizeof(double) * in_len[i]);
+        d_in[i] = pl->stage_dev + off;
+        off += in_len[i];
+    }
+    std::memcpy(h + off, x0, sizeof(double) * n);
+    const double* d_x0 = pl->stage_dev + off;
+    off += n;
+    const size_t out_off = off;
+    double* d_out[3];
+    for (int i = 0; i < 3; ++i) {
+        d_out[i] = pl->stage_dev + off;
+        off += out_len[i];
+    }
+    BMPC_HIP_TRY(hipMemcpyAsync(pl->stage_dev, h, sizeof(double) * out_off, hipMemcpyHostToDevice, s));
+    bmpc_status st = bmpc_lqr_solve(pl, d_in[0], d_in[1], d_in[2], d_in[3], d_in[4], d_in[5], d_in[6], d_in[7], d_x0,
+                                    d_out[0], d_out[1], d_out[2], nullptr, nullptr, nullptr, nullptr, variant, s);
+    if (st != BMPC_OK) {
+        (void)hipStreamSynchronize(s);
+        return st;
+    }
+    BMPC_HIP_TRY(hipMemcpyAsync(h + out_off, pl->stage_dev + out_off, sizeof(double) * (total - out_off),
+                                hipMemcpyDeviceToHost, s));
+    BMPC_HIP_TRY(hipStreamSynchronize(s));
+    double* out[3] = {x, u, lam};
+    off = out_off;
+    for (int i = 0; i < 3; ++i) {
+        std::memcpy(out[i], h + off, sizeof(double) * out_len[i]);
+        off += out_len[i];
+    }
     return BMPC_OK;
 }
 

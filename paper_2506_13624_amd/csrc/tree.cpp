@@ -162,6 +162,57 @@ bmpc_status tree_on_device(bmpc_tree* t)
     return BMPC_OK;
 }
 
+// Breadth-first relabelling of a tree given in any node order: one root
+// (parent -1), every other node with one parent in [0, N).  Children keep
+// the order of their caller indices, so the result is the library's
+// stage-major order with contiguous children.  Every node is some node's
+// child exactly once, so a node that the walk from the root does not reach
+// lies on a parent cycle.
+static bmpc_status breadth_first_order(const int32_t* parent, int N, std::vector<int32_t>& order,
+                                       std::vector<int32_t>& lib_parent)
+{
+    if (N <= 0) return fail(BMPC_ERR_INVALID_ARG, "num_nodes must be positive (got %d)", N);
+    if (!parent) return fail(BMPC_ERR_INVALID_ARG, "parent is NULL");
+    int root = -1;
+    std::vector<int32_t> off(N + 1, 0);
+    for (int i = 0; i < N; ++i) {
+        const int p = parent[i];
+        if (p == -1) {
+            if (root >= 0)
+                return fail(BMPC_ERR_TOPOLOGY, "nodes %d and %d both have parent -1", root, i);
+            root = i;
+        } else if (p < 0 || p >= N || p == i) {
+            return fail(BMPC_ERR_TOPOLOGY, "node %d: parent %d is not a node index other than %d",
+                        i, p, i);
+        } else {
+            off[p + 1]++;
+        }
+    }
+    if (root < 0) return fail(BMPC_ERR_TOPOLOGY, "no node has parent -1");
+    for (int i = 0; i < N; ++i) off[i + 1] += off[i];
+    std::vector<int32_t> kids(N > 1 ? N - 1 : 1), fill(off.begin(), off.end() - 1);
+    for (int i = 0; i < N; ++i)
+        if (parent[i] >= 0) kids[fill[parent[i]]++] = i;
+    order.assign(N, -1);
+    std::vector<int32_t> lib_id(N, -1);
+    order[0] = root;
+    lib_id[root] = 0;
+    int tail = 1;
+    for (int head = 0; head < tail; ++head) {
+        const int n = order[head];
+        for (int c = off[n]; c < off[n + 1]; ++c) {
+            lib_id[kids[c]] = tail;
+            order[tail++] = kids[c];
+        }
+    }
+    if (tail != N)
+        return fail(BMPC_ERR_TOPOLOGY,
+                    "only %d of %d nodes descend from the root: the parents form a cycle", tail, N);
+    lib_parent.assign(N, -1);
+    for (int k = 1; k < N; ++k) lib_parent[k] = lib_id[parent[order[k]]];
+    return BMPC_OK;
+}
+
 }  // namespace bmpc
 
 using namespace bmpc;
@@ -189,6 +240,40 @@ BMPC_API bmpc_status bmpc_tree_create(const int32_t* parent, int32_t num_nodes, 
         delete t;
         return st;
     }
+    *out = t;
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_tree_order(const int32_t* parent, int32_t num_nodes, int32_t* order,
+                                     int32_t* lib_parent)
+{
+    if (!order) return fail(BMPC_ERR_INVALID_ARG, "order is NULL");
+    std::vector<int32_t> ord, lp;
+    bmpc_status st = breadth_first_order(parent, num_nodes, ord, lp);
+    if (st != BMPC_OK) return st;
+    std::memcpy(order, ord.data(), sizeof(int32_t) * num_nodes);
+    if (lib_parent) std::memcpy(lib_parent, lp.data(), sizeof(int32_t) * num_nodes);
+    return BMPC_OK;
+}
+
+BMPC_API bmpc_status bmpc_tree_create_any(const int32_t* parent, int32_t num_nodes, int32_t* order,
+                                          bmpc_tree** out)
+{
+    if (!out) return fail(BMPC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    std::vector<int32_t> ord, lp;
+    bmpc_status st = breadth_first_order(parent, num_nodes, ord, lp);
+    if (st != BMPC_OK) return st;
+    auto* t = new bmpc_tree();
+    st = analyse(lp.data(), num_nodes, t->h);
+    if (st != BMPC_OK) {
+        delete t;
+        return st;
+    }
+    bool identity = true;
+    for (int k = 0; k < num_nodes; ++k) identity = identity && ord[k] == k;
+    if (!identity) t->order = ord;
+    if (order) std::memcpy(order, ord.data(), sizeof(int32_t) * num_nodes);
     *out = t;
     return BMPC_OK;
 }

@@ -125,3 +125,75 @@ def test_binding_rejects_mistyped_or_short_arrays_before_the_call(L):
                                torch.zeros(5, dtype=torch.float32))
     finally:
         L._dims.pop(L._key(fake), None)
+
+
+def _shuffled(parent, seed):
+    """The same tree with node i renamed sigma[i] (root anywhere)."""
+    rng = np.random.default_rng(seed)
+    sigma = rng.permutation(len(parent)).astype(np.int32)
+    cpar = np.full(len(parent), -1, dtype=np.int32)
+    for i, p in enumerate(parent):
+        cpar[sigma[i]] = -1 if p < 0 else sigma[p]
+    return cpar, sigma
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tree_order_of_a_shuffled_tree(L, seed):
+    """Library order of a tree in any node order: a permutation that keeps
+    every parent link, gives a parent array the library accepts, and lists
+    each node's children in increasing caller index (which fixes it)."""
+    base = [S.tree_parent(9, [1, 3, 6], 3), S.tree_parent(12, [0, 4, 8], 2),
+            np.array([-1, 0, 1, 1, 2, 3, 4, 5, 5, 6, 7, 8], dtype=np.int32)][seed % 3]
+    cpar, _ = _shuffled(base, seed)
+    order, lpar = L.bmpc_tree_order(cpar)
+    N = len(cpar)
+    assert sorted(order.tolist()) == list(range(N))
+    assert cpar[order[0]] == -1
+    inv = np.empty(N, dtype=np.int64)
+    inv[order] = np.arange(N)
+    for k in range(1, N):
+        assert lpar[k] == inv[cpar[order[k]]]
+    for k in range(2, N):
+        if lpar[k] == lpar[k - 1]:
+            assert order[k] > order[k - 1]
+    t = L.bmpc_tree_create(lpar)
+    t2, order2 = L.bmpc_tree_create_any(cpar)
+    try:
+        assert L.bmpc_tree_info(t) == L.bmpc_tree_info(t2)
+        np.testing.assert_array_equal(order, order2)
+    finally:
+        L.bmpc_tree_destroy(t)
+        L.bmpc_tree_destroy(t2)
+
+
+def test_tree_order_is_identity_on_library_order(L):
+    par = S.tree_parent(12, [0, 4, 8], 2)
+    order, lpar = L.bmpc_tree_order(par)
+    np.testing.assert_array_equal(order, np.arange(len(par)))
+    np.testing.assert_array_equal(lpar, par)
+
+
+@pytest.mark.parametrize("parent", [[-1, -1], [1, 0], [-1, 2, 1], [-1, 5], [-1, 1], [0]])
+def test_tree_order_rejects_non_trees(L, parent):
+    with pytest.raises(L.BmpcError) as e:
+        L.bmpc_tree_order(parent)
+    assert e.value.status == 2
+    with pytest.raises(L.BmpcError):
+        L.bmpc_tree_create_any(parent)
+
+
+def test_host_lqr_binding_rejects_short_arrays_before_the_call(L):
+    t = L.bmpc_tree_create(S.tree_parent(3, [0], 2))
+    try:
+        plan_dims = (7, 4, 2)
+        fake = ctypes.c_void_p(12345)
+        L._dims[L._key(fake)] = plan_dims
+        N, n, m = plan_dims
+        arrs = [np.zeros(N * n * n), np.zeros(N * n * m), np.zeros(N * n), np.zeros(N * n * n),
+                np.zeros(N * m * m), np.zeros(N * m * n), np.zeros(N * n), np.zeros(N * m - 1),
+                np.zeros(n)]
+        with pytest.raises(ValueError, match="r:"):
+            L.bmpc_lqr_solve_host(fake, *arrs)
+    finally:
+        L._dims.pop(12345, None)
+        L.bmpc_tree_destroy(t)

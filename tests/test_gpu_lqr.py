@@ -393,3 +393,93 @@ def test_nx30_not_positive_definite_reports_node():
     inst.B[8] = 0.0
     g, st, bad = gpu_lqr(inst, L.LAYOUT_NODE_MAJOR)
     assert st == 3 and bad == 5
+
+
+@pytest.mark.parametrize("layout", [L.LAYOUT_NODE_MAJOR, L.LAYOUT_ELEM_MAJOR])
+@pytest.mark.parametrize("name,dims", [("random_a", (4, 2)), ("ternary", (6, 3)),
+                                       ("microbench", (12, 4))])
+def test_lqr_in_caller_node_order(name, dims, layout):
+    """A tree and its data in a shuffled node order: bmpc_tree_create_any,
+    the data gathered into the library's order (bit-exact), solved, and the
+    solution scattered back; it equals the oracle's on the original order."""
+    par = S.lqr_microbench(0).parent if name == "microbench" else TREES[name]
+    N = len(par)
+    nx, nu = dims
+    print(f"caller order tree={name} N={N} dims={dims} layout={layout}", flush=True)
+    inst = S.lqr_on(par, nx, nu, seed=23, random_cost=True)
+    o = oracle.tree_lqr_inst(inst)
+    rng = np.random.default_rng(5)
+    sigma = rng.permutation(N)
+    cpar = np.full(N, -1, dtype=np.int32)
+    for i, p in enumerate(par):
+        cpar[sigma[i]] = -1 if p < 0 else sigma[p]
+
+    def caller(a):
+        out = np.empty_like(a)
+        out[sigma] = a
+        return out
+
+    tree, order = L.bmpc_tree_create_any(cpar)
+    plan = L.bmpc_lqr_plan_create(tree, nx, nu, layout)
+    try:
+        lib = {}
+        for k in "ABcQRMqr":
+            a = caller(getattr(inst, k))
+            w = int(np.prod(a.shape[1:]))
+            lib[k] = empty(a.shape)
+            L.bmpc_tree_permute(tree, L.TO_LIBRARY_ORDER, layout, w, to_device(a, layout), lib[k])
+            np.testing.assert_array_equal(from_device(lib[k], a.shape, layout), a[order])
+        x0 = to_device(inst.x0, layout)
+        lo = {"x": (N, nx), "u": (N, nu), "lam": (N, nx)}
+        out = {k: empty(s) for k, s in lo.items()}
+        L.bmpc_lqr_solve(plan, lib["A"], lib["B"], lib["c"], lib["Q"], lib["R"], lib["M"],
+                         lib["q"], lib["r"], x0, out["x"], out["u"], out["lam"])
+        st, bad = L.bmpc_lqr_check(plan)
+        assert st == 0, bad
+        for k, s in lo.items():
+            back = empty(s)
+            w = int(np.prod(s[1:]))
+            L.bmpc_tree_permute(tree, L.TO_CALLER_ORDER, layout, w, out[k], back)
+            g = from_device(back, s, layout)
+            ref = caller(o[k])
+            if k == "u":  # leaves carry no control
+                leaf = np.ones(N, dtype=bool)
+                leaf[cpar[cpar >= 0]] = False
+                g, ref = g[~leaf], ref[~leaf]
+            e = relerr(g, ref)
+            assert e <= TOL, f"{k}: relative error {e:.3e}"
+    finally:
+        L.bmpc_lqr_plan_destroy(plan)
+        L.bmpc_tree_destroy(tree)
+
+
+@pytest.mark.parametrize("layout", [L.LAYOUT_NODE_MAJOR, L.LAYOUT_ELEM_MAJOR])
+@pytest.mark.parametrize("name,dims", [("random_b", (4, 2)), ("microbench", (12, 4))])
+def test_lqr_host_arrays_equal_device_solve(name, dims, layout):
+    """bmpc_lqr_solve_host stages host arrays through pinned memory and runs
+    the same kernels: its x, u, lam equal the device-array solve bit for bit
+    and the oracle to 1e-9, on two calls in a row (staging blocks reused)."""
+    par = S.lqr_microbench(0).parent if name == "microbench" else TREES[name]
+    N = len(par)
+    nx, nu = dims
+    print(f"host staging tree={name} N={N} dims={dims} layout={layout}", flush=True)
+    tree = L.bmpc_tree_create(par)
+    plan = L.bmpc_lqr_plan_create(tree, nx, nu, layout)
+    try:
+        for seed in (29, 31):
+            inst = S.lqr_on(par, nx, nu, seed=seed, random_cost=True)
+            o = oracle.tree_lqr_inst(inst)
+            g, st, _ = gpu_lqr(inst, layout, want_gains=False)
+            assert st == 0
+            host = [to_device(getattr(inst, k), layout).cpu().numpy() for k in "ABcQRMqr"]
+            hx, hu, hl = L.bmpc_lqr_solve_host(plan, *host, inst.x0)
+            st, bad = L.bmpc_lqr_check(plan)
+            assert st == 0, bad
+            for k, flat, s in (("x", hx, (N, nx)), ("u", hu, (N, nu)), ("lam", hl, (N, nx))):
+                a = from_device(torch.from_numpy(flat), s, layout)
+                np.testing.assert_array_equal(a, g[k])
+                e = relerr(a, o[k])
+                assert e <= TOL, f"{k}: relative error {e:.3e}"
+    finally:
+        L.bmpc_lqr_plan_destroy(plan)
+        L.bmpc_tree_destroy(tree)
