@@ -494,6 +494,26 @@ def run_bmpc(args, torch, L):
     torch.cuda.synchronize()
     ms_tuned = ev0.elapsed_time(ev1)
     s_tuned = L.bmpc_batch_stats(b, len(insts))
+    # the same tuned cold launch captured once into a HIP graph and replayed
+    # (a cold start reads only the problem data, so every replay repeats the
+    # eager launch's solves: same statuses and iteration counts)
+    gs = torch.cuda.Stream()
+    L.bmpc_graph_begin(gs)
+    L.bmpc_batch_launch(b, st, warm=0, stream=gs)
+    cold_graph = L.bmpc_graph_end(gs)
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    cold_graph_ms, cold_graph_same = [], []
+    for _ in range(3):
+        g0.record(gs)
+        L.bmpc_graph_launch(cold_graph, gs)
+        g1.record(gs)
+        ss = L.bmpc_batch_stats(b, len(insts), stream=gs)
+        cold_graph_ms.append(g0.elapsed_time(g1))
+        cold_graph_same.append(all(x["status"] == y["status"] and x["inner_it"] == y["inner_it"]
+                                   for x, y in zip(ss, s_tuned)))
+    L.bmpc_graph_destroy(cold_graph)
+    s_cold_graph = ss
     # the same with a cap of 200 inner iterations per problem
     st_cap = L.bmpc_settings_default(max_iter_total=200)
     ev0.record()
@@ -528,14 +548,11 @@ def run_bmpc(args, torch, L):
     # closed loop: [shift, warm solve] captured once in a HIP graph, replayed
     L.bmpc_batch_launch(b, st, warm=7)  # solution of the shifted problems
     torch.cuda.synchronize()
-    gs = torch.cuda.Stream()
     L.bmpc_graph_begin(gs)
     L.bmpc_batch_shift(b, stream=gs)
     L.bmpc_batch_launch(b, st, warm=7, stream=gs)
     graph = L.bmpc_graph_end(gs)
     loop_ms, loop_conv = [], []
-    g0 = torch.cuda.Event(enable_timing=True)
-    g1 = torch.cuda.Event(enable_timing=True)
     for _ in range(5):
         g0.record(gs)
         L.bmpc_graph_launch(graph, gs)
@@ -579,6 +596,11 @@ def run_bmpc(args, torch, L):
                        # the launch ends with its longest-running problem
                        "most_iterations": slowest(s_tuned, insts),
                        "not_converged_by_status": not_converged(s_tuned)},
+        "cold_tuned_graph_replay": {"captured": "tuned cold launch", "replays": len(cold_graph_ms),
+                                    "ms_per_replay": [round(v, 3) for v in cold_graph_ms],
+                                    "converged": conv(s_cold_graph),
+                                    "solves_per_s": round(conv(s_cold_graph) / (min(cold_graph_ms) / 1e3), 1),
+                                    "same_statuses_and_iterations_as_eager": all(cold_graph_same)},
         "cold_tuned_cap_200_iterations": {"ms": round(ms_cap, 3), "converged": conv(s_cap),
                                           "mean_inner_it": mean_it(s_cap),
                                           "solves_per_s": round(conv(s_cap) / (ms_cap / 1e3), 1)},
