@@ -161,6 +161,13 @@ def cpu_baseline_lqr(inst, budget_s=10.0):
                       f"8,185-node tree in {el:.1f} s, one solve per thread on {cores} host cores"}
 
 
+def _stages(parent):
+    st = np.zeros(len(parent), dtype=np.int64)
+    for i in range(1, len(parent)):
+        st[i] = st[parent[i]] + 1
+    return st
+
+
 def run_lqr(args, torch, L):
     from paper_2506_13624_amd.layout import empty, to_device
     import bmpc_synth as S
@@ -268,6 +275,53 @@ def run_lqr(args, torch, L):
                 "fp64_frac": round(alg["bwd_flops"] / bwd_avg_s / 1e12 / FP64_PEAK_TFLOPS, 5)}
     kernels = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]} for k, v in prof_all.items()}
     ms_step = elapsed_ms / args.steps
+
+    # Dependency floor: the same backward kernel on the tree's critical path
+    # alone, one root-to-leaf path of the same depth with a leaf stub on each
+    # of its branch nodes (so every merge on the path is still done), timed
+    # like the full tree.  Its time is what the depth costs with no width.
+    stages = _stages(par)
+    depth = int(stages.max())
+    branch_stages = sorted({int(v) for v in stages[np.bincount(par[1:], minlength=N) > 1]})
+    cat = list(range(-1, depth))  # main path: node k at stage k
+    for s_ in branch_stages:
+        cat.append(s_)  # leaf stub on the path's branch node
+    cat_order, cat_par = L.bmpc_tree_order(np.array(cat, dtype=np.int32))
+    cinst = S.lqr_on(cat_par, nx, nu, seed=77)
+    ctree = L.bmpc_tree_create(cat_par)
+    cplan = L.bmpc_lqr_plan_create(ctree, nx, nu, layout)
+    Nc = len(cat_par)
+    cd = {k: to_device(getattr(cinst, k), layout) for k in "ABcQRMqr"}
+    cx0 = to_device(cinst.x0, layout)
+    couts = [empty((Nc, nx)), empty((Nc, nu)), empty((Nc, nx))]
+
+    def cstep():
+        L.bmpc_lqr_solve(cplan, cd["A"], cd["B"], cd["c"], cd["Q"], cd["R"], cd["M"], cd["q"], cd["r"],
+                         cx0, *couts, variant=L.RICCATI_LEVEL)
+    for _ in range(max(1, args.warmup)):
+        cstep()
+    torch.cuda.synchronize()
+    L.bmpc_profile_only(bwd_name)
+    L.bmpc_profile_enable(True)
+    for _ in range(args.steps):
+        cstep()
+    torch.cuda.synchronize()
+    cprof = L.bmpc_profile_read()
+    L.bmpc_profile_enable(False)
+    L.bmpc_profile_only(None)
+    cst, cbad = L.bmpc_lqr_check(cplan)
+    if cst != 0:
+        raise RuntimeError(f"critical-path LQR solve failed (status {cst}, node {cbad})")
+    c_ms, c_n = cprof[bwd_name]
+    c_us = c_ms / c_n * 1e3
+    dependency_floor = {
+        "tree": f"one root-to-leaf path of {depth + 1} nodes with a leaf stub on each of its "
+                f"{len(branch_stages)} branch nodes ({Nc} nodes)",
+        "kernel": bwd_name, "backward_us": round(c_us, 2), "per_stage_us": round(c_us / (depth + 1), 3),
+        "full_tree_backward_us": round(bwd_avg_s * 1e6, 2),
+        "full_tree_over_floor": round(bwd_avg_s * 1e6 / c_us, 3)}
+    L.bmpc_lqr_plan_destroy(cplan)
+    L.bmpc_tree_destroy(ctree)
     out = {
         "metric": METRIC,
         "value": round(N / (ms_step / 1e3), 1),
@@ -286,6 +340,7 @@ def run_lqr(args, torch, L):
         "solve_algorithmic_bytes": solve_bytes,
         "solve_GBps": round(solve_bytes / (ms_step * 1e-3) / 1e9, 2),
         "roofline": roofline,
+        "dependency_floor": dependency_floor,
     }
     L.bmpc_lqr_plan_destroy(plan)
 
