@@ -168,6 +168,57 @@ def _stages(parent):
     return st
 
 
+def critical_path_floor(torch, L, par, nx, nu, layout, bwd_name, full_us, steps, warmup, seed=77):
+    """Dependency floor of a level-parallel backward kernel: the same kernel
+    on the tree's critical path alone, one root-to-leaf path of the same
+    depth with a leaf stub on each of its branch nodes (so every merge on the
+    path is still done), timed like the full tree.  Its time is what the
+    depth costs with no width."""
+    import bmpc_synth as S
+    from paper_2506_13624_amd.layout import empty, to_device
+
+    N = len(par)
+    stages = _stages(par)
+    depth = int(stages.max())
+    branch_stages = sorted({int(v) for v in stages[np.bincount(par[1:], minlength=N) > 1]})
+    # deepest leaf's path in any order: node k at stage k, then the stubs
+    cat = list(range(-1, depth)) + branch_stages
+    _, cat_par = L.bmpc_tree_order(np.array(cat, dtype=np.int32))
+    cinst = S.lqr_on(cat_par, nx, nu, seed=seed)
+    ctree = L.bmpc_tree_create(cat_par)
+    cplan = L.bmpc_lqr_plan_create(ctree, nx, nu, layout)
+    Nc = len(cat_par)
+    cd = {k: to_device(getattr(cinst, k), layout) for k in "ABcQRMqr"}
+    cx0 = to_device(cinst.x0, layout)
+    couts = [empty((Nc, nx)), empty((Nc, nu)), empty((Nc, nx))]
+
+    def cstep():
+        L.bmpc_lqr_solve(cplan, cd["A"], cd["B"], cd["c"], cd["Q"], cd["R"], cd["M"], cd["q"], cd["r"],
+                         cx0, *couts, variant=L.RICCATI_LEVEL)
+    for _ in range(max(1, warmup)):
+        cstep()
+    torch.cuda.synchronize()
+    L.bmpc_profile_only(bwd_name)
+    L.bmpc_profile_enable(True)
+    for _ in range(steps):
+        cstep()
+    torch.cuda.synchronize()
+    cprof = L.bmpc_profile_read()
+    L.bmpc_profile_enable(False)
+    L.bmpc_profile_only(None)
+    cst, cbad = L.bmpc_lqr_check(cplan)
+    L.bmpc_lqr_plan_destroy(cplan)
+    L.bmpc_tree_destroy(ctree)
+    if cst != 0:
+        raise RuntimeError(f"critical-path LQR solve failed (status {cst}, node {cbad})")
+    c_ms, c_n = cprof[bwd_name]
+    c_us = c_ms / c_n * 1e3
+    return {"tree": f"one root-to-leaf path of {depth + 1} nodes with a leaf stub on each of its "
+                    f"{len(branch_stages)} branch nodes ({Nc} nodes)",
+            "kernel": bwd_name, "backward_us": round(c_us, 2), "per_stage_us": round(c_us / (depth + 1), 3),
+            "full_tree_backward_us": round(full_us, 2), "full_tree_over_floor": round(full_us / c_us, 3)}
+
+
 def run_lqr(args, torch, L):
     from paper_2506_13624_amd.layout import empty, to_device
     import bmpc_synth as S
@@ -276,52 +327,8 @@ def run_lqr(args, torch, L):
     kernels = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]} for k, v in prof_all.items()}
     ms_step = elapsed_ms / args.steps
 
-    # Dependency floor: the same backward kernel on the tree's critical path
-    # alone, one root-to-leaf path of the same depth with a leaf stub on each
-    # of its branch nodes (so every merge on the path is still done), timed
-    # like the full tree.  Its time is what the depth costs with no width.
-    stages = _stages(par)
-    depth = int(stages.max())
-    branch_stages = sorted({int(v) for v in stages[np.bincount(par[1:], minlength=N) > 1]})
-    cat = list(range(-1, depth))  # main path: node k at stage k
-    for s_ in branch_stages:
-        cat.append(s_)  # leaf stub on the path's branch node
-    cat_order, cat_par = L.bmpc_tree_order(np.array(cat, dtype=np.int32))
-    cinst = S.lqr_on(cat_par, nx, nu, seed=77)
-    ctree = L.bmpc_tree_create(cat_par)
-    cplan = L.bmpc_lqr_plan_create(ctree, nx, nu, layout)
-    Nc = len(cat_par)
-    cd = {k: to_device(getattr(cinst, k), layout) for k in "ABcQRMqr"}
-    cx0 = to_device(cinst.x0, layout)
-    couts = [empty((Nc, nx)), empty((Nc, nu)), empty((Nc, nx))]
-
-    def cstep():
-        L.bmpc_lqr_solve(cplan, cd["A"], cd["B"], cd["c"], cd["Q"], cd["R"], cd["M"], cd["q"], cd["r"],
-                         cx0, *couts, variant=L.RICCATI_LEVEL)
-    for _ in range(max(1, args.warmup)):
-        cstep()
-    torch.cuda.synchronize()
-    L.bmpc_profile_only(bwd_name)
-    L.bmpc_profile_enable(True)
-    for _ in range(args.steps):
-        cstep()
-    torch.cuda.synchronize()
-    cprof = L.bmpc_profile_read()
-    L.bmpc_profile_enable(False)
-    L.bmpc_profile_only(None)
-    cst, cbad = L.bmpc_lqr_check(cplan)
-    if cst != 0:
-        raise RuntimeError(f"critical-path LQR solve failed (status {cst}, node {cbad})")
-    c_ms, c_n = cprof[bwd_name]
-    c_us = c_ms / c_n * 1e3
-    dependency_floor = {
-        "tree": f"one root-to-leaf path of {depth + 1} nodes with a leaf stub on each of its "
-                f"{len(branch_stages)} branch nodes ({Nc} nodes)",
-        "kernel": bwd_name, "backward_us": round(c_us, 2), "per_stage_us": round(c_us / (depth + 1), 3),
-        "full_tree_backward_us": round(bwd_avg_s * 1e6, 2),
-        "full_tree_over_floor": round(bwd_avg_s * 1e6 / c_us, 3)}
-    L.bmpc_lqr_plan_destroy(cplan)
-    L.bmpc_tree_destroy(ctree)
+    dependency_floor = critical_path_floor(torch, L, par, nx, nu, layout, bwd_name, bwd_avg_s * 1e6,
+                                           args.steps, args.warmup)
     out = {
         "metric": METRIC,
         "value": round(N / (ms_step / 1e3), 1),
@@ -953,6 +960,9 @@ def run_large_tree(args, torch, L):
                      "backward_fp64_frac": round(alg["bwd_flops"] / (bwd_us * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 6),
                      "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1]}
                                  for k, v in prof.items()}}
+    lvl_kernel = next(k for k in res["level"]["kernels"] if k.startswith("lqr_backward_level"))
+    res["level"]["dependency_floor"] = critical_path_floor(torch, L, par, 4, 2, L.LAYOUT_NODE_MAJOR, lvl_kernel,
+                                                           res["level"]["backward_us"], steps, 5)
     # the same subproblem in FP32, and in mixed precision (FP32 sweeps, FP64
     # residuals, refinement steps added until the FP64 residual floor)
     L.bmpc_lqr_solve(plan, Ae, Be, c, Q, R, M, q, r, x0, *outs, variant=L.RICCATI_LEVEL)
