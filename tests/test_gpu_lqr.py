@@ -483,3 +483,39 @@ def test_lqr_host_arrays_equal_device_solve(name, dims, layout):
     finally:
         L.bmpc_lqr_plan_destroy(plan)
         L.bmpc_tree_destroy(tree)
+
+
+@pytest.mark.parametrize("layout", [L.LAYOUT_NODE_MAJOR, L.LAYOUT_ELEM_MAJOR])
+def test_tree_permute_identity_and_round_trip(layout):
+    """On a tree from bmpc_tree_create the two orders agree (a copy); on a
+    reordered tree a gather then a scatter returns the input bit for bit.
+    src == dst is rejected before any device work."""
+    par = TREES["random_b"]
+    N = len(par)
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal((N, 7))
+    tree = L.bmpc_tree_create(par)
+    try:
+        src = to_device(a, layout)
+        dst = empty((N, 7))
+        L.bmpc_tree_permute(tree, L.TO_LIBRARY_ORDER, layout, 7, src, dst)
+        np.testing.assert_array_equal(from_device(dst, (N, 7), layout), a)
+        with pytest.raises(L.BmpcError) as e:
+            L.bmpc_tree_permute(tree, L.TO_CALLER_ORDER, layout, 7, src, src)
+        assert e.value.status == 1
+    finally:
+        L.bmpc_tree_destroy(tree)
+    cpar = np.full(N, -1, dtype=np.int32)
+    sigma = rng.permutation(N)
+    for i, p in enumerate(par):
+        cpar[sigma[i]] = -1 if p < 0 else sigma[p]
+    tree, order = L.bmpc_tree_create_any(cpar)
+    try:
+        src = to_device(a, layout)
+        mid, back = empty((N, 7)), empty((N, 7))
+        L.bmpc_tree_permute(tree, L.TO_LIBRARY_ORDER, layout, 7, src, mid)
+        L.bmpc_tree_permute(tree, L.TO_CALLER_ORDER, layout, 7, mid, back)
+        np.testing.assert_array_equal(from_device(mid, (N, 7), layout), a[order])
+        np.testing.assert_array_equal(from_device(back, (N, 7), layout), a)
+    finally:
+        L.bmpc_tree_destroy(tree)
